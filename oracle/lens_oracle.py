@@ -1,0 +1,520 @@
+"""FP64 CPU oracle of the batched strong-lens forward model and likelihood.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, plain definition that the
+GPU path is checked against.  Only the test-suite, the package smoke check
+and the benchmark's CPU-baseline leg may import it; the product never does,
+and it imports nothing from the product.  It shares no code with the HIP
+kernels.
+
+Everything is written with plain PyTorch CPU operations in float64 on whole
+sub-pixel grids; the gradient is PyTorch autograd applied to this same plain
+definition (no hand-written derivative).  Inputs that arrive as float32 are
+promoted once, so the oracle evaluates exactly the values the GPU sees.
+
+What is computed (paper Sec. 3, "Methodology"; Sec. 4.2 footnote on
+supersampling).  The paper names the model components and defers their
+formulas to the GIGA-Lens 1.0 paper, which is not available here, so each
+formula below is a published lensing result, restated:
+
+  grid        integer-supersampled pixel grid centred on the cutout
+  ellipticity (e1, e2) -> axis ratio q = (1-c)/(1+c), angle phi = atan2(e2,e1)/2,
+              c = |e|; profiles are evaluated in the frame rotated by phi
+              about each component's own centre
+  EPL         deflection of kappa = (2-t)/2 (b/R)^t, R = sqrt(q^2 x'^2 + y'^2),
+              t = gamma - 1, b = theta_E sqrt(q), by the hypergeometric series
+              of Tessore & Metcalf (2015, A&A 580, A79)
+  SIE         the same profile at t = 1 in closed form (Kormann et al. 1994)
+  shear       alpha = (g1 x + g2 y, g2 x - g1 y) about the origin
+  lens eq.    beta = theta - alpha_mass - alpha_shear
+  Sersic      I_e exp(-b_n[(R/R_e)^(1/n) - 1]), R = sqrt(q x'^2 + y'^2/q),
+              b_n = 1.9992 n - 0.3271; lens light at theta, sources at beta
+  downsample  mean over the s x s sub-pixels of each pixel
+  PSF         zero-padded 'same' 2-D convolution with an odd K x K kernel
+  logL        -1/2 sum w (d - m)^2  (Gaussian, w = inverse variance)
+
+Pins: tests/test_oracle_*.py check these functions against closed forms,
+invariants, library routines and brute force (SIS, EPL->SIE at gamma = 2,
+Poisson equation, Keeton's 1-D integral, Sersic flux via the incomplete
+gamma function, delta-PSF, chi-square statistics, finite differences).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+DT = torch.float64
+R_MIN = 1e-6             # arcsec; radii are clamped to this (both profiles)
+SERIES_REL_TOL = 1e-17   # EPL series stops once every term is below this x |sum|
+SERIES_MAX_TERMS = 500
+
+PRIOR_UNIFORM, PRIOR_NORMAL, PRIOR_LOGNORMAL, PRIOR_TRUNCNORMAL = 0, 1, 2, 3
+
+
+def _t(x) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(DT)
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), dtype=DT)
+
+
+# ---------------------------------------------------------------------------
+# Parameter layout (Sec. 3 lists the parameters of each component)
+# ---------------------------------------------------------------------------
+def n_params(spec) -> int:
+    return (8 if spec.mass_model == "EPL" else 7) + 7 * (spec.n_lens_light + spec.n_source)
+
+
+def unpack(theta: torch.Tensor, spec) -> Dict[str, object]:
+    """Split one parameter vector into named components (canonical order)."""
+    i = 0
+    out: Dict[str, object] = {}
+    out["theta_E"] = theta[i]; i += 1
+    if spec.mass_model == "EPL":
+        out["gamma"] = theta[i]; i += 1
+    else:
+        out["gamma"] = None
+    out["m_e1"], out["m_e2"], out["m_x"], out["m_y"] = theta[i], theta[i + 1], theta[i + 2], theta[i + 3]
+    i += 4
+    out["g1"], out["g2"] = theta[i], theta[i + 1]
+    i += 2
+    lights, sources = [], []
+    for _ in range(spec.n_lens_light):
+        lights.append(tuple(theta[i + k] for k in range(7))); i += 7
+    for _ in range(spec.n_source):
+        sources.append(tuple(theta[i + k] for k in range(7))); i += 7
+    out["lights"], out["sources"] = lights, sources
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Step 1: supersampled grid (Sec. 4.2 footnote: integer supersampling)
+# ---------------------------------------------------------------------------
+def subpixel_grid(nx: int, ny: int, pix: float, s: int) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Sub-pixel centre coordinates, arrays [ny*s, nx*s] (row = y, column = x).
+
+    Pixel (i, j) is centred at x_j = (j - (nx-1)/2) pix, y_i = (i - (ny-1)/2) pix;
+    its sub-pixel (a, b) is offset by ((b + 1/2)/s - 1/2) pix in x and
+    ((a + 1/2)/s - 1/2) pix in y.
+    """
+    xc = (torch.arange(nx, dtype=DT) - (nx - 1) / 2.0) * pix
+    yc = (torch.arange(ny, dtype=DT) - (ny - 1) / 2.0) * pix
+    off = ((torch.arange(s, dtype=DT) + 0.5) / s - 0.5) * pix
+    xs = (xc[:, None] + off[None, :]).reshape(-1)
+    ys = (yc[:, None] + off[None, :]).reshape(-1)
+    Y, X = torch.meshgrid(ys, xs, indexing="ij")
+    return X, Y
+
+
+# ---------------------------------------------------------------------------
+# Step 2: ellipticity and rotated frame (Sec. 3: eccentricities e1, e2)
+# ---------------------------------------------------------------------------
+def ellipticity_to_q_phi(e1, e2):
+    c = torch.sqrt(e1 * e1 + e2 * e2)
+    q = (1.0 - c) / (1.0 + c)
+    phi = 0.5 * torch.atan2(e2, e1)
+    return q, phi
+
+
+def to_frame(x, y, x0, y0, phi):
+    dx, dy = x - x0, y - y0
+    cp, sp = torch.cos(phi), torch.sin(phi)
+    return cp * dx + sp * dy, -sp * dx + cp * dy
+
+
+def from_frame(ax, ay, phi):
+    cp, sp = torch.cos(phi), torch.sin(phi)
+    return cp * ax - sp * ay, sp * ax + cp * ay
+
+
+# ---------------------------------------------------------------------------
+# Step 3: EPL deflection, Tessore & Metcalf (2015) series
+# ---------------------------------------------------------------------------
+def epl_deflection(x, y, theta_E, gamma, e1, e2, x0, y0, n_terms: Optional[int] = None,
+                   return_terms: bool = False):
+    """Deflection of the elliptical power law, in the image frame.
+
+    In the rotated frame, with R = sqrt(q^2 x'^2 + y'^2) and
+    e^{i phi_R} = (q x' + i y') / R:
+        alpha' = 2b/(1+q) (b/R)^(t-1) e^{i phi_R} sum_n W_n,
+        W_0 = 1,  W_n = W_{n-1} * [-f (2n - 2 + t)/(2n + 2 - t)] e^{2 i phi_R},
+    f = (1-q)/(1+q).  The series is summed until every term is below
+    SERIES_REL_TOL of the running sum (or exactly ``n_terms`` terms beyond
+    W_0 if given).  alpha = 0 where R < R_MIN.
+    """
+    q, phi = ellipticity_to_q_phi(e1, e2)
+    t = gamma - 1.0
+    b = theta_E * torch.sqrt(q)
+    f = (1.0 - q) / (1.0 + q)
+    xp, yp = to_frame(x, y, x0, y0, phi)
+    R2 = q * q * xp * xp + yp * yp
+    inside = R2 < R_MIN * R_MIN
+    R = torch.sqrt(torch.where(inside, torch.full_like(R2, R_MIN * R_MIN), R2))
+    ec, es = q * xp / R, yp / R                    # e^{i phi_R}
+    c2, s2 = ec * ec - es * es, 2.0 * ec * es      # e^{2 i phi_R}
+    wr, wi = torch.ones_like(R), torch.zeros_like(R)
+    sr, si = wr, wi
+    n = 1
+    used = 0
+    while True:
+        ratio = -f * (2.0 * n - 2.0 + t) / (2.0 * n + 2.0 - t)
+        wr, wi = ratio * (wr * c2 - wi * s2), ratio * (wr * s2 + wi * c2)
+        sr, si = sr + wr, si + wi
+        used = n
+        if n_terms is not None:
+            if n >= n_terms:
+                break
+        else:
+            with torch.no_grad():
+                mag_t = torch.sqrt(wr * wr + wi * wi).max()
+                mag_s = torch.sqrt(sr * sr + si * si).min()
+            if mag_t <= SERIES_REL_TOL * mag_s or n >= SERIES_MAX_TERMS:
+                break
+        n += 1
+    pref = 2.0 * b / (1.0 + q) * torch.pow(b / R, t - 1.0)
+    axp = pref * (ec * sr - es * si)
+    ayp = pref * (ec * si + es * sr)
+    zero = torch.zeros_like(axp)
+    axp = torch.where(inside, zero, axp)
+    ayp = torch.where(inside, zero, ayp)
+    ax, ay = from_frame(axp, ayp, phi)
+    if return_terms:
+        return ax, ay, used
+    return ax, ay
+
+
+def sie_deflection(x, y, theta_E, e1, e2, x0, y0):
+    """Singular isothermal ellipsoid (t = 1) in closed form.
+
+    With psi = sqrt(q^2 x'^2 + y'^2) and s = sqrt(1 - q^2):
+        alpha'_x = b/s atan(s x'/psi),  alpha'_y = b/s atanh(s y'/psi),
+    b = theta_E sqrt(q); the q -> 1 limit is b (x', y')/psi.  alpha = 0 where
+    psi < R_MIN.
+    """
+    q, phi = ellipticity_to_q_phi(e1, e2)
+    b = theta_E * torch.sqrt(q)
+    xp, yp = to_frame(x, y, x0, y0, phi)
+    R2 = q * q * xp * xp + yp * yp
+    inside = R2 < R_MIN * R_MIN
+    psi = torch.sqrt(torch.where(inside, torch.full_like(R2, R_MIN * R_MIN), R2))
+    s = torch.sqrt(1.0 - q * q)
+    if float(s.detach()) > 1e-7:
+        axp = b / s * torch.atan(s * xp / psi)
+        ayp = b / s * torch.atanh(s * yp / psi)
+    else:
+        axp = b * xp / psi
+        ayp = b * yp / psi
+    zero = torch.zeros_like(axp)
+    axp = torch.where(inside, zero, axp)
+    ayp = torch.where(inside, zero, ayp)
+    return from_frame(axp, ayp, phi)
+
+
+def shear_deflection(x, y, g1, g2):
+    """External shear about the origin: alpha = (g1 x + g2 y, g2 x - g1 y)."""
+    return g1 * x + g2 * y, g2 * x - g1 * y
+
+
+# ---------------------------------------------------------------------------
+# Step 6: elliptical Sersic surface brightness
+# ---------------------------------------------------------------------------
+def sersic_bn(n):
+    """Capaccioli (1989) linear approximation of the Sersic b_n."""
+    return 1.9992 * n - 0.3271
+
+
+def sersic(x, y, R_e, n, e1, e2, xc, yc, I_e):
+    """I_e exp(-b_n [(R/R_e)^(1/n) - 1]), R = sqrt(q x'^2 + y'^2/q) >= R_MIN."""
+    q, phi = ellipticity_to_q_phi(e1, e2)
+    xp, yp = to_frame(x, y, xc, yc, phi)
+    R2 = q * xp * xp + yp * yp / q
+    R = torch.sqrt(torch.clamp(R2, min=R_MIN * R_MIN))
+    return I_e * torch.exp(-sersic_bn(n) * (torch.pow(R / R_e, 1.0 / n) - 1.0))
+
+
+# ---------------------------------------------------------------------------
+# Steps 7-10: sub-pixel image, downsample, PSF, likelihood
+# ---------------------------------------------------------------------------
+def ellipticity_valid(theta: torch.Tensor, spec) -> bool:
+    """False if any component has |e| >= 1 (q <= 0: no valid profile)."""
+    p = unpack(theta.detach(), spec)
+    es = [(p["m_e1"], p["m_e2"])] + [(c[2], c[3]) for c in p["lights"] + p["sources"]]
+    return all(float(a * a + b * b) < 1.0 for a, b in es)
+
+
+def subpixel_image(theta: torch.Tensor, spec, n_terms: Optional[int] = None) -> torch.Tensor:
+    """Surface brightness on the supersampled grid, [ny*s, nx*s]."""
+    X, Y = subpixel_grid(spec.nx, spec.ny, spec.pix_scale, spec.supersample)
+    p = unpack(theta, spec)
+    if spec.mass_model == "EPL":
+        ax, ay = epl_deflection(X, Y, p["theta_E"], p["gamma"], p["m_e1"], p["m_e2"],
+                                p["m_x"], p["m_y"], n_terms=n_terms)
+    else:
+        ax, ay = sie_deflection(X, Y, p["theta_E"], p["m_e1"], p["m_e2"], p["m_x"], p["m_y"])
+    sx, sy = shear_deflection(X, Y, p["g1"], p["g2"])
+    bx, by = X - ax - sx, Y - ay - sy
+    v = torch.zeros_like(X)
+    for c in p["lights"]:
+        v = v + sersic(X, Y, *c)
+    for c in p["sources"]:
+        v = v + sersic(bx, by, *c)
+    return v
+
+
+def downsample(v: torch.Tensor, s: int) -> torch.Tensor:
+    """Mean over each s x s block: [ny*s, nx*s] -> [ny, nx]."""
+    ny, nx = v.shape[0] // s, v.shape[1] // s
+    return v.reshape(ny, s, nx, s).mean(dim=(1, 3))
+
+
+def convolve_psf(img: torch.Tensor, psf) -> torch.Tensor:
+    """m[i, j] = sum_{u,v} P[u, v] img[i - u + h, j - v + h], zero outside, h = (K-1)/2."""
+    P = _t(psf)
+    K = P.shape[0]
+    h = (K - 1) // 2
+    ny, nx = img.shape
+    pad = torch.zeros((ny + 2 * h, nx + 2 * h), dtype=img.dtype)
+    pad[h:h + ny, h:h + nx] = img
+    out = torch.zeros_like(img)
+    for u in range(K):
+        for v in range(K):
+            r0, c0 = 2 * h - u, 2 * h - v
+            out = out + P[u, v] * pad[r0:r0 + ny, c0:c0 + nx]
+    return out
+
+
+def model_image(theta, spec, psf, n_terms: Optional[int] = None) -> torch.Tensor:
+    """PSF-convolved, downsampled model image [ny, nx] (float64)."""
+    th = _t(theta)
+    return convolve_psf(downsample(subpixel_image(th, spec, n_terms), spec.supersample), psf)
+
+
+def chi2(model: torch.Tensor, data, invvar) -> torch.Tensor:
+    d, w = _t(data), _t(invvar)
+    return (w * (d - model) ** 2).sum()
+
+
+def loglike(theta, spec, psf, data, invvar) -> float:
+    th = _t(theta)
+    if not ellipticity_valid(th, spec):
+        return -math.inf
+    with torch.no_grad():
+        return float(-0.5 * chi2(model_image(th, spec, psf), data, invvar))
+
+
+def loglike_and_grad(theta, spec, psf, data, invvar, n_terms: Optional[int] = None):
+    """(logL, dlogL/dtheta[d]) by autograd through the plain definition."""
+    th = _t(theta).clone().requires_grad_(True)
+    if not ellipticity_valid(th, spec):
+        return -math.inf, np.zeros(th.shape[0])
+    L = -0.5 * chi2(model_image(th, spec, psf, n_terms), data, invvar)
+    (g,) = torch.autograd.grad(L, th)
+    return float(L.detach()), g.numpy()
+
+
+def gradient_scale(theta, spec, psf, data, invvar) -> np.ndarray:
+    """S_j = sum_pix |r_pix * dm_pix/dtheta_j| with r = w (d - m).
+
+    The L1 size of the terms whose sum is the gradient component j; the
+    parity tolerance of a gradient component is relative to |g_j| + S_j.
+    """
+    th = _t(theta).clone().requires_grad_(True)
+    m = model_image(th, spec, psf)
+    r = (_t(invvar) * (_t(data) - m)).detach()
+    d = th.shape[0]
+    J = torch.autograd.functional.jacobian(lambda z: model_image(z, spec, psf).reshape(-1), th.detach())
+    return (r.reshape(-1, 1).abs() * J.abs()).sum(0).numpy()
+
+
+# ---------------------------------------------------------------------------
+# Batched helpers (one particle at a time: slow by design)
+# ---------------------------------------------------------------------------
+def batch_model_images(thetas, spec, psf) -> np.ndarray:
+    return np.stack([model_image(th, spec, psf).numpy() for th in np.asarray(thetas)])
+
+
+def batch_loglike(thetas, spec, psf, data, invvar) -> np.ndarray:
+    return np.array([loglike(th, spec, psf, data, invvar) for th in np.asarray(thetas)])
+
+
+def batch_loglike_grad(thetas, spec, psf, data, invvar):
+    L, G = [], []
+    for th in np.asarray(thetas):
+        l, g = loglike_and_grad(th, spec, psf, data, invvar)
+        L.append(l); G.append(g)
+    return np.array(L), np.stack(G)
+
+
+# ---------------------------------------------------------------------------
+# Prior and bijection to the unconstrained space (Sec. 3.1: tilde quantities;
+# Sec. 4.2 eq. sim-dist: uniform, normal, log-normal, truncated normal)
+# ---------------------------------------------------------------------------
+def _log_ndtr(z):
+    return torch.special.log_ndtr(z)
+
+
+def to_constrained(u: torch.Tensor, table) -> Tuple[torch.Tensor, torch.Tensor]:
+    """theta = T(u) per parameter, and log|dtheta/du| summed over parameters.
+
+    uniform / truncnormal on [lo, hi]: theta = lo + (hi - lo) sigmoid(u)
+    normal: theta = u;  lognormal: theta = exp(u)
+    """
+    tab = _t(table)
+    out = []
+    logj = torch.zeros((), dtype=DT)
+    for k in range(tab.shape[0]):
+        kind = int(tab[k, 0])
+        uk = u[k]
+        if kind in (PRIOR_UNIFORM, PRIOR_TRUNCNORMAL):
+            lo, hi = (tab[k, 1], tab[k, 2]) if kind == PRIOR_UNIFORM else (tab[k, 3], tab[k, 4])
+            sgm = torch.sigmoid(uk)
+            out.append(lo + (hi - lo) * sgm)
+            logj = logj + torch.log(hi - lo) + torch.nn.functional.logsigmoid(uk) + torch.nn.functional.logsigmoid(-uk)
+        elif kind == PRIOR_NORMAL:
+            out.append(uk)
+        elif kind == PRIOR_LOGNORMAL:
+            out.append(torch.exp(uk))
+            logj = logj + uk
+        else:
+            raise ValueError(kind)
+    return torch.stack(out), logj
+
+
+def to_unconstrained(theta: torch.Tensor, table) -> torch.Tensor:
+    tab = _t(table)
+    out = []
+    for k in range(tab.shape[0]):
+        kind = int(tab[k, 0])
+        x = theta[k]
+        if kind in (PRIOR_UNIFORM, PRIOR_TRUNCNORMAL):
+            lo, hi = (tab[k, 1], tab[k, 2]) if kind == PRIOR_UNIFORM else (tab[k, 3], tab[k, 4])
+            p = (x - lo) / (hi - lo)
+            out.append(torch.log(p) - torch.log1p(-p))
+        elif kind == PRIOR_NORMAL:
+            out.append(x)
+        elif kind == PRIOR_LOGNORMAL:
+            out.append(torch.log(x))
+        else:
+            raise ValueError(kind)
+    return torch.stack(out)
+
+
+def log_prior(theta: torch.Tensor, table) -> torch.Tensor:
+    """Sum of the per-parameter log densities on the constrained values."""
+    tab = _t(table)
+    lp = torch.zeros((), dtype=DT)
+    half_log_2pi = 0.5 * math.log(2.0 * math.pi)
+    for k in range(tab.shape[0]):
+        kind = int(tab[k, 0])
+        x = theta[k]
+        a, b = tab[k, 1], tab[k, 2]
+        if kind == PRIOR_UNIFORM:
+            lp = lp - torch.log(b - a)
+        elif kind == PRIOR_NORMAL:
+            lp = lp - 0.5 * ((x - a) / b) ** 2 - torch.log(b) - half_log_2pi
+        elif kind == PRIOR_LOGNORMAL:
+            lx = torch.log(x)
+            lp = lp - 0.5 * ((lx - a) / b) ** 2 - torch.log(b) - half_log_2pi - lx
+        elif kind == PRIOR_TRUNCNORMAL:
+            lo, hi = tab[k, 3], tab[k, 4]
+            z = torch.special.ndtr((hi - a) / b) - torch.special.ndtr((lo - a) / b)
+            lp = lp - 0.5 * ((x - a) / b) ** 2 - torch.log(b) - half_log_2pi - torch.log(z)
+        else:
+            raise ValueError(kind)
+    return lp
+
+
+def log_posterior_unconstrained(u, spec, psf, data, invvar, table, with_jacobian: bool):
+    """logL(T(u)) + log prior(T(u)) [+ log|J|] and its gradient w.r.t. u.
+
+    The HMC target includes the Jacobian of the bijection; the MAP objective
+    (multi-start gradient descent) does not, so its optimum is the MAP of
+    the constrained parameters.
+    """
+    uu = _t(u).clone().requires_grad_(True)
+    th, logj = to_constrained(uu, table)
+    if not ellipticity_valid(th, spec):
+        return -math.inf, np.zeros(uu.shape[0])
+    L = -0.5 * chi2(model_image(th, spec, psf), data, invvar) + log_prior(th, table)
+    if with_jacobian:
+        L = L + logj
+    (g,) = torch.autograd.grad(L, uu)
+    return float(L.detach()), g.numpy()
+
+
+# ---------------------------------------------------------------------------
+# Optimiser and sampler (Sec. 3: multi-start MAP with Adam; HMC)
+# ---------------------------------------------------------------------------
+def adam_step(x, g, m, v, k: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015) minimising a loss with gradient g.
+
+    k is the 1-based step number used in the bias corrections.
+    """
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** k)
+    vh = v / (1 - b2 ** k)
+    return x - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def leapfrog(u, p, grad_fn, eps: float, L: int, inv_mass):
+    """L leapfrog steps of Hamiltonian dynamics with diagonal mass matrix.
+
+    grad_fn(u) returns the gradient of log p(u).  Half kick, drift, half
+    kick per step (Neal 2011).
+    """
+    u = np.array(u, dtype=np.float64)
+    p = np.array(p, dtype=np.float64)
+    g = grad_fn(u)
+    for _ in range(L):
+        p = p + 0.5 * eps * g
+        u = u + eps * inv_mass * p
+        g = grad_fn(u)
+        p = p + 0.5 * eps * g
+    return u, p
+
+
+def hamiltonian(logp: float, p, inv_mass) -> float:
+    p = np.asarray(p, dtype=np.float64)
+    return -logp + 0.5 * float(np.sum(p * p * inv_mass))
+
+
+# ---------------------------------------------------------------------------
+# Counter-based RNG: Philox (Salmon et al. 2011, "Parallel random numbers:
+# as easy as 1, 2, 3").  Each round multiplies words 0 and 2 by the round
+# multipliers, swaps the halves of the products into the four output words
+# xor-ed with the odd words and the key, and the key is bumped by the Weyl
+# constants between rounds.
+# ---------------------------------------------------------------------------
+_PHILOX_CONST = {
+    32: (0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85),
+    64: (0xD2E7470EE14C6C93, 0xCA5A826395121157, 0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B),
+}
+
+
+def philox4(counter: Sequence[int], key: Sequence[int], width: int = 32, rounds: int = 10) -> List[int]:
+    """One Philox4xW block: 4 counter words, 2 key words -> 4 output words."""
+    m0, m1, w0, w1 = _PHILOX_CONST[width]
+    mask = (1 << width) - 1
+    c0, c1, c2, c3 = (int(w) & mask for w in counter)
+    k0, k1 = (int(w) & mask for w in key)
+    for r in range(rounds):
+        if r > 0:
+            k0 = (k0 + w0) & mask
+            k1 = (k1 + w1) & mask
+        p0 = m0 * c0
+        p1 = m1 * c2
+        hi0, lo0 = p0 >> width, p0 & mask
+        hi1, lo1 = p1 >> width, p1 & mask
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ k0) & mask, lo1, (hi0 ^ c3 ^ k1) & mask, lo0
+    return [c0, c1, c2, c3]
+
+
+def philox4x32(counter: Sequence[int], key: Sequence[int], rounds: int = 10) -> List[int]:
+    return philox4(counter, key, 32, rounds)
+
+
+def uniform_from_bits(w: int) -> float:
+    """((w >> 8) + 1/2) * 2^-24: a uniform in (0, 1), exact in float32."""
+    return ((w >> 8) + 0.5) * (2.0 ** -24)
