@@ -1,0 +1,177 @@
+"""Benchmark: batched logL + gradient evaluations per second at 100x100 px.
+
+Workload (one GPU): 100x100 pixels at 0.05"/px, 3x3 supersampling, EPL +
+external shear, one Sersic lens light, two Sersic sources, 21x21 PSF,
+4096 particles drawn from the uniform prior box (synthetic, seeded).
+One step = one multi-start MAP step over all particles: bijection + log
+prior, forward model, likelihood and adjoint gradient, Adam update.
+
+Prints ONE JSON line.  Timing: W untimed warm-up steps, then K steps between
+two device synchronisations; the dominant kernel's average duration is read
+from HIP events recorded around each of its launches on the launch stream.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "batched logL+grad evals/s at 100x100 px; time-to-MAP learned vs plain init"
+PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32 / FP64
+PEAK_FP32_PACKED = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--particles", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    return ap.parse_args()
+
+
+def adjoint_flops_per_subpixel(K_mean, NL, NS, epl=True):
+    """Algorithmic flops of the adjoint pass per sub-pixel (FMA = 2, other = 1).
+
+    Counted from the operations the pass must perform: recompute of the
+    sub-pixel forward model (float64 deflection with a K-term series, shear,
+    lens equation, float32 Sersic values) and the reverse sweep (series
+    derivatives, chain through the deflection, Sersic adjoints and the
+    accumulated sums).  See the design doc for the itemised count.
+    """
+    series_fwd = 8 * K_mean                     # complex Horner, 4 FMA per term
+    series_adj = 8 * K_mean * (2 if epl else 1)  # S'(z) and dS/dt
+    mass_fwd = 40 + (60 if epl else 0)          # offsets, U, 1/R, V0, z, pow, alpha
+    shear_lens = 12
+    sersic_fwd = 18                             # offset, R^2, log2, 2 exp2, mults
+    sersic_adj = 30                             # + 8 accumulations, 1/R^2, beta adjoint
+    mass_adj = 70
+    return (series_fwd + series_adj + mass_fwd + shear_lens + mass_adj
+            + (NL + NS) * (sersic_fwd + sersic_adj))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2606_30633_amd import lens, synth
+
+    dev = torch.device("cuda", 0)
+    spec = synth.config2_spec()
+    sysm = synth.config2_system()
+    P = args.particles
+    th = synth.particles_box(sysm, P, 0)
+    psf_t = torch.tensor(sysm.psf, device=dev)
+    inv_t = torch.tensor(sysm.invvar, device=dev)
+    # observed image: forward model at the truth (GPU) + seeded noise
+    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
+    model = lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
+    data = (model + torch.tensor(sysm.noise, device=dev)).contiguous()
+    plan0.close()
+    plan = lens.LensPlan(spec, psf_t, data, inv_t, P, dev)
+    theta = torch.tensor(th, device=dev)
+    logl = torch.empty(P, device=dev)
+    grad = torch.empty((P, spec.n_params), device=dev)
+
+    def step():
+        lens.lens_loglike_grad(plan, theta, logl, grad)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.enable_timing(False)
+    tim = plan.read_timing()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    evals_per_s = P / (ms_step * 1e-3)
+
+    # dominant kernel: adjoint sub-pixel pass
+    adj_ms, adj_n = tim["adjoint"]
+    adj_avg_ms = adj_ms / max(adj_n, 1)
+    kp_mean = float(np.mean(_series_terms(th, spec)))
+    nsub = (spec.nx * spec.supersample) * (spec.ny * spec.supersample)
+    fl_sub = adjoint_flops_per_subpixel(kp_mean, spec.n_lens_light, spec.n_source, True)
+    flops_launch = fl_sub * nsub * P
+    achieved = flops_launch / (adj_avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None,
+                "kernel": "k_adjoint", "avg_ms": round(adj_avg_ms, 4),
+                "frac_of_fp32_packed_peak": round(achieved / PEAK_FP32_PACKED, 4),
+                "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(spec, sysm, th[:args.cpu_sample])
+
+    out = {
+        "metric": METRIC, "value": round(evals_per_s, 1), "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "100x100 px, s=3, EPL+shear, 1 Sersic lens, 2 Sersic sources, "
+                               "21x21 PSF, logL+grad over particles", "particles": P,
+                   "sub_pixels_per_particle": nsub, "params": spec.n_params},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _series_terms(th, spec):
+    """Series length per particle (host mirror of the kernel's rule, for the flop count)."""
+    o = 2
+    c = np.hypot(th[:, o], th[:, o + 1]).astype(np.float64)
+    t = th[:, 1].astype(np.float64) - 1.0
+    out = []
+    for ci, ti in zip(c, t):
+        if ci <= 0:
+            out.append(4)
+            continue
+        cn, Dn, cp, K = 1.0, 0.0, 1.0, 0
+        for n in range(1, 128):
+            a, b = 2 * n - 2 + ti, 2 * n + 2 - ti
+            cn *= a / b
+            Dn += 1 / a + 1 / b
+            cp *= ci
+            K = n
+            nxt = cn * (2 * n + ti) / (2 * n + 4 - ti)
+            if (n + 2) * nxt * (Dn + 2) * cp / (1 - ci) ** 2 < 2.0 ** -34:
+                break
+        out.append(((K + 4) // 4) * 4)
+    return np.array(out)
+
+
+def cpu_baseline(spec, sysm, th_sample):
+    """The FP64 oracle timed on the host cores on a bounded sample."""
+    import torch
+    from oracle import lens_oracle as O
+    model = O.model_image(sysm.truth, spec, sysm.psf).numpy()
+    data = (model + sysm.noise).astype(np.float32)
+    O.loglike_and_grad(th_sample[0], spec, sysm.psf, data, sysm.invvar)   # warm-up
+    t0 = time.perf_counter()
+    for t in th_sample:
+        O.loglike_and_grad(t, spec, sysm.psf, data, sysm.invvar)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(th_sample) / dt, 3), "unit": "evals/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{len(th_sample)} particles of the same workload, logL+grad (FP64 autograd)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * lens_api.h -- C ABI of the batched strong-lens likelihood library (liblens.so).
+ *
+ * The library evaluates, for many parameter vectors ("particles" or "chains")
+ * of one lens system at once, the forward model of the paper's Sec. 3
+ * (elliptical power-law or SIE mass + external shear, elliptical Sersic lens
+ * light and sources, a supersampled pixel grid as in the Sec. 4.2 footnote),
+ * downsampling, PSF convolution and a Gaussian log-likelihood, together with
+ * the gradient of the log-likelihood with respect to every parameter.  On
+ * top of that it runs the paper's multi-start MAP stage (Sec. 3: gradient
+ * descent with Adam, every particle independent, Sec. 3.1) and HMC
+ * transitions (Sec. 3: HMC; Sec. 3.1: independent chains).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are DEVICE pointers owned by the caller; h_* are host
+ *    pointers, read during the call only.  The library never frees caller
+ *    memory and never keeps caller pointers beyond a call, except the
+ *    system arrays handed to lens_plan_create (PSF, data, inverse variance),
+ *    which must stay valid and unchanged while the plan lives.
+ *  - Every compute call is asynchronous on the given stream (a hipStream_t
+ *    passed as void*; NULL is the default stream).  Launch errors are
+ *    returned as LENS_EHIP; faults inside kernels surface at the caller's
+ *    next synchronisation.
+ *  - Arrays are row-major float32.  Parameters are [P][d] in the canonical
+ *    order (see lens_num_params); images are [P][ny][nx], row = y.
+ *  - Results are bitwise deterministic for a given plan and launch shape:
+ *    no floating-point atomics; reductions run in a fixed order.
+ *  - A particle whose parameters are not all finite gets logL = NaN and a
+ *    NaN gradient.  A particle with an ellipticity |e| >= 1 on any
+ *    component has no valid profile: logL = -inf and gradient 0.
+ *  - Functions return a lens_status and never throw.
+ *
+ * Canonical parameter order (d = n_mass + 7 * (n_lens_light + n_source)):
+ *   mass   : theta_E ["], [gamma (EPL only)], e1, e2, x ["], y ["]
+ *   shear  : g1, g2                                      (n_mass = 7 | 8)
+ *   Sersic : R_e ["], n, e1, e2, x ["], y ["], I_e       per component,
+ *            lens-light components first, then sources.
+ */
+#ifndef LENS_API_H
+#define LENS_API_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lens_status;
+#define LENS_OK            0
+#define LENS_EINVAL       -1   /* bad argument (NULL pointer, size, descriptor) */
+#define LENS_EUNSUPPORTED -2   /* valid request outside what the library builds */
+#define LENS_EHIP         -3   /* a HIP runtime call or kernel launch failed */
+#define LENS_ENOMEM       -4   /* device or host allocation failed */
+
+#define LENS_MASS_SIE 0        /* singular isothermal ellipsoid (gamma = 2) */
+#define LENS_MASS_EPL 1        /* elliptical power law, free slope gamma */
+
+#define LENS_MAX_LENS_LIGHT 3
+#define LENS_MAX_SOURCE     3
+#define LENS_MAX_PSF       31
+#define LENS_MAX_SIDE     256
+
+/* Geometry and composition of one lens system (Sec. 3 model components).
+ * Sub-pixel (a, b) of pixel (i, j) sits at
+ *   x = (s*j + b - (s*nx - 1)/2) * pix_scale / s,
+ *   y = (s*i + a - (s*ny - 1)/2) * pix_scale / s          (arcsec).      */
+typedef struct lens_model_desc {
+    int32_t nx, ny;         /* image size in pixels, 1..LENS_MAX_SIDE */
+    float   pix_scale;      /* arcsec per pixel, > 0 */
+    int32_t supersample;    /* s >= 1: s x s sub-pixels per pixel, averaged */
+    int32_t psf_size;       /* odd K, 1..LENS_MAX_PSF; PSF centre at (K-1)/2 */
+    int32_t mass_model;     /* LENS_MASS_SIE | LENS_MASS_EPL (+ external shear) */
+    int32_t n_lens_light;   /* 0..LENS_MAX_LENS_LIGHT Sersic components at theta */
+    int32_t n_source;       /* 1..LENS_MAX_SOURCE Sersic components at beta */
+} lens_model_desc;
+
+typedef struct lens_plan lens_plan;   /* opaque; owns device scratch */
+
+/* Human-readable text of a status code (static storage). */
+const char* lens_status_string(lens_status s);
+
+/* Number of parameters d of a model, or -1 if the descriptor is invalid. */
+int32_t lens_num_params(const lens_model_desc* desc);
+
+/* Create a plan for one system and up to max_particles particles per call.
+ *   d_psf    [K][K]   PSF, used as given (normally normalised to sum 1);
+ *                     convolution is m = sum_{u,v} P[u][v] img[i-u+h][j-v+h],
+ *                     zero outside the image, h = (K-1)/2.
+ *   d_data   [ny][nx] observed image d.
+ *   d_invvar [ny][nx] inverse variance w = 1/sigma^2 per pixel (>= 0).
+ * The plan copies desc, allocates its device scratch (proportional to
+ * max_particles * nx * ny) and keeps the three device pointers.
+ * Errors: LENS_EINVAL for a bad descriptor/pointer, LENS_ENOMEM. */
+lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf,
+                             const float* d_data, const float* d_invvar,
+                             int32_t max_particles, lens_plan** out);
+lens_status lens_plan_destroy(lens_plan* plan);
+
+/* Tuning knob of the sub-pixel kernels: pixels handled per thread of one
+ * work-group (1..64).  Changes only the launch shape, never the result
+ * beyond float rounding of the reductions. */
+lens_status lens_plan_set_pixels_per_thread(lens_plan* plan, int32_t ppt);
+
+/* Forward model (Sec. 3): PSF-convolved, downsampled model images.
+ *   d_theta [P][d] in, d_images [P][ny][nx] out.  1 <= P <= max_particles. */
+lens_status lens_forward(lens_plan* plan, int32_t P, const float* d_theta,
+                         float* d_images, void* stream);
+
+/* Gaussian log-likelihood logL = -1/2 sum_pix w (d - m)^2 per particle
+ * (the constant -1/2 sum log(2 pi / w) is not included).
+ *   d_theta [P][d] in, d_logl [P] out. */
+lens_status lens_loglike(lens_plan* plan, int32_t P, const float* d_theta,
+                         float* d_logl, void* stream);
+
+/* logL and its gradient dlogL/dtheta by a hand-written adjoint.
+ *   d_theta [P][d] in; d_logl [P] out; d_grad [P][d] out;
+ *   d_logl64 [P] out, optional (NULL): logL accumulated in float64. */
+lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
+                              float* d_logl, float* d_grad, double* d_logl64,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (diagnostics, not part of the model).
+ * With timing enabled, every kernel a plan launches is bracketed by two HIP
+ * events recorded on the call's stream; lens_plan_read_timing synchronises
+ * on those events, writes per-kernel totals and resets them.  Kernel slots:
+ * LENS_K_PROLOGUE .. LENS_K_FINALIZE.  Timing must be off while a stream is
+ * being captured into a graph.
+ *   h_ms    [LENS_NUM_KERNEL_SLOTS] total milliseconds per slot (out)
+ *   h_count [LENS_NUM_KERNEL_SLOTS] launches per slot (out)
+ * Up to 65536 launches per slot are recorded between reads; more are
+ * counted but not timed (LENS_EUNSUPPORTED from the read).
+ * ------------------------------------------------------------------------- */
+#define LENS_K_PROLOGUE 0
+#define LENS_K_RENDER   1
+#define LENS_K_PSF      2
+#define LENS_K_ADJOINT  3
+#define LENS_K_FINALIZE 4
+#define LENS_NUM_KERNEL_SLOTS 8
+
+lens_status lens_plan_enable_timing(lens_plan* plan, int32_t enable);
+lens_status lens_plan_read_timing(lens_plan* plan, double* h_ms, int64_t* h_count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LENS_API_H */

@@ -318,13 +318,16 @@ def gradient_scale(theta, spec, psf, data, invvar) -> np.ndarray:
 
     The L1 size of the terms whose sum is the gradient component j; the
     parity tolerance of a gradient component is relative to |g_j| + S_j.
+    The Jacobian dm/dtheta is taken in forward mode (one tangent per
+    parameter).
     """
-    th = _t(theta).clone().requires_grad_(True)
-    m = model_image(th, spec, psf)
-    r = (_t(invvar) * (_t(data) - m)).detach()
-    d = th.shape[0]
-    J = torch.autograd.functional.jacobian(lambda z: model_image(z, spec, psf).reshape(-1), th.detach())
-    return (r.reshape(-1, 1).abs() * J.abs()).sum(0).numpy()
+    th = _t(theta)
+    with torch.no_grad():
+        m = model_image(th, spec, psf)
+    r = (_t(invvar) * (_t(data) - m)).reshape(-1, 1)
+    J = torch.autograd.functional.jacobian(lambda z: model_image(z, spec, psf).reshape(-1), th,
+                                           strategy="forward-mode", vectorize=True)
+    return (r.abs() * J.abs()).sum(0).numpy()
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,112 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lens_api.h"
+
+namespace lens {
+
+// ---------------------------------------------------------------------------
+// Per-particle constant block (float words), written by the prologue kernel
+// and read by every per-sub-pixel kernel through wave-uniform (scalar) loads.
+// ---------------------------------------------------------------------------
+constexpr int C_VALID = 0;    // 1 valid, 0 no valid profile (-inf), 2 non-finite (NaN)
+constexpr int C_KP = 1;       // padded series length KP (KP+1 multiple of 4), as float
+// Mass block in float64 (word offsets, 8-byte aligned):
+constexpr int D_X0 = 4;       // mass centre
+constexpr int D_Y0 = 6;
+constexpr int D_E1 = 8;       // mass ellipticity eps = e1 + i e2
+constexpr int D_E2 = 10;
+constexpr int D_UA = 12;      // U = (w - eps conj(w)) / (1 + |eps|):
+constexpr int D_UB = 14;      //   Ux = UA wx - UE wy,  Uy = UB wy - UE wx
+constexpr int D_UE = 16;
+constexpr int D_C0 = 18;      // theta_E sqrt(1 - c^2)  (= 2b/(1+q))
+constexpr int D_K0 = 20;      // (t-1) log2 b
+constexpr int D_K1 = 22;      // (t-1)/2
+constexpr int D_G1 = 24;      // external shear
+constexpr int D_G2 = 26;
+constexpr int C_SERS = 32;    // Sersic components: SERS_STRIDE words each, float64 fields
+constexpr int SERS_STRIDE = 24;
+constexpr int S_XC = 0, S_YC = 2, S_A11 = 4, S_A12 = 6, S_A22 = 8, S_IE = 10,
+              S_KU = 12, S_KU0 = 14, S_BL = 16;   // float64 (word offsets)
+constexpr int S_KAP2 = 18;                         // float32
+constexpr int MAX_COMP = LENS_MAX_LENS_LIGHT + LENS_MAX_SOURCE;
+constexpr int KMAX_PAD = 128;            // entries per coefficient array
+constexpr int C_COEF_S = 176;            // float64 c_0..c_KP (2 words each)
+constexpr int C_COEF_Z = C_COEF_S + 2 * KMAX_PAD;   // float (m+1) c_{m+1}: S'(z)
+constexpr int C_COEF_T = C_COEF_Z + KMAX_PAD;       // float dc_n/dt
+constexpr int CSTRIDE = C_COEF_T + KMAX_PAD;        // 688 words
+constexpr int KMAX_TERMS = KMAX_PAD - 1;
+
+static_assert(C_SERS + MAX_COMP * SERS_STRIDE <= C_COEF_S, "constant layout");
+static_assert(C_COEF_S % 4 == 0 && C_COEF_Z % 4 == 0 && C_COEF_T % 4 == 0 && CSTRIDE % 4 == 0,
+              "16-byte alignment of the coefficient arrays");
+
+// Adjoint accumulator layout (per particle, summed over sub-pixels).
+constexpr int A_H = 0;        // sum Re(conj(G) alpha)
+constexpr int A_T = 1;        // slope term
+constexpr int A_ZE = 2;       // complex, 2 words
+constexpr int A_UW = 4;       // complex
+constexpr int A_UC = 6;
+constexpr int A_UB = 7;       // complex
+constexpr int A_SH = 9;       // complex: sum G * theta
+constexpr int A_SERS = 11;    // 8 words per Sersic component
+constexpr int A_SERS_STRIDE = 8;
+constexpr int AS_E = 0, AS_WU = 1, AS_WUL = 2, AS_QXX = 3, AS_QXY = 4, AS_QYY = 5,
+              AS_QX = 6, AS_QY = 7;
+
+inline int n_acc(int ncomp) { return A_SERS + A_SERS_STRIDE * ncomp; }
+
+constexpr float RMIN2 = 1e-12f;   // radii are clamped to 1e-6 arcsec
+constexpr double RMIN2D = 1e-12;
+
+// Grid geometry of one system, passed by value to kernels.
+struct Geo {
+    int nx, ny, s, npix;
+    double h;         // pix_scale / s
+    double cx, cy;    // (s*nx - 1)/2, (s*ny - 1)/2
+    float inv_s2;
+};
+
+inline Geo make_geo(const lens_model_desc& d) {
+    Geo g;
+    g.nx = d.nx; g.ny = d.ny; g.s = d.supersample; g.npix = d.nx * d.ny;
+    g.h = (double)d.pix_scale / (double)d.supersample;
+    g.cx = 0.5 * (double)(d.supersample * d.nx - 1);
+    g.cy = 0.5 * (double)(d.supersample * d.ny - 1);
+    g.inv_s2 = 1.0f / (float)(d.supersample * d.supersample);
+    return g;
+}
+
+struct ModelInfo {
+    int mass_model, n_lens_light, n_source, d;
+};
+
+// Launchers (lens_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_prologue(const ModelInfo& mi, int P, const float* theta, float* consts,
+                           hipStream_t st);
+hipError_t launch_render(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
+                         float* img, hipStream_t st);
+// mode 0: PSF-convolve img -> out (images); 1: logL; 2: logL + adjoint image (in place)
+// wflip: flipped PSF in float64 (model convolution), wpsf: PSF in float32 (adjoint).
+hipError_t launch_psf(const ModelInfo& mi, const Geo& g, int K, int mode, int P,
+                      const float* consts, float* img, const double* wflip, const float* wpsf,
+                      const float* data, const float* invvar, float* out, float* logl,
+                      double* logl64, hipStream_t st);
+hipError_t launch_adjoint(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
+                          const float* gimg, double* partial, hipStream_t st);
+hipError_t launch_finalize(const ModelInfo& mi, int P, int nchunks, const float* theta,
+                           const float* consts, const double* partial, float* grad,
+                           hipStream_t st);
+hipError_t launch_flip(int K, const float* psf, double* flipped, hipStream_t st);
+size_t psf_lds_bytes(const Geo& g, int K);
+constexpr size_t MAX_LDS_BYTES = 160 * 1024 - 256;   // dynamic part; statics need < 256 B
+
+inline int chunks_for(int npix, int ppt) {
+    const int per_block = 256 * ppt;
+    return (npix + per_block - 1) / per_block;
+}
+
+}  // namespace lens

@@ -1,0 +1,880 @@
+// HIP kernels (gfx950) of the batched strong-lens forward model, Gaussian
+// log-likelihood and its adjoint gradient.
+//
+// Model (paper Sec. 3): elliptical power-law (EPL) or SIE mass + external
+// shear; elliptical Sersic lens light evaluated on the image plane and
+// Sersic sources evaluated at beta = theta - alpha; integer supersampling
+// (Sec. 4.2 footnote), mean downsampling, PSF convolution, Gaussian logL.
+//
+// Kernels, in launch order for one call over P particles:
+//   k_prologue  one thread per particle: derived constants (float words) into
+//               a per-particle block read later with wave-uniform loads.
+//   k_render    grid (P, pixel chunks): each thread owns whole pixels and sums
+//               their s*s sub-pixel values (ray shooting + light) -> image.
+//   k_psf       one work-group per particle: image tile in LDS with a zero
+//               halo, register-blocked direct correlation with the flipped
+//               PSF (= true convolution), residual and chi^2 (float64 sum),
+//               then the adjoint (correlation with the unflipped PSF) of the
+//               residual, written back in place.
+//   k_adjoint   grid (P, pixel chunks): recomputes every sub-pixel and
+//               accumulates the reverse-mode sums that the gradient needs;
+//               fixed-order work-group reduction to float64 partials.
+//   k_finalize  one thread per particle: sums the partials in fixed order and
+//               applies the per-particle chain rule -> dlogL/dtheta.
+//
+// Parametrisation used on the device (equivalent to the rotated-frame
+// definition, but smooth in the complex ellipticity eps = e1 + i e2, so the
+// gradient with respect to e1, e2 stays well conditioned as |eps| -> 0):
+//   c = |eps|, q = (1-c)/(1+c), w = (x - x0) + i (y - y0).
+//   EPL (Tessore & Metcalf 2015): U = (w - eps conj(w))/(1+c) equals
+//   e^{i phi}(q x' + i y') in the image frame, so R = |U|, V0 = U/R and
+//       alpha = theta_E sqrt(1-c^2) (b/R)^(t-1) V0 S(z),  z = -conj(eps) V0^2,
+//       S(z) = sum_n c_n z^n,  c_n = prod_{k<=n} (2k-2+t)/(2k+2-t),
+//   with b = theta_E sqrt(q), t = gamma - 1.  SIE is the t = 1 member.
+//   Sersic: R^2 = q x'^2 + y'^2/q = a11 dx^2 + 2 a12 dx dy + a22 dy^2 with
+//       a11 = (1+c^2-2e1)/(1-c^2), a22 = (1+c^2+2e1)/(1-c^2), a12 = -2e2/(1-c^2).
+#include <math.h>
+
+#include <type_traits>
+
+#include "lens_internal.h"
+
+namespace lens {
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+constexpr float HALF_LN2 = 0.34657359027997264f;
+
+// ---------------------------------------------------------------------------
+// Precision split.  Near the cusp of a compact Sersic profile the model value
+// is very sensitive to the evaluation point; FP32 rounding of the grid
+// coordinates (~1e-7") or of the deflection (~1e-7 relative) would change
+// pixel values by ~1e-4 relative.  Near the optimum the residual d - m is a
+// small difference of large numbers, so the model value itself must be good
+// to ~1e-8 relative for the gradient to keep its accuracy.  Hence:
+//   float64: grid coordinates, mass deflection, shear, lens equation, the
+//            Sersic values of the model image, the sub-pixel sum, the PSF
+//            convolution of the model and the residual (float64 FMA issues
+//            at the rate of unpacked float32 FMA on this GPU; exp2/log2 are
+//            evaluated by range reduction + polynomials, below);
+//   float32: the adjoint sweep (Sersic derivatives, series derivatives,
+//            chain rule), whose terms need only ~1e-7 relative accuracy.
+// ---------------------------------------------------------------------------
+struct SersicK {
+    double xc, yc, a11, a12, a22, ie, ku, ku0, bl;   // model value (float64)
+    float a11f, a12f, a22f, ief, kuf, ku0f, blf, kap2;  // adjoint (float32)
+};
+
+template <int NC>
+struct PK {
+    double x0, y0, e1, e2, ua, ub, ue, c0, k0, k1, g1, g2;
+    float e1f, e2f, k1f;
+    int kp;
+    SersicK s[NC > 0 ? NC : 1];
+};
+
+__device__ __forceinline__ double ldd(const float* __restrict__ C, int w) {
+    return *reinterpret_cast<const double*>(C + w);
+}
+
+template <int NC>
+__device__ __forceinline__ PK<NC> load_pk(const float* __restrict__ C) {
+    PK<NC> k;
+    k.x0 = ldd(C, D_X0); k.y0 = ldd(C, D_Y0); k.e1 = ldd(C, D_E1); k.e2 = ldd(C, D_E2);
+    k.ua = ldd(C, D_UA); k.ub = ldd(C, D_UB); k.ue = ldd(C, D_UE); k.c0 = ldd(C, D_C0);
+    k.k0 = ldd(C, D_K0); k.k1 = ldd(C, D_K1); k.g1 = ldd(C, D_G1); k.g2 = ldd(C, D_G2);
+    k.e1f = (float)k.e1; k.e2f = (float)k.e2; k.k1f = (float)k.k1;
+    k.kp = (int)C[C_KP];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const float* S = C + C_SERS + c * SERS_STRIDE;
+        SersicK& q = k.s[c];
+        q.xc = ldd(S, S_XC); q.yc = ldd(S, S_YC);
+        q.a11 = ldd(S, S_A11); q.a12 = ldd(S, S_A12); q.a22 = ldd(S, S_A22);
+        q.ie = ldd(S, S_IE); q.ku = ldd(S, S_KU); q.ku0 = ldd(S, S_KU0); q.bl = ldd(S, S_BL);
+        q.a11f = (float)q.a11; q.a12f = (float)q.a12; q.a22f = (float)q.a22;
+        q.ief = (float)q.ie; q.kuf = (float)q.ku; q.ku0f = (float)q.ku0; q.blf = (float)q.bl;
+        q.kap2 = S[S_KAP2];
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// float64 exp2 / log2 for the model values (no float64 transcendental
+// instructions exist; these are accurate to ~1e-13 relative, far below the
+// float32 output rounding).
+// ---------------------------------------------------------------------------
+constexpr double LN2_D = 0.69314718055994530942;
+
+// log2 x for normal x > 0: x = m 2^e, m in [sqrt(1/2), sqrt(2));
+// ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1),
+// |s| <= 0.1716; terms up to s^15 (truncation < 1e-12).
+__device__ __forceinline__ double log2_d(double x) {
+    double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double den = m + 1.0;
+    double r = __builtin_amdgcn_rcp(den);
+    r = r * fma(-den, r, 2.0);
+    r = r * fma(-den, r, 2.0);
+    const double sv = (m - 1.0) * r;
+    const double z = sv * sv;
+    constexpr double c = 2.0 / LN2_D;
+    double p = c / 15.0;
+    p = fma(p, z, c / 13.0);
+    p = fma(p, z, c / 11.0);
+    p = fma(p, z, c / 9.0);
+    p = fma(p, z, c / 7.0);
+    p = fma(p, z, c / 5.0);
+    p = fma(p, z, c / 3.0);
+    p = fma(p, z, c);
+    return fma(sv, p, (double)e);
+}
+
+// 2^v: v = n + f, n = rint(v), |f| <= 1/2; 2^f = e^y, y = f ln2, |y| < 0.347,
+// by the Taylor series of e^y to y^11 (truncation < 1e-14), scaled by 2^n.
+__device__ __forceinline__ double exp2_d(double v) {
+    v = fmin(fmax(v, -1100.0), 1100.0);
+    const double n = rint(v);
+    const double y = (v - n) * LN2_D;
+    double p = 1.0 / 39916800.0;                 // 1/11!
+    p = fma(p, y, 1.0 / 3628800.0);
+    p = fma(p, y, 1.0 / 362880.0);
+    p = fma(p, y, 1.0 / 40320.0);
+    p = fma(p, y, 1.0 / 5040.0);
+    p = fma(p, y, 1.0 / 720.0);
+    p = fma(p, y, 1.0 / 120.0);
+    p = fma(p, y, 1.0 / 24.0);
+    p = fma(p, y, 1.0 / 6.0);
+    p = fma(p, y, 0.5);
+    p = fma(p, y, 1.0);
+    p = fma(p, y, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)n);
+}
+
+// ---------------------------------------------------------------------------
+// Sersic value and adjoint, given the offset (dx, dy) from the centre
+// ---------------------------------------------------------------------------
+// Model value I_e exp(-b_n [(R/R_e)^(1/n) - 1]) in float64.
+__device__ __forceinline__ double sersic_val(double dx, double dy, const SersicK& s) {
+    double r2 = fma(s.a11 * dx, dx, fma(2.0 * s.a12 * dx, dy, s.a22 * dy * dy));
+    r2 = fmax(r2, RMIN2D);
+    const double u = exp2_d(fma(s.ku, log2_d(r2), s.ku0));   // (R/R_e)^(1/n)
+    return s.ie * exp2_d(s.bl * (1.0 - u));
+}
+
+// Accumulates, for the adjoint gs of this sub-pixel value, the sums that
+// the per-particle chain rule needs (see k_finalize), and for a source the
+// adjoint of its evaluation point (gbx, gby).
+template <bool SRC>
+__device__ __forceinline__ void sersic_adj(float dx, float dy, float gs, const SersicK& s, float* a,
+                                           float& gbx, float& gby) {
+    float r2 = fmaf(s.a11f * dx, dx, fmaf(2.0f * s.a12f * dx, dy, s.a22f * dy * dy));
+    const bool cl = r2 < RMIN2;
+    r2 = cl ? RMIN2 : r2;
+    const float L = flog2(r2);
+    const float u = fexp2(fmaf(s.kuf, L, s.ku0f));
+    const float E = fexp2(s.blf * (1.0f - u));
+    const float gE = gs * E;
+    const float wu = gE * s.ief * u;
+    const float qp = cl ? 0.0f : wu * frcp(r2);
+    const float tx = qp * dx, ty = qp * dy;
+    a[AS_E] += gE;
+    a[AS_WU] += wu;
+    a[AS_WUL] = fmaf(wu, L, a[AS_WUL]);
+    a[AS_QX] += tx;
+    a[AS_QY] += ty;
+    a[AS_QXX] = fmaf(tx, dx, a[AS_QXX]);
+    a[AS_QXY] = fmaf(tx, dy, a[AS_QXY]);
+    a[AS_QYY] = fmaf(ty, dy, a[AS_QYY]);
+    if (SRC) {
+        gbx = fmaf(s.kap2, fmaf(s.a11f, tx, s.a12f * ty), gbx);
+        gby = fmaf(s.kap2, fmaf(s.a12f, tx, s.a22f * ty), gby);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// EPL series by Horner.  S(z) = sum c_n z^n in float64 (it sets the
+// deflection); S'(z) and dS/dt in float32 (adjoint only), each from its own
+// coefficient array.  Coefficients are read 16 bytes at a time with
+// wave-uniform loads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void series_d(const float* __restrict__ C, int kp, double zx, double zy,
+                                         double& sx, double& sy) {
+    const double* cS = reinterpret_cast<const double*>(C + C_COEF_S);
+    sx = 0.0; sy = 0.0;
+    for (int base = kp - 3; base >= 0; base -= 4) {
+        const double2 hi = *reinterpret_cast<const double2*>(cS + base + 2);
+        const double2 lo = *reinterpret_cast<const double2*>(cS + base);
+        const double cs_[4] = {hi.y, hi.x, lo.y, lo.x};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double nsx = fma(sx, zx, fma(-sy, zy, cs_[q]));
+            const double nsy = fma(sx, zy, sy * zx);
+            sx = nsx; sy = nsy;
+        }
+    }
+}
+
+template <bool WT>
+__device__ __forceinline__ void series_adj(const float* __restrict__ C, int kp, float zx, float zy,
+                                           float& dx, float& dy, float& tx, float& ty) {
+    const float* cZ = C + C_COEF_Z;
+    const float* cT = C + C_COEF_T;
+    dx = 0.f; dy = 0.f; tx = 0.f; ty = 0.f;
+    for (int base = kp - 3; base >= 0; base -= 4) {
+        const float4 c = *reinterpret_cast<const float4*>(cZ + base);
+        float4 ct = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (WT) ct = *reinterpret_cast<const float4*>(cT + base);
+        const float cz_[4] = {c.w, c.z, c.y, c.x};
+        const float ct_[4] = {ct.w, ct.z, ct.y, ct.x};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float ndx = fmaf(dx, zx, fmaf(-dy, zy, cz_[q]));
+            const float ndy = fmaf(dx, zy, dy * zx);
+            dx = ndx; dy = ndy;
+            if (WT) {
+                const float ntx = fmaf(tx, zx, fmaf(-ty, zy, ct_[q]));
+                const float nty = fmaf(tx, zy, ty * zx);
+                tx = ntx; ty = nty;
+            }
+        }
+    }
+}
+
+// 1/sqrt(x) in float64: hardware estimate + two Newton steps.
+__device__ __forceinline__ double rsqrt_d(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
+// Intermediates of the deflection kept (as float32) for the adjoint.
+struct MassState {
+    float wx, wy, ux, uy, vx, vy, ir, A, B, zx, zy, sx, sy, f, L2, ax, ay;
+    bool inside;
+};
+
+// Mass deflection in float64; with KEEP the float32 intermediates are saved.
+template <int MASS, bool KEEP, int NC>
+__device__ __forceinline__ void deflect(double x, double y, const PK<NC>& k,
+                                        const float* __restrict__ C, double& ax, double& ay,
+                                        MassState* ms) {
+    const double wx = x - k.x0, wy = y - k.y0;
+    const double ux = fma(k.ua, wx, -k.ue * wy);
+    const double uy = fma(k.ub, wy, -k.ue * wx);
+    double r2 = fma(ux, ux, uy * uy);
+    const bool inside = r2 < RMIN2D;
+    r2 = inside ? RMIN2D : r2;
+    const double ir = rsqrt_d(r2);
+    const double vx = ux * ir, vy = uy * ir;
+    const double A = fma(vx, vx, -vy * vy), B = 2.0 * vx * vy;
+    const double zx = -fma(k.e1, A, k.e2 * B);
+    const double zy = -fma(k.e1, B, -k.e2 * A);
+    double sx, sy;
+    series_d(C, k.kp, zx, zy, sx, sy);
+    double f = k.c0, L2 = 0.0;
+    if (MASS == LENS_MASS_EPL) {
+        L2 = log2(r2);
+        f *= exp2(fma(-k.k1, L2, k.k0));
+    }
+    ax = inside ? 0.0 : f * fma(vx, sx, -vy * sy);
+    ay = inside ? 0.0 : f * fma(vx, sy, vy * sx);
+    if (KEEP) {
+        ms->wx = (float)wx; ms->wy = (float)wy; ms->ux = (float)ux; ms->uy = (float)uy;
+        ms->vx = (float)vx; ms->vy = (float)vy; ms->ir = (float)ir;
+        ms->A = (float)A; ms->B = (float)B; ms->zx = (float)zx; ms->zy = (float)zy;
+        ms->sx = (float)sx; ms->sy = (float)sy; ms->f = (float)f; ms->L2 = (float)L2;
+        ms->ax = (float)ax; ms->ay = (float)ay; ms->inside = inside;
+    }
+}
+
+template <int MASS, int NL, int NS>
+__device__ __forceinline__ double subpix_value(double x, double y, const PK<NL + NS>& k,
+                                               const float* __restrict__ C) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) v += sersic_val(x - k.s[c].xc, y - k.s[c].yc, k.s[c]);
+    double ax, ay;
+    deflect<MASS, false, NL + NS>(x, y, k, C, ax, ay, nullptr);
+    const double bx = x - ax - fma(k.g1, x, k.g2 * y);
+    const double by = y - ay - fma(k.g2, x, -k.g1 * y);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+        const SersicK& sc = k.s[NL + c];
+        v += sersic_val(bx - sc.xc, by - sc.yc, sc);
+    }
+    return v;
+}
+
+// Reverse sweep of one sub-pixel: accumulates into acc[] (layout A_*).
+template <int MASS, int NL, int NS>
+__device__ __forceinline__ void subpix_adjoint(double x, double y, float gs, const PK<NL + NS>& k,
+                                               const float* __restrict__ C, float* acc) {
+    float dummy0 = 0.f, dummy1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < NL; ++c)
+        sersic_adj<false>((float)(x - k.s[c].xc), (float)(y - k.s[c].yc), gs, k.s[c],
+                          acc + A_SERS + A_SERS_STRIDE * c, dummy0, dummy1);
+
+    MassState m;
+    double axd, ayd;
+    deflect<MASS, true, NL + NS>(x, y, k, C, axd, ayd, &m);
+    const double bx = x - axd - fma(k.g1, x, k.g2 * y);
+    const double by = y - ayd - fma(k.g2, x, -k.g1 * y);
+
+    // sources at beta, collecting the adjoint of beta
+    float gbx = 0.f, gby = 0.f;
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+        const SersicK& sc = k.s[NL + c];
+        sersic_adj<true>((float)(bx - sc.xc), (float)(by - sc.yc), gs, sc,
+                         acc + A_SERS + A_SERS_STRIDE * (NL + c), gbx, gby);
+    }
+
+    // G = dL/dalpha = -dL/dbeta (mass and shear deflections enter beta alike)
+    const float xf = (float)x, yf = (float)y;
+    float Gx = -gbx, Gy = -gby;
+    acc[A_SH] = fmaf(Gx, xf, fmaf(-Gy, yf, acc[A_SH]));        // Re(G theta)
+    acc[A_SH + 1] = fmaf(Gx, yf, fmaf(Gy, xf, acc[A_SH + 1]));  // Im(G theta)
+    if (m.inside) { Gx = 0.f; Gy = 0.f; }
+
+    float dx, dy, tx, ty;
+    series_adj<MASS == LENS_MASS_EPL>(C, k.kp, m.zx, m.zy, dx, dy, tx, ty);
+    const float vx = m.vx, vy = m.vy, sx = m.sx, sy = m.sy;
+    const float h = fmaf(Gx, m.ax, Gy * m.ay);                // Re(conj(G) alpha)
+    acc[A_H] += h;
+    const float vbx = Gx * m.f, vby = Gy * m.f;               // adjoint of V = V0 S
+    if (MASS == LENS_MASS_EPL) {
+        const float vtx = fmaf(vx, tx, -vy * ty), vty = fmaf(vx, ty, vy * tx);   // V0 dS/dt
+        acc[A_T] += fmaf(vbx, vtx, fmaf(vby, vty, -h * (HALF_LN2 * m.L2)));
+    }
+    // Zb = Vb conj(V0 S'(z))
+    const float vdx = fmaf(vx, dx, -vy * dy), vdy = fmaf(vx, dy, vy * dx);
+    const float zbx = fmaf(vbx, vdx, vby * vdy);
+    const float zby = fmaf(vby, vdx, -vbx * vdy);
+    acc[A_ZE] = fmaf(zbx, m.A, fmaf(zby, m.B, acc[A_ZE]));            // Zb conj(V0)^2
+    acc[A_ZE + 1] = fmaf(zby, m.A, fmaf(-zbx, m.B, acc[A_ZE + 1]));
+    // adjoint of V0: Vb conj(S) - 2 Zb eps conj(V0)
+    const float px = fmaf(k.e1f, vx, k.e2f * vy), py = fmaf(k.e2f, vx, -k.e1f * vy);
+    const float gvx = fmaf(vbx, sx, vby * sy) - 2.0f * fmaf(zbx, px, -zby * py);
+    const float gvy = fmaf(vby, sx, -vbx * sy) - 2.0f * fmaf(zbx, py, zby * px);
+    // adjoint of U through V0 = U/|U| and ln R (slope factor)
+    const float rho = (MASS == LENS_MASS_EPL) ? -2.0f * k.k1f * h : 0.0f;
+    const float sv = fmaf(gvx, vx, gvy * vy) - rho;
+    const float gux = fmaf(-vx, sv, gvx) * m.ir;
+    const float guy = fmaf(-vy, sv, gvy) * m.ir;
+    acc[A_UB] += gux;
+    acc[A_UB + 1] += guy;
+    acc[A_UW] = fmaf(gux, m.wx, fmaf(-guy, m.wy, acc[A_UW]));          // conj(GU) conj(w)
+    acc[A_UW + 1] = fmaf(-gux, m.wy, fmaf(-guy, m.wx, acc[A_UW + 1]));
+    acc[A_UC] = fmaf(gux, m.ux, fmaf(guy, m.uy, acc[A_UC]));            // Re(conj(GU) U)
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a 256-thread work-group (fixed order).  red: >= 4 doubles of LDS.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+__global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
+                           float* __restrict__ consts) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const float* th = theta + (size_t)p * mi.d;
+    float* C = consts + (size_t)p * CSTRIDE;
+    bool finite = true;
+    for (int k = 0; k < mi.d; ++k) finite = finite && isfinite(th[k]);
+    const bool epl = mi.mass_model == LENS_MASS_EPL;
+    int o = 0;
+    const double tE = th[o++];
+    const double gam = epl ? (double)th[o++] : 2.0;
+    const double e1 = th[o], e2 = th[o + 1];
+    const double x0 = th[o + 2], y0 = th[o + 3], g1 = th[o + 4], g2 = th[o + 5];
+    o += 6;
+    const double c2 = e1 * e1 + e2 * e2, c = sqrt(c2);
+    const double t = gam - 1.0;
+    bool ok = c < 1.0 && tE > 0.0 && t > 0.0 && t < 2.0;
+    const double ip = 1.0 / (1.0 + c);
+    double* Dm = reinterpret_cast<double*>(C);
+    Dm[D_X0 / 2] = x0; Dm[D_Y0 / 2] = y0; Dm[D_E1 / 2] = e1; Dm[D_E2 / 2] = e2;
+    Dm[D_UA / 2] = (1.0 - e1) * ip;
+    Dm[D_UB / 2] = (1.0 + e1) * ip;
+    Dm[D_UE / 2] = e2 * ip;
+    Dm[D_C0 / 2] = tE * sqrt(fmax(1.0 - c2, 0.0));
+    const double b = tE * sqrt(fmax((1.0 - c) / (1.0 + c), 0.0));
+    Dm[D_K0 / 2] = (t - 1.0) * log2(b);
+    Dm[D_K1 / 2] = 0.5 * (t - 1.0);
+    Dm[D_G1 / 2] = g1; Dm[D_G2 / 2] = g2;
+    const int nc = mi.n_lens_light + mi.n_source;
+    for (int k = 0; k < nc; ++k, o += 7) {
+        const double Re = th[o], n = th[o + 1], se1 = th[o + 2], se2 = th[o + 3];
+        const double cs2 = se1 * se1 + se2 * se2;
+        ok = ok && cs2 < 1.0 && Re > 0.0 && n > 0.0;
+        const double D = 1.0 - cs2;
+        float* S = C + C_SERS + k * SERS_STRIDE;
+        double* Sd = reinterpret_cast<double*>(S);
+        Sd[S_XC / 2] = th[o + 4]; Sd[S_YC / 2] = th[o + 5];
+        Sd[S_A11 / 2] = (1.0 + cs2 - 2.0 * se1) / D;
+        Sd[S_A22 / 2] = (1.0 + cs2 + 2.0 * se1) / D;
+        Sd[S_A12 / 2] = -2.0 * se2 / D;
+        Sd[S_IE / 2] = th[o + 6];
+        const double bn = 1.9992 * n - 0.3271;
+        Sd[S_KU / 2] = 0.5 / n;
+        Sd[S_KU0 / 2] = -log2(Re) / n;
+        Sd[S_BL / 2] = bn * 1.4426950408889634;
+        S[S_KAP2] = (float)(-bn / n);
+    }
+    // Series coefficients c_n(t), (n+1) c_{n+1} for S'(z), and dc_n/dt = c_n D_n,
+    // D_n = sum_{k<=n} [1/(2k-2+t) + 1/(2k+2-t)].  Length K: the first n at
+    // which a bound on the remaining terms of S and S' falls below 2^-34.
+    double* cS = reinterpret_cast<double*>(C + C_COEF_S);
+    float* cZ = C + C_COEF_Z;
+    float* cT = C + C_COEF_T;
+    cS[0] = 1.0; cT[0] = 0.0f;
+    int K = 0;
+    if (ok && c > 0.0) {
+        double cn = 1.0, Dn = 0.0, cpow = 1.0;
+        for (int n = 1; n <= KMAX_TERMS; ++n) {
+            const double a = 2.0 * n - 2.0 + t, bb = 2.0 * n + 2.0 - t;
+            cn *= a / bb;
+            Dn += 1.0 / a + 1.0 / bb;
+            cpow *= c;
+            cS[n] = cn;
+            cZ[n - 1] = (float)(n * cn);
+            cT[n] = (float)(cn * Dn);
+            K = n;
+            const double next = cn * (2.0 * n + t) / (2.0 * n + 4.0 - t);
+            const double tail = (n + 2.0) * next * (Dn + 2.0) * cpow / ((1.0 - c) * (1.0 - c));
+            if (tail < 5.820766091346741e-11) break;
+        }
+    }
+    const int KP = ((K + 1 + 3) / 4) * 4 - 1;
+    for (int n = K + 1; n <= KP; ++n) { cS[n] = 0.0; cT[n] = 0.0f; }
+    for (int n = K; n <= KP; ++n) cZ[n] = 0.0f;
+    C[C_KP] = (float)KP;
+    C[C_VALID] = !finite ? 2.0f : (ok ? 1.0f : 0.0f);
+}
+
+template <int MASS, int NL, int NS>
+__global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts, Geo g, int ppb,
+                                                float* __restrict__ img) {
+    const int p = blockIdx.x;
+    const float* __restrict__ C = consts + (size_t)p * CSTRIDE;
+    const int pix0 = blockIdx.y * ppb;
+    const int pix1 = min(pix0 + ppb, g.npix);
+    float* out = img + (size_t)p * g.npix;
+    if (C[C_VALID] != 1.0f) {
+        for (int pix = pix0 + threadIdx.x; pix < pix1; pix += 256) out[pix] = __builtin_nanf("");
+        return;
+    }
+    const PK<NL + NS> k = load_pk<NL + NS>(C);
+    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += 256) {
+        const int i = pix / g.nx, j = pix - i * g.nx;
+        double acc = 0.0;
+        for (int a = 0; a < g.s; ++a) {
+            const double y = ((double)(g.s * i + a) - g.cy) * g.h;
+            for (int b = 0; b < g.s; ++b) {
+                const double x = ((double)(g.s * j + b) - g.cx) * g.h;
+                acc += subpix_value<MASS, NL, NS>(x, y, k, C);
+            }
+        }
+        out[pix] = (float)(acc * (double)g.inv_s2);
+    }
+}
+
+template <int MASS, int NL, int NS>
+__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ consts, Geo g, int ppb,
+                                                 const float* __restrict__ gimg,
+                                                 double* __restrict__ partial) {
+    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
+    __shared__ double red[NACC][4];
+    const int p = blockIdx.x;
+    const int nch = gridDim.y;
+    const float* __restrict__ C = consts + (size_t)p * CSTRIDE;
+    double* outp = partial + ((size_t)p * nch + blockIdx.y) * NACC;
+    if (C[C_VALID] != 1.0f) {
+        if (threadIdx.x < NACC) outp[threadIdx.x] = 0.0;
+        return;
+    }
+    const PK<NL + NS> k = load_pk<NL + NS>(C);
+    float acc[NACC];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.f;
+    const int pix0 = blockIdx.y * ppb;
+    const int pix1 = min(pix0 + ppb, g.npix);
+    const float* gp = gimg + (size_t)p * g.npix;
+    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += 256) {
+        const int i = pix / g.nx, j = pix - i * g.nx;
+        const float gs = gp[pix] * g.inv_s2;
+        for (int a = 0; a < g.s; ++a) {
+            const double y = ((double)(g.s * i + a) - g.cy) * g.h;
+            for (int b = 0; b < g.s; ++b) {
+                const double x = ((double)(g.s * j + b) - g.cx) * g.h;
+                subpix_adjoint<MASS, NL, NS>(x, y, gs, k, C, acc);
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+        const double v = wave_sum((double)acc[q]);
+        if (lane == 0) red[q][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NACC) {
+        const int q = threadIdx.x;
+        outp[q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+    }
+}
+
+// Register-blocked correlation of an LDS tile with a K x K kernel:
+// m[r] = sum_{u,v} w[u][v] tile[i+u][j0+v+r]; accumulator type T (float64 for
+// the model convolution, float32 for the adjoint).
+template <int K, int RW, typename T>
+__device__ __forceinline__ void correlate(const float* lds, int stride, int i, int j0,
+                                          const T* __restrict__ w, T (&m)[RW]) {
+    constexpr int NQ = (RW + K - 1 + 3) / 4;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) m[r] = (T)0;
+    for (int u = 0; u < K; ++u) {
+        const float4* row = reinterpret_cast<const float4*>(lds + (i + u) * stride + j0);
+        T seg[4 * NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float4 t4 = row[q];
+            seg[4 * q] = (T)t4.x; seg[4 * q + 1] = (T)t4.y; seg[4 * q + 2] = (T)t4.z;
+            seg[4 * q + 3] = (T)t4.w;
+        }
+        const T* wr = w + u * K;
+#pragma unroll
+        for (int v = 0; v < K; ++v) {
+            const T wv = wr[v];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) m[r] = fma(wv, seg[v + r], m[r]);
+        }
+    }
+}
+
+constexpr int PSF_RW = 4;
+
+inline void psf_tile(const Geo& g, int K, int& stride, int& rows) {
+    const int nsx = (g.nx + PSF_RW - 1) / PSF_RW;
+    const int nq = (PSF_RW + K - 1 + 3) / 4;
+    stride = (nsx - 1) * PSF_RW + 4 * nq;
+    rows = g.ny + K - 1;
+}
+
+template <int K, int MODE>
+__global__ __launch_bounds__(256) void k_psf(const float* __restrict__ consts, Geo g, float* img,
+                                             const double* __restrict__ wflip,
+                                             const float* __restrict__ wpsf,
+                                             const float* __restrict__ data,
+                                             const float* __restrict__ invvar, float* out,
+                                             float* logl, double* logl64, int stride, int rows) {
+    extern __shared__ float4 lds4[];
+    __shared__ double red[4];
+    float* lds = reinterpret_cast<float*>(lds4);
+    constexpr int H = (K - 1) / 2;
+    constexpr int RW = PSF_RW;
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const float valid = consts[(size_t)p * CSTRIDE + C_VALID];
+    float* buf = img + (size_t)p * g.npix;
+    if (MODE != 0 && valid != 1.0f) {
+        if (tid == 0) {
+            const float v = valid == 2.0f ? __builtin_nanf("") : -__builtin_inff();
+            logl[p] = v;
+            if (logl64) logl64[p] = (double)v;
+        }
+        return;
+    }
+    const int total = rows * stride;
+    for (int q = tid; q < total; q += 256) lds[q] = 0.f;
+    __syncthreads();
+    for (int pix = tid; pix < g.npix; pix += 256) {
+        const int i = pix / g.nx, j = pix - i * g.nx;
+        lds[(i + H) * stride + j + H] = buf[pix];
+    }
+    __syncthreads();
+    const int nsx = (g.nx + RW - 1) / RW, nstrips = nsx * g.ny;
+    double chi = 0.0;
+    for (int st = tid; st < nstrips; st += 256) {
+        const int i = st / nsx, j0 = (st - i * nsx) * RW;
+        double m[RW];
+        correlate<K, RW, double>(lds, stride, i, j0, wflip, m);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int j = j0 + r;
+            if (j < g.nx) {
+                const int idx = i * g.nx + j;
+                if (MODE == 0) {
+                    out[(size_t)p * g.npix + idx] = (float)m[r];
+                } else {
+                    const double dlt = (double)data[idx] - m[r];
+                    const double w = (double)invvar[idx];
+                    chi = fma(w * dlt, dlt, chi);
+                    if (MODE == 2) buf[idx] = (float)(w * dlt);
+                }
+            }
+        }
+    }
+    if (MODE == 0) return;
+    chi = block_sum(chi, red);
+    if (tid == 0) {
+        logl[p] = (float)(-0.5 * chi);
+        if (logl64) logl64[p] = -0.5 * chi;
+    }
+    if (MODE == 2) {
+        __syncthreads();
+        for (int pix = tid; pix < g.npix; pix += 256) {
+            const int i = pix / g.nx, j = pix - i * g.nx;
+            lds[(i + H) * stride + j + H] = buf[pix];
+        }
+        __syncthreads();
+        for (int st = tid; st < nstrips; st += 256) {
+            const int i = st / nsx, j0 = (st - i * nsx) * RW;
+            float m[RW];
+            correlate<K, RW, float>(lds, stride, i, j0, wpsf, m);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int j = j0 + r;
+                if (j < g.nx) buf[i * g.nx + j] = m[r];
+            }
+        }
+    }
+}
+
+__global__ void k_finalize(ModelInfo mi, int P, int nchunks, const float* __restrict__ theta,
+                           const float* __restrict__ consts, const double* __restrict__ partial,
+                           float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int nc = mi.n_lens_light + mi.n_source;
+    const int nacc = A_SERS + A_SERS_STRIDE * nc;
+    const float* th = theta + (size_t)p * mi.d;
+    float* g = grad + (size_t)p * mi.d;
+    const float valid = consts[(size_t)p * CSTRIDE + C_VALID];
+    if (valid != 1.0f) {
+        const float v = valid == 2.0f ? __builtin_nanf("") : 0.0f;
+        for (int q = 0; q < mi.d; ++q) g[q] = v;
+        return;
+    }
+    const double* base = partial + (size_t)p * nchunks * nacc;
+    auto acc = [&](int q) {
+        double s = 0.0;
+        for (int ch = 0; ch < nchunks; ++ch) s += base[(size_t)ch * nacc + q];
+        return s;
+    };
+    const bool epl = mi.mass_model == LENS_MASS_EPL;
+    int o = 0;
+    const double tE = th[o++];
+    const double t = epl ? (double)th[o++] - 1.0 : 1.0;
+    const double e1 = th[o], e2 = th[o + 1];
+    const double c2 = e1 * e1 + e2 * e2, c = sqrt(c2);
+    const double H = acc(A_H);
+    // alpha = theta_E sqrt(1-c^2) (b/R)^(t-1) V0 S,  b = theta_E sqrt((1-c)/(1+c))
+    g[0] = (float)(H * t / tE);
+    if (epl) {
+        const double lnb = log(tE) + 0.5 * log((1.0 - c) / (1.0 + c));
+        g[1] = (float)(acc(A_T) + lnb * H);
+    }
+    const double gc = -H * c / (1.0 - c2) - (t - 1.0) * H / (1.0 - c2) - acc(A_UC) / (1.0 + c);
+    const double ec1 = c > 0.0 ? e1 / c : 0.0, ec2 = c > 0.0 ? e2 / c : 0.0;
+    g[o] = (float)(gc * ec1 - acc(A_ZE) - acc(A_UW) / (1.0 + c));
+    g[o + 1] = (float)(gc * ec2 + acc(A_ZE + 1) + acc(A_UW + 1) / (1.0 + c));
+    const double ubx = acc(A_UB), uby = acc(A_UB + 1);
+    const double wbx = (ubx - (ubx * e1 + uby * e2)) / (1.0 + c);
+    const double wby = (uby - (ubx * e2 - uby * e1)) / (1.0 + c);
+    g[o + 2] = (float)(-wbx);
+    g[o + 3] = (float)(-wby);
+    g[o + 4] = (float)acc(A_SH);
+    g[o + 5] = (float)acc(A_SH + 1);
+    o += 6;
+    for (int k = 0; k < nc; ++k, o += 7) {
+        const int ab = A_SERS + A_SERS_STRIDE * k;
+        const double Re = th[o], n = th[o + 1], se1 = th[o + 2], se2 = th[o + 3], Ie = th[o + 6];
+        const double bn = 1.9992 * n - 0.3271;
+        const double kap = -bn / (2.0 * n);
+        const double aE = acc(ab + AS_E), aWU = acc(ab + AS_WU), aWUL = acc(ab + AS_WUL);
+        const double qxx = acc(ab + AS_QXX), qxy = acc(ab + AS_QXY), qyy = acc(ab + AS_QYY);
+        const double qx = acc(ab + AS_QX), qy = acc(ab + AS_QY);
+        // I = I_e exp(-b_n (u - 1)), u = (R/R_e)^(1/n)
+        g[o + 6] = (float)aE;
+        g[o] = (float)(bn / (n * Re) * aWU);
+        const double wulnr = 0.34657359027997264 * aWUL - log(Re) * aWU;   // sum W u ln(R/R_e)
+        g[o + 1] = (float)(-1.9992 * (aWU - Ie * aE) + bn / (n * n) * wulnr);
+        const double cs2 = se1 * se1 + se2 * se2, D = 1.0 - cs2, D2 = D * D;
+        const double a11 = (1.0 + cs2 - 2.0 * se1) / D, a22 = (1.0 + cs2 + 2.0 * se1) / D,
+                     a12 = -2.0 * se2 / D;
+        const double gA11 = kap * qxx, gA12 = 2.0 * kap * qxy, gA22 = kap * qyy;
+        const double n11 = 1.0 + cs2 - 2.0 * se1, n22 = 1.0 + cs2 + 2.0 * se1;
+        const double d11_1 = (2.0 * se1 - 2.0) / D + n11 * 2.0 * se1 / D2;
+        const double d11_2 = 2.0 * se2 / D + n11 * 2.0 * se2 / D2;
+        const double d22_1 = (2.0 * se1 + 2.0) / D + n22 * 2.0 * se1 / D2;
+        const double d22_2 = 2.0 * se2 / D + n22 * 2.0 * se2 / D2;
+        const double d12_1 = -4.0 * se2 * se1 / D2;
+        const double d12_2 = -2.0 / D - 4.0 * se2 * se2 / D2;
+        g[o + 2] = (float)(gA11 * d11_1 + gA12 * d12_1 + gA22 * d22_1);
+        g[o + 3] = (float)(gA11 * d11_2 + gA12 * d12_2 + gA22 * d22_2);
+        g[o + 4] = (float)(-2.0 * kap * (a11 * qx + a12 * qy));
+        g[o + 5] = (float)(-2.0 * kap * (a12 * qx + a22 * qy));
+    }
+}
+
+__global__ void k_flip(int K, const float* __restrict__ psf, double* __restrict__ flipped) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= K * K) return;
+    const int u = q / K, v = q - u * K;
+    flipped[(K - 1 - u) * K + (K - 1 - v)] = (double)psf[q];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers: template dispatch on (mass model, #lens light, #sources) and K
+// ---------------------------------------------------------------------------
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Calls f(IC<mass>, IC<n_lens_light>, IC<n_source>) for the compiled
+// combinations; returns false for any other.
+template <int M, class F>
+bool dispatch_ls(int nl, int ns, F&& f) {
+    switch (nl * 4 + ns) {
+        case 0 * 4 + 1: f(IC<M>{}, IC<0>{}, IC<1>{}); return true;
+        case 0 * 4 + 2: f(IC<M>{}, IC<0>{}, IC<2>{}); return true;
+        case 0 * 4 + 3: f(IC<M>{}, IC<0>{}, IC<3>{}); return true;
+        case 1 * 4 + 1: f(IC<M>{}, IC<1>{}, IC<1>{}); return true;
+        case 1 * 4 + 2: f(IC<M>{}, IC<1>{}, IC<2>{}); return true;
+        case 1 * 4 + 3: f(IC<M>{}, IC<1>{}, IC<3>{}); return true;
+        case 2 * 4 + 1: f(IC<M>{}, IC<2>{}, IC<1>{}); return true;
+        case 2 * 4 + 2: f(IC<M>{}, IC<2>{}, IC<2>{}); return true;
+        case 2 * 4 + 3: f(IC<M>{}, IC<2>{}, IC<3>{}); return true;
+        case 3 * 4 + 1: f(IC<M>{}, IC<3>{}, IC<1>{}); return true;
+        case 3 * 4 + 2: f(IC<M>{}, IC<3>{}, IC<2>{}); return true;
+        case 3 * 4 + 3: f(IC<M>{}, IC<3>{}, IC<3>{}); return true;
+        default: return false;
+    }
+}
+
+template <class F>
+bool dispatch_model(const ModelInfo& mi, F&& f) {
+    if (mi.mass_model == LENS_MASS_EPL)
+        return dispatch_ls<LENS_MASS_EPL>(mi.n_lens_light, mi.n_source, f);
+    return dispatch_ls<LENS_MASS_SIE>(mi.n_lens_light, mi.n_source, f);
+}
+
+hipError_t launch_prologue(const ModelInfo& mi, int P, const float* theta, float* consts,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_prologue, dim3((P + 63) / 64), dim3(64), 0, st, mi, P, theta, consts);
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
+                         float* img, hipStream_t st) {
+    const int nch = chunks_for(g.npix, ppt);
+    const dim3 grid(P, nch);
+    const int ppb = 256 * ppt;
+    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
+        hipLaunchKernelGGL((k_render<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
+                           grid, dim3(256), 0, st, consts, g, ppb, img);
+    });
+    if (!done) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
+                          const float* gimg, double* partial, hipStream_t st) {
+    const int nch = chunks_for(g.npix, ppt);
+    const dim3 grid(P, nch);
+    const int ppb = 256 * ppt;
+    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
+        hipLaunchKernelGGL((k_adjoint<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
+                           grid, dim3(256), 0, st, consts, g, ppb, gimg, partial);
+    });
+    if (!done) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_psf_k(const Geo& g, int mode, int P, const float* consts, float* img,
+                               const double* wflip, const float* wpsf, const float* data,
+                               const float* invvar, float* out, float* logl, double* logl64,
+                               hipStream_t st) {
+    int stride, rows;
+    psf_tile(g, K, stride, rows);
+    const size_t shm = (size_t)stride * rows * sizeof(float);
+    static bool attr_set[3] = {false, false, false};
+    auto go = [&](auto kern) {
+        if (!attr_set[mode]) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)MAX_LDS_BYTES);
+            attr_set[mode] = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(P), dim3(256), shm, st, consts, g, img, wflip, wpsf, data,
+                           invvar, out, logl, logl64, stride, rows);
+    };
+    if (mode == 0) go(k_psf<K, 0>);
+    else if (mode == 1) go(k_psf<K, 1>);
+    else go(k_psf<K, 2>);
+    return hipGetLastError();
+}
+
+hipError_t launch_psf(const ModelInfo& mi, const Geo& g, int K, int mode, int P,
+                      const float* consts, float* img, const double* wflip, const float* wpsf,
+                      const float* data, const float* invvar, float* out, float* logl,
+                      double* logl64, hipStream_t st) {
+    (void)mi;
+    switch (K) {
+#define LENS_PSF_CASE(KK) \
+    case KK: return launch_psf_k<KK>(g, mode, P, consts, img, wflip, wpsf, data, invvar, out, logl, logl64, st);
+        LENS_PSF_CASE(1) LENS_PSF_CASE(3) LENS_PSF_CASE(5) LENS_PSF_CASE(7) LENS_PSF_CASE(9)
+        LENS_PSF_CASE(11) LENS_PSF_CASE(13) LENS_PSF_CASE(15) LENS_PSF_CASE(17) LENS_PSF_CASE(19)
+        LENS_PSF_CASE(21) LENS_PSF_CASE(23) LENS_PSF_CASE(25) LENS_PSF_CASE(27) LENS_PSF_CASE(29)
+        LENS_PSF_CASE(31)
+#undef LENS_PSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_finalize(const ModelInfo& mi, int P, int nchunks, const float* theta,
+                           const float* consts, const double* partial, float* grad,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3((P + 63) / 64), dim3(64), 0, st, mi, P, nchunks, theta,
+                       consts, partial, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(int K, const float* psf, double* flipped, hipStream_t st) {
+    hipLaunchKernelGGL(k_flip, dim3((K * K + 255) / 256), dim3(256), 0, st, K, psf, flipped);
+    return hipGetLastError();
+}
+
+size_t psf_lds_bytes(const Geo& g, int K) {
+    int stride, rows;
+    psf_tile(g, K, stride, rows);
+    return (size_t)stride * rows * sizeof(float);
+}
+
+}  // namespace lens

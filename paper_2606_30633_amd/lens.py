@@ -1,0 +1,215 @@
+"""ctypes binding of liblens.so (C ABI in include/lens_api.h).
+
+Argument marshalling only: every step of the likelihood path runs in the
+library's HIP kernels.  PyTorch provides device memory and the stream.
+The functions keep the C names (lens_forward, lens_loglike, ...).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblens.so")
+
+LENS_OK, LENS_EINVAL, LENS_EUNSUPPORTED, LENS_EHIP, LENS_ENOMEM = 0, -1, -2, -3, -4
+LENS_MASS_SIE, LENS_MASS_EPL = 0, 1
+
+_lib = None
+
+
+class LensError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {lens_status_string(status)} ({status})")
+        self.status = status
+
+
+class lens_model_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pix_scale", ctypes.c_float),
+        ("supersample", ctypes.c_int32), ("psf_size", ctypes.c_int32),
+        ("mass_model", ctypes.c_int32), ("n_lens_light", ctypes.c_int32),
+        ("n_source", ctypes.c_int32),
+    ]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+
+_SIGNATURES = {
+    "lens_status_string": (ctypes.c_char_p, [_I]),
+    "lens_num_params": (_I, [ctypes.POINTER(lens_model_desc)]),
+    "lens_plan_create": (_I, [ctypes.POINTER(lens_model_desc), _P, _P, _P, _I, ctypes.POINTER(_P)]),
+    "lens_plan_destroy": (_I, [_P]),
+    "lens_plan_set_pixels_per_thread": (_I, [_P, _I]),
+    "lens_forward": (_I, [_P, _I, _P, _P, _P]),
+    "lens_loglike": (_I, [_P, _I, _P, _P, _P]),
+    "lens_loglike_grad": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "lens_plan_enable_timing": (_I, [_P, _I]),
+    "lens_plan_read_timing": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+}
+
+KERNEL_SLOTS = ("prologue", "render", "psf", "adjoint", "finalize")
+NUM_KERNEL_SLOTS = 8
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblens.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def lens_status_string(status: int) -> str:
+    return load_library().lens_status_string(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != LENS_OK:
+        raise LensError(status, what)
+
+
+_MASS = {"SIE": LENS_MASS_SIE, "EPL": LENS_MASS_EPL}
+
+
+def desc_from_spec(spec) -> lens_model_desc:
+    return lens_model_desc(
+        spec.nx, spec.ny, spec.pix_scale, spec.supersample, spec.psf_size,
+        _MASS.get(spec.mass_model, -1), spec.n_lens_light, spec.n_source)
+
+
+def lens_num_params(spec) -> int:
+    d = desc_from_spec(spec)
+    return int(load_library().lens_num_params(ctypes.byref(d)))
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f32(x, device) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.float32)
+    return t.to(device).contiguous()
+
+
+class LensPlan:
+    """One lens system on the GPU: owns the C plan and the system arrays."""
+
+    def __init__(self, spec, psf, data, invvar, max_particles: int, device="cuda"):
+        load_library()
+        self.spec = spec
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.psf = _dev_f32(psf, self.device)
+        self.data = _dev_f32(data, self.device)
+        self.invvar = _dev_f32(invvar, self.device)
+        self.max_particles = int(max_particles)
+        self.desc = desc_from_spec(spec)
+        self.d = lens_num_params(spec)
+        handle = ctypes.c_void_p()
+        _check(_lib.lens_plan_create(ctypes.byref(self.desc), self.psf.data_ptr(), self.data.data_ptr(),
+                                     self.invvar.data_ptr(), self.max_particles, ctypes.byref(handle)),
+               "lens_plan_create")
+        self.handle = handle
+
+    def set_pixels_per_thread(self, ppt: int):
+        _check(_lib.lens_plan_set_pixels_per_thread(self.handle, int(ppt)), "lens_plan_set_pixels_per_thread")
+
+    def enable_timing(self, on: bool = True):
+        _check(_lib.lens_plan_enable_timing(self.handle, 1 if on else 0), "lens_plan_enable_timing")
+
+    def read_timing(self):
+        """{kernel: (total_ms, launches)} since the last read; synchronises."""
+        ms = (ctypes.c_double * NUM_KERNEL_SLOTS)()
+        cnt = (ctypes.c_int64 * NUM_KERNEL_SLOTS)()
+        _check(_lib.lens_plan_read_timing(self.handle, ms, cnt), "lens_plan_read_timing")
+        return {name: (ms[k], cnt[k]) for k, name in enumerate(KERNEL_SLOTS)}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lens_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _theta(self, theta: torch.Tensor) -> torch.Tensor:
+        if theta.dtype != torch.float32 or theta.device != self.device or not theta.is_contiguous():
+            raise ValueError("theta must be a contiguous float32 tensor on the plan's device")
+        if theta.dim() != 2 or theta.shape[1] != self.d:
+            raise ValueError(f"theta must be [P, {self.d}]")
+        return theta
+
+
+def lens_forward(plan: LensPlan, theta: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    th = plan._theta(theta)
+    P = th.shape[0]
+    if out is None:
+        out = torch.empty((P, plan.spec.ny, plan.spec.nx), dtype=torch.float32, device=plan.device)
+    _check(_lib.lens_forward(plan.handle, P, th.data_ptr(), out.data_ptr(), _stream(stream)), "lens_forward")
+    return out
+
+
+def lens_loglike(plan: LensPlan, theta: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    th = plan._theta(theta)
+    P = th.shape[0]
+    if out is None:
+        out = torch.empty(P, dtype=torch.float32, device=plan.device)
+    _check(_lib.lens_loglike(plan.handle, P, th.data_ptr(), out.data_ptr(), _stream(stream)), "lens_loglike")
+    return out
+
+
+def lens_loglike_grad(plan: LensPlan, theta: torch.Tensor, logl: Optional[torch.Tensor] = None,
+                      grad: Optional[torch.Tensor] = None, logl64: Optional[torch.Tensor] = None,
+                      want_logl64: bool = False, stream=None):
+    th = plan._theta(theta)
+    P = th.shape[0]
+    if logl is None:
+        logl = torch.empty(P, dtype=torch.float32, device=plan.device)
+    if grad is None:
+        grad = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
+    if logl64 is None and want_logl64:
+        logl64 = torch.empty(P, dtype=torch.float64, device=plan.device)
+    _check(_lib.lens_loglike_grad(plan.handle, P, th.data_ptr(), logl.data_ptr(), grad.data_ptr(),
+                                  None if logl64 is None else logl64.data_ptr(), _stream(stream)),
+           "lens_loglike_grad")
+    if logl64 is not None:
+        return logl, grad, logl64
+    return logl, grad
+
+
+class LensLogLike(torch.autograd.Function):
+    """logL(theta) per particle with the library's adjoint as its backward."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, plan: LensPlan):
+        logl, grad = lens_loglike_grad(plan, theta.detach().contiguous())
+        ctx.save_for_backward(grad)
+        return logl
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return gout[:, None] * grad, None

@@ -51,6 +51,10 @@ class ModelSpec:
     n_lens_light: int = 1
     n_source: int = 1
 
+    def __post_init__(self):
+        # the pixel scale is a float32 input of the GPU path: keep it float32-exact
+        object.__setattr__(self, "pix_scale", float(np.float32(self.pix_scale)))
+
     @property
     def n_mass(self) -> int:
         return 8 if self.mass_model == MASS_EPL else 7

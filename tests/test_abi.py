@@ -1,0 +1,55 @@
+"""The C-ABI library loads and exports every symbol include/*.h declares.
+
+Host-only: no call here touches the GPU.
+"""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2606_30633_amd import lens, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                             txt, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_is_built():
+    assert os.path.exists(lens.LIB_PATH), "run __graft_entry__.build()"
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert {"lens_forward", "lens_loglike", "lens_loglike_grad", "lens_plan_create"} <= names
+    lib = ctypes.CDLL(lens.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_param_counts():
+    assert lens.lens_status_string(0) == "ok"
+    assert "invalid" in lens.lens_status_string(-1)
+    assert lens.lens_num_params(synth.config1_spec()) == 21
+    assert lens.lens_num_params(synth.config2_spec()) == 29
+    assert lens.lens_num_params(synth.paper_spec(80, 2, 11)) == 22
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-1), dict(pix_scale=0.0), dict(supersample=0), dict(psf_size=4),
+    dict(psf_size=33), dict(mass_model="XYZ"), dict(n_lens_light=4), dict(n_source=0),
+])
+def test_invalid_descriptors_rejected(bad):
+    import dataclasses
+    spec = dataclasses.replace(synth.config1_spec(), **bad)
+    assert lens.lens_num_params(spec) == -1
