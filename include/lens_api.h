@@ -121,6 +121,73 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
                               void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Prior and bijection to the unconstrained space (Sec. 3.1: the tilde
+ * quantities are the parameters mapped to an unconstrained space; Sec. 4.2,
+ * eq. sim-dist: uniform, normal, log-normal and truncated-normal priors).
+ * Per parameter j, theta_j = T_j(u_j):
+ *   LENS_PRIOR_UNIFORM     (a, b): theta = a + (b - a) sigmoid(u)
+ *   LENS_PRIOR_TRUNCNORMAL (mu, sigma, lo, hi): theta = lo + (hi - lo) sigmoid(u),
+ *                          density N(mu, sigma) restricted to [lo, hi]
+ *   LENS_PRIOR_NORMAL      (mu, sigma): theta = u
+ *   LENS_PRIOR_LOGNORMAL   (mu, sigma): log theta ~ N(mu, sigma), theta = exp(u)
+ * The log prior is the sum of the per-parameter log densities of theta.
+ * ------------------------------------------------------------------------- */
+#define LENS_PRIOR_UNIFORM     0
+#define LENS_PRIOR_NORMAL      1
+#define LENS_PRIOR_LOGNORMAL   2
+#define LENS_PRIOR_TRUNCNORMAL 3
+
+/* Set the plan's prior.  h_table [d][5] host floats, row = (kind, a, b, c, d)
+ * with the arguments above (unused entries ignored).  Copied to the device.
+ * Errors: LENS_EINVAL for an unknown kind, sigma <= 0, or an empty interval. */
+lens_status lens_plan_set_prior(lens_plan* plan, const float* h_table);
+
+/* Log posterior in the unconstrained space and its gradient:
+ *   logp(u) = logL(T(u)) + log prior(T(u)) [+ log|dT/du| if with_jacobian]
+ *   d_u [P][d] in; d_logp [P] out (float64); d_grad [P][d] out = dlogp/du;
+ *   d_theta [P][d] out, optional: T(u) rounded to float32 (the point at
+ *   which the likelihood is evaluated).
+ * The MAP objective omits the Jacobian (its optimum is the MAP of theta);
+ * the HMC target includes it.  Requires lens_plan_set_prior. */
+lens_status lens_logpost_grad(lens_plan* plan, int32_t P, const float* d_u,
+                              int32_t with_jacobian, float* d_theta, double* d_logp,
+                              float* d_grad, void* stream);
+
+/* Multi-start MAP (Sec. 3, Sec. 3.1: every particle descends independently;
+ * Sec. 3.2: Adam for MAP).  Runs n_steps Adam updates (Kingma & Ba 2015,
+ * bias-corrected) of loss(u) = -(logL + log prior)(T(u)) on all P particles.
+ *   d_u [P][d] in/out; d_m, d_v [P][d] in/out Adam moments (zero to start);
+ *   d_loss [P] out: the loss at the last evaluated point (before the last
+ *   update).  The step counter (1-based, for the bias correction and the
+ *   learning-rate schedule lr_k = lr * decay^(k-1)) lives in the plan:
+ *   lens_map_reset restarts it.  use_graph != 0 captures one step into a HIP
+ *   graph on first use and replays it (the graph is re-captured when P or
+ *   any pointer or hyper-parameter changes). */
+lens_status lens_map_reset(lens_plan* plan);
+lens_status lens_map_adam(lens_plan* plan, int32_t P, float* d_u, float* d_m, float* d_v,
+                          int32_t n_steps, float lr, float decay, float beta1, float beta2,
+                          float eps, float* d_loss, int32_t use_graph, void* stream);
+
+/* HMC transitions (Sec. 3: HMC; Sec. 3.1: independent chains per GPU),
+ * target logp(u) with the Jacobian, diagonal mass matrix.  One transition:
+ * momenta p ~ N(0, M) from Philox4x32-10 (Salmon et al. 2011) with key =
+ * seed and counter = (chain, transition, block, 0), Box-Muller in float64;
+ * n_leapfrog steps of half kick / drift / half kick with step size eps;
+ * energy H = -logp + p^T M^-1 p / 2 in float64; Metropolis accept with the
+ * uniform from counter block ceil(d/4).
+ *   d_u [C][d], d_grad [C][d] (= dlogp/du), d_logp [C] (float64): the chain
+ *   state, in/out; must be consistent on entry (lens_logpost_grad with
+ *   with_jacobian = 1).  d_inv_mass [d]: M^-1 diagonal.
+ *   d_samples [n_transitions][C][d] out, optional; d_accepts [C] in/out,
+ *   optional: incremented on every accepted transition.
+ *   transition0: index of the first transition (counter word 1); successive
+ *   transitions use transition0 + 1, ...  use_graph as for lens_map_adam. */
+lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, double* d_logp,
+                         const float* d_inv_mass, float eps, int32_t n_leapfrog,
+                         int32_t n_transitions, uint64_t seed, uint64_t transition0,
+                         float* d_samples, int32_t* d_accepts, int32_t use_graph, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (diagnostics, not part of the model).
  * With timing enabled, every kernel a plan launches is bracketed by two HIP
  * events recorded on the call's stream; lens_plan_read_timing synchronises
@@ -137,6 +204,7 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
 #define LENS_K_PSF      2
 #define LENS_K_ADJOINT  3
 #define LENS_K_FINALIZE 4
+#define LENS_K_POSTERIOR 5   /* bijection, prior, Adam / HMC kick and accept */
 #define LENS_NUM_KERNEL_SLOTS 8
 
 lens_status lens_plan_enable_timing(lens_plan* plan, int32_t enable);

@@ -428,18 +428,30 @@ def log_prior(theta: torch.Tensor, table) -> torch.Tensor:
     return lp
 
 
-def log_posterior_unconstrained(u, spec, psf, data, invvar, table, with_jacobian: bool):
+def log_posterior_unconstrained(u, spec, psf, data, invvar, table, with_jacobian: bool,
+                                theta_float32: bool = False):
     """logL(T(u)) + log prior(T(u)) [+ log|J|] and its gradient w.r.t. u.
 
     The HMC target includes the Jacobian of the bijection; the MAP objective
     (multi-start gradient descent) does not, so its optimum is the MAP of
-    the constrained parameters.
+    the constrained parameters.  With ``theta_float32`` the likelihood is
+    evaluated at T(u) rounded to float32 (the parameter vector a float32
+    likelihood interface receives); the prior, the Jacobian and the chain
+    rule dT/du stay at the float64 T(u).
     """
     uu = _t(u).clone().requires_grad_(True)
     th, logj = to_constrained(uu, table)
     if not ellipticity_valid(th, spec):
         return -math.inf, np.zeros(uu.shape[0])
-    L = -0.5 * chi2(model_image(th, spec, psf), data, invvar) + log_prior(th, table)
+    lp = log_prior(th, table)
+    if theta_float32:
+        th_f = th.detach().to(torch.float32).to(DT)
+        L, gL = loglike_and_grad(th_f, spec, psf, data, invvar)
+        dth = torch.autograd.grad(th.sum(), uu, retain_graph=True)[0]   # elementwise map
+        rest = lp + (logj if with_jacobian else 0.0)
+        (gr,) = torch.autograd.grad(rest, uu)
+        return float(L) + float(rest.detach()), (torch.tensor(gL) * dth + gr).numpy()
+    L = -0.5 * chi2(model_image(th, spec, psf), data, invvar) + lp
     if with_jacobian:
         L = L + logj
     (g,) = torch.autograd.grad(L, uu)
@@ -521,3 +533,50 @@ def philox4x32(counter: Sequence[int], key: Sequence[int], rounds: int = 10) -> 
 def uniform_from_bits(w: int) -> float:
     """((w >> 8) + 1/2) * 2^-24: a uniform in (0, 1), exact in float32."""
     return ((w >> 8) + 0.5) * (2.0 ** -24)
+
+
+def box_muller(a: float, b: float) -> Tuple[float, float]:
+    """Two standard normals from two uniforms (Box & Muller 1958)."""
+    r = math.sqrt(-2.0 * math.log(a))
+    return r * math.cos(2.0 * math.pi * b), r * math.sin(2.0 * math.pi * b)
+
+
+def hmc_momenta(d: int, seed: int, chain: int, t: int) -> np.ndarray:
+    """Standard normals for one chain and transition.
+
+    Philox4x32-10 with key (seed low word, seed high word) and counter
+    (chain, t, block, 0); each block's four words give two Box-Muller pairs.
+    """
+    key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
+    z = []
+    for blk in range((d + 3) // 4):
+        w = philox4x32([chain, t, blk, 0], key)
+        z += list(box_muller(uniform_from_bits(w[0]), uniform_from_bits(w[1])))
+        z += list(box_muller(uniform_from_bits(w[2]), uniform_from_bits(w[3])))
+    return np.array(z[:d])
+
+
+def hmc_accept_uniform(d: int, seed: int, chain: int, t: int) -> float:
+    key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
+    return uniform_from_bits(philox4x32([chain, t, (d + 3) // 4, 0], key)[0])
+
+
+def hmc_transition(u, logp_grad_fn, inv_mass, eps: float, L: int, seed: int, chain: int, t: int):
+    """One HMC transition (Neal 2011) with Philox momenta and Metropolis accept.
+
+    logp_grad_fn(u) -> (logp, dlogp/du).  Momenta p = z / sqrt(inv_mass);
+    H = -logp + p^T M^-1 p / 2; accept iff log(uniform) < H0 - H1.
+    Returns (u_next, logp_next, accepted, H0, H1, log_uniform).
+    """
+    u = np.asarray(u, dtype=np.float64)
+    inv_mass = np.asarray(inv_mass, dtype=np.float64)
+    d = u.shape[0]
+    p = hmc_momenta(d, seed, chain, t) / np.sqrt(inv_mass)
+    lp0, _ = logp_grad_fn(u)
+    H0 = hamiltonian(lp0, p, inv_mass)
+    u1, p1 = leapfrog(u, p, lambda z: logp_grad_fn(z)[1], eps, L, inv_mass)
+    lp1, _ = logp_grad_fn(u1)
+    H1 = hamiltonian(lp1, p1, inv_mass) if np.isfinite(lp1) else math.inf
+    lu = math.log(hmc_accept_uniform(d, seed, chain, t))
+    acc = bool(np.isfinite(H1) and lu < H0 - H1)
+    return (u1 if acc else u), (lp1 if acc else lp0), acc, H0, H1, lu

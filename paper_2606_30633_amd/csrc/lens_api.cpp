@@ -3,10 +3,12 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <new>
 #include <vector>
 
 #include "lens_internal.h"
+#include "lens_sampler.h"
 
 using namespace lens;
 
@@ -14,6 +16,7 @@ using namespace lens;
 struct KernelTimer {
     static constexpr int kMaxRecords = 65536;
     bool enabled = false;
+    bool capturing = false;
     std::vector<hipEvent_t> ev[LENS_NUM_KERNEL_SLOTS];
     int used[LENS_NUM_KERNEL_SLOTS] = {0};
     int64_t count[LENS_NUM_KERNEL_SLOTS] = {0};
@@ -42,7 +45,7 @@ struct TimedLaunch {
     hipStream_t st;
     hipEvent_t stop = nullptr;
     TimedLaunch(KernelTimer* t_, int slot_, hipStream_t st_) : t(t_), slot(slot_), st(st_) {
-        if (!t->enabled) return;
+        if (!t->enabled || t->capturing) return;
         t->count[slot]++;
         hipEvent_t start = t->take(slot);
         stop = start ? t->take(slot) : nullptr;
@@ -51,6 +54,17 @@ struct TimedLaunch {
     }
     ~TimedLaunch() {
         if (stop) (void)hipEventRecord(stop, st);
+    }
+};
+
+// One captured HIP graph and the arguments it was captured with.
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key.clear();
     }
 };
 
@@ -69,6 +83,22 @@ struct lens_plan {
     double* partial;
     size_t partial_words;
     KernelTimer timer;
+    // inference stages
+    PriorRow* prior;          // [d] device, null until lens_plan_set_prior
+    float* theta;             // [maxP][d] T(u)
+    float* gtheta;            // [maxP][d] dlogL/dtheta
+    float* logl;              // [maxP]
+    double* logl64;           // [maxP]
+    double* logp;             // [maxP] (MAP path)
+    float* gradu;             // [maxP][d] (MAP path)
+    float* hmc_u0;            // [maxP][d]
+    float* hmc_g0;            // [maxP][d]
+    float* hmc_p;             // [maxP][d]
+    double* hmc_logp0;        // [maxP]
+    double* hmc_h0;           // [maxP]
+    int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC base
+    hipStream_t cap_stream;
+    GraphCache map_graph, hmc_graph;
 };
 
 namespace {
@@ -117,6 +147,14 @@ lens_status lens_plan_destroy(lens_plan* plan) {
     if (plan->consts) (void)hipFree(plan->consts);
     if (plan->imgbuf) (void)hipFree(plan->imgbuf);
     if (plan->partial) (void)hipFree(plan->partial);
+    plan->map_graph.reset();
+    plan->hmc_graph.reset();
+    void* bufs[] = {plan->prior, plan->theta, plan->gtheta, plan->logl, plan->logl64, plan->logp,
+                    plan->gradu, plan->hmc_u0, plan->hmc_g0, plan->hmc_p, plan->hmc_logp0,
+                    plan->hmc_h0, plan->counters};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     plan->timer.release();
     delete plan;
     return LENS_OK;
@@ -155,7 +193,30 @@ lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf, co
         lens_plan_destroy(p);
         return LENS_ENOMEM;
     }
-    if (launch_flip(K, d_psf, p->psf_flip, nullptr) != hipSuccess ||
+    const size_t Pd = (size_t)max_particles * p->mi.d;
+    const size_t Pn = (size_t)max_particles;
+    if (hipMalloc(&p->theta, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&p->gtheta, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&p->logl, sizeof(float) * Pn) != hipSuccess ||
+        hipMalloc(&p->logl64, sizeof(double) * Pn) != hipSuccess ||
+        hipMalloc(&p->logp, sizeof(double) * Pn) != hipSuccess ||
+        hipMalloc(&p->gradu, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&p->hmc_u0, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&p->hmc_g0, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&p->hmc_p, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&p->hmc_logp0, sizeof(double) * Pn) != hipSuccess ||
+        hipMalloc(&p->hmc_h0, sizeof(double) * Pn) != hipSuccess ||
+        hipMalloc(&p->counters, sizeof(int) * 8) != hipSuccess) {
+        lens_plan_destroy(p);
+        return LENS_ENOMEM;
+    }
+    if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        lens_plan_destroy(p);
+        return LENS_EHIP;
+    }
+    if (launch_set_int(p->counters, 0, nullptr) != hipSuccess ||
+        launch_set_int(p->counters + 1, 0, nullptr) != hipSuccess ||
+        launch_flip(K, d_psf, p->psf_flip, nullptr) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         lens_plan_destroy(p);
         return LENS_EHIP;
@@ -208,11 +269,10 @@ lens_status lens_loglike(lens_plan* plan, int32_t P, const float* d_theta, float
                                  plan->invvar, nullptr, d_logl, nullptr, st));
 }
 
-lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
-                              float* d_grad, double* d_logl64, void* stream) {
-    if (!plan || !d_theta || !d_logl || !d_grad || P < 1 || P > plan->max_particles)
-        return LENS_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
+// Enqueues logL + gradient for theta (no argument checks).
+static lens_status loglike_grad_enqueue(lens_plan* plan, int32_t P, const float* d_theta,
+                                        float* d_logl, float* d_grad, double* d_logl64,
+                                        hipStream_t st) {
     lens_status s = front(plan, P, d_theta, st);
     if (s != LENS_OK) return s;
     hipError_t e;
@@ -233,6 +293,212 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta, 
     TimedLaunch tl(&plan->timer, LENS_K_FINALIZE, st);
     return hip_status(launch_finalize(plan->mi, P, nch, d_theta, plan->consts, plan->partial,
                                       d_grad, st));
+}
+
+lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
+                              float* d_grad, double* d_logl64, void* stream) {
+    if (!plan || !d_theta || !d_logl || !d_grad || P < 1 || P > plan->max_particles)
+        return LENS_EINVAL;
+    return loglike_grad_enqueue(plan, P, d_theta, d_logl, d_grad, d_logl64, (hipStream_t)stream);
+}
+
+// Enqueues logp(u) and dlogp/du (no argument checks).  theta_out may be null.
+static lens_status logpost_enqueue(lens_plan* plan, int32_t P, const float* d_u, int with_jac,
+                                   float* theta_out, double* d_logp, float* d_grad,
+                                   hipStream_t st) {
+    const int d = plan->mi.d;
+    float* th = theta_out ? theta_out : plan->theta;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, st);
+        if (launch_bijection(P, d, plan->prior, d_u, th, st) != hipSuccess) return LENS_EHIP;
+    }
+    lens_status s = loglike_grad_enqueue(plan, P, th, plan->logl, plan->gtheta, plan->logl64, st);
+    if (s != LENS_OK) return s;
+    TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, st);
+    return hip_status(launch_posterior(P, d, plan->prior, d_u, plan->logl64, plan->gtheta,
+                                       with_jac, d_logp, d_grad, st));
+}
+
+lens_status lens_plan_set_prior(lens_plan* plan, const float* h_table) {
+    if (!plan || !h_table) return LENS_EINVAL;
+    const int d = plan->mi.d;
+    std::vector<PriorRow> rows(d);
+    const double half_log_2pi = 0.91893853320467274178;
+    for (int j = 0; j < d; ++j) {
+        const float* r = h_table + 5 * j;
+        const int kind = (int)r[0];
+        PriorRow& q = rows[j];
+        q.kind = kind;
+        q.a = r[1];
+        q.b = r[2];
+        q.pad0 = q.pad1 = 0.0;
+        if (kind == LENS_PRIOR_UNIFORM) {
+            if (!(r[2] > r[1])) return LENS_EINVAL;
+            q.lo = r[1];
+            q.hi = r[2];
+            q.cst = -std::log((double)r[2] - (double)r[1]);
+        } else if (kind == LENS_PRIOR_NORMAL || kind == LENS_PRIOR_LOGNORMAL) {
+            if (!(r[2] > 0.0f)) return LENS_EINVAL;
+            q.lo = q.hi = 0.0;
+            q.cst = -std::log((double)r[2]) - half_log_2pi;
+        } else if (kind == LENS_PRIOR_TRUNCNORMAL) {
+            if (!(r[2] > 0.0f) || !(r[4] > r[3])) return LENS_EINVAL;
+            q.lo = r[3];
+            q.hi = r[4];
+            const double zl = ((double)r[3] - r[1]) / r[2], zh = ((double)r[4] - r[1]) / r[2];
+            const double mass = 0.5 * (std::erfc(-zh / std::sqrt(2.0)) - std::erfc(-zl / std::sqrt(2.0)));
+            q.cst = -std::log((double)r[2]) - half_log_2pi - std::log(mass);
+        } else {
+            return LENS_EINVAL;
+        }
+    }
+    if (!plan->prior && hipMalloc(&plan->prior, sizeof(PriorRow) * d) != hipSuccess)
+        return LENS_ENOMEM;
+    if (hipMemcpy(plan->prior, rows.data(), sizeof(PriorRow) * d, hipMemcpyHostToDevice) != hipSuccess)
+        return LENS_EHIP;
+    plan->map_graph.reset();
+    plan->hmc_graph.reset();
+    return LENS_OK;
+}
+
+lens_status lens_logpost_grad(lens_plan* plan, int32_t P, const float* d_u, int32_t with_jacobian,
+                              float* d_theta, double* d_logp, float* d_grad, void* stream) {
+    if (!plan || !d_u || !d_logp || !d_grad || P < 1 || P > plan->max_particles) return LENS_EINVAL;
+    if (!plan->prior) return LENS_EINVAL;
+    return logpost_enqueue(plan, P, d_u, with_jacobian != 0, d_theta, d_logp, d_grad,
+                           (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// Runs `repeats` copies of the work that `enqueue` puts on a stream, either
+// eagerly on st or through a HIP graph captured once per key.
+template <class F>
+static lens_status run_maybe_graph(lens_plan* plan, GraphCache& gc, const std::vector<uint64_t>& key,
+                                   bool use_graph, int repeats, hipStream_t st, F&& enqueue) {
+    if (!use_graph) {
+        for (int r = 0; r < repeats; ++r) {
+            lens_status s = enqueue(st);
+            if (s != LENS_OK) return s;
+        }
+        return LENS_OK;
+    }
+    if (!gc.exec || gc.key != key) {
+        gc.reset();
+        hipGraph_t graph = nullptr;
+        plan->timer.capturing = true;
+        if (hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            plan->timer.capturing = false;
+            return LENS_EHIP;
+        }
+        lens_status s = enqueue(plan->cap_stream);
+        hipError_t e = hipStreamEndCapture(plan->cap_stream, &graph);
+        plan->timer.capturing = false;
+        if (s != LENS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (e != hipSuccess) return LENS_EHIP;
+        e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            gc.exec = nullptr;
+            return LENS_EHIP;
+        }
+        gc.key = key;
+    }
+    for (int r = 0; r < repeats; ++r)
+        if (hipGraphLaunch(gc.exec, st) != hipSuccess) return LENS_EHIP;
+    return LENS_OK;
+}
+
+extern "C" {
+
+static uint64_t fbits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+
+lens_status lens_map_reset(lens_plan* plan) {
+    if (!plan) return LENS_EINVAL;
+    if (launch_set_int(plan->counters, 0, nullptr) != hipSuccess) return LENS_EHIP;
+    return hip_status(hipDeviceSynchronize());
+}
+
+lens_status lens_map_adam(lens_plan* plan, int32_t P, float* d_u, float* d_m, float* d_v,
+                          int32_t n_steps, float lr, float decay, float beta1, float beta2,
+                          float eps, float* d_loss, int32_t use_graph, void* stream) {
+    if (!plan || !d_u || !d_m || !d_v || P < 1 || P > plan->max_particles || n_steps < 0)
+        return LENS_EINVAL;
+    if (!plan->prior || !(lr > 0.0f) || !(decay > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return LENS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const AdamHyper hp{lr, decay, beta1, beta2, eps};
+    const int d = plan->mi.d;
+    auto step = [&](hipStream_t s) -> lens_status {
+        lens_status r = logpost_enqueue(plan, P, d_u, 0, nullptr, plan->logp, plan->gradu, s);
+        if (r != LENS_OK) return r;
+        TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+        if (launch_adam(P, d, plan->gradu, plan->logp, d_u, d_m, d_v, plan->counters, hp, d_loss, s) !=
+            hipSuccess)
+            return LENS_EHIP;
+        return hip_status(launch_add_int(plan->counters, 1, s));
+    };
+    const std::vector<uint64_t> key = {(uint64_t)P, (uint64_t)(uintptr_t)d_u, (uint64_t)(uintptr_t)d_m,
+                                       (uint64_t)(uintptr_t)d_v, (uint64_t)(uintptr_t)d_loss,
+                                       fbits(lr), fbits(decay), fbits(beta1), fbits(beta2), fbits(eps),
+                                       (uint64_t)plan->ppt};
+    return run_maybe_graph(plan, plan->map_graph, key, use_graph != 0, n_steps, st, step);
+}
+
+lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, double* d_logp,
+                         const float* d_inv_mass, float eps, int32_t n_leapfrog,
+                         int32_t n_transitions, uint64_t seed, uint64_t transition0,
+                         float* d_samples, int32_t* d_accepts, int32_t use_graph, void* stream) {
+    if (!plan || !d_u || !d_grad || !d_logp || !d_inv_mass || C < 1 || C > plan->max_particles ||
+        n_leapfrog < 1 || n_transitions < 0 || !(eps > 0.0f))
+        return LENS_EINVAL;
+    if (!plan->prior) return LENS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int d = plan->mi.d;
+    HmcArgs a;
+    a.u = d_u; a.grad = d_grad; a.logp = d_logp;
+    a.u0 = plan->hmc_u0; a.g0 = plan->hmc_g0; a.logp0 = plan->hmc_logp0;
+    a.p = plan->hmc_p; a.h0 = plan->hmc_h0; a.inv_mass = d_inv_mass;
+    a.samples = d_samples; a.accepts = d_accepts;
+    a.tcount = plan->counters + 1;
+    a.seed = seed;
+    a.transition0 = transition0;
+    a.eps = eps;
+    auto transition = [&](hipStream_t s) -> lens_status {
+        {
+            TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+            if (launch_hmc_begin(C, d, a, s) != hipSuccess) return LENS_EHIP;
+        }
+        for (int l = 0; l < n_leapfrog; ++l) {
+            if (l > 0) {
+                TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+                if (launch_hmc_kick_drift(C, d, a, s) != hipSuccess) return LENS_EHIP;
+            }
+            lens_status r = logpost_enqueue(plan, C, d_u, 1, nullptr, d_logp, d_grad, s);
+            if (r != LENS_OK) return r;
+        }
+        {
+            TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+            if (launch_hmc_end(C, d, a, s) != hipSuccess) return LENS_EHIP;
+        }
+        return hip_status(launch_add_int(plan->counters + 1, 1, s));
+    };
+    // transition counter of this run starts at zero (outside any graph)
+    if (launch_set_int(plan->counters + 1, 0, st) != hipSuccess) return LENS_EHIP;
+    const std::vector<uint64_t> key = {(uint64_t)C, (uint64_t)(uintptr_t)d_u, (uint64_t)(uintptr_t)d_grad,
+                                       (uint64_t)(uintptr_t)d_logp, (uint64_t)(uintptr_t)d_inv_mass,
+                                       fbits(eps), (uint64_t)n_leapfrog, seed, transition0,
+                                       (uint64_t)(uintptr_t)d_samples, (uint64_t)(uintptr_t)d_accepts,
+                                       (uint64_t)plan->ppt};
+    return run_maybe_graph(plan, plan->hmc_graph, key, use_graph != 0, n_transitions, st, transition);
 }
 
 lens_status lens_plan_enable_timing(lens_plan* plan, int32_t enable) {

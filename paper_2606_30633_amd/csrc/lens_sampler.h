@@ -1,0 +1,52 @@
+// Internal declarations of the inference-stage kernels (lens_sampler.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lens {
+
+// One prior row on the device (float64): kind, (a, b) = (lo, hi) of a uniform
+// or (mu, sigma) otherwise, [lo, hi] of the sigmoid map, log-density constant.
+struct PriorRow {
+    double kind, a, b, lo, hi, cst, pad0, pad1;
+};
+
+struct AdamHyper {
+    float lr, decay, beta1, beta2, eps;
+};
+
+// Pointers and scalars of one HMC run (device pointers).
+struct HmcArgs {
+    float* u;          // [C][d] position
+    float* grad;       // [C][d] dlogp/du at u
+    double* logp;      // [C]
+    float* u0;         // [C][d] saved start of the transition
+    float* g0;         // [C][d]
+    double* logp0;     // [C]
+    float* p;          // [C][d] momentum
+    double* h0;        // [C] initial energy
+    const float* inv_mass;   // [d]
+    float* samples;    // [T][C][d] or null
+    int* accepts;      // [C] or null
+    const int* tcount; // transitions done in this run
+    uint64_t seed;
+    uint64_t transition0;
+    float eps;
+};
+
+hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u, float* theta,
+                            hipStream_t st);
+hipError_t launch_posterior(int P, int d, const PriorRow* table, const float* u, const double* logl,
+                            const float* gtheta, int with_jac, double* logp, float* grad_u,
+                            hipStream_t st);
+hipError_t launch_adam(int P, int d, const float* grad_u, const double* logp, float* u, float* m,
+                       float* v, const int* step, const AdamHyper& hp, float* loss,
+                       hipStream_t st);
+hipError_t launch_add_int(int* c, int inc, hipStream_t st);
+hipError_t launch_set_int(int* c, int val, hipStream_t st);
+hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st);
+hipError_t launch_hmc_kick_drift(int C, int d, const HmcArgs& a, hipStream_t st);
+hipError_t launch_hmc_end(int C, int d, const HmcArgs& a, hipStream_t st);
+
+}  // namespace lens

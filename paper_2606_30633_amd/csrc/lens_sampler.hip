@@ -1,0 +1,287 @@
+// Kernels of the inference stages around the likelihood (gfx950):
+// prior + bijection to the unconstrained space, posterior gradient, Adam
+// (multi-start MAP) and HMC leapfrog / Metropolis accept with a Philox
+// counter-based generator.  All per-particle or per-element; float64 where
+// a value feeds an energy or a sum over parameters.
+#include <math.h>
+#include <stdint.h>
+
+#include "lens_internal.h"
+#include "lens_sampler.h"
+
+namespace lens {
+
+// ---------------------------------------------------------------------------
+// Bijection and prior (per parameter)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double softplus_d(double x) {
+    return x > 0.0 ? x + log1p(exp(-x)) : log1p(exp(x));
+}
+
+// theta = T(u), dtheta/du, log|dtheta/du|, d log|dtheta/du| / du
+__device__ __forceinline__ void bijection(const PriorRow& r, double u, double& th, double& dth,
+                                          double& logj, double& dlogj) {
+    const int kind = (int)r.kind;
+    if (kind == LENS_PRIOR_UNIFORM || kind == LENS_PRIOR_TRUNCNORMAL) {
+        const double s = 1.0 / (1.0 + exp(-u));
+        const double w = r.hi - r.lo;
+        th = r.lo + w * s;
+        dth = w * s * (1.0 - s);
+        logj = log(w) - softplus_d(-u) - softplus_d(u);
+        dlogj = 1.0 - 2.0 * s;
+    } else if (kind == LENS_PRIOR_LOGNORMAL) {
+        th = exp(u);
+        dth = th;
+        logj = u;
+        dlogj = 1.0;
+    } else {
+        th = u;
+        dth = 1.0;
+        logj = 0.0;
+        dlogj = 0.0;
+    }
+}
+
+// log prior density of theta and its derivative
+__device__ __forceinline__ void log_prior(const PriorRow& r, double th, double& lp, double& dlp) {
+    const int kind = (int)r.kind;
+    if (kind == LENS_PRIOR_UNIFORM) {
+        lp = r.cst;
+        dlp = 0.0;
+    } else if (kind == LENS_PRIOR_LOGNORMAL) {
+        const double lx = log(th);
+        const double z = (lx - r.a) / r.b;
+        lp = r.cst - 0.5 * z * z - lx;
+        dlp = (-z / r.b - 1.0) / th;
+    } else {
+        const double z = (th - r.a) / r.b;
+        lp = r.cst - 0.5 * z * z;
+        dlp = -z / r.b;
+    }
+}
+
+__global__ void k_bijection(int P, int d, const PriorRow* __restrict__ table,
+                            const float* __restrict__ u, float* __restrict__ theta) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P * d) return;
+    const int j = q % d;
+    double th, dth, lj, dlj;
+    bijection(table[j], (double)u[q], th, dth, lj, dlj);
+    theta[q] = (float)th;
+}
+
+// logp = logL(theta) + log prior(theta) [+ log J]; grad_u = (g_theta + dlp) dth [+ dlogJ]
+__global__ void k_posterior(int P, int d, const PriorRow* __restrict__ table,
+                            const float* __restrict__ u, const double* __restrict__ logl,
+                            const float* __restrict__ gtheta, int with_jac,
+                            double* __restrict__ logp, float* __restrict__ grad_u) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double L = logl[p];
+    const float* up = u + (size_t)p * d;
+    const float* gp = gtheta + (size_t)p * d;
+    float* go = grad_u + (size_t)p * d;
+    if (!isfinite(L)) {
+        logp[p] = L;
+        const float z = isnan(L) ? __builtin_nanf("") : 0.0f;
+        for (int j = 0; j < d; ++j) go[j] = z;
+        return;
+    }
+    double lp_sum = 0.0, lj_sum = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double th, dth, lj, dlj, lp, dlp;
+        bijection(table[j], (double)up[j], th, dth, lj, dlj);
+        log_prior(table[j], th, lp, dlp);
+        lp_sum += lp;
+        lj_sum += lj;
+        go[j] = (float)(((double)gp[j] + dlp) * dth + (with_jac ? dlj : 0.0));
+    }
+    logp[p] = L + lp_sum + (with_jac ? lj_sum : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Adam on loss = -logp (Kingma & Ba 2015), element-wise
+// ---------------------------------------------------------------------------
+__global__ void k_adam(int P, int d, const float* __restrict__ grad_u, const double* __restrict__ logp,
+                       float* __restrict__ u, float* __restrict__ m, float* __restrict__ v,
+                       const int* __restrict__ step, AdamHyper hp, float* __restrict__ loss) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P * d) return;
+    const int k = *step + 1;
+    const float g = -grad_u[q];
+    const float mq = fmaf(hp.beta1, m[q], (1.0f - hp.beta1) * g);
+    const float vq = fmaf(hp.beta2, v[q], (1.0f - hp.beta2) * g * g);
+    m[q] = mq;
+    v[q] = vq;
+    const double bc1 = 1.0 - pow((double)hp.beta1, (double)k);
+    const double bc2 = 1.0 - pow((double)hp.beta2, (double)k);
+    const double lr = (double)hp.lr * pow((double)hp.decay, (double)(k - 1));
+    const double mh = (double)mq / bc1, vh = (double)vq / bc2;
+    u[q] = (float)((double)u[q] - lr * mh / (sqrt(vh) + (double)hp.eps));
+    if (q % d == 0 && loss) loss[q / d] = (float)(-logp[q / d]);
+}
+
+__global__ void k_add_int(int* c, int inc) { *c += inc; }
+__global__ void k_set_int(int* c, int val) { *c = val; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw 2011): 10 rounds of two 32x32
+// multiplications whose high/low halves are mixed into the four words,
+// with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k.x += W0; k.y += W1; }
+        const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+        const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ double uniform01(uint32_t w) {
+    return ((double)(w >> 8) + 0.5) * (1.0 / 16777216.0);
+}
+
+// Box-Muller: two uniforms -> two standard normals (float64)
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1) {
+    const double r = sqrt(-2.0 * log(uniform01(a)));
+    const double ang = 6.283185307179586476925 * uniform01(b);
+    z0 = r * cos(ang);
+    z1 = r * sin(ang);
+}
+
+// Momenta for one chain: words of counter blocks (chain, t, 0..), 4 normals per block.
+__device__ __forceinline__ double momentum(uint2 key, uint32_t chain, uint32_t t, int j) {
+    const uint4 w = philox(make_uint4(chain, t, (uint32_t)(j >> 2), 0u), key);
+    double z0, z1;
+    if ((j & 2) == 0) box_muller(w.x, w.y, z0, z1);
+    else box_muller(w.z, w.w, z0, z1);
+    return (j & 1) ? z1 : z0;
+}
+
+// Start of a transition: save the state, draw momenta, H0, first half kick + drift.
+__global__ void k_hmc_begin(int C, int d, HmcArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const uint32_t t = (uint32_t)(a.transition0 + (uint64_t)*a.tcount);
+    const uint2 key = make_uint2((uint32_t)(a.seed & 0xffffffffu), (uint32_t)(a.seed >> 32));
+    float* u = a.u + (size_t)c * d;
+    float* g = a.grad + (size_t)c * d;
+    float* u0 = a.u0 + (size_t)c * d;
+    float* g0 = a.g0 + (size_t)c * d;
+    float* p = a.p + (size_t)c * d;
+    double kin = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double im = (double)a.inv_mass[j];
+        const double pj = momentum(key, (uint32_t)c, t, j) / sqrt(im);
+        kin += pj * pj * im;
+        u0[j] = u[j];
+        g0[j] = g[j];
+        const float ph = (float)(pj + 0.5 * (double)a.eps * (double)g[j]);
+        p[j] = ph;
+        u[j] = fmaf(a.eps * a.inv_mass[j], ph, u[j]);
+    }
+    a.logp0[c] = a.logp[c];
+    a.h0[c] = -a.logp[c] + 0.5 * kin;
+}
+
+// Interior of the trajectory: full kick with the new gradient, then drift.
+__global__ void k_hmc_kick_drift(int C, int d, HmcArgs a) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= C * d) return;
+    const int j = q % d;
+    const float ph = fmaf(a.eps, a.grad[q], a.p[q]);
+    a.p[q] = ph;
+    a.u[q] = fmaf(a.eps * a.inv_mass[j], ph, a.u[q]);
+}
+
+// End: last half kick, H1, Metropolis accept (float64 energies), sample.
+__global__ void k_hmc_end(int C, int d, HmcArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int tl = *a.tcount;
+    const uint32_t t = (uint32_t)(a.transition0 + (uint64_t)tl);
+    const uint2 key = make_uint2((uint32_t)(a.seed & 0xffffffffu), (uint32_t)(a.seed >> 32));
+    float* u = a.u + (size_t)c * d;
+    float* g = a.grad + (size_t)c * d;
+    float* p = a.p + (size_t)c * d;
+    double kin = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double pj = (double)p[j] + 0.5 * (double)a.eps * (double)g[j];
+        kin += pj * pj * (double)a.inv_mass[j];
+    }
+    const double h1 = -a.logp[c] + 0.5 * kin;
+    const uint4 w = philox(make_uint4((uint32_t)c, t, (uint32_t)((d + 3) / 4), 0u), key);
+    const double lu = log(uniform01(w.x));
+    const bool accept = isfinite(h1) && (lu < a.h0[c] - h1);
+    if (!accept) {
+        const float* u0 = a.u0 + (size_t)c * d;
+        const float* g0 = a.g0 + (size_t)c * d;
+        for (int j = 0; j < d; ++j) { u[j] = u0[j]; g[j] = g0[j]; }
+        a.logp[c] = a.logp0[c];
+    }
+    if (a.accepts && accept) a.accepts[c] += 1;
+    if (a.samples) {
+        float* s = a.samples + ((size_t)tl * C + c) * d;
+        for (int j = 0; j < d; ++j) s[j] = u[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline dim3 blocks_for(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u, float* theta,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_bijection, blocks_for((long)P * d, 256), dim3(256), 0, st, P, d, table, u,
+                       theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_posterior(int P, int d, const PriorRow* table, const float* u, const double* logl,
+                            const float* gtheta, int with_jac, double* logp, float* grad_u,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_posterior, blocks_for(P, 64), dim3(64), 0, st, P, d, table, u, logl,
+                       gtheta, with_jac, logp, grad_u);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(int P, int d, const float* grad_u, const double* logp, float* u, float* m,
+                       float* v, const int* step, const AdamHyper& hp, float* loss,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, blocks_for((long)P * d, 256), dim3(256), 0, st, P, d, grad_u, logp, u,
+                       m, v, step, hp, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_int(int* c, int inc, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_int, dim3(1), dim3(1), 0, st, c, inc);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* c, int val, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, c, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_hmc_begin, blocks_for(C, 64), dim3(64), 0, st, C, d, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmc_kick_drift(int C, int d, const HmcArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_hmc_kick_drift, blocks_for((long)C * d, 256), dim3(256), 0, st, C, d, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmc_end(int C, int d, const HmcArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_hmc_end, blocks_for(C, 64), dim3(64), 0, st, C, d, a);
+    return hipGetLastError();
+}
+
+}  // namespace lens

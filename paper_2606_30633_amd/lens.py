@@ -48,11 +48,18 @@ _SIGNATURES = {
     "lens_forward": (_I, [_P, _I, _P, _P, _P]),
     "lens_loglike": (_I, [_P, _I, _P, _P, _P]),
     "lens_loglike_grad": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "lens_plan_set_prior": (_I, [_P, _P]),
+    "lens_logpost_grad": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
+    "lens_map_reset": (_I, [_P]),
+    "lens_map_adam": (_I, [_P, _I, _P, _P, _P, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, ctypes.c_float, _P, _I, _P]),
+    "lens_hmc_run": (_I, [_P, _I, _P, _P, _P, _P, ctypes.c_float, _I, _I, ctypes.c_uint64,
+                          ctypes.c_uint64, _P, _P, _I, _P]),
     "lens_plan_enable_timing": (_I, [_P, _I]),
     "lens_plan_read_timing": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 
-KERNEL_SLOTS = ("prologue", "render", "psf", "adjoint", "finalize")
+KERNEL_SLOTS = ("prologue", "render", "psf", "adjoint", "finalize", "posterior")
 NUM_KERNEL_SLOTS = 8
 
 
@@ -131,6 +138,15 @@ class LensPlan:
 
     def set_pixels_per_thread(self, ppt: int):
         _check(_lib.lens_plan_set_pixels_per_thread(self.handle, int(ppt)), "lens_plan_set_pixels_per_thread")
+
+    def set_prior(self, table):
+        """Prior table [d, 5] (kind, a, b, c, d) as in include/lens_api.h."""
+        import numpy as np
+        t = np.ascontiguousarray(np.asarray(table, dtype=np.float32))
+        if t.shape != (self.d, 5):
+            raise ValueError(f"prior table must be [{self.d}, 5]")
+        _check(_lib.lens_plan_set_prior(self.handle, t.ctypes.data_as(ctypes.c_void_p)), "lens_plan_set_prior")
+        self._prior = t
 
     def enable_timing(self, on: bool = True):
         _check(_lib.lens_plan_enable_timing(self.handle, 1 if on else 0), "lens_plan_enable_timing")
@@ -213,3 +229,65 @@ class LensLogLike(torch.autograd.Function):
     def backward(ctx, gout):
         (grad,) = ctx.saved_tensors
         return gout[:, None] * grad, None
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def lens_logpost_grad(plan: LensPlan, u: torch.Tensor, with_jacobian: bool, logp=None, grad=None,
+                      theta=None, want_theta: bool = False, stream=None):
+    """logp(u) (float64) and dlogp/du in the unconstrained space."""
+    uu = plan._theta(u)
+    P = uu.shape[0]
+    if logp is None:
+        logp = torch.empty(P, dtype=torch.float64, device=plan.device)
+    if grad is None:
+        grad = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
+    if theta is None and want_theta:
+        theta = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
+    _check(_lib.lens_logpost_grad(plan.handle, P, uu.data_ptr(), 1 if with_jacobian else 0, _ptr(theta),
+                                  logp.data_ptr(), grad.data_ptr(), _stream(stream)), "lens_logpost_grad")
+    if theta is not None:
+        return logp, grad, theta
+    return logp, grad
+
+
+def lens_map_reset(plan: LensPlan):
+    _check(_lib.lens_map_reset(plan.handle), "lens_map_reset")
+
+
+def lens_map_adam(plan: LensPlan, u: torch.Tensor, m: torch.Tensor, v: torch.Tensor, n_steps: int,
+                  lr: float, decay: float = 1.0, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, loss: Optional[torch.Tensor] = None, use_graph: bool = False,
+                  stream=None):
+    """n_steps Adam updates of u (in place) on -(logL + log prior)."""
+    uu = plan._theta(u)
+    plan._theta(m)
+    plan._theta(v)
+    _check(_lib.lens_map_adam(plan.handle, uu.shape[0], uu.data_ptr(), m.data_ptr(), v.data_ptr(),
+                              int(n_steps), lr, decay, beta1, beta2, eps, _ptr(loss),
+                              1 if use_graph else 0, _stream(stream)), "lens_map_adam")
+    return loss
+
+
+def lens_hmc_run(plan: LensPlan, u: torch.Tensor, grad: torch.Tensor, logp: torch.Tensor,
+                 inv_mass: torch.Tensor, eps: float, n_leapfrog: int, n_transitions: int, seed: int,
+                 transition0: int = 0, samples: Optional[torch.Tensor] = None,
+                 accepts: Optional[torch.Tensor] = None, use_graph: bool = False, stream=None):
+    """HMC transitions of C chains in place (state: u, grad = dlogp/du, logp float64)."""
+    uu = plan._theta(u)
+    plan._theta(grad)
+    C = uu.shape[0]
+    if logp.dtype != torch.float64 or logp.shape != (C,):
+        raise ValueError("logp must be float64 [C]")
+    if inv_mass.dtype != torch.float32 or inv_mass.shape != (plan.d,):
+        raise ValueError("inv_mass must be float32 [d]")
+    if samples is not None and samples.shape != (n_transitions, C, plan.d):
+        raise ValueError("samples must be [n_transitions, C, d]")
+    if accepts is not None and (accepts.dtype != torch.int32 or accepts.shape != (C,)):
+        raise ValueError("accepts must be int32 [C]")
+    _check(_lib.lens_hmc_run(plan.handle, C, uu.data_ptr(), grad.data_ptr(), logp.data_ptr(),
+                             inv_mass.data_ptr(), eps, int(n_leapfrog), int(n_transitions), int(seed),
+                             int(transition0), _ptr(samples), _ptr(accepts), 1 if use_graph else 0,
+                             _stream(stream)), "lens_hmc_run")

@@ -262,3 +262,41 @@ def test_philox4x32_known_answers():
     ]
     for c, k, out in kat:
         assert O.philox4x32(c, k) == out
+
+
+def test_philox_box_muller_momenta_are_standard_normal():
+    z = np.concatenate([O.hmc_momenta(29, 1234, c, t) for c in range(40) for t in range(20)])
+    assert abs(z.mean()) < 4 / math.sqrt(len(z))
+    assert abs(z.var() - 1) < 0.05
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    u = np.array([O.hmc_accept_uniform(29, 1234, c, t) for c in range(50) for t in range(20)])
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+def test_philox_hmc_transition_samples_gaussian():
+    cov = np.array([[1.0, 0.4], [0.4, 0.5]])
+    P = np.linalg.inv(cov)
+    f = lambda u: (-0.5 * u @ P @ u, -(P @ u))
+    u = np.zeros(2)
+    acc, out = 0, []
+    for t in range(3000):
+        u, lp, a, *_ = O.hmc_transition(u, f, np.ones(2), 0.3, 5, 99, 0, t)
+        acc += a
+        out.append(u)
+    s = np.array(out[200:])
+    assert acc > 2000
+    assert np.abs(s.mean(0)).max() < 0.15
+    np.testing.assert_allclose(np.cov(s.T), cov, atol=0.12)
+
+
+def test_float32_theta_posterior_close_to_float64():
+    spec = SMALL_SIE
+    sysm, psf, model, data = _system(spec)
+    table = synth.prior_table(sysm.prior)
+    th = synth.particles_box(sysm, 2, 3).astype(np.float64)
+    for t in th:
+        u = O.to_unconstrained(torch.tensor(t), table).numpy().astype(np.float32)
+        a, ga = O.log_posterior_unconstrained(u, spec, psf, data, sysm.invvar, table, True)
+        b, gb = O.log_posterior_unconstrained(u, spec, psf, data, sysm.invvar, table, True, theta_float32=True)
+        assert abs(a - b) <= 1e-6 * abs(a)
+        assert np.linalg.norm(ga - gb) <= 1e-5 * np.linalg.norm(ga)
