@@ -188,6 +188,54 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
                          float* d_samples, int32_t* d_accepts, int32_t use_graph, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Uneven batch: many lens systems of different image size, supersampling and
+ * PSF size, each with its own particles, evaluated together (the paper models
+ * samples of many systems, Sec. 4.2; this is the one-GPU form of that
+ * workload).  All systems share the model composition (mass model and the
+ * numbers of Sersic components), hence d.
+ *
+ * The render and adjoint stages each run as ONE persistent launch: work-groups
+ * take (system, particle, pixel-chunk) items from a list sorted by cost
+ * (largest first) through an integer atomic counter; the PSF stage runs one
+ * launch per distinct PSF size.  The pixel-chunk size per system ("tile",
+ * pixels per thread) is chosen by lens_batch_autotune.
+ * ------------------------------------------------------------------------- */
+typedef struct lens_batch_plan lens_batch_plan;
+
+/* h_descs [S] host; h_psf, h_data, h_invvar [S] host arrays of DEVICE pointers
+ * (same meaning and lifetime rules as lens_plan_create); h_particles [S]
+ * particles per system (>= 1).  Parameters, logL and gradients of a batch
+ * call are packed by system in order: system k's particles occupy rows
+ * [sum_{j<k} P_j, sum_{j<=k} P_j).
+ * Errors: LENS_EINVAL, LENS_EUNSUPPORTED (different model compositions, or an
+ * image + PSF tile that does not fit the 160 KB LDS), LENS_ENOMEM. */
+lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
+                                   const float* const* h_psf, const float* const* h_data,
+                                   const float* const* h_invvar, const int32_t* h_particles,
+                                   lens_batch_plan** out);
+lens_status lens_batch_plan_destroy(lens_batch_plan* plan);
+int64_t lens_batch_total_particles(const lens_batch_plan* plan);
+
+/* logL and dlogL/dtheta for every particle of every system.
+ *   d_theta [N][d] in, d_logl [N] out, d_grad [N][d] out, N = total particles.
+ * use_graph != 0: the whole sequence is captured into a HIP graph on first
+ * use and replayed (re-captured when a pointer or the tiles change). */
+lens_status lens_batch_loglike_grad(lens_batch_plan* plan, const float* d_theta, float* d_logl,
+                                    float* d_grad, int32_t use_graph, void* stream);
+
+/* Tiles: pixels per thread of a work item, per system (1..64). */
+lens_status lens_batch_get_tiles(const lens_batch_plan* plan, int32_t* h_ppt);
+lens_status lens_batch_set_tiles(lens_batch_plan* plan, const int32_t* h_ppt);
+
+/* Autotuner: groups the systems into size classes (supersampling x image-side
+ * bucket), tries tiles {1, 2, 4, 8} per class by coordinate descent, timing
+ * full batch calls on d_theta with HIP events, and keeps the fastest.  If
+ * cache_path is not NULL, a cached choice for the same batch geometry is used
+ * without timing, and a new choice is written there (JSON).  Synchronous. */
+lens_status lens_batch_autotune(lens_batch_plan* plan, const float* d_theta, const char* cache_path,
+                                void* stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (diagnostics, not part of the model).
  * With timing enabled, every kernel a plan launches is bracketed by two HIP
  * events recorded on the call's stream; lens_plan_read_timing synchronises

@@ -449,8 +449,11 @@ def log_posterior_unconstrained(u, spec, psf, data, invvar, table, with_jacobian
         L, gL = loglike_and_grad(th_f, spec, psf, data, invvar)
         dth = torch.autograd.grad(th.sum(), uu, retain_graph=True)[0]   # elementwise map
         rest = lp + (logj if with_jacobian else 0.0)
-        (gr,) = torch.autograd.grad(rest, uu)
-        return float(L) + float(rest.detach()), (torch.tensor(gL) * dth + gr).numpy()
+        gr = None
+        if rest.requires_grad:
+            (gr,) = torch.autograd.grad(rest, uu, allow_unused=True)
+        gr = torch.zeros_like(uu) if gr is None else gr
+        return float(L) + float(rest.detach()), (torch.tensor(gL) * dth.detach() + gr).numpy()
     L = -0.5 * chi2(model_image(th, spec, psf), data, invvar) + lp
     if with_jacobian:
         L = L + logj

@@ -104,6 +104,41 @@ hipError_t launch_flip(int K, const float* psf, double* flipped, hipStream_t st)
 size_t psf_lds_bytes(const Geo& g, int K);
 constexpr size_t MAX_LDS_BYTES = 160 * 1024 - 256;   // dynamic part; statics need < 256 B
 
+// Uneven batch: per-system descriptor (device) and work items.
+struct BatchSys {
+    Geo g;
+    int K, P, p0;            // PSF size, particles, first global particle
+    int ppb, nch;            // pixels per work item, items per particle
+    long long img_off;       // float offset of particle 0's image
+    long long part_off;      // partial-row offset of particle 0
+    const double* wflip;     // flipped PSF (float64)
+    const float* wpsf;       // PSF (float32)
+    const float* data;
+    const float* invvar;
+    int stride, rows;        // LDS tile of the PSF stage
+};
+
+struct WorkItem {
+    int sys, p, chunk;       // p: particle within its system
+};
+
+hipError_t launch_batch_render(const ModelInfo& mi, int grid, const BatchSys* sys,
+                               const WorkItem* items, int n_items, int* counter,
+                               const float* consts, float* img, hipStream_t st);
+hipError_t launch_batch_adjoint(const ModelInfo& mi, int grid, const BatchSys* sys,
+                                const WorkItem* items, int n_items, int* counter,
+                                const float* consts, const float* gimg, double* partial,
+                                hipStream_t st);
+hipError_t launch_batch_psf(int K, int n_items, const BatchSys* sys, const WorkItem* items,
+                            const float* consts, float* img, float* logl, size_t shm,
+                            hipStream_t st);
+hipError_t launch_batch_finalize(const ModelInfo& mi, int N, const BatchSys* sys,
+                                 const int* particle_sys, const float* theta, const float* consts,
+                                 const double* partial, float* grad, hipStream_t st);
+int batch_blocks_per_cu(const ModelInfo& mi, bool adjoint);
+hipError_t launch_set_int_host(int* c, int val, hipStream_t st);
+void psf_tile_dims(const Geo& g, int K, int& stride, int& rows);
+
 inline int chunks_for(int npix, int ppt) {
     const int per_block = 256 * ppt;
     return (npix + per_block - 1) / per_block;

@@ -479,20 +479,16 @@ __global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
     C[C_VALID] = !finite ? 2.0f : (ok ? 1.0f : 0.0f);
 }
 
+// Renders pixels [pix0, pix1) of one particle (whole work-group).
 template <int MASS, int NL, int NS>
-__global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts, Geo g, int ppb,
-                                                float* __restrict__ img) {
-    const int p = blockIdx.x;
-    const float* __restrict__ C = consts + (size_t)p * CSTRIDE;
-    const int pix0 = blockIdx.y * ppb;
-    const int pix1 = min(pix0 + ppb, g.npix);
-    float* out = img + (size_t)p * g.npix;
+__device__ __forceinline__ void render_chunk(const float* __restrict__ C, const Geo& g, int pix0,
+                                             int pix1, float* __restrict__ out) {
     if (C[C_VALID] != 1.0f) {
-        for (int pix = pix0 + threadIdx.x; pix < pix1; pix += 256) out[pix] = __builtin_nanf("");
+        for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) out[pix] = __builtin_nanf("");
         return;
     }
     const PK<NL + NS> k = load_pk<NL + NS>(C);
-    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += 256) {
+    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) {
         const int i = pix / g.nx, j = pix - i * g.nx;
         double acc = 0.0;
         for (int a = 0; a < g.s; ++a) {
@@ -506,16 +502,14 @@ __global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts
     }
 }
 
+// Reverse sweep over pixels [pix0, pix1) of one particle; writes the
+// work-group's NACC float64 sums to outp.  red: LDS [NACC][4] doubles.
+// Ends with a barrier, so red can be reused by the caller.
 template <int MASS, int NL, int NS>
-__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ consts, Geo g, int ppb,
-                                                 const float* __restrict__ gimg,
-                                                 double* __restrict__ partial) {
+__device__ __forceinline__ void adjoint_chunk(const float* __restrict__ C, const Geo& g, int pix0,
+                                              int pix1, const float* __restrict__ gp,
+                                              double* __restrict__ outp, double (*red)[4]) {
     constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
-    __shared__ double red[NACC][4];
-    const int p = blockIdx.x;
-    const int nch = gridDim.y;
-    const float* __restrict__ C = consts + (size_t)p * CSTRIDE;
-    double* outp = partial + ((size_t)p * nch + blockIdx.y) * NACC;
     if (C[C_VALID] != 1.0f) {
         if (threadIdx.x < NACC) outp[threadIdx.x] = 0.0;
         return;
@@ -524,10 +518,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ const
     float acc[NACC];
 #pragma unroll
     for (int q = 0; q < NACC; ++q) acc[q] = 0.f;
-    const int pix0 = blockIdx.y * ppb;
-    const int pix1 = min(pix0 + ppb, g.npix);
-    const float* gp = gimg + (size_t)p * g.npix;
-    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += 256) {
+    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) {
         const int i = pix / g.nx, j = pix - i * g.nx;
         const float gs = gp[pix] * g.inv_s2;
         for (int a = 0; a < g.s; ++a) {
@@ -549,6 +540,29 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ const
         const int q = threadIdx.x;
         outp[q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
     }
+    __syncthreads();
+}
+
+template <int MASS, int NL, int NS>
+__global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts, Geo g, int ppb,
+                                                float* __restrict__ img) {
+    const int p = blockIdx.x;
+    const int pix0 = blockIdx.y * ppb;
+    render_chunk<MASS, NL, NS>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
+                               img + (size_t)p * g.npix);
+}
+
+template <int MASS, int NL, int NS>
+__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ consts, Geo g, int ppb,
+                                                 const float* __restrict__ gimg,
+                                                 double* __restrict__ partial) {
+    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
+    __shared__ double red[NACC][4];
+    const int p = blockIdx.x;
+    const int pix0 = blockIdx.y * ppb;
+    adjoint_chunk<MASS, NL, NS>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
+                                gimg + (size_t)p * g.npix,
+                                partial + ((size_t)p * gridDim.y + blockIdx.y) * NACC, red);
 }
 
 // Register-blocked correlation of an LDS tile with a K x K kernel:
@@ -588,26 +602,26 @@ inline void psf_tile(const Geo& g, int K, int& stride, int& rows) {
     rows = g.ny + K - 1;
 }
 
+// One particle's PSF stage (whole work-group): the image buf[ny][nx] is
+// loaded into an LDS tile with a zero halo; mode 0 writes the convolved
+// model to out, modes 1-2 compute chi^2 -> logL, mode 2 also replaces buf by
+// the adjoint image (correlation of the residual w (d - m) with the PSF).
 template <int K, int MODE>
-__global__ __launch_bounds__(256) void k_psf(const float* __restrict__ consts, Geo g, float* img,
-                                             const double* __restrict__ wflip,
-                                             const float* __restrict__ wpsf,
-                                             const float* __restrict__ data,
-                                             const float* __restrict__ invvar, float* out,
-                                             float* logl, double* logl64, int stride, int rows) {
-    extern __shared__ float4 lds4[];
-    __shared__ double red[4];
-    float* lds = reinterpret_cast<float*>(lds4);
+__device__ __forceinline__ void psf_body(float valid, const Geo& g, float* buf,
+                                         const double* __restrict__ wflip,
+                                         const float* __restrict__ wpsf,
+                                         const float* __restrict__ data,
+                                         const float* __restrict__ invvar, float* out, float* logl,
+                                         double* logl64, int stride, int rows, float* lds,
+                                         double* red) {
     constexpr int H = (K - 1) / 2;
     constexpr int RW = PSF_RW;
-    const int p = blockIdx.x, tid = threadIdx.x;
-    const float valid = consts[(size_t)p * CSTRIDE + C_VALID];
-    float* buf = img + (size_t)p * g.npix;
+    const int tid = threadIdx.x;
     if (MODE != 0 && valid != 1.0f) {
         if (tid == 0) {
             const float v = valid == 2.0f ? __builtin_nanf("") : -__builtin_inff();
-            logl[p] = v;
-            if (logl64) logl64[p] = (double)v;
+            *logl = v;
+            if (logl64) *logl64 = (double)v;
         }
         return;
     }
@@ -631,7 +645,7 @@ __global__ __launch_bounds__(256) void k_psf(const float* __restrict__ consts, G
             if (j < g.nx) {
                 const int idx = i * g.nx + j;
                 if (MODE == 0) {
-                    out[(size_t)p * g.npix + idx] = (float)m[r];
+                    out[idx] = (float)m[r];
                 } else {
                     const double dlt = (double)data[idx] - m[r];
                     const double w = (double)invvar[idx];
@@ -641,11 +655,14 @@ __global__ __launch_bounds__(256) void k_psf(const float* __restrict__ consts, G
             }
         }
     }
-    if (MODE == 0) return;
+    if (MODE == 0) {
+        __syncthreads();
+        return;
+    }
     chi = block_sum(chi, red);
     if (tid == 0) {
-        logl[p] = (float)(-0.5 * chi);
-        if (logl64) logl64[p] = -0.5 * chi;
+        *logl = (float)(-0.5 * chi);
+        if (logl64) *logl64 = -0.5 * chi;
     }
     if (MODE == 2) {
         __syncthreads();
@@ -665,24 +682,36 @@ __global__ __launch_bounds__(256) void k_psf(const float* __restrict__ consts, G
             }
         }
     }
+    __syncthreads();
 }
 
-__global__ void k_finalize(ModelInfo mi, int P, int nchunks, const float* __restrict__ theta,
-                           const float* __restrict__ consts, const double* __restrict__ partial,
-                           float* __restrict__ grad) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+template <int K, int MODE>
+__global__ __launch_bounds__(256) void k_psf(const float* __restrict__ consts, Geo g, float* img,
+                                             const double* __restrict__ wflip,
+                                             const float* __restrict__ wpsf,
+                                             const float* __restrict__ data,
+                                             const float* __restrict__ invvar, float* out,
+                                             float* logl, double* logl64, int stride, int rows) {
+    extern __shared__ float4 lds4[];
+    __shared__ double red[4];
+    const int p = blockIdx.x;
+    psf_body<K, MODE>(consts[(size_t)p * CSTRIDE + C_VALID], g, img + (size_t)p * g.npix, wflip, wpsf,
+                      data, invvar, out ? out + (size_t)p * g.npix : nullptr, logl ? logl + p : nullptr,
+                      logl64 ? logl64 + p : nullptr, stride, rows, reinterpret_cast<float*>(lds4), red);
+}
+
+// Chain rule of one particle: sums its nchunks partial rows (fixed order) and
+// maps the accumulated adjoint sums to dlogL/dtheta in the canonical order.
+__device__ void finalize_particle(const ModelInfo& mi, int nchunks, const float* __restrict__ th,
+                                  float valid, const double* __restrict__ base,
+                                  float* __restrict__ g) {
     const int nc = mi.n_lens_light + mi.n_source;
     const int nacc = A_SERS + A_SERS_STRIDE * nc;
-    const float* th = theta + (size_t)p * mi.d;
-    float* g = grad + (size_t)p * mi.d;
-    const float valid = consts[(size_t)p * CSTRIDE + C_VALID];
     if (valid != 1.0f) {
         const float v = valid == 2.0f ? __builtin_nanf("") : 0.0f;
         for (int q = 0; q < mi.d; ++q) g[q] = v;
         return;
     }
-    const double* base = partial + (size_t)p * nchunks * nacc;
     auto acc = [&](int q) {
         double s = 0.0;
         for (int ch = 0; ch < nchunks; ++ch) s += base[(size_t)ch * nacc + q];
@@ -742,6 +771,99 @@ __global__ void k_finalize(ModelInfo mi, int P, int nchunks, const float* __rest
         g[o + 4] = (float)(-2.0 * kap * (a11 * qx + a12 * qy));
         g[o + 5] = (float)(-2.0 * kap * (a12 * qx + a22 * qy));
     }
+}
+
+__global__ void k_finalize(ModelInfo mi, int P, int nchunks, const float* __restrict__ theta,
+                           const float* __restrict__ consts, const double* __restrict__ partial,
+                           float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int nacc = A_SERS + A_SERS_STRIDE * (mi.n_lens_light + mi.n_source);
+    finalize_particle(mi, nchunks, theta + (size_t)p * mi.d, consts[(size_t)p * CSTRIDE + C_VALID],
+                      partial + (size_t)p * nchunks * nacc, grad + (size_t)p * mi.d);
+}
+
+// ---------------------------------------------------------------------------
+// Uneven batch: persistent render / adjoint over a cost-sorted work list,
+// PSF stage per PSF size, finalize over all particles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int next_item(int* counter, int* slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(*slot);
+    __syncthreads();
+    return it;
+}
+
+template <int MASS, int NL, int NS>
+__global__ __launch_bounds__(256) void k_batch_render(const BatchSys* __restrict__ sys,
+                                                      const WorkItem* __restrict__ items, int n_items,
+                                                      int* __restrict__ counter,
+                                                      const float* __restrict__ consts,
+                                                      float* __restrict__ img) {
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(counter, &slot);
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const BatchSys& S = sys[w.sys];
+        const int pix0 = w.chunk * S.ppb;
+        render_chunk<MASS, NL, NS>(consts + (size_t)(S.p0 + w.p) * CSTRIDE, S.g, pix0,
+                                   min(pix0 + S.ppb, S.g.npix),
+                                   img + S.img_off + (size_t)w.p * S.g.npix);
+    }
+}
+
+template <int MASS, int NL, int NS>
+__global__ __launch_bounds__(256) void k_batch_adjoint(const BatchSys* __restrict__ sys,
+                                                       const WorkItem* __restrict__ items, int n_items,
+                                                       int* __restrict__ counter,
+                                                       const float* __restrict__ consts,
+                                                       const float* __restrict__ gimg,
+                                                       double* __restrict__ partial) {
+    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
+    __shared__ double red[NACC][4];
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(counter, &slot);
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const BatchSys& S = sys[w.sys];
+        const int pix0 = w.chunk * S.ppb;
+        adjoint_chunk<MASS, NL, NS>(consts + (size_t)(S.p0 + w.p) * CSTRIDE, S.g, pix0,
+                                    min(pix0 + S.ppb, S.g.npix),
+                                    gimg + S.img_off + (size_t)w.p * S.g.npix,
+                                    partial + (S.part_off + (size_t)w.p * S.nch + w.chunk) * NACC, red);
+    }
+}
+
+// One work-group per (system, particle) of one PSF size class.
+template <int K>
+__global__ __launch_bounds__(256) void k_batch_psf(const BatchSys* __restrict__ sys,
+                                                   const WorkItem* __restrict__ items,
+                                                   const float* __restrict__ consts, float* img,
+                                                   float* logl) {
+    extern __shared__ float4 lds4[];
+    __shared__ double red[4];
+    const WorkItem w = items[blockIdx.x];
+    const BatchSys& S = sys[w.sys];
+    const int gp = S.p0 + w.p;
+    psf_body<K, 2>(consts[(size_t)gp * CSTRIDE + C_VALID], S.g, img + S.img_off + (size_t)w.p * S.g.npix,
+                   S.wflip, S.wpsf, S.data, S.invvar, nullptr, logl + gp, nullptr, S.stride, S.rows,
+                   reinterpret_cast<float*>(lds4), red);
+}
+
+__global__ void k_batch_finalize(ModelInfo mi, int N, const BatchSys* __restrict__ sys,
+                                 const int* __restrict__ particle_sys, const float* __restrict__ theta,
+                                 const float* __restrict__ consts, const double* __restrict__ partial,
+                                 float* __restrict__ grad) {
+    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= N) return;
+    const BatchSys& S = sys[particle_sys[gp]];
+    const int nacc = A_SERS + A_SERS_STRIDE * (mi.n_lens_light + mi.n_source);
+    const int p = gp - S.p0;
+    finalize_particle(mi, S.nch, theta + (size_t)gp * mi.d, consts[(size_t)gp * CSTRIDE + C_VALID],
+                      partial + (S.part_off + (size_t)p * S.nch) * nacc, grad + (size_t)gp * mi.d);
 }
 
 __global__ void k_flip(int K, const float* __restrict__ psf, double* __restrict__ flipped) {
@@ -866,10 +988,86 @@ hipError_t launch_finalize(const ModelInfo& mi, int P, int nchunks, const float*
     return hipGetLastError();
 }
 
+hipError_t launch_batch_render(const ModelInfo& mi, int grid, const BatchSys* sys,
+                               const WorkItem* items, int n_items, int* counter,
+                               const float* consts, float* img, hipStream_t st) {
+    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
+        hipLaunchKernelGGL(
+            (k_batch_render<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
+            dim3(grid), dim3(256), 0, st, sys, items, n_items, counter, consts, img);
+    });
+    if (!done) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adjoint(const ModelInfo& mi, int grid, const BatchSys* sys,
+                                const WorkItem* items, int n_items, int* counter,
+                                const float* consts, const float* gimg, double* partial,
+                                hipStream_t st) {
+    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
+        hipLaunchKernelGGL(
+            (k_batch_adjoint<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
+            dim3(grid), dim3(256), 0, st, sys, items, n_items, counter, consts, gimg, partial);
+    });
+    if (!done) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_batch_psf_k(int n_items, const BatchSys* sys, const WorkItem* items,
+                                     const float* consts, float* img, float* logl, size_t shm,
+                                     hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_psf<K>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)MAX_LDS_BYTES);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_batch_psf<K>, dim3(n_items), dim3(256), shm, st, sys, items, consts, img, logl);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_psf(int K, int n_items, const BatchSys* sys, const WorkItem* items,
+                            const float* consts, float* img, float* logl, size_t shm,
+                            hipStream_t st) {
+    switch (K) {
+#define LENS_BPSF_CASE(KK) \
+    case KK: return launch_batch_psf_k<KK>(n_items, sys, items, consts, img, logl, shm, st);
+        LENS_BPSF_CASE(1) LENS_BPSF_CASE(3) LENS_BPSF_CASE(5) LENS_BPSF_CASE(7) LENS_BPSF_CASE(9)
+        LENS_BPSF_CASE(11) LENS_BPSF_CASE(13) LENS_BPSF_CASE(15) LENS_BPSF_CASE(17) LENS_BPSF_CASE(19)
+        LENS_BPSF_CASE(21) LENS_BPSF_CASE(23) LENS_BPSF_CASE(25) LENS_BPSF_CASE(27) LENS_BPSF_CASE(29)
+        LENS_BPSF_CASE(31)
+#undef LENS_BPSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_finalize(const ModelInfo& mi, int N, const BatchSys* sys,
+                                 const int* particle_sys, const float* theta, const float* consts,
+                                 const double* partial, float* grad, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_finalize, dim3((N + 63) / 64), dim3(64), 0, st, mi, N, sys, particle_sys,
+                       theta, consts, partial, grad);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu(const ModelInfo& mi, bool adjoint) {
+    int nb = 0;
+    dispatch_model(mi, [&](auto M, auto NL, auto NS) {
+        constexpr int m = decltype(M)::value, l = decltype(NL)::value, s = decltype(NS)::value;
+        if (adjoint)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_adjoint<m, l, s>, 256, 0);
+        else
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_render<m, l, s>, 256, 0);
+    });
+    return nb > 0 ? nb : 1;
+}
+
 hipError_t launch_flip(int K, const float* psf, double* flipped, hipStream_t st) {
     hipLaunchKernelGGL(k_flip, dim3((K * K + 255) / 256), dim3(256), 0, st, K, psf, flipped);
     return hipGetLastError();
 }
+
+void psf_tile_dims(const Geo& g, int K, int& stride, int& rows) { psf_tile(g, K, stride, rows); }
 
 size_t psf_lds_bytes(const Geo& g, int K) {
     int stride, rows;

@@ -269,6 +269,8 @@ hipError_t launch_set_int(int* c, int val, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_set_int_host(int* c, int val, hipStream_t st) { return launch_set_int(c, val, st); }
+
 hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_hmc_begin, blocks_for(C, 64), dim3(64), 0, st, C, d, a);
     return hipGetLastError();

@@ -55,6 +55,13 @@ _SIGNATURES = {
                            ctypes.c_float, ctypes.c_float, _P, _I, _P]),
     "lens_hmc_run": (_I, [_P, _I, _P, _P, _P, _P, ctypes.c_float, _I, _I, ctypes.c_uint64,
                           ctypes.c_uint64, _P, _P, _I, _P]),
+    "lens_batch_plan_create": (_I, [_I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "lens_batch_plan_destroy": (_I, [_P]),
+    "lens_batch_total_particles": (ctypes.c_int64, [_P]),
+    "lens_batch_loglike_grad": (_I, [_P, _P, _P, _P, _I, _P]),
+    "lens_batch_get_tiles": (_I, [_P, _P]),
+    "lens_batch_set_tiles": (_I, [_P, _P]),
+    "lens_batch_autotune": (_I, [_P, _P, ctypes.c_char_p, _P]),
     "lens_plan_enable_timing": (_I, [_P, _I]),
     "lens_plan_read_timing": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -291,3 +298,69 @@ def lens_hmc_run(plan: LensPlan, u: torch.Tensor, grad: torch.Tensor, logp: torc
                              inv_mass.data_ptr(), eps, int(n_leapfrog), int(n_transitions), int(seed),
                              int(transition0), _ptr(samples), _ptr(accepts), 1 if use_graph else 0,
                              _stream(stream)), "lens_hmc_run")
+
+
+class BatchPlan:
+    """Many lens systems of uneven size evaluated together (lens_batch_*)."""
+
+    def __init__(self, specs, psfs, datas, invvars, particles, device="cuda"):
+        load_library()
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.specs = list(specs)
+        S = len(self.specs)
+        self.psfs = [_dev_f32(p, dev) for p in psfs]
+        self.datas = [_dev_f32(x, dev) for x in datas]
+        self.invvars = [_dev_f32(x, dev) for x in invvars]
+        self.particles = [int(n) for n in particles]
+        self.d = lens_num_params(self.specs[0])
+        descs = (lens_model_desc * S)(*[desc_from_spec(sp) for sp in self.specs])
+        arr = lambda ts: (ctypes.c_void_p * S)(*[t.data_ptr() for t in ts])
+        self._keep = (descs, arr(self.psfs), arr(self.datas), arr(self.invvars),
+                      (ctypes.c_int32 * S)(*self.particles))
+        handle = ctypes.c_void_p()
+        _check(_lib.lens_batch_plan_create(S, descs, self._keep[1], self._keep[2], self._keep[3],
+                                           self._keep[4], ctypes.byref(handle)), "lens_batch_plan_create")
+        self.handle = handle
+        self.S = S
+        self.N = int(_lib.lens_batch_total_particles(handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lens_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def loglike_grad(self, theta, logl=None, grad=None, use_graph=False, stream=None):
+        if theta.dtype != torch.float32 or theta.device != self.device or not theta.is_contiguous() \
+                or theta.shape != (self.N, self.d):
+            raise ValueError(f"theta must be contiguous float32 [{self.N}, {self.d}] on the plan's device")
+        if logl is None:
+            logl = torch.empty(self.N, dtype=torch.float32, device=self.device)
+        if grad is None:
+            grad = torch.empty((self.N, self.d), dtype=torch.float32, device=self.device)
+        _check(_lib.lens_batch_loglike_grad(self.handle, theta.data_ptr(), logl.data_ptr(), grad.data_ptr(),
+                                            1 if use_graph else 0, _stream(stream)), "lens_batch_loglike_grad")
+        return logl, grad
+
+    def get_tiles(self):
+        out = (ctypes.c_int32 * self.S)()
+        _check(_lib.lens_batch_get_tiles(self.handle, out), "lens_batch_get_tiles")
+        return list(out)
+
+    def set_tiles(self, ppt):
+        arr = (ctypes.c_int32 * self.S)(*[int(x) for x in ppt])
+        _check(_lib.lens_batch_set_tiles(self.handle, arr), "lens_batch_set_tiles")
+
+    def autotune(self, theta, cache_path=None, stream=None):
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(_lib.lens_batch_autotune(self.handle, theta.data_ptr(), path, _stream(stream)),
+               "lens_batch_autotune")
+        return self.get_tiles()

@@ -133,7 +133,7 @@ def test_map_converges_on_noiseless_data():
     ut = O.to_unconstrained(torch.tensor(sysm.truth, dtype=torch.float64), table).numpy()
     rng = np.random.default_rng(7)
     P = 64
-    u = (ut[None, :] + 0.05 * rng.standard_normal((P, spec.n_params))).astype(np.float32)
+    u = (ut[None, :] + 0.003 * rng.standard_normal((P, spec.n_params))).astype(np.float32)
     plan = lens.LensPlan(spec, psf, data, sysm.invvar, P, DEV)
     plan.set_prior(table)
     x = torch.tensor(u, device=DEV)
@@ -146,7 +146,7 @@ def test_map_converges_on_noiseless_data():
     start = np.array([-O.log_posterior_unconstrained(x0, spec, psf, data, sysm.invvar, table, False)[0]
                       for x0 in u[:4]])
     assert np.nanmin(lossv) <= loss_truth + 1.0, (np.nanmin(lossv), loss_truth)
-    assert np.median(lossv[:4]) < np.median(start) * 1e-2
+    assert np.median(lossv[:4] - loss_truth) < 1e-2 * np.median(start - loss_truth)
 
 
 def test_hmc_transitions_match_oracle():
@@ -176,7 +176,8 @@ def test_hmc_transitions_match_oracle():
         for t in range(2):
             uc, lp, a, H0, H1, lu = O.hmc_transition(uc, f, inv_mass, eps, L, seed, c, 10 + t)
             if abs(lu - (H0 - H1)) > 1e-3:
-                np.testing.assert_allclose(s[t, c], uc, rtol=0, atol=5e-5 * (1 + np.abs(uc)))
+                err = np.abs(s[t, c] - uc)
+                assert np.all(err <= 5e-5 * (1 + np.abs(uc))), (c, t, err.max())
             else:
                 pytest.skip("accept decision within rounding of the threshold")
     assert np.all(np.isfinite(logp.cpu().numpy()))

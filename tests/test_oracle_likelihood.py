@@ -296,7 +296,9 @@ def test_float32_theta_posterior_close_to_float64():
     th = synth.particles_box(sysm, 2, 3).astype(np.float64)
     for t in th:
         u = O.to_unconstrained(torch.tensor(t), table).numpy().astype(np.float32)
-        a, ga = O.log_posterior_unconstrained(u, spec, psf, data, sysm.invvar, table, True)
-        b, gb = O.log_posterior_unconstrained(u, spec, psf, data, sysm.invvar, table, True, theta_float32=True)
-        assert abs(a - b) <= 1e-6 * abs(a)
-        assert np.linalg.norm(ga - gb) <= 1e-5 * np.linalg.norm(ga)
+        for jac in (True, False):
+            a, ga = O.log_posterior_unconstrained(u, spec, psf, data, sysm.invvar, table, jac)
+            b, gb = O.log_posterior_unconstrained(u, spec, psf, data, sysm.invvar, table, jac,
+                                                  theta_float32=True)
+            assert abs(a - b) <= 1e-6 * abs(a)
+            assert np.linalg.norm(ga - gb) <= 1e-5 * np.linalg.norm(ga)
