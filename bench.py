@@ -26,6 +26,11 @@ sys.path.insert(0, ROOT)
 METRIC = "batched logL+grad evals/s at 100x100 px; time-to-MAP learned vs plain init"
 PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed FP32 / FP64
 PEAK_FP32_PACKED = 157.3
+# HBM bytes per k_adjoint launch of this workload from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes, scaled by a plain 256 MiB copy (profiles/
+# map_step_100px_4096p_counters.txt).  Valid only for the kernel source it was
+# measured on; reported as null otherwise.
+TRAFFIC_MEASURED = {"kernel_src_sha256_16": "b8372caf39a9a853", "bytes": 191320251}
 
 
 def parse():
@@ -36,10 +41,13 @@ def parse():
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after timing, copy a buffer of this many MiB (plain copy kernel, "
+                         "for scaling HBM byte counters)")
     return ap.parse_args()
 
 
-def adjoint_flops_per_subpixel(K_mean, NL, NS, epl=True):
+def adjoint_flops_per_subpixel(K_s, K_a, NL, NS, epl=True):
     """Algorithmic flops of the adjoint pass per sub-pixel (FMA = 2, other = 1).
 
     Counted from the operations the pass must perform: recompute of the
@@ -48,8 +56,8 @@ def adjoint_flops_per_subpixel(K_mean, NL, NS, epl=True):
     derivatives, chain through the deflection, Sersic adjoints and the
     accumulated sums).  See the design doc for the itemised count.
     """
-    series_fwd = 8 * K_mean                     # complex Horner, 4 FMA per term
-    series_adj = 8 * K_mean * (2 if epl else 1)  # S'(z) and dS/dt
+    series_fwd = 8 * K_s                        # complex Horner (float64 S), 4 FMA per step
+    series_adj = 8 * K_a * (2 if epl else 1)    # S'(z) and dS/dt (float32)
     mass_fwd = 40 + (60 if epl else 0)          # offsets, U, 1/R, V0, z, pow, alpha
     shear_lens = 12
     sersic_fwd = 18                             # offset, R^2, log2, 2 exp2, mults
@@ -111,16 +119,25 @@ def main():
     # dominant kernel: adjoint sub-pixel pass
     adj_ms, adj_n = tim["adjoint"]
     adj_avg_ms = adj_ms / max(adj_n, 1)
-    kp_mean = float(np.mean(_series_terms(th, spec)))
+    steps = _series_terms(th, spec).mean(axis=0)
     nsub = (spec.nx * spec.supersample) * (spec.ny * spec.supersample)
-    fl_sub = adjoint_flops_per_subpixel(kp_mean, spec.n_lens_light, spec.n_source, True)
+    fl_sub = adjoint_flops_per_subpixel(steps[0], steps[1], spec.n_lens_light, spec.n_source, True)
     flops_launch = fl_sub * nsub * P
     achieved = flops_launch / (adj_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4),
+                "traffic": _measured_traffic() if P == 4096 else None,
                 "kernel": "k_adjoint", "avg_ms": round(adj_avg_ms, 4),
                 "frac_of_fp32_packed_peak": round(achieved / PEAK_FP32_PACKED, 4),
                 "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
+
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb * (1 << 20)
+        src = torch.ones(nb // 4, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -140,6 +157,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2606_30633_amd", "csrc", "lens_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return TRAFFIC_MEASURED["bytes"] if h == TRAFFIC_MEASURED["kernel_src_sha256_16"] else None
+
+
 def _to_unconstrained_box(th, table):
     """Inverse of the scaled-sigmoid map for uniform-box starting points."""
     lo, hi = table[:, 1].astype(np.float64), table[:, 2].astype(np.float64)
@@ -149,27 +173,29 @@ def _to_unconstrained_box(th, table):
 
 
 def _series_terms(th, spec):
-    """Series length per particle (host mirror of the kernel's rule, for the flop count)."""
+    """Mean Horner steps per particle (host mirror of the kernel's tail bounds)."""
     o = 2
     c = np.hypot(th[:, o], th[:, o + 1]).astype(np.float64)
     t = th[:, 1].astype(np.float64) - 1.0
     out = []
     for ci, ti in zip(c, t):
-        if ci <= 0:
-            out.append(4)
-            continue
-        cn, Dn, cp, K = 1.0, 0.0, 1.0, 0
-        for n in range(1, 128):
-            a, b = 2 * n - 2 + ti, 2 * n + 2 - ti
-            cn *= a / b
-            Dn += 1 / a + 1 / b
-            cp *= ci
-            K = n
-            nxt = cn * (2 * n + ti) / (2 * n + 4 - ti)
-            if (n + 2) * nxt * (Dn + 2) * cp / (1 - ci) ** 2 < 2.0 ** -34:
+        cn, Dn, cp, K, KA = 1.0, 0.0, 1.0, -1, -1
+        for n in range(127):
+            a, b = 2 * n + ti, 2 * n + 4 - ti
+            cn1 = cn * a / b
+            Dn1 = Dn + 1 / a + 1 / b
+            ts = cn1 * cp * ci / (1 - ci)
+            ta = max((n + 1) * cn1 * cp, cn1 * (Dn1 + 1) * cp * ci) / (1 - ci) ** 2
+            if KA < 0 and ta < 2.0 ** -25:
+                KA = n
+            if K < 0 and ts < 2.0 ** -31:
+                K = n
+            if K >= 0 and KA >= 0:
                 break
-        out.append(((K + 4) // 4) * 4)
-    return np.array(out)
+            cn, Dn, cp = cn1, Dn1, cp * ci
+        KA = max(KA, 1)
+        out.append((((K + 4) // 4) * 4, ((KA + 4) // 4) * 4))
+    return np.array(out, dtype=np.float64)
 
 
 def cpu_baseline(spec, sysm, th_sample):

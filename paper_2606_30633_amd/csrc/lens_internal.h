@@ -13,7 +13,8 @@ namespace lens {
 // and read by every per-sub-pixel kernel through wave-uniform (scalar) loads.
 // ---------------------------------------------------------------------------
 constexpr int C_VALID = 0;    // 1 valid, 0 no valid profile (-inf), 2 non-finite (NaN)
-constexpr int C_KP = 1;       // padded series length KP (KP+1 multiple of 4), as float
+constexpr int C_KP = 1;       // padded length KP of the float64 series S (KP+1 multiple of 4), as float
+constexpr int C_KPA = 2;      // padded length of the float32 series S'(z), dS/dt (adjoint), as float
 // Mass block in float64 (word offsets, 8-byte aligned):
 constexpr int D_X0 = 4;       // mass centre
 constexpr int D_Y0 = 6;

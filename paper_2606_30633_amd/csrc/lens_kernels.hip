@@ -72,7 +72,7 @@ template <int NC>
 struct PK {
     double x0, y0, e1, e2, ua, ub, ue, c0, k0, k1, g1, g2;
     float e1f, e2f, k1f;
-    int kp;
+    int kp, kpa;
     SersicK s[NC > 0 ? NC : 1];
 };
 
@@ -88,6 +88,7 @@ __device__ __forceinline__ PK<NC> load_pk(const float* __restrict__ C) {
     k.k0 = ldd(C, D_K0); k.k1 = ldd(C, D_K1); k.g1 = ldd(C, D_G1); k.g2 = ldd(C, D_G2);
     k.e1f = (float)k.e1; k.e2f = (float)k.e2; k.k1f = (float)k.k1;
     k.kp = (int)C[C_KP];
+    k.kpa = (int)C[C_KPA];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const float* S = C + C_SERS + c * SERS_STRIDE;
@@ -282,8 +283,8 @@ __device__ __forceinline__ void deflect(double x, double y, const PK<NC>& k,
     series_d(C, k.kp, zx, zy, sx, sy);
     double f = k.c0, L2 = 0.0;
     if (MASS == LENS_MASS_EPL) {
-        L2 = log2(r2);
-        f *= exp2(fma(-k.k1, L2, k.k0));
+        L2 = log2_d(r2);
+        f *= exp2_d(fma(-k.k1, L2, k.k0));
     }
     ax = inside ? 0.0 : f * fma(vx, sx, -vy * sy);
     ay = inside ? 0.0 : f * fma(vx, sy, vy * sx);
@@ -347,7 +348,7 @@ __device__ __forceinline__ void subpix_adjoint(double x, double y, float gs, con
     if (m.inside) { Gx = 0.f; Gy = 0.f; }
 
     float dx, dy, tx, ty;
-    series_adj<MASS == LENS_MASS_EPL>(C, k.kp, m.zx, m.zy, dx, dy, tx, ty);
+    series_adj<MASS == LENS_MASS_EPL>(C, k.kpa, m.zx, m.zy, dx, dy, tx, ty);
     const float vx = m.vx, vy = m.vy, sx = m.sx, sy = m.sy;
     const float h = fmaf(Gx, m.ax, Gy * m.ay);                // Re(conj(G) alpha)
     acc[A_H] += h;
@@ -449,33 +450,46 @@ __global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
         S[S_KAP2] = (float)(-bn / n);
     }
     // Series coefficients c_n(t), (n+1) c_{n+1} for S'(z), and dc_n/dt = c_n D_n,
-    // D_n = sum_{k<=n} [1/(2k-2+t) + 1/(2k+2-t)].  Length K: the first n at
-    // which a bound on the remaining terms of S and S' falls below 2^-34.
+    // D_n = sum_{k<=n} [1/(2k-2+t) + 1/(2k+2-t)], |z| = c, c_n decreasing.
+    // Truncation after z^K leaves at most c_{K+1} c^{K+1}/(1-c) in S (kept
+    // below 2^-31: the deflection must be good to ~3e-9 relative), and at
+    // most (K+1) c_{K+1} c^K/(1-c)^2 in S' and c_{K+1}(D_{K+1}+1) c^{K+1}/(1-c)^2
+    // in dS/dt (below 2^-25: float32 adjoint).
     double* cS = reinterpret_cast<double*>(C + C_COEF_S);
     float* cZ = C + C_COEF_Z;
     float* cT = C + C_COEF_T;
     cS[0] = 1.0; cT[0] = 0.0f;
-    int K = 0;
-    if (ok && c > 0.0) {
-        double cn = 1.0, Dn = 0.0, cpow = 1.0;
-        for (int n = 1; n <= KMAX_TERMS; ++n) {
-            const double a = 2.0 * n - 2.0 + t, bb = 2.0 * n + 2.0 - t;
-            cn *= a / bb;
-            Dn += 1.0 / a + 1.0 / bb;
-            cpow *= c;
-            cS[n] = cn;
-            cZ[n - 1] = (float)(n * cn);
-            cT[n] = (float)(cn * Dn);
-            K = n;
-            const double next = cn * (2.0 * n + t) / (2.0 * n + 4.0 - t);
-            const double tail = (n + 2.0) * next * (Dn + 2.0) * cpow / ((1.0 - c) * (1.0 - c));
-            if (tail < 5.820766091346741e-11) break;
+    int K = -1, KA = -1;
+    if (ok) {
+        double cn = 1.0, Dn = 0.0, cpow = 1.0;   // c_n, D_n, c^n
+        const double om = 1.0 - c;
+        for (int n = 0; n < KMAX_TERMS; ++n) {
+            const double a = 2.0 * (n + 1) - 2.0 + t, bb = 2.0 * (n + 1) + 2.0 - t;
+            const double cn1 = cn * a / bb, Dn1 = Dn + 1.0 / a + 1.0 / bb;
+            cS[n + 1] = cn1;
+            cZ[n] = (float)((n + 1) * cn1);
+            cT[n + 1] = (float)(cn1 * Dn1);
+            const double tail_s = cn1 * cpow * c / om;
+            const double tail_a = fmax((n + 1) * cn1 * cpow, cn1 * (Dn1 + 1.0) * cpow * c) / (om * om);
+            if (KA < 0 && tail_a < 2.9802322387695312e-08) KA = n;
+            if (K < 0 && tail_s < 4.656612873077393e-10) K = n;
+            if (K >= 0 && KA >= 0) break;
+            cn = cn1; Dn = Dn1; cpow *= c;
         }
+        if (K < 0) K = KMAX_TERMS - 1;
+        if (KA < 0) KA = KMAX_TERMS - 1;
+        // S' keeps one term more than the S' bound asks, so that S'(0) = c_1 always
+        KA = KA < 1 ? 1 : KA;
+    } else {
+        K = 0; KA = 1;
     }
-    const int KP = ((K + 1 + 3) / 4) * 4 - 1;
-    for (int n = K + 1; n <= KP; ++n) { cS[n] = 0.0; cT[n] = 0.0f; }
-    for (int n = K; n <= KP; ++n) cZ[n] = 0.0f;
+    const int KP = ((K + 1 + 3) / 4) * 4 - 1;     // S: c_0..c_K
+    const int KPA = ((KA + 1 + 3) / 4) * 4 - 1;   // adjoint: S' terms 0..KA-1, dS/dt terms 0..KA
+    for (int n = K + 1; n <= KP; ++n) cS[n] = 0.0;
+    for (int n = KA + 1; n <= KPA; ++n) cT[n] = 0.0f;
+    for (int n = KA; n <= KPA; ++n) cZ[n] = 0.0f;
     C[C_KP] = (float)KP;
+    C[C_KPA] = (float)KPA;
     C[C_VALID] = !finite ? 2.0f : (ok ? 1.0f : 0.0f);
 }
 
