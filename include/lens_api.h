@@ -236,6 +236,80 @@ lens_status lens_batch_autotune(lens_batch_plan* plan, const float* d_theta, con
                                 void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Learned initializer.  A convolutional network regresses, from a 64x64
+ * image of a system, 14 lens parameters and their log-variances; its
+ * Gaussian proposals replace part of the prior-sampled starting particles of
+ * the multi-start MAP stage (Sec. 3: MAP by multi-start gradient descent).
+ * The network is not part of the paper; it is trained here on images that
+ * lens_forward simulates.
+ *
+ * Architecture (fixed): input [B][64][64] bf16 (one channel); six 3x3
+ * convolutions, padding 1, ReLU, channels 32-32-64-64-128-128, strides
+ * 1-2-1-2-1-2; global average pooling; dense 128 -> 256 (ReLU) -> 28.
+ * Outputs [B][28]: mu_k (k < 14) and log sigma_k^2 (14 + k) of the
+ * standardised targets.  Flat parameter vector (float32), in this order:
+ * for each convolution W[cout][3][3][cin] then bias[cout]; dense W[256][128],
+ * bias[256]; dense W[28][256], bias[28].
+ * All contractions run on BF16 matrix cores with FP32 accumulation; the
+ * activations and gradients passed between layers are bf16 (round to
+ * nearest even).  Training loss: mean over the batch of the Gaussian
+ * negative log-likelihood sum_k [(z_k - mu_k)^2 e^{-s_k} + s_k] / 2.
+ * ------------------------------------------------------------------------- */
+typedef struct lens_cnn lens_cnn;
+#define LENS_CNN_SIDE    64
+#define LENS_CNN_TARGETS 14
+#define LENS_CNN_OUTPUTS 28
+
+/* Network with room for batches up to max_batch; weights He-initialised from
+ * Philox4x32-10 with the given seed.  Errors: LENS_EINVAL, LENS_ENOMEM. */
+lens_status lens_cnn_create(int32_t max_batch, uint64_t seed, lens_cnn** out);
+lens_status lens_cnn_destroy(lens_cnn* net);
+int64_t lens_cnn_num_params(void);
+/* d_params [lens_cnn_num_params()] float32 device copy in/out. */
+lens_status lens_cnn_get_params(lens_cnn* net, float* d_params, void* stream);
+lens_status lens_cnn_set_params(lens_cnn* net, const float* d_params, void* stream);
+
+/* Network input from surface-brightness images: optional Gaussian noise
+ * N(0, sigma^2) (Philox, key seed, counter counter0 + pixel index), then
+ * asinh(x / (3 sigma)), rounded to bf16.  d_images [n][64][64] float,
+ * d_out [n][64][64] bf16 (uint16 storage). */
+lens_status lens_cnn_prepare_images(int32_t n_images, const float* d_images, float sigma,
+                                    int32_t add_noise, uint64_t seed, uint64_t counter0,
+                                    uint16_t* d_out, void* stream);
+
+/* Inference: d_img [B][64][64] bf16 -> d_out [B][28] float. */
+lens_status lens_cnn_forward(lens_cnn* net, int32_t B, const uint16_t* d_img, float* d_out,
+                             void* stream);
+/* Mean loss over the batch (d_loss [1]) and, if d_grads != NULL, its gradient
+ * with respect to the flat parameter vector.  d_target [B][14] standardised. */
+lens_status lens_cnn_loss_grad(lens_cnn* net, int32_t B, const uint16_t* d_img,
+                               const float* d_target, float* d_loss, float* d_grads,
+                               void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean loss. */
+lens_status lens_cnn_train_step(lens_cnn* net, int32_t B, const uint16_t* d_img,
+                                const float* d_target, float lr, float* d_loss, void* stream);
+
+/* Proposal map: d parameters with the prior table of lens_plan_set_prior;
+ * h_slot[j] = k routes network output k (0..13) to parameter j, -1 draws
+ * parameter j from its prior; target k is standardised as
+ * (theta - h_mean[k]) / h_std[k]; sigma is the image noise level used by the
+ * input transform. */
+lens_status lens_cnn_set_target_map(lens_cnn* net, int32_t d, const float* h_prior_table,
+                                    const int32_t* h_slot, const float* h_mean,
+                                    const float* h_std, float sigma);
+
+/* Starting particles for S systems: d_img64 [S][64][64] float images (crop or
+ * zero-pad to 64x64 at the native pixel scale), n_per_system draws each:
+ * mapped parameters theta_j = mean_k + std_k (mu_k + e^{s_k/2} z), z ~ N(0,1),
+ * the others from the prior; Philox4x32-10 with the given seed, counter
+ * (system, draw, parameter).  d_theta_out [S][n][d]; d_flags [S] (optional):
+ * 1 if a proposal had to be clipped into the prior support, else 0.  Falling
+ * back to prior-sampled starts is the caller's decision (see the time-to-MAP
+ * driver).  Requires lens_cnn_set_target_map. */
+lens_status init_propose(lens_cnn* net, int32_t S, const float* d_img64, int32_t n_per_system,
+                         uint64_t seed, float* d_theta_out, int32_t* d_flags, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (diagnostics, not part of the model).
  * With timing enabled, every kernel a plan launches is bracketed by two HIP
  * events recorded on the call's stream; lens_plan_read_timing synchronises

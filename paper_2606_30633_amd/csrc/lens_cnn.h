@@ -1,0 +1,71 @@
+// Internal declarations of the learned initializer (lens_cnn.hip, lens_cnn_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lens_api.h"
+
+namespace lens {
+
+constexpr int CNN_IN = 64;       // input side
+constexpr int CNN_CONV = 6;      // 3x3 convolutions, ReLU after each
+constexpr int CNN_C6 = 128;      // channels of the last convolution
+constexpr int CNN_H1 = 256;      // hidden width of the MLP
+constexpr int CNN_NT = 14;       // regressed parameters
+constexpr int CNN_OUT = 2 * CNN_NT;   // means + log-variances
+constexpr int CNN_MAXD = 64;
+
+struct CnnLayer {
+    int cin, cout, stride;
+    long long w_off, b_off;   // offsets into the flat parameter vector
+};
+
+// Where the network's outputs go in a parameter vector, and the prior of the rest.
+struct CnnTargetMap {
+    int d;
+    int prior_kind[CNN_MAXD];
+    double prior[CNN_MAXD][4];   // (a, b, lo, hi) as in lens_plan_set_prior
+    int cnn_slot[CNN_MAXD];      // network output index, or -1: drawn from the prior
+    double mean[CNN_NT], stdv[CNN_NT];
+};
+
+struct CnnNet {
+    int max_batch;
+    long long nparams;
+    CnnLayer conv[CNN_CONV];
+    CnnLayer fc1, fc2;
+    float* params;      // fp32 master copy
+    float* grads;
+    float* adam_m;
+    float* adam_v;
+    __bf16* wbf;        // bf16 copy used by the GEMMs
+    __bf16* act[CNN_CONV];
+    __bf16* dact[CNN_CONV];
+    __bf16* pooled;
+    float* dpooled;
+    __bf16* hidden;
+    __bf16* dhidden;
+    float* out;
+    __bf16* dout;
+    float* wpart;
+    double* colpart;
+    double* losspart;
+    CnnTargetMap* tmap;   // device copy
+    __bf16* prep;         // prepared images for init_propose
+    int step;
+    float sigma;
+    bool has_map;
+};
+
+hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st);
+hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* target, float* loss, hipStream_t st);
+hipError_t cnn_adam(CnnNet& net, float lr, int step, hipStream_t st);
+hipError_t cnn_init(CnnNet& net, uint64_t seed, hipStream_t st);
+hipError_t cnn_params_to_bf16(CnnNet& net, hipStream_t st);
+hipError_t cnn_prepare(long long n, const float* img, float sigma, int add_noise, uint64_t seed, uint64_t counter0,
+                       __bf16* out, hipStream_t st);
+hipError_t cnn_propose(int S, int s0, int n, int d, const float* net_out, const CnnTargetMap* tm, uint64_t seed,
+                       float* theta, int* flags, hipStream_t st);
+
+}  // namespace lens

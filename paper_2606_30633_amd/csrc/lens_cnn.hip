@@ -1,0 +1,643 @@
+// Learned initializer: a small convolutional network that regresses lens
+// parameters (and their log-variances) from a 64x64 image, trained and run
+// with hand-written BF16 matrix-core (MFMA) kernels with FP32 accumulation.
+//
+// Every dense contraction (convolution forward, data gradient, weight
+// gradient; fully connected forward and backward) is one generic GEMM kernel
+// C[M][N] = sum_k A(m, k) B(k, n) whose operand loads and epilogue are given
+// by small "op" structs (implicit GEMM: no im2col buffer).  Tiles: 64 x 64
+// outputs per 256-thread work-group, K in steps of 32 staged through LDS,
+// each wave computing 32 x 32 with 2 x 2 v_mfma_f32_16x16x32_bf16.
+// Activations and gradients between layers are bf16 (round to nearest even);
+// master weights, biases, Adam moments and reductions are fp32/fp64.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lens_cnn.h"
+
+namespace lens {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }   // RNE
+__device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+    return z;
+}
+
+// ---------------------------------------------------------------------------
+// Generic BF16 MFMA GEMM.  Op provides:
+//   bf16x8 loadA(int m, int k, int kend) : A(m, k..k+7), zero where m >= M or k >= kend
+//   bf16x8 loadB(int k, int n, int kend) : B(k..k+7, n), zero where n >= N or k >= kend
+//   void   store(int m, int n, float v, int split)
+// ---------------------------------------------------------------------------
+constexpr int GT = 64;    // output tile (M and N)
+constexpr int GK = 32;    // K step
+constexpr int LDSK = 40;  // padded LDS row (bf16)
+
+template <class Op>
+__global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_per_split) {
+    __shared__ __attribute__((aligned(16))) __bf16 As[GT][LDSK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[GT][LDSK];
+    const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+    const int kbeg = blockIdx.z * k_per_split;
+    const int kend = min(K, kbeg + k_per_split);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lr = t >> 2, lk = (t & 3) * 8;
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        const bf16x8 av = (m0 + lr < M) ? op.loadA(m0 + lr, k0 + lk, kend) : zero8();
+        const bf16x8 bv = (n0 + lr < N) ? op.loadB(k0 + lk, n0 + lr, kend) : zero8();
+        __syncthreads();
+        *reinterpret_cast<bf16x8*>(&As[lr][lk]) = av;
+        *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = bv;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[32 * wm + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[32 * wn + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + 32 * wm + 16 * i + 4 * (lane >> 4) + r;
+                const int n = n0 + 32 * wn + 16 * j + (lane & 15);
+                if (m < M && n < N) op.store(m, n, acc[i][j][r], blockIdx.z);
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Operand maps.  NHWC activations; conv weights W[co][ky][kx][ci] (row co of
+// length 9*Cin); fully connected W[out][in].
+// ---------------------------------------------------------------------------
+struct ConvShape {
+    int B, H, W, Cin, Ho, Wo, Cout, stride;
+};
+
+// forward: out[b,y,x,co] = relu(sum in[b, s y + ky - 1, s x + kx - 1, ci] W[co,ky,kx,ci] + bias)
+struct OpConvFwd {
+    ConvShape s;
+    const __bf16* in;
+    const __bf16* w;
+    const float* bias;
+    __bf16* out;
+    __device__ bf16x8 loadA(int m, int k, int kend) const {
+        const int hw = s.Ho * s.Wo;
+        const int b = m / hw, r = m - b * hw, y = r / s.Wo, x = r - y * s.Wo;
+        bf16x8 v = zero8();
+        if (s.Cin % 8 == 0) {
+            if (k >= kend) return v;
+            const int tap = k / s.Cin, ci = k - tap * s.Cin;
+            const int iy = y * s.stride + tap / 3 - 1, ix = x * s.stride + tap % 3 - 1;
+            if (iy < 0 || iy >= s.H || ix < 0 || ix >= s.W) return v;
+            return *reinterpret_cast<const bf16x8*>(in + ((size_t)(b * s.H + iy) * s.W + ix) * s.Cin + ci);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = k + q;
+            if (kk >= kend) break;
+            const int tap = kk / s.Cin, ci = kk - tap * s.Cin;
+            const int iy = y * s.stride + tap / 3 - 1, ix = x * s.stride + tap % 3 - 1;
+            if (iy >= 0 && iy < s.H && ix >= 0 && ix < s.W)
+                v[q] = in[((size_t)(b * s.H + iy) * s.W + ix) * s.Cin + ci];
+        }
+        return v;
+    }
+    __device__ bf16x8 loadB(int k, int n, int kend) const {
+        const int KK = 9 * s.Cin;
+        bf16x8 v = zero8();
+        if (KK % 8 == 0 && k + 8 <= kend) return *reinterpret_cast<const bf16x8*>(w + (size_t)n * KK + k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = w[(size_t)n * KK + k + q];
+        return v;
+    }
+    __device__ void store(int m, int n, float v, int) const {
+        out[(size_t)m * s.Cout + n] = to_bf16(fmaxf(v + bias[n], 0.0f));
+    }
+};
+
+// data gradient: dX[b,iy,ix,ci] = sum dZ[b,y,x,co] W[co,ky,kx,ci] over iy = s y + ky - 1,
+// then multiplied by the ReLU mask of the layer input (prev > 0) -> dZ of the previous layer
+struct OpConvDgrad {
+    ConvShape s;
+    const __bf16* dz;     // [B][Ho][Wo][Cout]
+    const __bf16* w;
+    const __bf16* prev;   // layer input (the previous layer's ReLU output)
+    __bf16* dprev;        // [B][H][W][Cin]
+    __device__ bf16x8 loadA(int m, int k, int kend) const {
+        const int hw = s.H * s.W;
+        const int b = m / hw, r = m - b * hw, iy = r / s.W, ix = r - iy * s.W;
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = k + q;
+            if (kk >= kend) break;
+            const int tap = kk / s.Cout, co = kk - tap * s.Cout;
+            const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
+            if (ty < 0 || tx < 0 || ty % s.stride || tx % s.stride) continue;
+            const int y = ty / s.stride, x = tx / s.stride;
+            if (y < s.Ho && x < s.Wo) v[q] = dz[((size_t)(b * s.Ho + y) * s.Wo + x) * s.Cout + co];
+        }
+        return v;
+    }
+    __device__ bf16x8 loadB(int k, int n, int kend) const {
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = k + q;
+            if (kk >= kend) break;
+            const int tap = kk / s.Cout, co = kk - tap * s.Cout;
+            v[q] = w[(size_t)co * 9 * s.Cin + tap * s.Cin + n];
+        }
+        return v;
+    }
+    __device__ void store(int m, int n, float v, int) const {
+        const size_t q = (size_t)m * s.Cin + n;
+        dprev[q] = to_bf16(from_bf16(prev[q]) > 0.0f ? v : 0.0f);
+    }
+};
+
+// weight gradient (split over K = B*Ho*Wo): dW[co][tap*Cin+ci] partial per split
+struct OpConvWgrad {
+    ConvShape s;
+    const __bf16* dz;   // [B*Ho*Wo][Cout]
+    const __bf16* in;   // layer input [B][H][W][Cin]
+    float* part;        // [splits][Cout][9*Cin]
+    __device__ bf16x8 loadA(int m, int k, int kend) const {
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = dz[(size_t)(k + q) * s.Cout + m];
+        return v;
+    }
+    __device__ bf16x8 loadB(int k, int n, int kend) const {
+        const int tap = n / s.Cin, ci = n - tap * s.Cin, ky = tap / 3, kx = tap % 3;
+        const int hw = s.Ho * s.Wo;
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = k + q;
+            if (kk >= kend) break;
+            const int b = kk / hw, r = kk - b * hw, y = r / s.Wo, x = r - y * s.Wo;
+            const int iy = y * s.stride + ky - 1, ix = x * s.stride + kx - 1;
+            if (iy >= 0 && iy < s.H && ix >= 0 && ix < s.W)
+                v[q] = in[((size_t)(b * s.H + iy) * s.W + ix) * s.Cin + ci];
+        }
+        return v;
+    }
+    __device__ void store(int m, int n, float v, int split) const {
+        part[((size_t)split * s.Cout + m) * 9 * s.Cin + n] = v;
+    }
+};
+
+// fully connected forward: y[b][n] = act(sum_k x[b][k] W[n][k] + bias[n])
+struct OpFcFwd {
+    int In, Out, relu;
+    const __bf16* x;
+    const __bf16* w;
+    const float* bias;
+    __bf16* ybf;     // bf16 output (hidden layer) or null
+    float* yf;       // fp32 output (final layer) or null
+    __device__ bf16x8 loadA(int m, int k, int kend) const {
+        bf16x8 v = zero8();
+        if (In % 8 == 0 && k + 8 <= kend) return *reinterpret_cast<const bf16x8*>(x + (size_t)m * In + k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = x[(size_t)m * In + k + q];
+        return v;
+    }
+    __device__ bf16x8 loadB(int k, int n, int kend) const {
+        bf16x8 v = zero8();
+        if (In % 8 == 0 && k + 8 <= kend) return *reinterpret_cast<const bf16x8*>(w + (size_t)n * In + k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = w[(size_t)n * In + k + q];
+        return v;
+    }
+    __device__ void store(int m, int n, float v, int) const {
+        float y = v + bias[n];
+        if (relu) y = fmaxf(y, 0.0f);
+        if (ybf) ybf[(size_t)m * Out + n] = to_bf16(y);
+        if (yf) yf[(size_t)m * Out + n] = y;
+    }
+};
+
+// fully connected data gradient: dx[b][k] = sum_n dy[b][n] W[n][k], masked by x > 0
+// (mask_src null: no mask, output fp32)
+struct OpFcDgrad {
+    int In, Out;
+    const __bf16* dy;     // [B][Out]
+    const __bf16* w;      // [Out][In]
+    const __bf16* mask_src;
+    __bf16* dxbf;
+    float* dxf;
+    __device__ bf16x8 loadA(int m, int k, int kend) const {
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = dy[(size_t)m * Out + k + q];
+        return v;
+    }
+    __device__ bf16x8 loadB(int k, int n, int kend) const {
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = w[(size_t)(k + q) * In + n];
+        return v;
+    }
+    __device__ void store(int m, int n, float v, int) const {
+        const size_t q = (size_t)m * In + n;
+        if (mask_src && !(from_bf16(mask_src[q]) > 0.0f)) v = 0.0f;
+        if (dxbf) dxbf[q] = to_bf16(v);
+        if (dxf) dxf[q] = v;
+    }
+};
+
+// fully connected weight gradient: dW[n][k] = sum_b dy[b][n] x[b][k]
+struct OpFcWgrad {
+    int In, Out;
+    const __bf16* dy;   // [B][Out]
+    const __bf16* x;    // [B][In]
+    float* dw;          // [Out][In]
+    __device__ bf16x8 loadA(int m, int k, int kend) const {
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = dy[(size_t)(k + q) * Out + m];
+        return v;
+    }
+    __device__ bf16x8 loadB(int k, int n, int kend) const {
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k + q < kend) v[q] = x[(size_t)(k + q) * In + n];
+        return v;
+    }
+    __device__ void store(int m, int n, float v, int) const { dw[(size_t)m * In + n] = v; }
+};
+
+template <class Op>
+static hipError_t gemm(const Op& op, int M, int N, int K, int splits, hipStream_t st) {
+    const int kps = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+    const int nz = (K + kps - 1) / kps;
+    hipLaunchKernelGGL(k_gemm<Op>, dim3((M + GT - 1) / GT, (N + GT - 1) / GT, nz), dim3(256), 0, st, op,
+                       M, N, K, kps);
+    return hipGetLastError();
+}
+
+static int gemm_splits(int M, int N, int K, int splits) {
+    const int kps = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+    return (K + kps - 1) / kps;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise / reduction kernels
+// ---------------------------------------------------------------------------
+// sum of split-K partials in fixed order: out[i] = sum_z part[z][i]
+__global__ void k_sum_splits(int nz, long long n, const float* __restrict__ part, float* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[(size_t)z * n + i];
+    out[i] = (float)s;
+}
+
+// column sums of a bf16 matrix [rows][cols] (bias gradients), fixed order:
+// stage 1 partial[chunk][col], stage 2 sums the chunks.
+__global__ void k_colsum_partial(int rows, int cols, int rows_per_chunk, const __bf16* __restrict__ x,
+                                 double* __restrict__ part) {
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int sub = threadIdx.x >> 6;   // 0..3
+    const int r0 = blockIdx.y * rows_per_chunk, r1 = min(rows, r0 + rows_per_chunk);
+    __shared__ double red[4][64];
+    double s = 0.0;
+    if (col < cols)
+        for (int r = r0 + sub; r < r1; r += 4) s += (double)from_bf16(x[(size_t)r * cols + col]);
+    red[sub][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (sub == 0 && col < cols)
+        part[(size_t)blockIdx.y * cols + col] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void k_colsum_final(int chunks, int cols, const double* __restrict__ part, float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    double s = 0.0;
+    for (int z = 0; z < chunks; ++z) s += part[(size_t)z * cols + c];
+    out[c] = (float)s;
+}
+
+// global average pool over HxW of a [B][H][W][C] bf16 tensor -> bf16 [B][C]
+__global__ void k_pool_fwd(int B, int HW, int C, const __bf16* __restrict__ x, __bf16* __restrict__ y) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= B * C) return;
+    const int b = q / C, c = q - b * C;
+    float s = 0.0f;
+    for (int p = 0; p < HW; ++p) s += from_bf16(x[((size_t)b * HW + p) * C + c]);
+    y[q] = to_bf16(s / (float)HW);
+}
+
+// pooling backward with the ReLU mask of the pooled activation: dz = dy/HW * (x > 0)
+__global__ void k_pool_bwd(int B, int HW, int C, const float* __restrict__ dy, const __bf16* __restrict__ x,
+                           __bf16* __restrict__ dz) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)B * HW * C) return;
+    const int c = (int)(q % C);
+    const int b = (int)(q / ((long long)HW * C));
+    const float g = dy[(size_t)b * C + c] / (float)HW;
+    dz[q] = to_bf16(from_bf16(x[q]) > 0.0f ? g : 0.0f);
+}
+
+// Gaussian negative log-likelihood per sample, mean over the batch:
+//   L = 1/B sum_b sum_j [ (z - mu)^2 exp(-s) / 2 + s / 2 ],  out = [mu(NT), s(NT)]
+// d out written as bf16 (input of the last layer's backward GEMMs).
+__global__ void k_nll(int B, const float* __restrict__ out, const float* __restrict__ target,
+                      __bf16* __restrict__ dout, double* __restrict__ loss_part) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    if (b < B) {
+        for (int j = 0; j < CNN_NT; ++j) {
+            const float mu = out[(size_t)b * CNN_OUT + j], s = out[(size_t)b * CNN_OUT + CNN_NT + j];
+            const float z = target[(size_t)b * CNN_NT + j];
+            const float e = expf(-s), r = z - mu;
+            l += 0.5 * (double)(r * r * e) + 0.5 * (double)s;
+            dout[(size_t)b * CNN_OUT + j] = to_bf16(-r * e / (float)B);
+            dout[(size_t)b * CNN_OUT + CNN_NT + j] = to_bf16(0.5f * (1.0f - r * r * e) / (float)B);
+        }
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(int nb, int B, const double* __restrict__ part, float* __restrict__ loss) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    *loss = (float)(s / B);
+}
+
+// Adam on the fp32 master parameters; refreshes the bf16 copies of weights.
+__global__ void k_cnn_adam(long long n, float* __restrict__ p, const float* __restrict__ g,
+                           float* __restrict__ m, float* __restrict__ v, __bf16* __restrict__ pbf,
+                           float lr, float b1, float b2, float eps, int step) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - powf(b1, (float)step));
+    const float vh = vi / (1.0f - powf(b2, (float)step));
+    const float pi = p[i] - lr * mh / (sqrtf(vh) + eps);
+    p[i] = pi;
+    pbf[i] = to_bf16(pi);
+}
+
+__global__ void k_to_bf16(long long n, const float* __restrict__ x, __bf16* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = to_bf16(x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al. 2011) for initial weights, noise and proposals
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox_c(uint4 c, uint2 k) {
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k.x += W0; k.y += W1; }
+        const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+        const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ double unif(uint32_t w) { return ((double)(w >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+// standard normal from counter (a, b, c): Box-Muller on words 0, 1
+__device__ __forceinline__ double normal_at(uint64_t seed, uint32_t a, uint32_t b, uint32_t c) {
+    const uint4 w = philox_c(make_uint4(a, b, c, 0x5eedu), make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+    return sqrt(-2.0 * log(unif(w.x))) * cos(6.283185307179586476925 * unif(w.y));
+}
+
+// He-normal initialisation of the weights of one tensor (fan_in), zero biases
+__global__ void k_init_normal(long long n, float scale, uint64_t seed, uint32_t tensor, float* __restrict__ p) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    p[i] = (float)(scale * normal_at(seed, (uint32_t)i, tensor, 1u));
+}
+
+// Noise, asinh(x / (3 sigma)) transform and bf16 rounding of simulated images
+__global__ void k_prepare(long long n, const float* __restrict__ img, float sigma, int add_noise, uint64_t seed,
+                          uint64_t counter0, __bf16* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = img[i];
+    if (add_noise) {
+        const uint64_t c = counter0 + (uint64_t)i;
+        x += sigma * normal_at(seed, (uint32_t)c, (uint32_t)(c >> 32), 2u);
+    }
+    out[i] = to_bf16((float)asinh(x / (3.0 * sigma)));
+}
+
+// ---------------------------------------------------------------------------
+// Proposals: CNN Gaussian for the mapped parameters, prior draws for the rest
+// ---------------------------------------------------------------------------
+__device__ double ndtri_d(double p) { return 1.4142135623730951 * erfinv(2.0 * p - 1.0); }
+__device__ double ndtr_d(double z) { return 0.5 * erfc(-z * 0.7071067811865476); }
+
+// One thread per proposal (system s0 + s, draw i); counters use the global
+// system index so that chunked calls draw the same numbers.
+__global__ void k_propose(int S, int s0, int n, int d, const float* __restrict__ net_out,
+                          const CnnTargetMap* __restrict__ tm, uint64_t seed, float* __restrict__ theta,
+                          int* __restrict__ flags) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)S * n) return;
+    const int s = (int)(q / n), i = (int)(q - (long long)s * n);
+    const uint32_t sg = (uint32_t)(s0 + s);
+    float* th = theta + (size_t)q * d;
+    int clipped = 0;
+    for (int j = 0; j < d; ++j) {
+        const int kind = tm->prior_kind[j];
+        const double a = tm->prior[j][0], b = tm->prior[j][1], lo = tm->prior[j][2], hi = tm->prior[j][3];
+        const int c = tm->cnn_slot[j];
+        double v;
+        if (c >= 0) {
+            const double mu = net_out[(size_t)s * CNN_OUT + c];
+            const double ls = fmin(fmax((double)net_out[(size_t)s * CNN_OUT + CNN_NT + c], -30.0), 10.0);
+            const double z = normal_at(seed, sg, (uint32_t)i, 16u + (uint32_t)j);
+            v = tm->mean[c] + tm->stdv[c] * (mu + exp(0.5 * ls) * z);
+            double vlo = -INFINITY, vhi = INFINITY;
+            if (kind == LENS_PRIOR_UNIFORM) { vlo = a; vhi = b; }
+            else if (kind == LENS_PRIOR_TRUNCNORMAL) { vlo = lo; vhi = hi; }
+            else if (kind == LENS_PRIOR_LOGNORMAL) { vlo = 0.0; }
+            const double eps = 1e-6 * (vhi - vlo < INFINITY ? (vhi - vlo) : 1.0);
+            if (v <= vlo) { v = vlo + eps; clipped = 1; }
+            if (v >= vhi) { v = vhi - eps; clipped = 1; }
+        } else {
+            const uint4 w = philox_c(make_uint4(sg, (uint32_t)i, 64u + (uint32_t)j, 0x9a1u),
+                                     make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+            const double u = unif(w.x);
+            if (kind == LENS_PRIOR_UNIFORM) v = a + (b - a) * u;
+            else if (kind == LENS_PRIOR_NORMAL) v = a + b * ndtri_d(u);
+            else if (kind == LENS_PRIOR_LOGNORMAL) v = exp(a + b * ndtri_d(u));
+            else {
+                const double pl = ndtr_d((lo - a) / b), ph = ndtr_d((hi - a) / b);
+                v = a + b * ndtri_d(pl + u * (ph - pl));
+            }
+        }
+        th[j] = (float)v;
+    }
+    if (flags && clipped) atomicOr(flags + s, 1);
+}
+
+__global__ void k_zero_int(int n, int* __restrict__ x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Network: forward / backward / step
+// ---------------------------------------------------------------------------
+static inline dim3 g1(long long n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st) {
+    const __bf16* x = img;
+    int H = CNN_IN;
+    for (int l = 0; l < CNN_CONV; ++l) {
+        const CnnLayer& L = net.conv[l];
+        ConvShape s{B, H, H, L.cin, H / L.stride, H / L.stride, L.cout, L.stride};
+        OpConvFwd op{s, x, net.wbf + L.w_off, net.params + L.b_off, net.act[l]};
+        if (gemm(op, B * s.Ho * s.Wo, L.cout, 9 * L.cin, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+        x = net.act[l];
+        H = s.Ho;
+    }
+    hipLaunchKernelGGL(k_pool_fwd, g1((long long)B * CNN_C6), dim3(256), 0, st, B, H * H, CNN_C6, x, net.pooled);
+    OpFcFwd f1{CNN_C6, CNN_H1, 1, net.pooled, net.wbf + net.fc1.w_off, net.params + net.fc1.b_off, net.hidden, nullptr};
+    if (gemm(f1, B, CNN_H1, CNN_C6, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+    OpFcFwd f2{CNN_H1, CNN_OUT, 0, net.hidden, net.wbf + net.fc2.w_off, net.params + net.fc2.b_off, nullptr, net.out};
+    if (gemm(f2, B, CNN_OUT, CNN_H1, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+    return hipGetLastError();
+}
+
+// bias gradient = column sums of dz [rows][cols]
+static hipError_t bias_grad(CnnNet& net, int rows, int cols, const __bf16* dz, float* db, hipStream_t st) {
+    const int rpc = 4096;
+    const int chunks = (rows + rpc - 1) / rpc;
+    hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 63) / 64, chunks), dim3(256), 0, st, rows, cols, rpc, dz,
+                       net.colpart);
+    hipLaunchKernelGGL(k_colsum_final, g1(cols, 128), dim3(128), 0, st, chunks, cols, net.colpart, db);
+    return hipGetLastError();
+}
+
+hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* target, float* loss, hipStream_t st) {
+    const int nb = (B + 255) / 256;
+    hipLaunchKernelGGL(k_nll, dim3(nb), dim3(256), 0, st, B, net.out, target, net.dout, net.losspart);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, st, nb, B, net.losspart, loss);
+    // fc2: dW, db, dhidden (masked by hidden > 0)
+    OpFcWgrad w2{CNN_H1, CNN_OUT, net.dout, net.hidden, net.grads + net.fc2.w_off};
+    if (gemm(w2, CNN_OUT, CNN_H1, B, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+    if (bias_grad(net, B, CNN_OUT, net.dout, net.grads + net.fc2.b_off, st) != hipSuccess) return hipErrorLaunchFailure;
+    OpFcDgrad d2{CNN_H1, CNN_OUT, net.dout, net.wbf + net.fc2.w_off, net.hidden, net.dhidden, nullptr};
+    if (gemm(d2, B, CNN_H1, CNN_OUT, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+    // fc1: dW, db, dpooled (fp32, pooled mask applied by the pooling backward)
+    OpFcWgrad w1{CNN_C6, CNN_H1, net.dhidden, net.pooled, net.grads + net.fc1.w_off};
+    if (gemm(w1, CNN_H1, CNN_C6, B, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+    if (bias_grad(net, B, CNN_H1, net.dhidden, net.grads + net.fc1.b_off, st) != hipSuccess) return hipErrorLaunchFailure;
+    OpFcDgrad d1{CNN_C6, CNN_H1, net.dhidden, net.wbf + net.fc1.w_off, nullptr, nullptr, net.dpooled};
+    if (gemm(d1, B, CNN_C6, CNN_H1, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+    // pooling backward into dz of the last conv layer
+    const int H6 = CNN_IN / 8;
+    hipLaunchKernelGGL(k_pool_bwd, g1((long long)B * H6 * H6 * CNN_C6), dim3(256), 0, st, B, H6 * H6, CNN_C6,
+                       net.dpooled, net.act[CNN_CONV - 1], net.dact[CNN_CONV - 1]);
+    int Hout = H6;
+    for (int l = CNN_CONV - 1; l >= 0; --l) {
+        const CnnLayer& L = net.conv[l];
+        const int H = Hout * L.stride;
+        ConvShape s{B, H, H, L.cin, Hout, Hout, L.cout, L.stride};
+        const __bf16* in = l == 0 ? img : net.act[l - 1];
+        const int K = B * Hout * Hout;
+        const int splits = gemm_splits(L.cout, 9 * L.cin, K, 32);
+        OpConvWgrad wg{s, net.dact[l], in, net.wpart};
+        if (gemm(wg, L.cout, 9 * L.cin, K, 32, st) != hipSuccess) return hipErrorLaunchFailure;
+        const long long nw = (long long)L.cout * 9 * L.cin;
+        hipLaunchKernelGGL(k_sum_splits, g1(nw), dim3(256), 0, st, splits, nw, net.wpart, net.grads + L.w_off);
+        if (bias_grad(net, K, L.cout, net.dact[l], net.grads + L.b_off, st) != hipSuccess) return hipErrorLaunchFailure;
+        if (l > 0) {
+            OpConvDgrad dg{s, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};
+            if (gemm(dg, B * H * H, L.cin, 9 * L.cout, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+        }
+        Hout = H;
+    }
+    return hipGetLastError();
+}
+
+hipError_t cnn_adam(CnnNet& net, float lr, int step, hipStream_t st) {
+    hipLaunchKernelGGL(k_cnn_adam, g1(net.nparams), dim3(256), 0, st, (long long)net.nparams, net.params, net.grads,
+                       net.adam_m, net.adam_v, net.wbf, lr, 0.9f, 0.999f, 1e-8f, step);
+    return hipGetLastError();
+}
+
+hipError_t cnn_init(CnnNet& net, uint64_t seed, hipStream_t st) {
+    auto he = [&](long long off, long long n, int fan_in, uint32_t tensor) {
+        hipLaunchKernelGGL(k_init_normal, g1(n), dim3(256), 0, st, n, (float)sqrt(2.0 / fan_in), seed, tensor,
+                           net.params + off);
+    };
+    uint32_t tensor = 0;
+    for (int l = 0; l < CNN_CONV; ++l) he(net.conv[l].w_off, (long long)net.conv[l].cout * 9 * net.conv[l].cin,
+                                          9 * net.conv[l].cin, tensor++);
+    he(net.fc1.w_off, (long long)CNN_H1 * CNN_C6, CNN_C6, tensor++);
+    // small output layer: predictions start near the standardised prior mean
+    hipLaunchKernelGGL(k_init_normal, g1((long long)CNN_OUT * CNN_H1), dim3(256), 0, st, (long long)CNN_OUT * CNN_H1,
+                       (float)(0.1 * sqrt(1.0 / CNN_H1)), seed, tensor++, net.params + net.fc2.w_off);
+    hipLaunchKernelGGL(k_to_bf16, g1(net.nparams), dim3(256), 0, st, (long long)net.nparams, net.params, net.wbf);
+    return hipGetLastError();
+}
+
+hipError_t cnn_params_to_bf16(CnnNet& net, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_bf16, g1(net.nparams), dim3(256), 0, st, (long long)net.nparams, net.params, net.wbf);
+    return hipGetLastError();
+}
+
+hipError_t cnn_prepare(long long n, const float* img, float sigma, int add_noise, uint64_t seed, uint64_t counter0,
+                       __bf16* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_prepare, g1(n), dim3(256), 0, st, n, img, sigma, add_noise, seed, counter0, out);
+    return hipGetLastError();
+}
+
+hipError_t cnn_propose(int S, int s0, int n, int d, const float* net_out, const CnnTargetMap* tm, uint64_t seed,
+                       float* theta, int* flags, hipStream_t st) {
+    if (flags) hipLaunchKernelGGL(k_zero_int, g1(S), dim3(256), 0, st, S, flags);
+    hipLaunchKernelGGL(k_propose, g1((long long)S * n, 64), dim3(64), 0, st, S, s0, n, d, net_out, tm, seed, theta,
+                       flags);
+    return hipGetLastError();
+}
+
+}  // namespace lens

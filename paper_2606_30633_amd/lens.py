@@ -62,6 +62,17 @@ _SIGNATURES = {
     "lens_batch_get_tiles": (_I, [_P, _P]),
     "lens_batch_set_tiles": (_I, [_P, _P]),
     "lens_batch_autotune": (_I, [_P, _P, ctypes.c_char_p, _P]),
+    "lens_cnn_create": (_I, [_I, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "lens_cnn_destroy": (_I, [_P]),
+    "lens_cnn_num_params": (ctypes.c_int64, []),
+    "lens_cnn_get_params": (_I, [_P, _P, _P]),
+    "lens_cnn_set_params": (_I, [_P, _P, _P]),
+    "lens_cnn_prepare_images": (_I, [_I, _P, ctypes.c_float, _I, ctypes.c_uint64, ctypes.c_uint64, _P, _P]),
+    "lens_cnn_forward": (_I, [_P, _I, _P, _P, _P]),
+    "lens_cnn_loss_grad": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "lens_cnn_train_step": (_I, [_P, _I, _P, _P, ctypes.c_float, _P, _P]),
+    "lens_cnn_set_target_map": (_I, [_P, _I, _P, _P, _P, _P, ctypes.c_float]),
+    "init_propose": (_I, [_P, _I, _P, _I, ctypes.c_uint64, _P, _P, _P]),
     "lens_plan_enable_timing": (_I, [_P, _I]),
     "lens_plan_read_timing": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -364,3 +375,106 @@ class BatchPlan:
         _check(_lib.lens_batch_autotune(self.handle, theta.data_ptr(), path, _stream(stream)),
                "lens_batch_autotune")
         return self.get_tiles()
+
+
+CNN_SIDE, CNN_TARGETS, CNN_OUTPUTS = 64, 14, 28
+
+
+class Cnn:
+    """The learned initializer's network (lens_cnn_*)."""
+
+    def __init__(self, max_batch: int, seed: int = 0, device="cuda"):
+        load_library()
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.max_batch = int(max_batch)
+        handle = ctypes.c_void_p()
+        _check(_lib.lens_cnn_create(self.max_batch, int(seed), ctypes.byref(handle)), "lens_cnn_create")
+        self.handle = handle
+        self.n_params = int(_lib.lens_cnn_num_params())
+        self.d = None
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lens_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(_lib.lens_cnn_get_params(self.handle, out.data_ptr(), _stream(None)), "lens_cnn_get_params")
+        return out
+
+    def set_params(self, p: torch.Tensor):
+        p = p.to(self.device, torch.float32).contiguous()
+        if p.numel() != self.n_params:
+            raise ValueError("wrong parameter count")
+        _check(_lib.lens_cnn_set_params(self.handle, p.data_ptr(), _stream(None)), "lens_cnn_set_params")
+
+    def prepare(self, images: torch.Tensor, sigma: float, add_noise: bool = False, seed: int = 0,
+                counter0: int = 0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """float [n, 64, 64] -> bf16 [n, 64, 64] network input (noise, asinh, rounding in a kernel)."""
+        x = images.to(self.device, torch.float32).contiguous()
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((n, CNN_SIDE, CNN_SIDE), dtype=torch.bfloat16, device=self.device)
+        _check(_lib.lens_cnn_prepare_images(n, x.data_ptr(), float(sigma), 1 if add_noise else 0, int(seed),
+                                            int(counter0), out.data_ptr(), _stream(None)), "lens_cnn_prepare_images")
+        return out
+
+    def forward(self, img: torch.Tensor) -> torch.Tensor:
+        B = img.shape[0]
+        if img.dtype != torch.bfloat16 or not img.is_contiguous():
+            raise ValueError("img must be contiguous bfloat16 [B, 64, 64]")
+        out = torch.empty((B, CNN_OUTPUTS), dtype=torch.float32, device=self.device)
+        _check(_lib.lens_cnn_forward(self.handle, B, img.data_ptr(), out.data_ptr(), _stream(None)), "lens_cnn_forward")
+        return out
+
+    def loss_grad(self, img: torch.Tensor, target: torch.Tensor):
+        B = img.shape[0]
+        t = target.to(self.device, torch.float32).contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grads = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(_lib.lens_cnn_loss_grad(self.handle, B, img.data_ptr(), t.data_ptr(), loss.data_ptr(), grads.data_ptr(),
+                                       _stream(None)), "lens_cnn_loss_grad")
+        return loss, grads
+
+    def train_step(self, img: torch.Tensor, target: torch.Tensor, lr: float, loss: Optional[torch.Tensor] = None):
+        B = img.shape[0]
+        t = target if (target.dtype == torch.float32 and target.is_contiguous()) else target.float().contiguous()
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(_lib.lens_cnn_train_step(self.handle, B, img.data_ptr(), t.data_ptr(), float(lr), loss.data_ptr(),
+                                        _stream(None)), "lens_cnn_train_step")
+        return loss
+
+    def set_target_map(self, prior_table, slot, mean, std, sigma: float):
+        import numpy as np
+        tab = np.ascontiguousarray(np.asarray(prior_table, dtype=np.float32))
+        sl = np.ascontiguousarray(np.asarray(slot, dtype=np.int32))
+        mu = np.ascontiguousarray(np.asarray(mean, dtype=np.float32))
+        sd = np.ascontiguousarray(np.asarray(std, dtype=np.float32))
+        d = tab.shape[0]
+        _check(_lib.lens_cnn_set_target_map(self.handle, d, tab.ctypes.data_as(ctypes.c_void_p),
+                                            sl.ctypes.data_as(ctypes.c_void_p), mu.ctypes.data_as(ctypes.c_void_p),
+                                            sd.ctypes.data_as(ctypes.c_void_p), float(sigma)),
+               "lens_cnn_set_target_map")
+        self.d = d
+
+
+def init_propose(net: Cnn, images64: torch.Tensor, n_per_system: int, seed: int, want_flags: bool = True):
+    """Starting particles [S, n, d] (and clip flags [S]) from the network's proposals."""
+    x = images64.to(net.device, torch.float32).contiguous()
+    S = x.shape[0]
+    theta = torch.empty((S, n_per_system, net.d), dtype=torch.float32, device=net.device)
+    flags = torch.empty(S, dtype=torch.int32, device=net.device) if want_flags else None
+    _check(_lib.init_propose(net.handle, S, x.data_ptr(), int(n_per_system), int(seed), theta.data_ptr(),
+                             _ptr(flags), _stream(None)), "init_propose")
+    return theta, flags

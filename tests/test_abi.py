@@ -53,3 +53,10 @@ def test_invalid_descriptors_rejected(bad):
     import dataclasses
     spec = dataclasses.replace(synth.config1_spec(), **bad)
     assert lens.lens_num_params(spec) == -1
+
+
+def test_cnn_parameter_count_matches_oracle_layout():
+    from oracle import cnn_oracle
+    lib = lens.load_library()
+    lib.lens_cnn_num_params.restype = ctypes.c_int64
+    assert lib.lens_cnn_num_params() == cnn_oracle.n_params()

@@ -1,0 +1,176 @@
+"""GPU: the learned initializer's BF16-MFMA network against the float64
+oracle (on bf16-rounded operands), training, and proposals."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+from oracle import cnn_oracle as C
+import cnn_cases
+from paper_2606_30633_amd import synth
+
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2606_30633_amd import lens  # noqa: E402
+
+DEV = "cuda"
+
+
+def test_exact_arithmetic_forward_and_gradients_match_oracle():
+    """Quarter-integer images and sparse +-1 weights: every sum is exact in
+    fp32 (bound checked in the oracle tests), so the network output agrees
+    bit for bit and the gradients to fp32 rounding of the final sums."""
+    p, img, tgt = cnn_cases.exact_case()
+    B = img.shape[0]
+    net = lens.Cnn(B, 0, DEV)
+    net.set_params(torch.tensor(p, dtype=torch.float32))
+    x = torch.tensor(img, dtype=torch.bfloat16, device=DEV)
+    out = net.forward(x).cpu().numpy()
+    L, g, out_ref = C.loss_and_grad(p, img, tgt)
+    np.testing.assert_array_equal(out, out_ref.astype(np.float32))
+    loss, grads = net.loss_grad(x, torch.tensor(tgt, dtype=torch.float32))
+    assert abs(loss.item() - L) <= 1e-6 * abs(L)
+    grads = grads.cpu().numpy()
+    o = 0
+    for name, shape in C.layout():
+        n = int(np.prod(shape))
+        a, r = grads[o:o + n], g[o:o + n]
+        o += n
+        err = np.abs(a - r).max()
+        assert err <= 1e-6 * max(1.0, np.abs(r).max()), (name, err, np.abs(r).max())
+
+
+def test_random_network_close_to_oracle():
+    B = 16
+    rng = np.random.default_rng(21)
+    net = lens.Cnn(B, 5, DEV)
+    p = net.get_params().cpu().numpy().astype(np.float64)
+    img = C.bf16(torch.tensor(rng.normal(size=(B, 64, 64)))).numpy()
+    tgt = rng.normal(size=(B, C.NT))
+    x = torch.tensor(img, dtype=torch.bfloat16, device=DEV)
+    out = net.forward(x).cpu().numpy()
+    L, g, out_ref = C.loss_and_grad(p, img, tgt)
+    scale = np.abs(out_ref).max()
+    assert np.abs(out - out_ref).max() <= 5e-3 * scale
+    loss, grads = net.loss_grad(x, torch.tensor(tgt, dtype=torch.float32))
+    assert abs(loss.item() - L) <= 5e-3 * abs(L)
+    grads = grads.cpu().numpy()
+    o = 0
+    for name, shape in C.layout():
+        n = int(np.prod(shape))
+        a, r = grads[o:o + n].astype(np.float64), g[o:o + n]
+        o += n
+        cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r) + 1e-300))
+        assert cos > 0.999, (name, cos)
+
+
+def test_prepare_transform_matches_oracle():
+    rng = np.random.default_rng(3)
+    img = rng.normal(scale=0.3, size=(4, 64, 64)).astype(np.float32)
+    net = lens.Cnn(4, 0, DEV)
+    x = net.prepare(torch.tensor(img), 0.01).float().cpu().numpy()
+    ref = C.asinh_transform(img, 0.01)
+    assert np.abs(x - ref).max() <= 2 ** -7 * np.abs(ref).max()
+    ulp = np.abs(x - ref) / np.maximum(np.abs(ref), 1e-30)
+    assert np.mean(ulp > 2 ** -9) < 1e-3
+
+
+def test_training_reduces_loss():
+    """Targets are translation-invariant image statistics (offset and noise
+    scale), which the pooled network can learn: the loss must fall well
+    below its starting value within 300 Adam steps."""
+    B, N = 64, 512
+    rng = np.random.default_rng(4)
+    m = rng.uniform(-1, 1, N)
+    c = rng.uniform(0.5, 2, N)
+    img = m[:, None, None] + c[:, None, None] * rng.normal(size=(N, 64, 64))
+    tgt = np.stack([2 * m if k % 2 == 0 else 2 * (c - 1.25) for k in range(C.NT)], axis=1)
+    x = torch.tensor(img, dtype=torch.bfloat16, device=DEV)
+    t = torch.tensor(tgt, dtype=torch.float32, device=DEV)
+    net = lens.Cnn(B, 1, DEV)
+    first = net.loss_grad(x[:B], t[:B])[0].item()
+    for it in range(300):
+        i = (it * B) % N
+        loss = net.train_step(x[i:i + B], t[i:i + B], 1e-3)
+        assert math.isfinite(loss.item())
+    last = np.mean([net.loss_grad(x[i:i + B], t[i:i + B])[0].item() for i in range(0, N, B)])
+    assert last < first - 4.0, (first, last)
+
+
+def _center_scale(row):
+    kind, a, b, lo, hi = (float(v) for v in row)
+    if kind == synth.PRIOR_UNIFORM:
+        return (a + b) / 2, (b - a) / 6, a, b
+    if kind == synth.PRIOR_NORMAL:
+        return a, b, -np.inf, np.inf
+    if kind == synth.PRIOR_LOGNORMAL:
+        return math.exp(a), math.exp(a) * b, 0.0, np.inf
+    return a, b, lo, hi
+
+
+def _fixed_output_net(table, mean, std, n=4):
+    """Network whose output is mu = 0.5, log variance = log 0.25 for every image."""
+    net = lens.Cnn(n, 0, DEV)
+    p = np.zeros(C.n_params(), np.float32)
+    p[-C.OUT:-C.NT] = 0.5
+    p[-C.NT:] = math.log(0.25)
+    net.set_params(torch.tensor(p))
+    slot = np.full(table.shape[0], -1, np.int32)
+    slot[:C.NT] = np.arange(C.NT)
+    net.set_target_map(table, slot, mean, std, 0.01)
+    return net
+
+
+def test_init_propose_distribution():
+    table = synth.prior_table(synth.paper_prior_dists())
+    d = table.shape[0]
+    cs = [_center_scale(table[k]) for k in range(C.NT)]
+    mean = np.array([c[0] for c in cs], np.float32)
+    std = np.array([0.1 * c[1] for c in cs], np.float32)
+    net = _fixed_output_net(table, mean, std)
+    imgs = torch.zeros((3, 64, 64), device=DEV)
+    th, flags = lens.init_propose(net, imgs, 20000, 77)
+    th2, _ = lens.init_propose(net, imgs, 20000, 77)
+    assert torch.equal(th, th2)
+    assert flags.cpu().tolist() == [0, 0, 0]
+    assert not torch.equal(th[0], th[1])
+    th = th.cpu().numpy().astype(np.float64)
+    for k in range(C.NT):
+        v = th[0, :, k]
+        mu, sd = float(mean[k]) + 0.5 * float(std[k]), 0.5 * float(std[k])
+        pv = stats.kstest(v, stats.norm(mu, sd).cdf).pvalue
+        assert pv > 1e-4, (k, pv)
+    # the remaining parameters are draws from their priors
+    for j in range(C.NT, d):
+        kind, a, b, c, e = (float(x) for x in table[j])
+        v = th[1, :, j]
+        if kind == synth.PRIOR_LOGNORMAL:
+            pv = stats.kstest(np.log(v), stats.norm(a, b).cdf).pvalue
+        elif kind == synth.PRIOR_UNIFORM:
+            pv = stats.kstest(v, stats.uniform(a, b - a).cdf).pvalue
+        elif kind == synth.PRIOR_NORMAL:
+            pv = stats.kstest(v, stats.norm(a, b).cdf).pvalue
+        else:
+            pv = stats.kstest(v, stats.truncnorm((c - a) / b, (e - a) / b, loc=a, scale=b).cdf).pvalue
+        assert pv > 1e-4, (j, pv)
+
+
+def test_init_propose_clips_to_support_and_flags():
+    table = synth.prior_table(synth.paper_prior_dists())
+    cs = [_center_scale(table[k]) for k in range(C.NT)]
+    mean = np.array([c[0] for c in cs], np.float32)
+    std = np.array([0.1 * c[1] for c in cs], np.float32)
+    mean[1] = 3.5          # power-law slope: truncated normal on [1, 3]
+    net = _fixed_output_net(table, mean, std)
+    th, flags = lens.init_propose(net, torch.zeros((5, 64, 64), device=DEV), 100, 3)
+    assert flags.cpu().tolist() == [1] * 5
+    g = th[..., 1].cpu().numpy()
+    assert (g > 1.0).all() and (g < 3.0).all()
+    # chunked evaluation (max batch 4 < 5 systems) draws the same numbers as one call
+    net2 = _fixed_output_net(table, mean, std, n=8)
+    th2, _ = lens.init_propose(net2, torch.zeros((5, 64, 64), device=DEV), 100, 3)
+    assert torch.equal(th, th2)
