@@ -153,6 +153,13 @@ lens_status lens_logpost_grad(lens_plan* plan, int32_t P, const float* d_u,
                               int32_t with_jacobian, float* d_theta, double* d_logp,
                               float* d_grad, void* stream);
 
+/* u = T^-1(theta) for starting points given in the constrained space
+ * (d_theta, d_u [P][d]).  Bounded parameters are clamped to the logit of
+ * [2^-24, 1 - 2^-24] of their support; log-normal ones to theta >= 1e-30.
+ * Requires lens_plan_set_prior. */
+lens_status lens_to_unconstrained(lens_plan* plan, int32_t P, const float* d_theta, float* d_u,
+                                  void* stream);
+
 /* Multi-start MAP (Sec. 3, Sec. 3.1: every particle descends independently;
  * Sec. 3.2: Adam for MAP).  Runs n_steps Adam updates (Kingma & Ba 2015,
  * bias-corrected) of loss(u) = -(logL + log prior)(T(u)) on all P particles.
@@ -235,6 +242,38 @@ lens_status lens_batch_set_tiles(lens_batch_plan* plan, const int32_t* h_ppt);
 lens_status lens_batch_autotune(lens_batch_plan* plan, const float* d_theta, const char* cache_path,
                                 void* stream);
 
+/* Inference stage over the whole batch (Sec. 3: multi-start MAP; Sec. 4.2:
+ * many systems modelled together).  One prior, set as for a single plan
+ * (lens_plan_set_prior), serves every system.  Arrays are packed as for
+ * lens_batch_loglike_grad: d_u, d_m, d_v, d_grad, d_theta [N][d];
+ * d_logp [N] float64; d_loss [N].  Semantics per particle are those of
+ * lens_logpost_grad and lens_map_adam; the Adam step counter lives in the
+ * batch plan (lens_batch_map_reset restarts it).  use_graph as for
+ * lens_batch_loglike_grad.  Errors: LENS_EINVAL (NULL pointer, no prior,
+ * invalid hyper-parameter), LENS_EHIP. */
+lens_status lens_batch_set_prior(lens_batch_plan* plan, const float* h_table);
+lens_status lens_batch_logpost_grad(lens_batch_plan* plan, const float* d_u, int32_t with_jacobian,
+                                    float* d_theta, double* d_logp, float* d_grad, void* stream);
+lens_status lens_batch_to_unconstrained(lens_batch_plan* plan, const float* d_theta, float* d_u,
+                                        void* stream);
+lens_status lens_batch_map_reset(lens_batch_plan* plan);
+lens_status lens_batch_map_adam(lens_batch_plan* plan, float* d_u, float* d_m, float* d_v,
+                                int32_t n_steps, float lr, float decay, float beta1, float beta2,
+                                float eps, float* d_loss, int32_t use_graph, void* stream);
+
+/* Best particle of every system (the multi-start MAP estimate is the best
+ * particle, Sec. 3): d_best [S] = min over system k's particles of d_val
+ * [N] (NaN counts as +inf), d_arg [S] = its global row (first on ties). */
+lens_status lens_batch_argmin(lens_batch_plan* plan, const float* d_val, float* d_best,
+                              int32_t* d_arg, void* stream);
+
+/* d_out [S][side][side]: each system's observed image on a centred
+ * side x side grid of the same pixel scale (pixel (i, j) takes source row
+ * i + (ny - side) / 2 and column j + (nx - side) / 2; a half-integer offset
+ * averages the two neighbours; outside the image, zero).  This is the
+ * learned initializer's view of a system (side = 64).  1 <= side <= 256. */
+lens_status lens_batch_center_views(lens_batch_plan* plan, int32_t side, float* d_out, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Learned initializer.  A convolutional network regresses, from a 64x64
  * image of a system, 14 lens parameters and their log-variances; its
@@ -308,6 +347,15 @@ lens_status lens_cnn_set_target_map(lens_cnn* net, int32_t d, const float* h_pri
  * driver).  Requires lens_cnn_set_target_map. */
 lens_status init_propose(lens_cnn* net, int32_t S, const float* d_img64, int32_t n_per_system,
                          uint64_t seed, float* d_theta_out, int32_t* d_flags, void* stream);
+
+/* Plain multi-start starting points: n_per_system draws from the prior for
+ * each of S systems (the prior branch of init_propose: Philox4x32-10 with
+ * the given seed, counter (system, draw, parameter), inverse-CDF draws).
+ * h_prior_table [d][5] as for lens_plan_set_prior; d_theta_out [S][n][d].
+ * Synchronous on stream (a small descriptor is staged through device memory
+ * that is freed before returning). */
+lens_status lens_prior_sample(int32_t d, const float* h_prior_table, int32_t S, int32_t n_per_system,
+                              uint64_t seed, float* d_theta_out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (diagnostics, not part of the model).

@@ -121,7 +121,45 @@ int nparams(const lens_model_desc* d) {
 
 lens_status hip_status(hipError_t e) { return e == hipSuccess ? LENS_OK : LENS_EHIP; }
 
+
 }  // namespace
+
+namespace lens {
+
+bool build_prior_rows(int d, const float* h_table, PriorRow* rows) {
+    const double half_log_2pi = 0.91893853320467274178;
+    for (int j = 0; j < d; ++j) {
+        const float* r = h_table + 5 * j;
+        const int kind = (int)r[0];
+        PriorRow& q = rows[j];
+        q.kind = kind;
+        q.a = r[1];
+        q.b = r[2];
+        q.pad0 = q.pad1 = 0.0;
+        if (kind == LENS_PRIOR_UNIFORM) {
+            if (!(r[2] > r[1])) return false;
+            q.lo = r[1];
+            q.hi = r[2];
+            q.cst = -std::log((double)r[2] - (double)r[1]);
+        } else if (kind == LENS_PRIOR_NORMAL || kind == LENS_PRIOR_LOGNORMAL) {
+            if (!(r[2] > 0.0f)) return false;
+            q.lo = q.hi = 0.0;
+            q.cst = -std::log((double)r[2]) - half_log_2pi;
+        } else if (kind == LENS_PRIOR_TRUNCNORMAL) {
+            if (!(r[2] > 0.0f) || !(r[4] > r[3])) return false;
+            q.lo = r[3];
+            q.hi = r[4];
+            const double zl = ((double)r[3] - r[1]) / r[2], zh = ((double)r[4] - r[1]) / r[2];
+            const double mass = 0.5 * (std::erfc(-zh / std::sqrt(2.0)) - std::erfc(-zl / std::sqrt(2.0)));
+            q.cst = -std::log((double)r[2]) - half_log_2pi - std::log(mass);
+        } else {
+            return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace lens
 
 extern "C" {
 
@@ -323,35 +361,7 @@ lens_status lens_plan_set_prior(lens_plan* plan, const float* h_table) {
     if (!plan || !h_table) return LENS_EINVAL;
     const int d = plan->mi.d;
     std::vector<PriorRow> rows(d);
-    const double half_log_2pi = 0.91893853320467274178;
-    for (int j = 0; j < d; ++j) {
-        const float* r = h_table + 5 * j;
-        const int kind = (int)r[0];
-        PriorRow& q = rows[j];
-        q.kind = kind;
-        q.a = r[1];
-        q.b = r[2];
-        q.pad0 = q.pad1 = 0.0;
-        if (kind == LENS_PRIOR_UNIFORM) {
-            if (!(r[2] > r[1])) return LENS_EINVAL;
-            q.lo = r[1];
-            q.hi = r[2];
-            q.cst = -std::log((double)r[2] - (double)r[1]);
-        } else if (kind == LENS_PRIOR_NORMAL || kind == LENS_PRIOR_LOGNORMAL) {
-            if (!(r[2] > 0.0f)) return LENS_EINVAL;
-            q.lo = q.hi = 0.0;
-            q.cst = -std::log((double)r[2]) - half_log_2pi;
-        } else if (kind == LENS_PRIOR_TRUNCNORMAL) {
-            if (!(r[2] > 0.0f) || !(r[4] > r[3])) return LENS_EINVAL;
-            q.lo = r[3];
-            q.hi = r[4];
-            const double zl = ((double)r[3] - r[1]) / r[2], zh = ((double)r[4] - r[1]) / r[2];
-            const double mass = 0.5 * (std::erfc(-zh / std::sqrt(2.0)) - std::erfc(-zl / std::sqrt(2.0)));
-            q.cst = -std::log((double)r[2]) - half_log_2pi - std::log(mass);
-        } else {
-            return LENS_EINVAL;
-        }
-    }
+    if (!build_prior_rows(d, h_table, rows.data())) return LENS_EINVAL;
     if (!plan->prior && hipMalloc(&plan->prior, sizeof(PriorRow) * d) != hipSuccess)
         return LENS_ENOMEM;
     if (hipMemcpy(plan->prior, rows.data(), sizeof(PriorRow) * d, hipMemcpyHostToDevice) != hipSuccess)
@@ -359,6 +369,12 @@ lens_status lens_plan_set_prior(lens_plan* plan, const float* h_table) {
     plan->map_graph.reset();
     plan->hmc_graph.reset();
     return LENS_OK;
+}
+
+lens_status lens_to_unconstrained(lens_plan* plan, int32_t P, const float* d_theta, float* d_u,
+                                  void* stream) {
+    if (!plan || !d_theta || !d_u || P < 1 || !plan->prior) return LENS_EINVAL;
+    return hip_status(launch_inverse_bijection(P, plan->mi.d, plan->prior, d_theta, d_u, (hipStream_t)stream));
 }
 
 lens_status lens_logpost_grad(lens_plan* plan, int32_t P, const float* d_u, int32_t with_jacobian,

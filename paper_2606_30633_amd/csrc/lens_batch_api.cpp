@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lens_internal.h"
+#include "lens_sampler.h"
 
 using namespace lens;
 
@@ -57,6 +58,19 @@ struct lens_batch_plan {
     hipGraphExec_t graph = nullptr;
     std::vector<uint64_t> graph_key;
     uint64_t tiles_version = 0;
+    // inference stage over all packed particles (one prior for every system)
+    int* d_p0 = nullptr;          // [S + 1] first particle of each system
+    ViewSrc* d_views = nullptr;   // [S]
+    PriorRow* prior = nullptr;    // [d], null until lens_batch_set_prior
+    float* theta = nullptr;       // [N][d] T(u)
+    float* gtheta = nullptr;      // [N][d] dlogL/dtheta
+    float* logl = nullptr;        // [N]
+    double* logl64 = nullptr;     // [N]
+    double* logp = nullptr;       // [N]
+    float* gradu = nullptr;       // [N][d]
+    int* map_step = nullptr;      // Adam steps taken since lens_batch_map_reset
+    hipGraphExec_t map_graph = nullptr;
+    std::vector<uint64_t> map_key;
 };
 
 static void free_classes(lens_batch_plan* b) {
@@ -138,14 +152,14 @@ static lens_status rebuild(lens_batch_plan* b) {
 }
 
 static lens_status enqueue(lens_batch_plan* b, const float* theta, float* logl, float* grad,
-                           hipStream_t st) {
+                           hipStream_t st, double* logl64 = nullptr) {
     if (launch_prologue(b->mi, b->N, theta, b->consts, st) != hipSuccess) return LENS_EHIP;
     if (launch_set_int_host(b->d_counter, 0, st) != hipSuccess) return LENS_EHIP;
     if (launch_batch_render(b->mi, b->grid_render, b->d_sys, b->d_items, b->n_items, b->d_counter,
                             b->consts, b->img, st) != hipSuccess)
         return LENS_EHIP;
     for (const auto& c : b->classes)
-        if (launch_batch_psf(c.K, c.n, b->d_sys, c.items, b->consts, b->img, logl, c.shm, st) !=
+        if (launch_batch_psf(c.K, c.n, b->d_sys, c.items, b->consts, b->img, logl, logl64, c.shm, st) !=
             hipSuccess)
             return LENS_EHIP;
     if (launch_set_int_host(b->d_counter + 1, 0, st) != hipSuccess) return LENS_EHIP;
@@ -163,10 +177,13 @@ extern "C" {
 lens_status lens_batch_plan_destroy(lens_batch_plan* b) {
     if (!b) return LENS_EINVAL;
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->map_graph) (void)hipGraphExecDestroy(b->map_graph);
     free_classes(b);
     for (double* w : b->wflip)
         if (w) (void)hipFree(w);
-    void* bufs[] = {b->consts, b->img, b->partial, b->d_sys, b->d_items, b->d_counter, b->d_particle_sys};
+    void* bufs[] = {b->consts, b->img,    b->partial, b->d_sys,  b->d_items, b->d_counter, b->d_particle_sys,
+                    b->d_p0,   b->d_views, b->prior,  b->theta,  b->gtheta,  b->logl,      b->logl64,
+                    b->logp,   b->gradu,  b->map_step};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -227,7 +244,16 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
               hipMalloc(&b->partial, sizeof(double) * (size_t)rows_max * nacc) == hipSuccess &&
               hipMalloc(&b->d_sys, sizeof(BatchSys) * S) == hipSuccess &&
               hipMalloc(&b->d_counter, sizeof(int) * 4) == hipSuccess &&
-              hipMalloc(&b->d_particle_sys, sizeof(int) * (size_t)N) == hipSuccess;
+              hipMalloc(&b->d_particle_sys, sizeof(int) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->d_p0, sizeof(int) * (size_t)(S + 1)) == hipSuccess &&
+              hipMalloc(&b->d_views, sizeof(ViewSrc) * (size_t)S) == hipSuccess &&
+              hipMalloc(&b->theta, sizeof(float) * (size_t)N * b->mi.d) == hipSuccess &&
+              hipMalloc(&b->gtheta, sizeof(float) * (size_t)N * b->mi.d) == hipSuccess &&
+              hipMalloc(&b->gradu, sizeof(float) * (size_t)N * b->mi.d) == hipSuccess &&
+              hipMalloc(&b->logl, sizeof(float) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->logl64, sizeof(double) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->logp, sizeof(double) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->map_step, sizeof(int)) == hipSuccess;
     for (int k = 0; ok && k < S; ++k)
         ok = hipMalloc(&b->wflip[k], sizeof(double) * h_descs[k].psf_size * h_descs[k].psf_size) ==
              hipSuccess;
@@ -240,8 +266,16 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
             lens_batch_plan_destroy(b);
             return LENS_EHIP;
         }
+    std::vector<int> p0(b->p0);
+    p0.push_back((int)N);
+    std::vector<ViewSrc> views(S);
+    for (int k = 0; k < S; ++k) views[k] = {h_data[k], h_descs[k].nx, h_descs[k].ny};
     if (hipMemcpy(b->d_particle_sys, psys.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice) !=
             hipSuccess ||
+        hipMemcpy(b->d_p0, p0.data(), sizeof(int) * (size_t)(S + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_views, views.data(), sizeof(ViewSrc) * (size_t)S, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        launch_set_int(b->map_step, 0, nullptr) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         lens_batch_plan_destroy(b);
@@ -310,6 +344,127 @@ lens_status lens_batch_loglike_grad(lens_batch_plan* b, const float* d_theta, fl
         b->graph_key = key;
     }
     return hipGraphLaunch(b->graph, st) == hipSuccess ? LENS_OK : LENS_EHIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Inference stage over the packed particles of all systems
+// ---------------------------------------------------------------------------
+static lens_status batch_hip(hipError_t e) { return e == hipSuccess ? LENS_OK : LENS_EHIP; }
+
+// logp(u) = logL(T(u)) + log prior(T(u)) [+ log|dT/du|] and dlogp/du (no argument checks)
+static lens_status batch_logpost(lens_batch_plan* b, const float* u, int with_jac, float* theta_out,
+                                 double* logp, float* grad_u, hipStream_t st) {
+    float* th = theta_out ? theta_out : b->theta;
+    if (launch_bijection(b->N, b->mi.d, b->prior, u, th, st) != hipSuccess) return LENS_EHIP;
+    lens_status s = enqueue(b, th, b->logl, b->gtheta, st, b->logl64);
+    if (s != LENS_OK) return s;
+    return batch_hip(launch_posterior(b->N, b->mi.d, b->prior, u, b->logl64, b->gtheta, with_jac, logp,
+                                      grad_u, st));
+}
+
+static uint64_t batch_fbits(float f) {
+    uint32_t v;
+    std::memcpy(&v, &f, 4);
+    return v;
+}
+
+extern "C" {
+
+lens_status lens_batch_set_prior(lens_batch_plan* b, const float* h_table) {
+    if (!b || !h_table) return LENS_EINVAL;
+    std::vector<PriorRow> rows(b->mi.d);
+    if (!build_prior_rows(b->mi.d, h_table, rows.data())) return LENS_EINVAL;
+    if (!b->prior && hipMalloc(&b->prior, sizeof(PriorRow) * b->mi.d) != hipSuccess) return LENS_ENOMEM;
+    if (hipMemcpy(b->prior, rows.data(), sizeof(PriorRow) * b->mi.d, hipMemcpyHostToDevice) != hipSuccess)
+        return LENS_EHIP;
+    if (b->map_graph) (void)hipGraphExecDestroy(b->map_graph);
+    b->map_graph = nullptr;
+    b->map_key.clear();
+    return LENS_OK;
+}
+
+lens_status lens_batch_logpost_grad(lens_batch_plan* b, const float* d_u, int32_t with_jacobian,
+                                    float* d_theta, double* d_logp, float* d_grad, void* stream) {
+    if (!b || !d_u || !d_logp || !d_grad || !b->prior) return LENS_EINVAL;
+    return batch_logpost(b, d_u, with_jacobian != 0, d_theta, d_logp, d_grad, (hipStream_t)stream);
+}
+
+lens_status lens_batch_map_reset(lens_batch_plan* b) {
+    if (!b) return LENS_EINVAL;
+    if (launch_set_int(b->map_step, 0, nullptr) != hipSuccess) return LENS_EHIP;
+    return batch_hip(hipDeviceSynchronize());
+}
+
+lens_status lens_batch_map_adam(lens_batch_plan* b, float* d_u, float* d_m, float* d_v, int32_t n_steps,
+                                float lr, float decay, float beta1, float beta2, float eps, float* d_loss,
+                                int32_t use_graph, void* stream) {
+    if (!b || !d_u || !d_m || !d_v || n_steps < 0 || !b->prior) return LENS_EINVAL;
+    if (!(lr > 0.0f) || !(decay > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps >= 0.0f))
+        return LENS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const AdamHyper hp{lr, decay, beta1, beta2, eps};
+    auto step = [&](hipStream_t s) -> lens_status {
+        lens_status r = batch_logpost(b, d_u, 0, nullptr, b->logp, b->gradu, s);
+        if (r != LENS_OK) return r;
+        if (launch_adam(b->N, b->mi.d, b->gradu, b->logp, d_u, d_m, d_v, b->map_step, hp, d_loss, s) !=
+            hipSuccess)
+            return LENS_EHIP;
+        return batch_hip(launch_add_int(b->map_step, 1, s));
+    };
+    if (!use_graph) {
+        for (int r = 0; r < n_steps; ++r) {
+            lens_status s = step(st);
+            if (s != LENS_OK) return s;
+        }
+        return LENS_OK;
+    }
+    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)d_u, (uint64_t)(uintptr_t)d_m,
+                                       (uint64_t)(uintptr_t)d_v, (uint64_t)(uintptr_t)d_loss,
+                                       batch_fbits(lr),          batch_fbits(decay),
+                                       batch_fbits(beta1),       batch_fbits(beta2),
+                                       batch_fbits(eps),         b->tiles_version};
+    if (!b->map_graph || b->map_key != key) {
+        if (b->map_graph) (void)hipGraphExecDestroy(b->map_graph);
+        b->map_graph = nullptr;
+        b->map_key.clear();
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return LENS_EHIP;
+        lens_status s = step(b->cap_stream);
+        const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (s != LENS_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return s != LENS_OK ? s : LENS_EHIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&b->map_graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            b->map_graph = nullptr;
+            return LENS_EHIP;
+        }
+        b->map_key = key;
+    }
+    for (int r = 0; r < n_steps; ++r)
+        if (hipGraphLaunch(b->map_graph, st) != hipSuccess) return LENS_EHIP;
+    return LENS_OK;
+}
+
+lens_status lens_batch_to_unconstrained(lens_batch_plan* b, const float* d_theta, float* d_u, void* stream) {
+    if (!b || !d_theta || !d_u || !b->prior) return LENS_EINVAL;
+    return batch_hip(launch_inverse_bijection(b->N, b->mi.d, b->prior, d_theta, d_u, (hipStream_t)stream));
+}
+
+lens_status lens_batch_argmin(lens_batch_plan* b, const float* d_val, float* d_best, int32_t* d_arg,
+                              void* stream) {
+    if (!b || !d_val || !d_best || !d_arg) return LENS_EINVAL;
+    return batch_hip(launch_segment_argmin(b->S, b->d_p0, d_val, d_best, d_arg, (hipStream_t)stream));
+}
+
+lens_status lens_batch_center_views(lens_batch_plan* b, int32_t side, float* d_out, void* stream) {
+    if (!b || !d_out || side < 1 || side > LENS_MAX_SIDE) return LENS_EINVAL;
+    return batch_hip(launch_center_views(b->S, side, b->d_views, d_out, (hipStream_t)stream));
 }
 
 }  // extern "C"

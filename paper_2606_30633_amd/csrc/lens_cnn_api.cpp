@@ -215,4 +215,31 @@ lens_status init_propose(lens_cnn* c, int32_t S, const float* d_img64, int32_t n
     return LENS_OK;
 }
 
+lens_status lens_prior_sample(int32_t d, const float* h_prior_table, int32_t S, int32_t n_per_system,
+                              uint64_t seed, float* d_theta_out, void* stream) {
+    if (d < 1 || d > CNN_MAXD || !h_prior_table || S < 1 || n_per_system < 1 || !d_theta_out) return LENS_EINVAL;
+    CnnTargetMap m{};
+    m.d = d;
+    for (int j = 0; j < d; ++j) {
+        const float* r = h_prior_table + 5 * j;
+        const int kind = (int)r[0];
+        if (kind < LENS_PRIOR_UNIFORM || kind > LENS_PRIOR_TRUNCNORMAL) return LENS_EINVAL;
+        if (kind == LENS_PRIOR_UNIFORM ? !(r[2] > r[1]) : !(r[2] > 0.0f)) return LENS_EINVAL;
+        if (kind == LENS_PRIOR_TRUNCNORMAL && !(r[4] > r[3])) return LENS_EINVAL;
+        m.prior_kind[j] = kind;
+        for (int i = 0; i < 4; ++i) m.prior[j][i] = r[1 + i];
+        m.cnn_slot[j] = -1;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    CnnTargetMap* dm = nullptr;
+    if (hipMalloc(&dm, sizeof(m)) != hipSuccess) return LENS_ENOMEM;
+    lens_status s = LENS_OK;
+    if (hipMemcpyAsync(dm, &m, sizeof(m), hipMemcpyHostToDevice, st) != hipSuccess ||
+        cnn_propose(S, 0, n_per_system, d, nullptr, dm, seed, d_theta_out, nullptr, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        s = LENS_EHIP;
+    (void)hipFree(dm);
+    return s;
+}
+
 }  // extern "C"

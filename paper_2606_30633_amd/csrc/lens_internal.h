@@ -131,7 +131,7 @@ hipError_t launch_batch_adjoint(const ModelInfo& mi, int grid, const BatchSys* s
                                 const float* consts, const float* gimg, double* partial,
                                 hipStream_t st);
 hipError_t launch_batch_psf(int K, int n_items, const BatchSys* sys, const WorkItem* items,
-                            const float* consts, float* img, float* logl, size_t shm,
+                            const float* consts, float* img, float* logl, double* logl64, size_t shm,
                             hipStream_t st);
 hipError_t launch_batch_finalize(const ModelInfo& mi, int N, const BatchSys* sys,
                                  const int* particle_sys, const float* theta, const float* consts,

@@ -73,11 +73,30 @@ struct PK {
     double x0, y0, e1, e2, ua, ub, ue, c0, k0, k1, g1, g2;
     float e1f, e2f, k1f;
     int kp, kpa;
+    bool quad;   // float32 adjoint series by the quadratic-division recurrence (|e| < 0.55)
     SersicK s[NC > 0 ? NC : 1];
 };
 
+// Per-particle constants are read through the constant address space: they
+// do not change during a kernel, so uniform loads of them are scalar loads
+// even through a pointer the compiler cannot otherwise reason about.
+typedef const __attribute__((address_space(4))) float cfloat_t;
+typedef const __attribute__((address_space(4))) double cdouble_t;
+
 __device__ __forceinline__ double ldd(const float* __restrict__ C, int w) {
-    return *reinterpret_cast<const double*>(C + w);
+    return *(cdouble_t*)(C + w);
+}
+__device__ __forceinline__ float ldf(const float* __restrict__ C, int w) { return *(cfloat_t*)(C + w); }
+
+__device__ __forceinline__ SersicK load_sersic(const float* __restrict__ S) {
+    SersicK q;
+    q.xc = ldd(S, S_XC); q.yc = ldd(S, S_YC);
+    q.a11 = ldd(S, S_A11); q.a12 = ldd(S, S_A12); q.a22 = ldd(S, S_A22);
+    q.ie = ldd(S, S_IE); q.ku = ldd(S, S_KU); q.ku0 = ldd(S, S_KU0); q.bl = ldd(S, S_BL);
+    q.a11f = (float)q.a11; q.a12f = (float)q.a12; q.a22f = (float)q.a22;
+    q.ief = (float)q.ie; q.kuf = (float)q.ku; q.ku0f = (float)q.ku0; q.blf = (float)q.bl;
+    q.kap2 = ldf(S, S_KAP2);
+    return q;
 }
 
 template <int NC>
@@ -87,20 +106,21 @@ __device__ __forceinline__ PK<NC> load_pk(const float* __restrict__ C) {
     k.ua = ldd(C, D_UA); k.ub = ldd(C, D_UB); k.ue = ldd(C, D_UE); k.c0 = ldd(C, D_C0);
     k.k0 = ldd(C, D_K0); k.k1 = ldd(C, D_K1); k.g1 = ldd(C, D_G1); k.g2 = ldd(C, D_G2);
     k.e1f = (float)k.e1; k.e2f = (float)k.e2; k.k1f = (float)k.k1;
-    k.kp = (int)C[C_KP];
-    k.kpa = (int)C[C_KPA];
+    k.kp = (int)ldf(C, C_KP);
+    k.kpa = (int)ldf(C, C_KPA);
+    k.quad = fma(k.e1, k.e1, k.e2 * k.e2) < 0.3025;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const float* S = C + C_SERS + c * SERS_STRIDE;
-        SersicK& q = k.s[c];
-        q.xc = ldd(S, S_XC); q.yc = ldd(S, S_YC);
-        q.a11 = ldd(S, S_A11); q.a12 = ldd(S, S_A12); q.a22 = ldd(S, S_A22);
-        q.ie = ldd(S, S_IE); q.ku = ldd(S, S_KU); q.ku0 = ldd(S, S_KU0); q.bl = ldd(S, S_BL);
-        q.a11f = (float)q.a11; q.a12f = (float)q.a12; q.a22f = (float)q.a22;
-        q.ief = (float)q.ie; q.kuf = (float)q.ku; q.ku0f = (float)q.ku0; q.blf = (float)q.bl;
-        q.kap2 = S[S_KAP2];
-    }
+    for (int c = 0; c < NC; ++c) k.s[c] = load_sersic(C + C_SERS + c * SERS_STRIDE);
     return k;
+}
+
+// The pointer itself, hidden from loop-invariant code motion and from the
+// scheduler (an empty volatile asm statement), so that the constants read
+// through it are loaded (scalar loads) where they are used instead of being
+// kept live, and spilled, across the whole sub-pixel loop.
+__device__ __forceinline__ const float* opaque(const float* p) {
+    asm volatile("" : "+s"(p));
+    return p;
 }
 
 // ---------------------------------------------------------------------------
@@ -200,40 +220,61 @@ __device__ __forceinline__ void sersic_adj(float dx, float dy, float gs, const S
 }
 
 // ---------------------------------------------------------------------------
-// EPL series by Horner.  S(z) = sum c_n z^n in float64 (it sets the
-// deflection); S'(z) and dS/dt in float32 (adjoint only), each from its own
-// coefficient array.  Coefficients are read 16 bytes at a time with
-// wave-uniform loads.
+// EPL series S(z) = sum a_n z^n with real coefficients at complex z.
+//
+// With r = 2 Re z and s = |z|^2, z is a root of w^2 - r w + s, so dividing
+// the polynomial by that real quadratic leaves the remainder A z + B:
+//   b_k = a_k + r b_{k+1} - s b_{k+2}  (k = K .. 1),  S = a_0 + z b_1 - s b_2.
+// Two real FMAs per term instead of the four of a complex Horner step (the
+// second-order recurrence of Goertzel's algorithm; Knuth, TAOCP vol. 2,
+// Sec. 4.6.4).  Its rounding error grows like 1/(1 - |z|)^2 near the real
+// axis: negligible in float64 for every |z| < 1, but above |z| ~ 0.55 worse
+// than Horner in float32, so the float32 adjoint series switch to Horner
+// there (|z| = c, uniform over a particle, so the branch does not diverge).
+// S in float64 (it sets the deflection); S'(z) and dS/dt in float32 (adjoint
+// only), each from its own coefficient array.  Coefficients are read with
+// wave-uniform (scalar) loads, four per step; the arrays hold a_0 .. a_kp
+// with kp + 1 a multiple of 4.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void series_d(const float* __restrict__ C, int kp, double zx, double zy,
                                          double& sx, double& sy) {
-    const double* cS = reinterpret_cast<const double*>(C + C_COEF_S);
-    sx = 0.0; sy = 0.0;
-    for (int base = kp - 3; base >= 0; base -= 4) {
-        const double2 hi = *reinterpret_cast<const double2*>(cS + base + 2);
-        const double2 lo = *reinterpret_cast<const double2*>(cS + base);
-        const double cs_[4] = {hi.y, hi.x, lo.y, lo.x};
+    cdouble_t* cS = (cdouble_t*)(C + C_COEF_S);
+    const double r = 2.0 * zx, s = fma(zx, zx, zy * zy);
+    double b1 = 0.0, b2 = 0.0;
+    int base = kp - 3;
+    for (; base >= 4; base -= 4) {
+        const double a_[4] = {cS[base + 3], cS[base + 2], cS[base + 1], cS[base]};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double nsx = fma(sx, zx, fma(-sy, zy, cs_[q]));
-            const double nsy = fma(sx, zy, sy * zx);
-            sx = nsx; sy = nsy;
+            const double b = fma(r, b1, fma(-s, b2, a_[q]));
+            b2 = b1;
+            b1 = b;
         }
     }
+    const double a_[3] = {cS[3], cS[2], cS[1]};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double b = fma(r, b1, fma(-s, b2, a_[q]));
+        b2 = b1;
+        b1 = b;
+    }
+    sx = fma(zx, b1, fma(-s, b2, cS[0]));
+    sy = zy * b1;
 }
 
+// float32 S'(z) -> (dx, dy) and, with WT, dS/dt -> (tx, ty).
 template <bool WT>
-__device__ __forceinline__ void series_adj(const float* __restrict__ C, int kp, float zx, float zy,
-                                           float& dx, float& dy, float& tx, float& ty) {
-    const float* cZ = C + C_COEF_Z;
-    const float* cT = C + C_COEF_T;
+__device__ __forceinline__ void series_adj_horner(const float* __restrict__ C, int kp, float zx, float zy,
+                                                  float& dx, float& dy, float& tx, float& ty) {
+    cfloat_t* cZ = (cfloat_t*)(C + C_COEF_Z);
+    cfloat_t* cT = (cfloat_t*)(C + C_COEF_T);
     dx = 0.f; dy = 0.f; tx = 0.f; ty = 0.f;
     for (int base = kp - 3; base >= 0; base -= 4) {
-        const float4 c = *reinterpret_cast<const float4*>(cZ + base);
-        float4 ct = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (WT) ct = *reinterpret_cast<const float4*>(cT + base);
-        const float cz_[4] = {c.w, c.z, c.y, c.x};
-        const float ct_[4] = {ct.w, ct.z, ct.y, ct.x};
+        const float cz_[4] = {cZ[base + 3], cZ[base + 2], cZ[base + 1], cZ[base]};
+        float ct_[4] = {0.f, 0.f, 0.f, 0.f};
+        if (WT) {
+            ct_[0] = cT[base + 3]; ct_[1] = cT[base + 2]; ct_[2] = cT[base + 1]; ct_[3] = cT[base];
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float ndx = fmaf(dx, zx, fmaf(-dy, zy, cz_[q]));
@@ -246,6 +287,64 @@ __device__ __forceinline__ void series_adj(const float* __restrict__ C, int kp, 
             }
         }
     }
+}
+
+template <bool WT>
+__device__ __forceinline__ void series_adj_quad(const float* __restrict__ C, int kp, float zx, float zy,
+                                                float& dx, float& dy, float& tx, float& ty) {
+    cfloat_t* cZ = (cfloat_t*)(C + C_COEF_Z);
+    cfloat_t* cT = (cfloat_t*)(C + C_COEF_T);
+    const float r = 2.0f * zx, s = fmaf(zx, zx, zy * zy);
+    float d1 = 0.f, d2 = 0.f, t1 = 0.f, t2 = 0.f;
+    int base = kp - 3;
+    for (; base >= 4; base -= 4) {
+        const float cz_[4] = {cZ[base + 3], cZ[base + 2], cZ[base + 1], cZ[base]};
+        float ct_[4] = {0.f, 0.f, 0.f, 0.f};
+        if (WT) {
+            ct_[0] = cT[base + 3]; ct_[1] = cT[base + 2]; ct_[2] = cT[base + 1]; ct_[3] = cT[base];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float b = fmaf(r, d1, fmaf(-s, d2, cz_[q]));
+            d2 = d1;
+            d1 = b;
+            if (WT) {
+                const float bt = fmaf(r, t1, fmaf(-s, t2, ct_[q]));
+                t2 = t1;
+                t1 = bt;
+            }
+        }
+    }
+    const float cz_[3] = {cZ[3], cZ[2], cZ[1]};
+    float ct_[3] = {0.f, 0.f, 0.f};
+    if (WT) {
+        ct_[0] = cT[3]; ct_[1] = cT[2]; ct_[2] = cT[1];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float b = fmaf(r, d1, fmaf(-s, d2, cz_[q]));
+        d2 = d1;
+        d1 = b;
+        if (WT) {
+            const float bt = fmaf(r, t1, fmaf(-s, t2, ct_[q]));
+            t2 = t1;
+            t1 = bt;
+        }
+    }
+    dx = fmaf(zx, d1, fmaf(-s, d2, cZ[0]));
+    dy = zy * d1;
+    tx = 0.f; ty = 0.f;
+    if (WT) {
+        tx = fmaf(zx, t1, fmaf(-s, t2, cT[0]));
+        ty = zy * t1;
+    }
+}
+
+template <bool WT>
+__device__ __forceinline__ void series_adj(const float* __restrict__ C, int kp, bool quad, float zx, float zy,
+                                           float& dx, float& dy, float& tx, float& ty) {
+    if (quad) series_adj_quad<WT>(C, kp, zx, zy, dx, dy, tx, ty);
+    else series_adj_horner<WT>(C, kp, zx, zy, dx, dy, tx, ty);
 }
 
 // 1/sqrt(x) in float64: hardware estimate + two Newton steps.
@@ -315,6 +414,31 @@ __device__ __forceinline__ double subpix_value(double x, double y, const PK<NL +
     return v;
 }
 
+// The same value with each component's float64 constants loaded right
+// before the component is evaluated: the ~40 float64 constants of a particle
+// do not fit the scalar register file together.
+template <int MASS, int NL, int NS>
+__device__ __forceinline__ double subpix_value_lean(double x, double y, const float* __restrict__ C) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) {
+        const SersicK s = load_sersic(opaque(C + C_SERS + c * SERS_STRIDE));
+        v += sersic_val(x - s.xc, y - s.yc, s);
+    }
+    const float* Cm = opaque(C);
+    const PK<0> k = load_pk<0>(Cm);
+    double ax, ay;
+    deflect<MASS, false, 0>(x, y, k, Cm, ax, ay, nullptr);
+    const double bx = x - ax - fma(k.g1, x, k.g2 * y);
+    const double by = y - ay - fma(k.g2, x, -k.g1 * y);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+        const SersicK s = load_sersic(opaque(C + C_SERS + (NL + c) * SERS_STRIDE));
+        v += sersic_val(bx - s.xc, by - s.yc, s);
+    }
+    return v;
+}
+
 // Reverse sweep of one sub-pixel: accumulates into acc[] (layout A_*).
 template <int MASS, int NL, int NS>
 __device__ __forceinline__ void subpix_adjoint(double x, double y, float gs, const PK<NL + NS>& k,
@@ -348,7 +472,7 @@ __device__ __forceinline__ void subpix_adjoint(double x, double y, float gs, con
     if (m.inside) { Gx = 0.f; Gy = 0.f; }
 
     float dx, dy, tx, ty;
-    series_adj<MASS == LENS_MASS_EPL>(C, k.kpa, m.zx, m.zy, dx, dy, tx, ty);
+    series_adj<MASS == LENS_MASS_EPL>(C, k.kpa, k.quad, m.zx, m.zy, dx, dy, tx, ty);
     const float vx = m.vx, vy = m.vy, sx = m.sx, sy = m.sy;
     const float h = fmaf(Gx, m.ax, Gy * m.ay);                // Re(conj(G) alpha)
     acc[A_H] += h;
@@ -501,7 +625,6 @@ __device__ __forceinline__ void render_chunk(const float* __restrict__ C, const 
         for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) out[pix] = __builtin_nanf("");
         return;
     }
-    const PK<NL + NS> k = load_pk<NL + NS>(C);
     for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) {
         const int i = pix / g.nx, j = pix - i * g.nx;
         double acc = 0.0;
@@ -509,7 +632,7 @@ __device__ __forceinline__ void render_chunk(const float* __restrict__ C, const 
             const double y = ((double)(g.s * i + a) - g.cy) * g.h;
             for (int b = 0; b < g.s; ++b) {
                 const double x = ((double)(g.s * j + b) - g.cx) * g.h;
-                acc += subpix_value<MASS, NL, NS>(x, y, k, C);
+                acc += subpix_value_lean<MASS, NL, NS>(x, y, C);
             }
         }
         out[pix] = (float)(acc * (double)g.inv_s2);
@@ -856,14 +979,15 @@ template <int K>
 __global__ __launch_bounds__(256) void k_batch_psf(const BatchSys* __restrict__ sys,
                                                    const WorkItem* __restrict__ items,
                                                    const float* __restrict__ consts, float* img,
-                                                   float* logl) {
+                                                   float* logl, double* logl64) {
     extern __shared__ float4 lds4[];
     __shared__ double red[4];
     const WorkItem w = items[blockIdx.x];
     const BatchSys& S = sys[w.sys];
     const int gp = S.p0 + w.p;
     psf_body<K, 2>(consts[(size_t)gp * CSTRIDE + C_VALID], S.g, img + S.img_off + (size_t)w.p * S.g.npix,
-                   S.wflip, S.wpsf, S.data, S.invvar, nullptr, logl + gp, nullptr, S.stride, S.rows,
+                   S.wflip, S.wpsf, S.data, S.invvar, nullptr, logl + gp, logl64 ? logl64 + gp : nullptr,
+                   S.stride, S.rows,
                    reinterpret_cast<float*>(lds4), red);
 }
 
@@ -1029,24 +1153,25 @@ hipError_t launch_batch_adjoint(const ModelInfo& mi, int grid, const BatchSys* s
 
 template <int K>
 static hipError_t launch_batch_psf_k(int n_items, const BatchSys* sys, const WorkItem* items,
-                                     const float* consts, float* img, float* logl, size_t shm,
-                                     hipStream_t st) {
+                                     const float* consts, float* img, float* logl, double* logl64,
+                                     size_t shm, hipStream_t st) {
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_psf<K>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)MAX_LDS_BYTES);
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_batch_psf<K>, dim3(n_items), dim3(256), shm, st, sys, items, consts, img, logl);
+    hipLaunchKernelGGL(k_batch_psf<K>, dim3(n_items), dim3(256), shm, st, sys, items, consts, img, logl,
+                       logl64);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_psf(int K, int n_items, const BatchSys* sys, const WorkItem* items,
-                            const float* consts, float* img, float* logl, size_t shm,
-                            hipStream_t st) {
+                            const float* consts, float* img, float* logl, double* logl64,
+                            size_t shm, hipStream_t st) {
     switch (K) {
 #define LENS_BPSF_CASE(KK) \
-    case KK: return launch_batch_psf_k<KK>(n_items, sys, items, consts, img, logl, shm, st);
+    case KK: return launch_batch_psf_k<KK>(n_items, sys, items, consts, img, logl, logl64, shm, st);
         LENS_BPSF_CASE(1) LENS_BPSF_CASE(3) LENS_BPSF_CASE(5) LENS_BPSF_CASE(7) LENS_BPSF_CASE(9)
         LENS_BPSF_CASE(11) LENS_BPSF_CASE(13) LENS_BPSF_CASE(15) LENS_BPSF_CASE(17) LENS_BPSF_CASE(19)
         LENS_BPSF_CASE(21) LENS_BPSF_CASE(23) LENS_BPSF_CASE(25) LENS_BPSF_CASE(27) LENS_BPSF_CASE(29)

@@ -35,6 +35,16 @@ struct HmcArgs {
     float eps;
 };
 
+// Observed image of one system of a batch (device pointer) for k_center_views.
+struct ViewSrc {
+    const float* data;
+    int nx, ny;
+};
+
+// Host: validated prior table [d][5] (kind, a, b, c, d) -> device rows.
+// Returns false on an unknown kind or an empty support.
+bool build_prior_rows(int d, const float* h_table, PriorRow* rows);
+
 hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u, float* theta,
                             hipStream_t st);
 hipError_t launch_posterior(int P, int d, const PriorRow* table, const float* u, const double* logl,
@@ -48,5 +58,11 @@ hipError_t launch_set_int(int* c, int val, hipStream_t st);
 hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_kick_drift(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_end(int C, int d, const HmcArgs& a, hipStream_t st);
+
+hipError_t launch_inverse_bijection(int P, int d, const PriorRow* table, const float* theta, float* u,
+                                    hipStream_t st);
+hipError_t launch_segment_argmin(int S, const int* p0, const float* val, float* best, int* arg,
+                                 hipStream_t st);
+hipError_t launch_center_views(int S, int side, const ViewSrc* src, float* out, hipStream_t st);
 
 }  // namespace lens

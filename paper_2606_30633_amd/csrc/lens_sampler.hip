@@ -60,6 +60,28 @@ __device__ __forceinline__ void log_prior(const PriorRow& r, double th, double& 
     }
 }
 
+// u = T^-1(theta); a bounded parameter at (or beyond) an end of its support
+// maps to the logit of 2^-24 (or 1 - 2^-24), a log-normal one <= 0 to log 1e-30.
+__global__ void k_inverse_bijection(int P, int d, const PriorRow* __restrict__ table,
+                                    const float* __restrict__ theta, float* __restrict__ u) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P * d) return;
+    const PriorRow& r = table[q % d];
+    const int kind = (int)r.kind;
+    const double th = (double)theta[q];
+    double v;
+    if (kind == LENS_PRIOR_UNIFORM || kind == LENS_PRIOR_TRUNCNORMAL) {
+        const double lim = 5.9604644775390625e-08;   // 2^-24
+        const double p = fmin(fmax((th - r.lo) / (r.hi - r.lo), lim), 1.0 - lim);
+        v = log(p) - log1p(-p);
+    } else if (kind == LENS_PRIOR_LOGNORMAL) {
+        v = log(fmax(th, 1e-30));
+    } else {
+        v = th;
+    }
+    u[q] = (float)v;
+}
+
 __global__ void k_bijection(int P, int d, const PriorRow* __restrict__ table,
                             const float* __restrict__ u, float* __restrict__ theta) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,6 +305,86 @@ hipError_t launch_hmc_kick_drift(int C, int d, const HmcArgs& a, hipStream_t st)
 
 hipError_t launch_hmc_end(int C, int d, const HmcArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_hmc_end, blocks_for(C, 64), dim3(64), 0, st, C, d, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batch helpers: best particle per system, centred fixed-size image views
+// ---------------------------------------------------------------------------
+// One work-group per system: minimum of val over the system's particles
+// [p0[k], p0[k+1]) and the (global) index of its first occurrence; NaN counts
+// as +inf.
+__global__ __launch_bounds__(256) void k_segment_argmin(const int* __restrict__ p0,
+                                                        const float* __restrict__ val,
+                                                        float* __restrict__ best, int* __restrict__ arg) {
+    const int k = blockIdx.x, t = threadIdx.x;
+    const int a = p0[k], b = p0[k + 1];
+    float bv = __builtin_inff();
+    int bi = b;
+    for (int i = a + t; i < b; i += 256) {
+        float x = val[i];
+        if (x != x) x = __builtin_inff();
+        if (x < bv || (x == bv && i < bi)) {
+            bv = x;
+            bi = i;
+        }
+    }
+    __shared__ float sv[256];
+    __shared__ int si[256];
+    sv[t] = bv;
+    si[t] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            const float ov = sv[t + o];
+            const int oi = si[t + o];
+            if (ov < sv[t] || (ov == sv[t] && oi < si[t])) {
+                sv[t] = ov;
+                si[t] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        best[k] = sv[0];
+        arg[k] = si[0] < b ? si[0] : a;
+    }
+}
+
+// out[k][i][j] = system k's image at the centre-aligned position of pixel
+// (i, j) of a side x side grid with the same pixel scale: source row
+// i + (ny - side) / 2 (likewise columns); a half-integer offset averages the
+// two neighbours, pixels outside the image count as zero.
+__global__ void k_center_views(int side, const ViewSrc* __restrict__ src, float* __restrict__ out) {
+    const int k = blockIdx.y;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= side * side) return;
+    const ViewSrc v = src[k];
+    const int i = q / side, j = q - i * side;
+    const int r2 = 2 * i + (v.ny - side), c2 = 2 * j + (v.nx - side);
+    const int r0 = (r2 - (r2 & 1)) / 2, r1 = (r2 + (r2 & 1)) / 2;
+    const int c0 = (c2 - (c2 & 1)) / 2, c1 = (c2 + (c2 & 1)) / 2;
+    auto at = [&](int r, int c) -> double {
+        return (r >= 0 && r < v.ny && c >= 0 && c < v.nx) ? (double)v.data[(size_t)r * v.nx + c] : 0.0;
+    };
+    const double val = 0.25 * (at(r0, c0) + at(r0, c1) + at(r1, c0) + at(r1, c1));
+    out[(size_t)k * side * side + q] = (float)val;
+}
+
+hipError_t launch_inverse_bijection(int P, int d, const PriorRow* table, const float* theta, float* u,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(k_inverse_bijection, blocks_for((long)P * d, 256), dim3(256), 0, st, P, d, table, theta, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_argmin(int S, const int* p0, const float* val, float* best, int* arg,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_segment_argmin, dim3(S), dim3(256), 0, st, p0, val, best, arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_center_views(int S, int side, const ViewSrc* src, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_center_views, dim3((side * side + 255) / 256, S), dim3(256), 0, st, side, src, out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,401 @@
+"""Learned initializer: training data, training loop, and the time-to-MAP
+comparison of learned against plain multi-start MAP.
+
+The network is not part of the paper: it proposes starting particles for
+the multi-start gradient-descent (MAP) stage of Sec. 3, which otherwise
+starts from prior draws.  Everything numerical runs in the library's HIP
+kernels (forward model, network training and inference, proposals, prior
+draws, bijection, posterior, Adam, per-system best); this module sequences
+the calls, shuffles indices and keeps the bookkeeping.
+
+Regressed parameters (14): the 8 mass parameters (theta_E, gamma, e1, e2,
+x, y, shear g1, g2) and 6 lens-light shape parameters (R_e, n, e1, e2, x,
+y), i.e. the first 14 of the 22 parameters of the EPL + shear + one Sersic
+lens light + one Sersic source model; lens amplitude and the 7 source
+parameters are drawn from the prior.
+
+Time-to-MAP of a system (per arm): wall-clock from the start of the arm
+(network inference and proposals included, plan creation excluded) until
+the best particle's log-posterior reaches L_ref - 1, with L_ref the best
+log-posterior found for that system by either arm or by a final polishing
+run from both arms' best particles.  Fallback: when the learned arm's best
+particle leaves a reduced chi^2 above 1 + 5 sqrt(2 / N_pix), the system is
+rerun from plain prior starts and that time is added to the learned arm.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import lens, synth
+
+N_TARGETS = 14
+SIDE = 64
+SIGMA = synth.SIGMA_NOISE
+
+
+def train_spec() -> synth.ModelSpec:
+    """Training images: 64x64 px at 0.05"/px, 2x2 supersampling, 21x21 PSF."""
+    return synth.paper_spec(SIDE, 2, 21)
+
+
+def _sync():
+    torch.cuda.synchronize()
+    return time.perf_counter()
+
+
+def simulate(n: int, seed: int, device, chunk: int = 8192):
+    """Parameters [n, 22] (numpy, from the simulation distribution) and the
+    noiseless model images [n, 64, 64] rendered by lens_forward."""
+    spec = train_spec()
+    theta = synth.draw_params(synth.paper_sim_dists(), n, seed).astype(np.float32)
+    psf = synth.double_gaussian_psf(spec.psf_size, spec.pix_scale)
+    zero = np.zeros((spec.ny, spec.nx), np.float32)
+    plan = lens.LensPlan(spec, psf, zero, zero + 1.0, min(chunk, n), device)
+    images = torch.empty((n, SIDE, SIDE), dtype=torch.float32, device=device)
+    th = torch.tensor(theta, device=device)
+    for i in range(0, n, chunk):
+        j = min(n, i + chunk)
+        lens.lens_forward(plan, th[i:j].contiguous(), out=images[i:j])
+    torch.cuda.synchronize()
+    plan.close()
+    return theta, images
+
+
+def target_standardization(theta: np.ndarray):
+    t = theta[:, :N_TARGETS].astype(np.float64)
+    return t.mean(axis=0).astype(np.float32), t.std(axis=0).astype(np.float32)
+
+
+@dataclass
+class TrainReport:
+    images: int
+    epochs: int
+    batch: int
+    seconds: float
+    images_per_s: float
+    loss_first: float
+    loss_last: float
+    val_nll: float
+    val_rmse_std: List[float] = field(default_factory=list)
+
+
+def train(net: lens.Cnn, images: torch.Tensor, theta: np.ndarray, mean, std, epochs: int, batch: int = 256,
+          lr: float = 1e-3, lr_final: float = 1e-4, seed: int = synth.SEED_CNN_TRAIN, log=print,
+          val=None) -> TrainReport:
+    """Adam on the Gaussian NLL of the standardised targets; fresh noise on
+    every pass (Philox, counter = image draw index)."""
+    dev = images.device
+    n = images.shape[0]
+    tgt = torch.tensor((theta[:, :N_TARGETS] - mean) / std, dtype=torch.float32, device=dev)
+    xb = torch.empty((batch, SIDE, SIDE), dtype=torch.bfloat16, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    steps = max(1, n // batch)
+    total = steps * epochs
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    first = None
+    t0 = _sync()
+    k = 0
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(dev)
+        for s in range(steps):
+            idx = perm[s * batch:(s + 1) * batch]
+            x = images.index_select(0, idx)
+            draw = (ep * steps + s) * batch
+            net.prepare(x, SIGMA, add_noise=True, seed=seed, counter0=draw * SIDE * SIDE, out=xb)
+            rate = lr * (lr_final / lr) ** (k / max(1, total - 1))
+            net.train_step(xb, tgt.index_select(0, idx), rate, loss)
+            k += 1
+            if first is None:
+                first = float(loss.item())
+        log(f"epoch {ep + 1}/{epochs} loss {float(loss.item()):.4f}")
+    t1 = _sync()
+    last = float(loss.item())
+    rep = TrainReport(n, epochs, batch, t1 - t0, steps * epochs * batch / (t1 - t0), first, last, float("nan"))
+    if val is not None:
+        vtheta, vimages = val
+        nll, rmse = evaluate(net, vimages, vtheta, mean, std)
+        rep.val_nll, rep.val_rmse_std = nll, rmse
+        log(f"validation nll {nll:.4f} rmse/std {np.round(rmse, 3).tolist()}")
+    return rep
+
+
+def evaluate(net: lens.Cnn, images: torch.Tensor, theta: np.ndarray, mean, std, seed: int = synth.SEED_CNN_VAL):
+    """Mean NLL and per-target RMSE of the predicted means (standardised units)."""
+    dev = images.device
+    n = images.shape[0]
+    B = net.max_batch
+    outs = []
+    for i in range(0, n, B):
+        j = min(n, i + B)
+        xb = net.prepare(images[i:j], SIGMA, add_noise=True, seed=seed, counter0=i * SIDE * SIDE)
+        outs.append(net.forward(xb))
+    out = torch.cat(outs).double().cpu().numpy()
+    z = (theta[:, :N_TARGETS].astype(np.float64) - mean) / std
+    mu, s = out[:, :N_TARGETS], out[:, N_TARGETS:]
+    nll = float(np.mean(np.sum(0.5 * (z - mu) ** 2 * np.exp(-s) + 0.5 * s, axis=1)))
+    rmse = np.sqrt(np.mean((z - mu) ** 2, axis=0))
+    return nll, rmse.tolist()
+
+
+def configure(net: lens.Cnn, mean, std):
+    table = synth.prior_table(synth.paper_prior_dists())
+    slot = np.full(table.shape[0], -1, np.int32)
+    slot[:N_TARGETS] = np.arange(N_TARGETS)
+    net.set_target_map(table, slot, mean, std, SIGMA)
+    return table
+
+
+# ---------------------------------------------------------------------------
+# Time-to-MAP
+# ---------------------------------------------------------------------------
+@dataclass
+class Systems:
+    specs: list
+    psfs: list
+    datas: list
+    invvars: list
+    truths: np.ndarray
+
+
+def make_systems(n: int, device) -> Systems:
+    """The uneven batch (sides 48-160 px, supersampling 2-4, PSF 11-31 px),
+    observed images = lens_forward at the seeded truth + seeded noise."""
+    specs = synth.uneven_batch_specs(n)
+    psfs, datas, invvars, truths = [], [], [], []
+    for k, spec in enumerate(specs):
+        s = synth.make_system_paper(spec, k)
+        zero = np.zeros((spec.ny, spec.nx), np.float32)
+        plan = lens.LensPlan(spec, s.psf, zero, s.invvar, 1, device)
+        model = lens.lens_forward(plan, torch.tensor(s.truth[None, :], device=device))[0]
+        datas.append((model + torch.tensor(s.noise, device=device)).contiguous())
+        psfs.append(torch.tensor(s.psf, device=device))
+        invvars.append(torch.tensor(s.invvar, device=device))
+        truths.append(s.truth)
+        torch.cuda.synchronize()
+        plan.close()
+    torch.cuda.synchronize()
+    return Systems(specs, psfs, datas, invvars, np.asarray(truths))
+
+
+def _plan(sy: Systems, per_system, table, idx=None):
+    idx = list(range(len(sy.specs))) if idx is None else list(idx)
+    per = per_system if isinstance(per_system, (list, tuple)) else [per_system] * len(idx)
+    bp = lens.BatchPlan([sy.specs[k] for k in idx], [sy.psfs[k] for k in idx], [sy.datas[k] for k in idx],
+                        [sy.invvars[k] for k in idx], per, sy.datas[0].device)
+    bp.set_prior(table)
+    return bp
+
+
+@dataclass
+class ArmRun:
+    t_init: float              # s, proposals + bijection
+    t_step: float              # s per Adam step (with per-system best tracking)
+    steps: int
+    best: np.ndarray           # [steps + 1, S] best log-posterior after t updates
+    best_u: torch.Tensor       # [S, d] best particle at the end
+
+
+def run_arm(bp: lens.BatchPlan, theta0_fn, steps: int, lr: float, lr_final: float, log=print,
+            tag: str = "", start_is_u: bool = False) -> ArmRun:
+    """theta0_fn() -> packed starting points [N, d] (timed; unconstrained if
+    start_is_u).  Then `steps` Adam updates (graph replay) with the
+    per-system best after each."""
+    dev = bp.device
+    decay = (lr_final / lr) ** (1.0 / max(1, steps - 1))
+    m = torch.zeros((bp.N, bp.d), dtype=torch.float32, device=dev)
+    v = torch.zeros_like(m)
+    loss = torch.empty(bp.N, dtype=torch.float32, device=dev)
+    hist = torch.empty((steps + 1, bp.S), dtype=torch.float32, device=dev)
+    bp.map_reset()
+    t0 = _sync()
+    start = theta0_fn()
+    u = start.clone() if start_is_u else bp.to_unconstrained(start)
+    t1 = _sync()
+    for t in range(steps):
+        bp.map_adam(u, m, v, 1, lr, decay, loss=loss, use_graph=True)
+        hist[t].copy_(bp.argmin(loss)[0])
+        if (t + 1) % 50 == 0:
+            torch.cuda.synchronize()
+            log(f"{tag} step {t + 1}/{steps}")
+    t2 = _sync()
+    logp, _ = bp.logpost_grad(u, False)
+    final = (-logp).float().contiguous()
+    bv, arg = bp.argmin(final)
+    hist[steps].copy_(bv)
+    best_u = u.index_select(0, arg.long())
+    torch.cuda.synchronize()
+    return ArmRun(t1 - t0, (t2 - t1) / max(1, steps), steps, -hist.double().cpu().numpy(), best_u)
+
+
+def polish(sy: Systems, table, us: List[torch.Tensor], steps: int = 400, lr: float = 2e-3, lr_final: float = 1e-5):
+    """Adam from each arm's best particle; returns the best log-posterior seen per system."""
+    S = len(sy.specs)
+    k = len(us)
+    bp = _plan(sy, k, table)
+    u = torch.stack(us, dim=1).reshape(S * k, -1).contiguous()
+    run = run_arm(bp, lambda: u, steps, lr, lr_final, log=lambda *_: None, start_is_u=True)
+    bp.close()
+    return run.best.max(axis=0)
+
+
+def best_chi2_nu(sy: Systems, table, best_u: torch.Tensor, idx=None) -> np.ndarray:
+    idx = list(range(len(sy.specs))) if idx is None else list(idx)
+    bp = _plan(sy, 1, table, idx)
+    _, _, theta = bp.logpost_grad(best_u.contiguous(), False, want_theta=True)
+    logl, _ = bp.loglike_grad(theta)
+    npix = np.array([sy.specs[k].nx * sy.specs[k].ny for k in idx], np.float64)
+    bp.close()
+    return -2.0 * logl.double().cpu().numpy() / npix
+
+
+def time_to_reach(run: ArmRun, target: np.ndarray) -> np.ndarray:
+    """Seconds until the best log-posterior of each system reaches target (inf if never)."""
+    out = np.full(run.best.shape[1], np.inf)
+    for s in range(run.best.shape[1]):
+        hit = np.nonzero(run.best[:, s] >= target[s])[0]
+        if hit.size:
+            out[s] = run.t_init + (hit[0] + 1) * run.t_step
+    return out
+
+
+def time_to_map_experiment(net: lens.Cnn, n_systems: int = 100, n_learned: int = 512, n_plain: int = 4096,
+                           steps: int = 300, lr: float = 2e-2, lr_final: float = 5e-4, seed: int = 7,
+                           device="cuda", log=print, autotune_cache: Optional[str] = None) -> Dict:
+    table = synth.prior_table(synth.paper_prior_dists())
+    sy = make_systems(n_systems, device)
+    S = n_systems
+    log(f"systems ready: {S}")
+
+    bpl = _plan(sy, n_learned, table)
+    bpp = _plan(sy, n_plain, table)
+    if autotune_cache:
+        th = lens.lens_prior_sample(table, S, n_learned, seed + 99, device).reshape(bpl.N, bpl.d)
+        bpl.autotune(th, autotune_cache)
+        th = lens.lens_prior_sample(table, S, n_plain, seed + 98, device).reshape(bpp.N, bpp.d)
+        bpp.autotune(th, autotune_cache)
+
+    def learned0():
+        views = bpl.center_views(SIDE)
+        th, flags = lens.init_propose(net, views, n_learned, seed)
+        learned0.flags = flags
+        return th.reshape(bpl.N, bpl.d)
+
+    learned = run_arm(bpl, learned0, steps, lr, lr_final, log, "learned")
+    log(f"learned arm: init {learned.t_init:.3f} s, {learned.t_step * 1e3:.2f} ms/step")
+    plain = run_arm(bpp, lambda: lens.lens_prior_sample(table, S, n_plain, seed + 1, device).reshape(bpp.N, bpp.d),
+                    steps, lr, lr_final, log, "plain")
+    log(f"plain arm: init {plain.t_init:.3f} s, {plain.t_step * 1e3:.2f} ms/step")
+
+    # fallback: reduced chi^2 of the learned arm's best particle
+    chi = best_chi2_nu(sy, table, learned.best_u)
+    npix = np.array([sp.nx * sp.ny for sp in sy.specs], np.float64)
+    fb = np.nonzero(chi > 1.0 + 5.0 * np.sqrt(2.0 / npix))[0]
+    log(f"fallback systems: {fb.tolist()}")
+    rerun = None
+    if fb.size:
+        bpf = _plan(sy, n_plain, table, fb)
+        rerun = run_arm(bpf, lambda: lens.lens_prior_sample(table, len(fb), n_plain, seed + 2, device)
+                        .reshape(bpf.N, bpf.d), steps, lr, lr_final, log, "fallback")
+        bpf.close()
+
+    ref = np.maximum(learned.best.max(axis=0), plain.best.max(axis=0))
+    pol = polish(sy, table, [learned.best_u, plain.best_u])
+    ref = np.maximum(ref, pol)
+    if rerun is not None:
+        ref[fb] = np.maximum(ref[fb], rerun.best.max(axis=0))
+    target = ref - 1.0
+    t_plain = time_to_reach(plain, target)
+    t_learn = time_to_reach(learned, target)
+    learned_total = learned.t_init + steps * learned.t_step
+    if rerun is not None:
+        t_fb = time_to_reach(rerun, target[fb])
+        t_learn[fb] = learned_total + t_fb
+    final_learned = learned.best[-1].copy()
+    if rerun is not None:
+        final_learned[fb] = np.maximum(final_learned[fb], rerun.best[-1])
+    d_final = final_learned - plain.best[-1]
+
+    def summ(t):
+        ok = np.isfinite(t)
+        return {"success_frac": float(ok.mean()),
+                "median_s": float(np.median(t[ok])) if ok.any() else None,
+                "mean_s": float(np.mean(t[ok])) if ok.any() else None,
+                "max_s": float(np.max(t[ok])) if ok.any() else None}
+
+    flags = getattr(learned0, "flags", None)
+    res = {
+        "systems": S, "steps": steps, "lr": lr, "lr_final": lr_final,
+        "learned": {"particles_per_system": n_learned, "t_init_s": learned.t_init,
+                    "ms_per_step": learned.t_step * 1e3, "total_s": learned_total,
+                    "clipped_proposal_systems": int(flags.sum().item()) if flags is not None else None,
+                    "fallback_systems": fb.tolist(), **summ(t_learn)},
+        "plain": {"particles_per_system": n_plain, "t_init_s": plain.t_init,
+                  "ms_per_step": plain.t_step * 1e3, "total_s": plain.t_init + steps * plain.t_step,
+                  **summ(t_plain)},
+        "speedup_median": (float(np.median(t_plain[np.isfinite(t_plain)]) /
+                                 np.median(t_learn[np.isfinite(t_learn)]))
+                           if np.isfinite(t_plain).any() and np.isfinite(t_learn).any() else None),
+        "final_logp_learned_minus_plain": {"median": float(np.median(d_final)), "min": float(np.min(d_final)),
+                                           "frac_within_1": float(np.mean(d_final >= -1.0))},
+        "per_system": {"time_learned_s": t_learn.tolist(), "time_plain_s": t_plain.tolist(),
+                       "L_ref": ref.tolist(), "final_learned": final_learned.tolist(),
+                       "final_plain": plain.best[-1].tolist(), "chi2_nu_learned": chi.tolist()},
+    }
+    bpl.close()
+    bpp.close()
+    return res
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="Train the learned initializer and compare time-to-MAP")
+    ap.add_argument("--train-images", type=int, default=200000)
+    ap.add_argument("--val-images", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--systems", type=int, default=100)
+    ap.add_argument("--learned", type=int, default=512)
+    ap.add_argument("--plain", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=2e-2)
+    ap.add_argument("--lr-final", type=float, default=5e-4)
+    ap.add_argument("--out", type=str, default=None)
+    args = ap.parse_args(argv)
+    dev = torch.device("cuda", 0)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.perf_counter()
+    theta, images = simulate(args.train_images, synth.SEED_CNN_TRAIN, dev)
+    vtheta, vimages = simulate(args.val_images, synth.SEED_CNN_VAL, dev)
+    t_sim = time.perf_counter() - t0
+    log(f"simulated {args.train_images} + {args.val_images} images in {t_sim:.1f} s")
+    mean, std = target_standardization(theta)
+    net = lens.Cnn(args.batch, 1, dev)
+    rep = train(net, images, theta, mean, std, args.epochs, args.batch, log=log, val=(vtheta, vimages))
+    del images
+    configure(net, mean, std)
+    res = time_to_map_experiment(net, args.systems, args.learned, args.plain, args.steps, args.lr, args.lr_final,
+                                 device=dev, log=log)
+    res["training"] = {"images": rep.images, "epochs": rep.epochs, "batch": rep.batch, "seconds": rep.seconds,
+                       "images_per_s": rep.images_per_s, "simulate_s": t_sim, "loss_first": rep.loss_first,
+                       "loss_last": rep.loss_last, "val_nll": rep.val_nll, "val_rmse_std": rep.val_rmse_std}
+    txt = json.dumps(res)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(txt + "\n")
+    summary = {k: v for k, v in res.items() if k != "per_system"}
+    print(json.dumps(summary), flush=True)
+
+
+if __name__ == "__main__":
+    main()

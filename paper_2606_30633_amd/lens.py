@@ -62,6 +62,16 @@ _SIGNATURES = {
     "lens_batch_get_tiles": (_I, [_P, _P]),
     "lens_batch_set_tiles": (_I, [_P, _P]),
     "lens_batch_autotune": (_I, [_P, _P, ctypes.c_char_p, _P]),
+    "lens_batch_set_prior": (_I, [_P, _P]),
+    "lens_batch_logpost_grad": (_I, [_P, _P, _I, _P, _P, _P, _P]),
+    "lens_batch_map_reset": (_I, [_P]),
+    "lens_batch_map_adam": (_I, [_P, _P, _P, _P, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, _P, _I, _P]),
+    "lens_batch_argmin": (_I, [_P, _P, _P, _P, _P]),
+    "lens_batch_to_unconstrained": (_I, [_P, _P, _P, _P]),
+    "lens_to_unconstrained": (_I, [_P, _I, _P, _P, _P]),
+    "lens_prior_sample": (_I, [_I, _P, _I, _I, ctypes.c_uint64, _P, _P]),
+    "lens_batch_center_views": (_I, [_P, _I, _P, _P]),
     "lens_cnn_create": (_I, [_I, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "lens_cnn_destroy": (_I, [_P]),
     "lens_cnn_num_params": (ctypes.c_int64, []),
@@ -195,12 +205,18 @@ class LensPlan:
         return theta
 
 
+def _check_out(t: torch.Tensor, shape, dtype, device):
+    if t.dtype != dtype or t.device != device or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"output must be a contiguous {dtype} tensor of shape {tuple(shape)} on {device}")
+
+
 def lens_forward(plan: LensPlan, theta: torch.Tensor, out: Optional[torch.Tensor] = None,
                  stream=None) -> torch.Tensor:
     th = plan._theta(theta)
     P = th.shape[0]
     if out is None:
         out = torch.empty((P, plan.spec.ny, plan.spec.nx), dtype=torch.float32, device=plan.device)
+    _check_out(out, (P, plan.spec.ny, plan.spec.nx), torch.float32, plan.device)
     _check(_lib.lens_forward(plan.handle, P, th.data_ptr(), out.data_ptr(), _stream(stream)), "lens_forward")
     return out
 
@@ -211,6 +227,7 @@ def lens_loglike(plan: LensPlan, theta: torch.Tensor, out: Optional[torch.Tensor
     P = th.shape[0]
     if out is None:
         out = torch.empty(P, dtype=torch.float32, device=plan.device)
+    _check_out(out, (P,), torch.float32, plan.device)
     _check(_lib.lens_loglike(plan.handle, P, th.data_ptr(), out.data_ptr(), _stream(stream)), "lens_loglike")
     return out
 
@@ -226,6 +243,10 @@ def lens_loglike_grad(plan: LensPlan, theta: torch.Tensor, logl: Optional[torch.
         grad = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
     if logl64 is None and want_logl64:
         logl64 = torch.empty(P, dtype=torch.float64, device=plan.device)
+    _check_out(logl, (P,), torch.float32, plan.device)
+    _check_out(grad, (P, plan.d), torch.float32, plan.device)
+    if logl64 is not None:
+        _check_out(logl64, (P,), torch.float64, plan.device)
     _check(_lib.lens_loglike_grad(plan.handle, P, th.data_ptr(), logl.data_ptr(), grad.data_ptr(),
                                   None if logl64 is None else logl64.data_ptr(), _stream(stream)),
            "lens_loglike_grad")
@@ -269,6 +290,15 @@ def lens_logpost_grad(plan: LensPlan, u: torch.Tensor, with_jacobian: bool, logp
     if theta is not None:
         return logp, grad, theta
     return logp, grad
+
+
+def lens_to_unconstrained(plan: LensPlan, theta: torch.Tensor, stream=None) -> torch.Tensor:
+    """u = T^-1(theta) under the plan's prior."""
+    th = plan._theta(theta)
+    u = torch.empty_like(th)
+    _check(_lib.lens_to_unconstrained(plan.handle, th.shape[0], th.data_ptr(), u.data_ptr(), _stream(stream)),
+           "lens_to_unconstrained")
+    return u
 
 
 def lens_map_reset(plan: LensPlan):
@@ -376,6 +406,66 @@ class BatchPlan:
                "lens_batch_autotune")
         return self.get_tiles()
 
+    def _rows(self, x, name):
+        if x.dtype != torch.float32 or x.device != self.device or not x.is_contiguous() \
+                or x.shape != (self.N, self.d):
+            raise ValueError(f"{name} must be contiguous float32 [{self.N}, {self.d}] on the plan's device")
+        return x
+
+    def set_prior(self, table):
+        import numpy as np
+        t = np.ascontiguousarray(np.asarray(table, dtype=np.float32))
+        if t.shape != (self.d, 5):
+            raise ValueError(f"prior table must be [{self.d}, 5]")
+        _check(_lib.lens_batch_set_prior(self.handle, t.ctypes.data_as(ctypes.c_void_p)), "lens_batch_set_prior")
+
+    def logpost_grad(self, u, with_jacobian: bool, want_theta: bool = False, stream=None):
+        """logp(u) (float64 [N]) and dlogp/du [N, d] for every packed particle."""
+        self._rows(u, "u")
+        logp = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        grad = torch.empty((self.N, self.d), dtype=torch.float32, device=self.device)
+        theta = torch.empty((self.N, self.d), dtype=torch.float32, device=self.device) if want_theta else None
+        _check(_lib.lens_batch_logpost_grad(self.handle, u.data_ptr(), 1 if with_jacobian else 0, _ptr(theta),
+                                            logp.data_ptr(), grad.data_ptr(), _stream(stream)),
+               "lens_batch_logpost_grad")
+        return (logp, grad, theta) if want_theta else (logp, grad)
+
+    def map_reset(self):
+        _check(_lib.lens_batch_map_reset(self.handle), "lens_batch_map_reset")
+
+    def map_adam(self, u, m, v, n_steps: int, lr: float, decay: float = 1.0, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, loss=None, use_graph: bool = False, stream=None):
+        """n_steps Adam updates of every packed particle (in place)."""
+        for x, nm in ((u, "u"), (m, "m"), (v, "v")):
+            self._rows(x, nm)
+        _check(_lib.lens_batch_map_adam(self.handle, u.data_ptr(), m.data_ptr(), v.data_ptr(), int(n_steps), lr,
+                                        decay, beta1, beta2, eps, _ptr(loss), 1 if use_graph else 0,
+                                        _stream(stream)), "lens_batch_map_adam")
+        return loss
+
+    def to_unconstrained(self, theta, stream=None):
+        self._rows(theta, "theta")
+        u = torch.empty_like(theta)
+        _check(_lib.lens_batch_to_unconstrained(self.handle, theta.data_ptr(), u.data_ptr(), _stream(stream)),
+               "lens_batch_to_unconstrained")
+        return u
+
+    def argmin(self, val, stream=None):
+        """(min [S], global row [S]) of val [N] over each system's particles."""
+        if val.dtype != torch.float32 or val.shape != (self.N,) or not val.is_contiguous():
+            raise ValueError(f"val must be contiguous float32 [{self.N}]")
+        best = torch.empty(self.S, dtype=torch.float32, device=self.device)
+        arg = torch.empty(self.S, dtype=torch.int32, device=self.device)
+        _check(_lib.lens_batch_argmin(self.handle, val.data_ptr(), best.data_ptr(), arg.data_ptr(),
+                                      _stream(stream)), "lens_batch_argmin")
+        return best, arg
+
+    def center_views(self, side: int = 64, stream=None):
+        out = torch.empty((self.S, side, side), dtype=torch.float32, device=self.device)
+        _check(_lib.lens_batch_center_views(self.handle, int(side), out.data_ptr(), _stream(stream)),
+               "lens_batch_center_views")
+        return out
+
 
 CNN_SIDE, CNN_TARGETS, CNN_OUTPUTS = 64, 14, 28
 
@@ -478,3 +568,15 @@ def init_propose(net: Cnn, images64: torch.Tensor, n_per_system: int, seed: int,
     _check(_lib.init_propose(net.handle, S, x.data_ptr(), int(n_per_system), int(seed), theta.data_ptr(),
                              _ptr(flags), _stream(None)), "init_propose")
     return theta, flags
+
+
+def lens_prior_sample(prior_table, S: int, n_per_system: int, seed: int, device="cuda", stream=None):
+    """[S, n, d] starting points drawn from the prior on the device."""
+    import numpy as np
+    load_library()
+    tab = np.ascontiguousarray(np.asarray(prior_table, dtype=np.float32))
+    d = tab.shape[0]
+    out = torch.empty((S, n_per_system, d), dtype=torch.float32, device=device)
+    _check(_lib.lens_prior_sample(d, tab.ctypes.data_as(ctypes.c_void_p), int(S), int(n_per_system), int(seed),
+                                  out.data_ptr(), _stream(stream)), "lens_prior_sample")
+    return out

@@ -98,3 +98,108 @@ def test_mixed_models_rejected():
     with pytest.raises(lens.LensError) as e:
         lens.BatchPlan([a, b], [np.ones((3, 3), np.float32)] * 2, [z, z], [z + 1, z + 1], [1, 1], DEV)
     assert e.value.status == lens.LENS_EUNSUPPORTED
+
+
+def _batch_with_prior(seed):
+    specs, cases = _batch(seed=seed)
+    table = synth.prior_table(synth.paper_prior_dists())
+    bp = lens.BatchPlan(specs, [c[1] for c in cases], [c[2] for c in cases], [c[0].invvar for c in cases],
+                        [c[3].shape[0] for c in cases], DEV)
+    bp.set_prior(table)
+    th = synth.draw_params(synth.paper_prior_dists(), bp.N, 5150 + seed)
+    u = np.stack([O.to_unconstrained(torch.tensor(t, dtype=torch.float64), table).numpy() for t in th])
+    return specs, cases, table, bp, u.astype(np.float32)
+
+
+@pytest.mark.parametrize("jac", [False, True])
+def test_batch_logpost_equals_single_plans_and_oracle(jac):
+    specs, cases, table, bp, u = _batch_with_prior(3)
+    print("batch logpost", specs, jac, flush=True)
+    lp, g, th = bp.logpost_grad(torch.tensor(u, device=DEV), jac, want_theta=True)
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    off = 0
+    for k, (spec, (sysm, psf, data, _)) in enumerate(zip(specs, cases)):
+        n = bp.particles[k]
+        plan = lens.LensPlan(spec, psf, data, sysm.invvar, n, DEV)
+        plan.set_prior(table)
+        lps, gs = lens.lens_logpost_grad(plan, torch.tensor(u[off:off + n], device=DEV), jac)
+        assert np.array_equal(lp[off:off + n], lps.cpu().numpy())
+        assert np.array_equal(g[off:off + n], gs.cpu().numpy())
+        lr, gr = O.log_posterior_unconstrained(u[off], spec, psf, data, sysm.invvar, table, jac,
+                                               theta_float32=True)
+        assert abs(lp[off] - lr) <= 1e-5 * abs(lr)
+        assert np.linalg.norm(g[off] - gr) <= 1e-5 * np.linalg.norm(gr)
+        off += n
+
+
+def test_batch_map_adam_graph_eager_and_single_plans():
+    specs, cases, table, bp, u = _batch_with_prior(4)
+    ue = torch.tensor(u, device=DEV)
+    me, ve = torch.zeros_like(ue), torch.zeros_like(ue)
+    le = torch.empty(bp.N, device=DEV)
+    bp.map_reset()
+    bp.map_adam(ue, me, ve, 3, 5e-3, decay=0.99, loss=le)
+    ug = torch.tensor(u, device=DEV)
+    mg, vg = torch.zeros_like(ug), torch.zeros_like(ug)
+    lg = torch.empty(bp.N, device=DEV)
+    bp.map_reset()
+    for _ in range(3):
+        bp.map_adam(ug, mg, vg, 1, 5e-3, decay=0.99, loss=lg, use_graph=True)
+        torch.cuda.synchronize()
+        bp.logpost_grad(ue, False)          # eager work between replays
+        torch.cuda.synchronize()
+    for a, b in ((ue, ug), (me, mg), (ve, vg), (le, lg)):
+        assert torch.equal(a, b)
+    off = 0
+    for k, (spec, (sysm, psf, data, _)) in enumerate(zip(specs, cases)):
+        n = bp.particles[k]
+        plan = lens.LensPlan(spec, psf, data, sysm.invvar, n, DEV)
+        plan.set_prior(table)
+        us = torch.tensor(u[off:off + n], device=DEV)
+        ms, vs = torch.zeros_like(us), torch.zeros_like(us)
+        ls = torch.empty(n, device=DEV)
+        lens.lens_map_reset(plan)
+        lens.lens_map_adam(plan, us, ms, vs, 3, 5e-3, decay=0.99, loss=ls)
+        assert torch.equal(us, ue[off:off + n]) and torch.equal(ls, le[off:off + n])
+        off += n
+
+
+def test_batch_argmin_exact():
+    specs, cases = _batch(seed=5, particles=(300, 1, 7, 256, 257, 3))
+    bp = lens.BatchPlan(specs, [c[1] for c in cases], [c[2] for c in cases], [c[0].invvar for c in cases],
+                        [c[3].shape[0] for c in cases], DEV)
+    rng = np.random.default_rng(9)
+    val = rng.integers(-5, 5, bp.N).astype(np.float32)      # many ties
+    val[rng.random(bp.N) < 0.1] = np.nan
+    val[bp.particles[0]] = np.nan                            # a one-particle system holding NaN
+    best, arg = bp.argmin(torch.tensor(val, device=DEV))
+    best, arg = best.cpu().numpy(), arg.cpu().numpy()
+    off = 0
+    for k, n in enumerate(bp.particles):
+        seg = np.where(np.isnan(val[off:off + n]), np.inf, val[off:off + n])
+        i = int(np.argmin(seg))                              # first occurrence
+        assert best[k] == seg[i] and arg[k] == off + i, k
+        off += n
+
+
+def test_batch_center_views_exact():
+    specs, cases = _batch(seed=6)
+    bp = lens.BatchPlan(specs, [c[1] for c in cases], [c[2] for c in cases], [c[0].invvar for c in cases],
+                        [c[3].shape[0] for c in cases], DEV)
+    for side in (64, 31, 20):
+        views = bp.center_views(side).cpu().numpy()
+        for k, (spec, c) in enumerate(zip(specs, cases)):
+            img = c[2].astype(np.float64)
+            ref = np.zeros((side, side))
+            for i in range(side):
+                for j in range(side):
+                    r2, c2 = 2 * i + spec.ny - side, 2 * j + spec.nx - side
+                    rs = {(r2 - (r2 & 1)) // 2, (r2 + (r2 & 1)) // 2}
+                    cs = {(c2 - (c2 & 1)) // 2, (c2 + (c2 & 1)) // 2}
+                    acc = 0.0
+                    for r in sorted(rs) * (2 // len(rs)):
+                        for cc in sorted(cs) * (2 // len(cs)):
+                            if 0 <= r < spec.ny and 0 <= cc < spec.nx:
+                                acc += img[r, cc]
+                    ref[i, j] = 0.25 * acc
+            np.testing.assert_allclose(views[k], ref.astype(np.float32), rtol=1e-6, atol=1e-7)

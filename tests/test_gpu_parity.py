@@ -257,3 +257,24 @@ def test_autograd_function():
     (L * w).sum().backward()
     _, G = lens.lens_loglike_grad(plan, torch.tensor(th, device=DEV))
     torch.testing.assert_close(x.grad, w[:, None] * G)
+
+
+@pytest.mark.parametrize("mass", ["EPL", "SIE"])
+def test_high_ellipticity_series(mass):
+    """Mass ellipticities |e| from 0.3 to 0.85, on and off the real axis of the
+    series variable: covers both float32 series forms of the adjoint (switch
+    at |e| = 0.55) and the long float64 series."""
+    spec = synth.ModelSpec(40, 40, 0.06, 2, 7, mass, 1, 1)
+    sysm, psf, data, th = make_case(spec, 8, 10)
+    th = th.copy()
+    o = 2 if mass == "EPL" else 1
+    for p, (c, ang) in enumerate([(0.3, 0.0), (0.5, 0.4), (0.54, 0.0), (0.56, 0.0), (0.6, 1.2),
+                                  (0.7, 0.0), (0.7, 2.5), (0.8, 0.7), (0.85, 0.0), (0.85, 3.0)]):
+        th[p, o:o + 2] = [c * math.cos(ang), c * math.sin(ang)]
+    _log(f"high ellipticity {mass}")
+    plan = _plan(spec, psf, data, sysm.invvar, th.shape[0])
+    tt = torch.tensor(th, device=DEV)
+    check_images(spec, psf, th, lens.lens_forward(plan, tt).cpu().numpy())
+    L, G = lens.lens_loglike_grad(plan, tt)
+    check_loglike(spec, psf, data, sysm.invvar, th, L.cpu().numpy())
+    check_grad(spec, psf, data, sysm.invvar, th, G.cpu().numpy())

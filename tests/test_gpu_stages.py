@@ -205,3 +205,61 @@ def test_hmc_graph_replays_equal_eager():
     g = run(True, 3)
     for (xe, le), (xg, lg) in zip(e, g):
         assert torch.equal(xe, xg) and torch.equal(le, lg)
+
+
+def test_prior_sample_distribution_and_determinism():
+    from scipy import stats
+    table = synth.prior_table(synth.paper_prior_dists())
+    th = lens.lens_prior_sample(table, 3, 20000, 11, DEV)
+    assert torch.equal(th, lens.lens_prior_sample(table, 3, 20000, 11, DEV))
+    assert not torch.equal(th[0], th[1])
+    th = th.cpu().numpy().astype(np.float64)
+    for j in range(table.shape[0]):
+        kind, a, b, c, e = (float(x) for x in table[j])
+        v = th[2, :, j]
+        if kind == synth.PRIOR_LOGNORMAL:
+            pv = stats.kstest(np.log(v), stats.norm(a, b).cdf).pvalue
+        elif kind == synth.PRIOR_UNIFORM:
+            pv = stats.kstest(v, stats.uniform(a, b - a).cdf).pvalue
+        elif kind == synth.PRIOR_NORMAL:
+            pv = stats.kstest(v, stats.norm(a, b).cdf).pvalue
+        else:
+            pv = stats.kstest(v, stats.truncnorm((c - a) / b, (e - a) / b, loc=a, scale=b).cdf).pvalue
+        assert pv > 1e-4, (j, pv)
+
+
+def test_to_unconstrained_matches_oracle_and_round_trips():
+    spec = synth.paper_spec(48, 2, 11)
+    sysm, psf, data, table, u, plan = _setup(spec, 2, 64, "paper")
+    th = synth.draw_params(synth.paper_prior_dists(), 64, 99).astype(np.float32)
+    ug = lens.lens_to_unconstrained(plan, torch.tensor(th, device=DEV)).cpu().numpy()
+    ur = np.stack([O.to_unconstrained(torch.tensor(t.astype(np.float64)), table).numpy() for t in th])
+    np.testing.assert_allclose(ug, ur, rtol=2e-6, atol=2e-6)
+    _, _, back = lens.lens_logpost_grad(plan, torch.tensor(ug, device=DEV), False, want_theta=True)
+    np.testing.assert_allclose(back.cpu().numpy(), th, rtol=2e-6, atol=1e-6)
+
+
+def test_learned_init_driver_miniature():
+    """End to end at a tiny scale: simulate, train, propose, both MAP arms,
+    fallback check and time-to-MAP bookkeeping."""
+    from paper_2606_30633_amd import learned_init as LI
+    dev = torch.device(DEV, 0)
+    theta, images = LI.simulate(1024, synth.SEED_CNN_TRAIN, dev)
+    assert images.shape == (1024, 64, 64) and bool(torch.isfinite(images).all())
+    vtheta, vimages = LI.simulate(256, synth.SEED_CNN_VAL, dev)
+    mean, std = LI.target_standardization(theta)
+    net = lens.Cnn(128, 1, dev)
+    rep = LI.train(net, images, theta, mean, std, 2, 128, log=_log, val=(vtheta, vimages))
+    assert np.isfinite(rep.loss_last) and np.isfinite(rep.val_nll)
+    LI.configure(net, mean, std)
+    res = LI.time_to_map_experiment(net, n_systems=3, n_learned=16, n_plain=64, steps=20, device=dev, log=_log)
+    for arm in ("learned", "plain"):
+        assert res[arm]["ms_per_step"] > 0
+        assert 0.0 <= res[arm]["success_frac"] <= 1.0
+    ps = res["per_system"]
+    L_ref = np.array(ps["L_ref"])
+    assert np.all(np.isfinite(L_ref))
+    # the reference is at least as good as what either arm reached
+    assert np.all(L_ref >= np.array(ps["final_learned"])) and np.all(L_ref >= np.array(ps["final_plain"]))
+    d = np.array(ps["final_learned"]) - np.array(ps["final_plain"])
+    assert abs(res["final_logp_learned_minus_plain"]["median"] - np.median(d)) < 1e-9 * max(1.0, abs(np.median(d)))
