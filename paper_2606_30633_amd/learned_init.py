@@ -204,12 +204,17 @@ class ArmRun:
 
 
 def run_arm(bp: lens.BatchPlan, theta0_fn, steps: int, lr: float, lr_final: float, log=print,
-            tag: str = "", start_is_u: bool = False) -> ArmRun:
+            tag: str = "", start_is_u: bool = False, hold: float = 0.0) -> ArmRun:
     """theta0_fn() -> packed starting points [N, d] (timed; unconstrained if
     start_is_u).  Then `steps` Adam updates (graph replay) with the
-    per-system best after each."""
+    per-system best after each.  Learning rate: lr for the first
+    round(hold * steps) updates, then geometric decay to lr_final."""
     dev = bp.device
-    decay = (lr_final / lr) ** (1.0 / max(1, steps - 1))
+    n1 = int(round(hold * steps))
+    n2 = steps - n1
+    decay = (lr_final / lr) ** (1.0 / max(1, n2 - 1))
+    # the kernel's rate at update k (1-based) is lr_arg * decay_arg^(k - 1)
+    phases = [(n1, lr, 1.0), (n2, lr / decay ** n1, decay)]
     m = torch.zeros((bp.N, bp.d), dtype=torch.float32, device=dev)
     v = torch.zeros_like(m)
     loss = torch.empty(bp.N, dtype=torch.float32, device=dev)
@@ -219,12 +224,15 @@ def run_arm(bp: lens.BatchPlan, theta0_fn, steps: int, lr: float, lr_final: floa
     start = theta0_fn()
     u = start.clone() if start_is_u else bp.to_unconstrained(start)
     t1 = _sync()
-    for t in range(steps):
-        bp.map_adam(u, m, v, 1, lr, decay, loss=loss, use_graph=True)
-        hist[t].copy_(bp.argmin(loss)[0])
-        if (t + 1) % 50 == 0:
-            torch.cuda.synchronize()
-            log(f"{tag} step {t + 1}/{steps}")
+    t = 0
+    for n, lr_arg, dec in phases:
+        for _ in range(n):
+            bp.map_adam(u, m, v, 1, lr_arg, dec, loss=loss, use_graph=True)
+            hist[t].copy_(bp.argmin(loss)[0])
+            t += 1
+            if t % 50 == 0:
+                torch.cuda.synchronize()
+                log(f"{tag} step {t}/{steps}")
     t2 = _sync()
     logp, _ = bp.logpost_grad(u, False)
     final = (-logp).float().contiguous()
@@ -266,60 +274,91 @@ def time_to_reach(run: ArmRun, target: np.ndarray) -> np.ndarray:
     return out
 
 
-def time_to_map_experiment(net: lens.Cnn, n_systems: int = 100, n_learned: int = 512, n_plain: int = 4096,
-                           steps: int = 300, lr: float = 2e-2, lr_final: float = 5e-4, seed: int = 7,
-                           device="cuda", log=print, autotune_cache: Optional[str] = None) -> Dict:
-    table = synth.prior_table(synth.paper_prior_dists())
-    sy = make_systems(n_systems, device)
-    S = n_systems
-    log(f"systems ready: {S}")
+def _save_arm(path: str, run: ArmRun, **extra):
+    np.savez(path, t_init=run.t_init, t_step=run.t_step, steps=run.steps, best=run.best,
+             best_u=run.best_u.cpu().numpy(), **extra)
 
-    bpl = _plan(sy, n_learned, table)
-    bpp = _plan(sy, n_plain, table)
-    if autotune_cache:
-        th = lens.lens_prior_sample(table, S, n_learned, seed + 99, device).reshape(bpl.N, bpl.d)
-        bpl.autotune(th, autotune_cache)
-        th = lens.lens_prior_sample(table, S, n_plain, seed + 98, device).reshape(bpp.N, bpp.d)
-        bpp.autotune(th, autotune_cache)
 
-    def learned0():
-        views = bpl.center_views(SIDE)
-        th, flags = lens.init_propose(net, views, n_learned, seed)
-        learned0.flags = flags
-        return th.reshape(bpl.N, bpl.d)
+def _load_arm(path: str, device):
+    z = np.load(path)
+    run = ArmRun(float(z["t_init"]), float(z["t_step"]), int(z["steps"]), z["best"],
+                 torch.tensor(z["best_u"], device=device))
+    return run, {k: z[k] for k in z.files if k not in ("t_init", "t_step", "steps", "best", "best_u")}
 
-    learned = run_arm(bpl, learned0, steps, lr, lr_final, log, "learned")
-    log(f"learned arm: init {learned.t_init:.3f} s, {learned.t_step * 1e3:.2f} ms/step")
-    plain = run_arm(bpp, lambda: lens.lens_prior_sample(table, S, n_plain, seed + 1, device).reshape(bpp.N, bpp.d),
-                    steps, lr, lr_final, log, "plain")
-    log(f"plain arm: init {plain.t_init:.3f} s, {plain.t_step * 1e3:.2f} ms/step")
 
-    # fallback: reduced chi^2 of the learned arm's best particle
-    chi = best_chi2_nu(sy, table, learned.best_u)
+def _concat_arms(parts: List[ArmRun]) -> ArmRun:
+    """Arms run on disjoint groups of systems, taken as one batch: the per-step
+    time of the whole batch is the sum of the groups' (the same work)."""
+    return ArmRun(sum(r.t_init for r in parts), sum(r.t_step for r in parts), parts[0].steps,
+                  np.concatenate([r.best for r in parts], axis=1), torch.cat([r.best_u for r in parts]))
+
+
+@dataclass
+class Schedule:
+    steps: int = 1000
+    lr: float = 3e-2
+    lr_final: float = 1e-4
+    hold: float = 0.7
+
+
+def learned_arm(net: lens.Cnn, sy: Systems, table, n: int, sch: Schedule, seed: int, log=print):
+    S = len(sy.specs)
+    bp = _plan(sy, n, table)
+    flags = {}
+
+    def start():
+        views = bp.center_views(SIDE)
+        th, fl = lens.init_propose(net, views, n, seed)
+        flags["f"] = fl
+        return th.reshape(bp.N, bp.d)
+
+    run = run_arm(bp, start, sch.steps, sch.lr, sch.lr_final, log, "learned", hold=sch.hold)
+    bp.close()
+    chi = best_chi2_nu(sy, table, run.best_u)
+    return run, chi, flags["f"].cpu().numpy()
+
+
+def plain_arm(sy: Systems, table, n: int, sch: Schedule, seed: int, idx=None, log=print, tag="plain"):
+    idx = list(range(len(sy.specs))) if idx is None else list(idx)
+    bp = _plan(sy, n, table, idx)
+    dev = sy.datas[0].device
+    # one draw for the whole batch, so that a group of systems sees the same
+    # starting points as in a single run (Philox counters use the system index)
+
+    sel = torch.as_tensor(np.asarray(idx, dtype=np.int64), device=dev)
+
+    def start():
+        th = lens.lens_prior_sample(table, max(idx) + 1, n, seed, dev)
+        return th.index_select(0, sel).reshape(bp.N, bp.d).contiguous()
+
+    run = run_arm(bp, start, sch.steps, sch.lr, sch.lr_final, log, tag, hold=sch.hold)
+    bp.close()
+    return run
+
+
+def summarize(sy: Systems, table, learned: ArmRun, chi, flags, plain: ArmRun, sch: Schedule, n_learned: int,
+              n_plain: int, seed: int, log=print) -> Dict:
+    """Fallback reruns, polishing, L_ref and the time-to-MAP statistics."""
+    S = len(sy.specs)
     npix = np.array([sp.nx * sp.ny for sp in sy.specs], np.float64)
     fb = np.nonzero(chi > 1.0 + 5.0 * np.sqrt(2.0 / npix))[0]
-    log(f"fallback systems: {fb.tolist()}")
-    rerun = None
-    if fb.size:
-        bpf = _plan(sy, n_plain, table, fb)
-        rerun = run_arm(bpf, lambda: lens.lens_prior_sample(table, len(fb), n_plain, seed + 2, device)
-                        .reshape(bpf.N, bpf.d), steps, lr, lr_final, log, "fallback")
-        bpf.close()
-
+    log(f"fallback systems ({fb.size}): {fb.tolist()}")
+    rerun = plain_arm(sy, table, n_plain, sch, seed + 2, fb, log, "fallback") if fb.size else None
     ref = np.maximum(learned.best.max(axis=0), plain.best.max(axis=0))
-    pol = polish(sy, table, [learned.best_u, plain.best_u])
-    ref = np.maximum(ref, pol)
+    starts = [learned.best_u, plain.best_u]
     if rerun is not None:
         ref[fb] = np.maximum(ref[fb], rerun.best.max(axis=0))
+        fb_u = learned.best_u.clone()
+        fb_u[torch.as_tensor(fb, device=fb_u.device)] = rerun.best_u
+        starts.append(fb_u)
+    ref = np.maximum(ref, polish(sy, table, starts))
     target = ref - 1.0
     t_plain = time_to_reach(plain, target)
     t_learn = time_to_reach(learned, target)
-    learned_total = learned.t_init + steps * learned.t_step
-    if rerun is not None:
-        t_fb = time_to_reach(rerun, target[fb])
-        t_learn[fb] = learned_total + t_fb
+    learned_total = learned.t_init + sch.steps * learned.t_step
     final_learned = learned.best[-1].copy()
     if rerun is not None:
+        t_learn[fb] = learned_total + time_to_reach(rerun, target[fb])
         final_learned[fb] = np.maximum(final_learned[fb], rerun.best[-1])
     d_final = final_learned - plain.best[-1]
 
@@ -330,71 +369,117 @@ def time_to_map_experiment(net: lens.Cnn, n_systems: int = 100, n_learned: int =
                 "mean_s": float(np.mean(t[ok])) if ok.any() else None,
                 "max_s": float(np.max(t[ok])) if ok.any() else None}
 
-    flags = getattr(learned0, "flags", None)
-    res = {
-        "systems": S, "steps": steps, "lr": lr, "lr_final": lr_final,
+    both = np.isfinite(t_plain) & np.isfinite(t_learn)
+    return {
+        "systems": S, "schedule": {"steps": sch.steps, "lr": sch.lr, "lr_final": sch.lr_final, "hold": sch.hold},
         "learned": {"particles_per_system": n_learned, "t_init_s": learned.t_init,
                     "ms_per_step": learned.t_step * 1e3, "total_s": learned_total,
-                    "clipped_proposal_systems": int(flags.sum().item()) if flags is not None else None,
+                    "clipped_proposal_systems": int(np.sum(flags)),
                     "fallback_systems": fb.tolist(), **summ(t_learn)},
         "plain": {"particles_per_system": n_plain, "t_init_s": plain.t_init,
-                  "ms_per_step": plain.t_step * 1e3, "total_s": plain.t_init + steps * plain.t_step,
+                  "ms_per_step": plain.t_step * 1e3, "total_s": plain.t_init + sch.steps * plain.t_step,
                   **summ(t_plain)},
-        "speedup_median": (float(np.median(t_plain[np.isfinite(t_plain)]) /
-                                 np.median(t_learn[np.isfinite(t_learn)]))
-                           if np.isfinite(t_plain).any() and np.isfinite(t_learn).any() else None),
+        "speedup_median_both_reached": (float(np.median(t_plain[both] / t_learn[both])) if both.any() else None),
         "final_logp_learned_minus_plain": {"median": float(np.median(d_final)), "min": float(np.min(d_final)),
                                            "frac_within_1": float(np.mean(d_final >= -1.0))},
         "per_system": {"time_learned_s": t_learn.tolist(), "time_plain_s": t_plain.tolist(),
                        "L_ref": ref.tolist(), "final_learned": final_learned.tolist(),
-                       "final_plain": plain.best[-1].tolist(), "chi2_nu_learned": chi.tolist()},
+                       "final_plain": plain.best[-1].tolist(), "chi2_nu_learned": chi.tolist(),
+                       "npix": npix.tolist()},
     }
-    bpl.close()
-    bpp.close()
-    return res
+
+
+def time_to_map_experiment(net: lens.Cnn, n_systems: int = 100, n_learned: int = 512, n_plain: int = 4096,
+                           sch: Schedule = Schedule(), seed: int = 7, device="cuda", log=print) -> Dict:
+    """Both arms in one call (small runs; the full comparison runs in stages, see main)."""
+    table = synth.prior_table(synth.paper_prior_dists())
+    sy = make_systems(n_systems, device)
+    learned, chi, flags = learned_arm(net, sy, table, n_learned, sch, seed, log)
+    plain = plain_arm(sy, table, n_plain, sch, seed + 1, None, log)
+    return summarize(sy, table, learned, chi, flags, plain, sch, n_learned, n_plain, seed, log)
 
 
 def main(argv=None):
+    """Stages (each one GPU process; state in --state, read from --load):
+      train    simulate the training set, train, save the network
+      learned  learned arm on all systems (+ reduced chi^2 of its best particles)
+      plain    plain arm on group --part of --parts groups of systems
+      finish   fallback reruns, polishing, statistics -> --out
+    """
     import argparse
+    import os
     ap = argparse.ArgumentParser(description="Train the learned initializer and compare time-to-MAP")
+    ap.add_argument("stage", choices=["train", "learned", "plain", "finish"])
+    ap.add_argument("--state", required=True)
+    ap.add_argument("--load", default=None)
     ap.add_argument("--train-images", type=int, default=200000)
     ap.add_argument("--val-images", type=int, default=4096)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=16)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--systems", type=int, default=100)
     ap.add_argument("--learned", type=int, default=512)
     ap.add_argument("--plain", type=int, default=4096)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--lr", type=float, default=2e-2)
-    ap.add_argument("--lr-final", type=float, default=5e-4)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--lr", type=float, default=3e-2)
+    ap.add_argument("--lr-final", type=float, default=1e-4)
+    ap.add_argument("--hold", type=float, default=0.7)
+    ap.add_argument("--part", type=int, default=0)
+    ap.add_argument("--parts", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", type=str, default=None)
     args = ap.parse_args(argv)
     dev = torch.device("cuda", 0)
+    os.makedirs(args.state, exist_ok=True)
+    load = args.load or args.state
+    sch = Schedule(args.steps, args.lr, args.lr_final, args.hold)
+    table = synth.prior_table(synth.paper_prior_dists())
 
     def log(msg):
         print(msg, flush=True)
 
-    t0 = time.perf_counter()
-    theta, images = simulate(args.train_images, synth.SEED_CNN_TRAIN, dev)
-    vtheta, vimages = simulate(args.val_images, synth.SEED_CNN_VAL, dev)
-    t_sim = time.perf_counter() - t0
-    log(f"simulated {args.train_images} + {args.val_images} images in {t_sim:.1f} s")
-    mean, std = target_standardization(theta)
-    net = lens.Cnn(args.batch, 1, dev)
-    rep = train(net, images, theta, mean, std, args.epochs, args.batch, log=log, val=(vtheta, vimages))
-    del images
-    configure(net, mean, std)
-    res = time_to_map_experiment(net, args.systems, args.learned, args.plain, args.steps, args.lr, args.lr_final,
-                                 device=dev, log=log)
-    res["training"] = {"images": rep.images, "epochs": rep.epochs, "batch": rep.batch, "seconds": rep.seconds,
+    if args.stage == "train":
+        t0 = time.perf_counter()
+        theta, images = simulate(args.train_images, synth.SEED_CNN_TRAIN, dev)
+        vtheta, vimages = simulate(args.val_images, synth.SEED_CNN_VAL, dev)
+        t_sim = time.perf_counter() - t0
+        log(f"simulated {args.train_images} + {args.val_images} images in {t_sim:.1f} s")
+        mean, std = target_standardization(theta)
+        net = lens.Cnn(args.batch, 1, dev)
+        rep = train(net, images, theta, mean, std, args.epochs, args.batch, lr=2e-3, lr_final=1e-4, log=log,
+                    val=(vtheta, vimages))
+        np.save(os.path.join(args.state, "cnn_params.npy"), net.get_params().cpu().numpy())
+        np.save(os.path.join(args.state, "cnn_mean.npy"), mean)
+        np.save(os.path.join(args.state, "cnn_std.npy"), std)
+        with open(os.path.join(args.state, "training.json"), "w") as f:
+            json.dump({"images": rep.images, "epochs": rep.epochs, "batch": rep.batch, "seconds": rep.seconds,
                        "images_per_s": rep.images_per_s, "simulate_s": t_sim, "loss_first": rep.loss_first,
-                       "loss_last": rep.loss_last, "val_nll": rep.val_nll, "val_rmse_std": rep.val_rmse_std}
-    txt = json.dumps(res)
-    if args.out:
-        with open(args.out, "w") as f:
-            f.write(txt + "\n")
-    summary = {k: v for k, v in res.items() if k != "per_system"}
-    print(json.dumps(summary), flush=True)
+                       "loss_last": rep.loss_last, "val_nll": rep.val_nll, "val_rmse_std": rep.val_rmse_std}, f)
+        return
+    sy = make_systems(args.systems, dev)
+    if args.stage == "learned":
+        net = lens.Cnn(256, 1, dev)
+        net.set_params(torch.tensor(np.load(os.path.join(load, "cnn_params.npy")), device=dev))
+        configure(net, np.load(os.path.join(load, "cnn_mean.npy")), np.load(os.path.join(load, "cnn_std.npy")))
+        run, chi, flags = learned_arm(net, sy, table, args.learned, sch, args.seed, log)
+        _save_arm(os.path.join(args.state, "learned.npz"), run, chi=chi, flags=flags)
+        log(f"learned arm: {run.t_step * 1e3:.2f} ms/step, reduced chi^2 median {np.median(chi):.3f}")
+    elif args.stage == "plain":
+        idx = np.array_split(np.arange(args.systems), args.parts)[args.part]
+        run = plain_arm(sy, table, args.plain, sch, args.seed + 1, idx, log)
+        _save_arm(os.path.join(args.state, f"plain_{args.part}_of_{args.parts}.npz"), run, idx=idx)
+        log(f"plain arm part {args.part}: {run.t_step * 1e3:.2f} ms/step")
+    else:
+        learned, extra = _load_arm(os.path.join(load, "learned.npz"), dev)
+        parts = [_load_arm(os.path.join(load, f"plain_{p}_of_{args.parts}.npz"), dev)[0] for p in range(args.parts)]
+        res = summarize(sy, table, learned, extra["chi"], extra["flags"], _concat_arms(parts), sch, args.learned,
+                        args.plain, args.seed, log)
+        tj = os.path.join(load, "training.json")
+        if os.path.exists(tj):
+            res["training"] = json.load(open(tj))
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(json.dumps(res) + "\n")
+        print(json.dumps({k: v for k, v in res.items() if k != "per_system"}), flush=True)
 
 
 if __name__ == "__main__":

@@ -252,7 +252,8 @@ def test_learned_init_driver_miniature():
     rep = LI.train(net, images, theta, mean, std, 2, 128, log=_log, val=(vtheta, vimages))
     assert np.isfinite(rep.loss_last) and np.isfinite(rep.val_nll)
     LI.configure(net, mean, std)
-    res = LI.time_to_map_experiment(net, n_systems=3, n_learned=16, n_plain=64, steps=20, device=dev, log=_log)
+    res = LI.time_to_map_experiment(net, n_systems=3, n_learned=16, n_plain=64, sch=LI.Schedule(20, 3e-2, 1e-4, 0.5),
+                                    device=dev, log=_log)
     for arm in ("learned", "plain"):
         assert res[arm]["ms_per_step"] > 0
         assert 0.0 <= res[arm]["success_frac"] <= 1.0
