@@ -30,7 +30,7 @@ PEAK_FP32_PACKED = 157.3
 # WRITE_SIZE passes, scaled by a plain 256 MiB copy (profiles/
 # map_step_100px_4096p_counters.txt).  Valid only for the kernel source it was
 # measured on; reported as null otherwise.
-TRAFFIC_MEASURED = {"kernel_src_sha256_16": "b8372caf39a9a853", "bytes": 191320251}
+TRAFFIC_MEASURED = {"kernel_src_sha256_16": "86578dd5bfec2b95", "bytes": 192019490}
 
 
 def parse():
@@ -54,10 +54,12 @@ def adjoint_flops_per_subpixel(K_s, K_a, NL, NS, epl=True):
     sub-pixel forward model (float64 deflection with a K-term series, shear,
     lens equation, float32 Sersic values) and the reverse sweep (series
     derivatives, chain through the deflection, Sersic adjoints and the
-    accumulated sums).  See the design doc for the itemised count.
+    accumulated sums).
     """
-    series_fwd = 8 * K_s                        # complex Horner (float64 S), 4 FMA per step
-    series_adj = 8 * K_a * (2 if epl else 1)    # S'(z) and dS/dt (float32)
+    # a real-coefficient series at a complex point: 2 FMA per term (the
+    # quadratic-division recurrence; the minimum for this evaluation)
+    series_fwd = 4 * K_s                        # S in float64
+    series_adj = 4 * K_a * (2 if epl else 1)    # S'(z) and dS/dt (float32)
     mass_fwd = 40 + (60 if epl else 0)          # offsets, U, 1/R, V0, z, pow, alpha
     shear_lens = 12
     sersic_fwd = 18                             # offset, R^2, log2, 2 exp2, mults

@@ -125,57 +125,66 @@ __device__ __forceinline__ const float* opaque(const float* p) {
 
 // ---------------------------------------------------------------------------
 // float64 exp2 / log2 for the model values (no float64 transcendental
-// instructions exist; these are accurate to ~1e-13 relative, far below the
-// float32 output rounding).
+// instructions exist).  Table-driven (Tang's method): a 64-entry table in
+// LDS reduces the argument to a tiny interval where a degree-5 polynomial
+// suffices; errors are ~1e-14, far below what the model values need.
+// Every kernel that evaluates them fills the table first (init_math_tab).
 // ---------------------------------------------------------------------------
 constexpr double LN2_D = 0.69314718055994530942;
 
-// log2 x for normal x > 0: x = m 2^e, m in [sqrt(1/2), sqrt(2));
-// ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1),
-// |s| <= 0.1716; terms up to s^15 (truncation < 1e-12).
-__device__ __forceinline__ double log2_d(double x) {
-    double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
-    int e = __builtin_amdgcn_frexp_exp(x);
-    const bool lo = m < 0.70710678118654752440;
-    m = lo ? 2.0 * m : m;
-    e = lo ? e - 1 : e;
-    const double den = m + 1.0;
-    double r = __builtin_amdgcn_rcp(den);
-    r = r * fma(-den, r, 2.0);
-    r = r * fma(-den, r, 2.0);
-    const double sv = (m - 1.0) * r;
-    const double z = sv * sv;
-    constexpr double c = 2.0 / LN2_D;
-    double p = c / 15.0;
-    p = fma(p, z, c / 13.0);
-    p = fma(p, z, c / 11.0);
-    p = fma(p, z, c / 9.0);
-    p = fma(p, z, c / 7.0);
-    p = fma(p, z, c / 5.0);
-    p = fma(p, z, c / 3.0);
-    p = fma(p, z, c);
-    return fma(sv, p, (double)e);
+struct MathTab {
+    double2 lg[64];   // (1/c_j, log2 c_j), c_j = 1 + (j + 1/2)/64
+    double ex[64];    // 2^(j/64)
+};
+__shared__ MathTab g_tab;
+
+// Threads 0..63 of the work-group fill the table; ends with a barrier.
+__device__ __forceinline__ void init_math_tab() {
+    const int j = threadIdx.x;
+    if (j < 64) {
+        const double ic = 1.0 / (1.0 + (j + 0.5) / 64.0);
+        g_tab.lg[j] = make_double2(ic, -log2(ic));
+        g_tab.ex[j] = exp2(j / 64.0);
+    }
+    __syncthreads();
 }
 
-// 2^v: v = n + f, n = rint(v), |f| <= 1/2; 2^f = e^y, y = f ln2, |y| < 0.347,
-// by the Taylor series of e^y to y^11 (truncation < 1e-14), scaled by 2^n.
+// log2 x for normal x > 0: x = m 2^e, m in [1, 2); with the table entry j
+// of m's leading six fraction bits, log2 m = log2 c_j + log2(1 + r),
+// r = m/c_j - 1, |r| < 2^-7, by the series of log(1 + r) to r^6.
+__device__ __forceinline__ double log2_d(double x) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(x);
+    const uint32_t hi = (uint32_t)(bits >> 32);
+    const int e = (int)(hi >> 20) - 1023;
+    const int j = (int)((hi >> 14) & 63u);
+    const double m = __longlong_as_double(
+        (long long)(((uint64_t)((hi & 0x000fffffu) | 0x3ff00000u) << 32) | (bits & 0xffffffffull)));
+    const double2 t = g_tab.lg[j];
+    const double r = fma(m, t.x, -1.0);
+    constexpr double k = 1.0 / LN2_D;
+    double p = fma(-r, k / 6.0, k / 5.0);
+    p = fma(-r, p, k / 4.0);
+    p = fma(-r, p, k / 3.0);
+    p = fma(-r, p, k / 2.0);
+    p = fma(-r, p, k);
+    return fma(r, p, (double)e + t.y);
+}
+
+// 2^v, v clamped to [-1100, 1100]: 64 v = 64 n + i + f', i in [0, 64),
+// |f'| <= 1/2; 2^v = 2^n 2^(i/64) e^y, y = f' ln2/64, |y| < 0.0055, by the
+// Taylor series of e^y to y^5.
 __device__ __forceinline__ double exp2_d(double v) {
     v = fmin(fmax(v, -1100.0), 1100.0);
-    const double n = rint(v);
-    const double y = (v - n) * LN2_D;
-    double p = 1.0 / 39916800.0;                 // 1/11!
-    p = fma(p, y, 1.0 / 3628800.0);
-    p = fma(p, y, 1.0 / 362880.0);
-    p = fma(p, y, 1.0 / 40320.0);
-    p = fma(p, y, 1.0 / 5040.0);
-    p = fma(p, y, 1.0 / 720.0);
-    p = fma(p, y, 1.0 / 120.0);
-    p = fma(p, y, 1.0 / 24.0);
-    p = fma(p, y, 1.0 / 6.0);
-    p = fma(p, y, 0.5);
-    p = fma(p, y, 1.0);
-    p = fma(p, y, 1.0);
-    return __builtin_amdgcn_ldexp(p, (int)n);
+    const double t = v * 64.0;
+    const double jd = rint(t);
+    const int ji = (int)jd;
+    const double y = (t - jd) * (LN2_D / 64.0);
+    double p = fma(y, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(y, p, 1.0 / 6.0);
+    p = fma(y, p, 0.5);
+    p = fma(y, p, 1.0);
+    p = fma(y, p, 1.0);
+    return __builtin_amdgcn_ldexp(g_tab.ex[ji & 63] * p, ji >> 6);
 }
 
 // ---------------------------------------------------------------------------
@@ -394,24 +403,6 @@ __device__ __forceinline__ void deflect(double x, double y, const PK<NC>& k,
         ms->sx = (float)sx; ms->sy = (float)sy; ms->f = (float)f; ms->L2 = (float)L2;
         ms->ax = (float)ax; ms->ay = (float)ay; ms->inside = inside;
     }
-}
-
-template <int MASS, int NL, int NS>
-__device__ __forceinline__ double subpix_value(double x, double y, const PK<NL + NS>& k,
-                                               const float* __restrict__ C) {
-    double v = 0.0;
-#pragma unroll
-    for (int c = 0; c < NL; ++c) v += sersic_val(x - k.s[c].xc, y - k.s[c].yc, k.s[c]);
-    double ax, ay;
-    deflect<MASS, false, NL + NS>(x, y, k, C, ax, ay, nullptr);
-    const double bx = x - ax - fma(k.g1, x, k.g2 * y);
-    const double by = y - ay - fma(k.g2, x, -k.g1 * y);
-#pragma unroll
-    for (int c = 0; c < NS; ++c) {
-        const SersicK& sc = k.s[NL + c];
-        v += sersic_val(bx - sc.xc, by - sc.yc, sc);
-    }
-    return v;
 }
 
 // The same value with each component's float64 constants loaded right
@@ -683,6 +674,7 @@ __device__ __forceinline__ void adjoint_chunk(const float* __restrict__ C, const
 template <int MASS, int NL, int NS>
 __global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts, Geo g, int ppb,
                                                 float* __restrict__ img) {
+    init_math_tab();
     const int p = blockIdx.x;
     const int pix0 = blockIdx.y * ppb;
     render_chunk<MASS, NL, NS>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
@@ -695,6 +687,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ const
                                                  double* __restrict__ partial) {
     constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
     __shared__ double red[NACC][4];
+    init_math_tab();
     const int p = blockIdx.x;
     const int pix0 = blockIdx.y * ppb;
     adjoint_chunk<MASS, NL, NS>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
@@ -939,6 +932,7 @@ __global__ __launch_bounds__(256) void k_batch_render(const BatchSys* __restrict
                                                       const float* __restrict__ consts,
                                                       float* __restrict__ img) {
     __shared__ int slot;
+    init_math_tab();
     for (;;) {
         const int it = next_item(counter, &slot);
         if (it >= n_items) break;
@@ -961,6 +955,7 @@ __global__ __launch_bounds__(256) void k_batch_adjoint(const BatchSys* __restric
     constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
     __shared__ double red[NACC][4];
     __shared__ int slot;
+    init_math_tab();
     for (;;) {
         const int it = next_item(counter, &slot);
         if (it >= n_items) break;

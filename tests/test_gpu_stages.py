@@ -256,11 +256,16 @@ def test_learned_init_driver_miniature():
                                     device=dev, log=_log)
     for arm in ("learned", "plain"):
         assert res[arm]["ms_per_step"] > 0
-        assert 0.0 <= res[arm]["success_frac"] <= 1.0
+        for blk in ("time_to_map", "time_to_map_polished_ref"):
+            assert 0.0 <= res[blk][arm]["success_frac"] <= 1.0
     ps = res["per_system"]
     L_ref = np.array(ps["L_ref"])
     assert np.all(np.isfinite(L_ref))
-    # the reference is at least as good as what either arm reached
+    # the reference is at least as good as what either arm reached, and the
+    # arm that set it reached it
     assert np.all(L_ref >= np.array(ps["final_learned"])) and np.all(L_ref >= np.array(ps["final_plain"]))
+    tl = np.array(res["time_to_map"]["per_system"]["time_learned_s"])
+    tp = np.array(res["time_to_map"]["per_system"]["time_plain_s"])
+    assert np.all(np.isfinite(tl) | np.isfinite(tp))
     d = np.array(ps["final_learned"]) - np.array(ps["final_plain"])
     assert abs(res["final_logp_learned_minus_plain"]["median"] - np.median(d)) < 1e-9 * max(1.0, abs(np.median(d)))
