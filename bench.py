@@ -40,7 +40,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--cpu-sample", type=int, default=320)
+    ap.add_argument("--workload", choices=["map", "hmc", "batch", "cnn"], default="map",
+                    help="map: the headline MAP step (default); hmc: 8192 chains x 10 leapfrog on the same "
+                         "system; batch: 100 uneven systems x 512 particles; cnn: network training")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB (plain copy kernel, "
                          "for scaling HBM byte counters)")
@@ -75,6 +78,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload != "map":
+        return {"hmc": run_hmc, "batch": run_batch, "cnn": run_cnn}[args.workload](args)
     import torch
     from paper_2606_30633_amd import lens, synth
 
@@ -214,6 +219,147 @@ def cpu_baseline(spec, sysm, th_sample):
     return {"value": round(len(th_sample) / dt, 3), "unit": "evals/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
             "sample": f"{len(th_sample)} particles of the same workload, logL+grad (FP64 autograd)"}
+
+
+def _line(args, value, unit, ms_step, workload, extra, roofline=None, dtype="f32+f64"):
+    out = {"metric": METRIC, "value": round(value, 1), "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": {"workload": workload, **extra},
+           "roofline": roofline, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def run_hmc(args):
+    """HMC on the headline system: 8192 chains, 10 leapfrog steps per transition,
+    graph-replayed transitions; value = logL+grad evals/s (chains x leapfrog x transitions/s)."""
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    dev = torch.device("cuda", 0)
+    spec, sysm = synth.config2_spec(), synth.config2_system()
+    C, L = 8192, 10
+    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
+    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
+            + torch.tensor(sysm.noise, device=dev)).contiguous()
+    plan = lens.LensPlan(spec, torch.tensor(sysm.psf, device=dev), data, torch.tensor(sysm.invvar, device=dev),
+                         C, dev)
+    plan.set_prior(synth.prior_table(sysm.prior))
+    d = spec.n_params
+    ut = lens.lens_to_unconstrained(plan, torch.tensor(sysm.truth[None, :], device=dev))
+    # diagonal of the Hessian at the truth by central differences of the gradient -> mass matrix
+    h = 1e-3
+    probe = ut.repeat(2 * d, 1)
+    for j in range(d):
+        probe[2 * j, j] += h
+        probe[2 * j + 1, j] -= h
+    _, g = lens.lens_logpost_grad(plan, probe.contiguous(), True)
+    hd = torch.stack([(g[2 * j, j] - g[2 * j + 1, j]) / (2 * h) for j in range(d)]).abs().clamp_min(1e-6)
+    inv_mass = (1.0 / hd).float().contiguous()
+    gen = torch.Generator(device="cpu").manual_seed(synth.SEED_HMC)
+    u = (ut + torch.randn((C, d), generator=gen).to(dev) * inv_mass.sqrt() * 0.5).contiguous()
+    logp, grad = lens.lens_logpost_grad(plan, u, True)
+    acc = torch.zeros(C, dtype=torch.int32, device=dev)
+    eps = 0.15
+    for t in range(args.warmup):
+        lens.lens_hmc_run(plan, u, grad, logp, inv_mass, eps, L, 1, synth.SEED_HMC, t, accepts=acc, use_graph=True)
+    torch.cuda.synchronize()
+    acc.zero_()
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        lens.lens_hmc_run(plan, u, grad, logp, inv_mass, eps, L, 1, synth.SEED_HMC, args.warmup + t, accepts=acc,
+                          use_graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    rate = float(acc.sum().item()) / (C * args.steps)
+    # one eager transition with per-kernel events for the adjoint's roofline
+    plan.enable_timing(True)
+    lens.lens_hmc_run(plan, u, grad, logp, inv_mass, eps, L, 1, synth.SEED_HMC, 10 ** 6, use_graph=False)
+    torch.cuda.synchronize()
+    plan.enable_timing(False)
+    tim = plan.read_timing()
+    adj_ms = tim["adjoint"][0] / max(tim["adjoint"][1], 1)
+    th = synth.particles_box(sysm, 64, 0)
+    steps_k = _series_terms(th, spec).mean(axis=0)
+    fl = adjoint_flops_per_subpixel(steps_k[0], steps_k[1], spec.n_lens_light, spec.n_source, True)
+    achieved = fl * (spec.nx * spec.supersample) ** 2 * C / (adj_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None, "kernel": "k_adjoint",
+            "avg_ms": round(adj_ms, 4), "note": "series lengths estimated from prior-box draws"}
+    _line(args, C * L / dt, "evals/s", dt * 1e3,
+          "HMC: 100x100 px EPL system, 8192 chains x 10 leapfrog per transition, hipGraph transitions",
+          {"chains": C, "leapfrog": L, "transitions_per_s": round(1.0 / dt, 3), "acceptance": round(rate, 4),
+           "eps": eps}, roof)
+
+
+def run_batch(args):
+    """100 uneven systems x 512 particles: one batched logL + gradient call per step (graph replay)."""
+    import tempfile
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    from paper_2606_30633_amd.learned_init import make_systems
+    dev = torch.device("cuda", 0)
+    sy = make_systems(100, dev)
+    P = 512
+    bp = lens.BatchPlan(sy.specs, sy.psfs, sy.datas, sy.invvars, [P] * 100, dev)
+    table = synth.prior_table(synth.paper_prior_dists())
+    theta = lens.lens_prior_sample(table, 100, P, synth.SEED_PARTICLES, dev).reshape(bp.N, bp.d).contiguous()
+    t0 = time.perf_counter()
+    with tempfile.TemporaryDirectory() as td:
+        tiles = bp.autotune(theta, os.path.join(td, "tiles.json"))
+    t_tune = time.perf_counter() - t0
+    logl = torch.empty(bp.N, device=dev)
+    grad = torch.empty((bp.N, bp.d), device=dev)
+    for _ in range(args.warmup):
+        bp.loglike_grad(theta, logl, grad, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bp.loglike_grad(theta, logl, grad, use_graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    sub = sum(sp.nx * sp.ny * sp.supersample ** 2 for sp in sy.specs) * P
+    _line(args, bp.N / dt, "evals/s", dt * 1e3,
+          "uneven batch: 100 systems (side 48-160 px, s 2-4, PSF 11-31), 512 particles each, "
+          "one persistent render + adjoint launch per step, autotuned tiles",
+          {"particles": bp.N, "sub_pixel_evals_per_s": round(sub / dt, 1), "autotune_s": round(t_tune, 2),
+           "tiles": {str(t): tiles.count(t) for t in sorted(set(tiles))}})
+
+
+def run_cnn(args):
+    """Training throughput of the learned initializer's network (BF16 MFMA)."""
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    from paper_2606_30633_amd.learned_init import simulate, target_standardization, SIGMA
+    dev = torch.device("cuda", 0)
+    B = 256
+    theta, images = simulate(B * 16, synth.SEED_CNN_TRAIN, dev)
+    mean, std = target_standardization(theta)
+    tgt = torch.tensor((theta[:, :14] - mean) / std, dtype=torch.float32, device=dev)
+    net = lens.Cnn(B, 1, dev)
+    xb = net.prepare(images, SIGMA, add_noise=True, seed=1)
+    loss = torch.empty(1, device=dev)
+    for i in range(args.warmup):
+        net.train_step(xb[(i % 16) * B:(i % 16 + 1) * B], tgt[(i % 16) * B:(i % 16 + 1) * B], 1e-3, loss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        k = i % 16
+        net.train_step(xb[k * B:(k + 1) * B], tgt[k * B:(k + 1) * B], 1e-3, loss)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # flops per image: forward convolutions + MLP, backward ~2x forward (no data gradient of the input)
+    fwd = 0.0
+    cin, H = 1, 64
+    for c, s in zip([32, 32, 64, 64, 128, 128], [1, 2, 1, 2, 1, 2]):
+        H //= s
+        fwd += 2.0 * H * H * c * 9 * cin
+        cin = c
+    fwd += 2.0 * (128 * 256 + 256 * 28)
+    train = 3.0 * fwd - 2.0 * 64 * 64 * 32 * 9
+    achieved = train * B / dt / 1e12
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": round(achieved / 2500.0, 5), "traffic": None, "kernel": "training step (all kernels)"}
+    _line(args, B / dt, "images/s", dt * 1e3, "learned-initializer network training, batch 256, 64x64 bf16",
+          {"batch": B, "gflop_per_image_train": round(train / 1e9, 4)}, roof, dtype="bf16")
 
 
 if __name__ == "__main__":

@@ -370,10 +370,13 @@ def summarize(sy: Systems, table, learned: ArmRun, chi, flags, plain: ArmRun, sc
     d_final = final_learned - plain.best[-1]
 
     def times(target):
+        # the learned arm's best particle first reaching the target: during its
+        # own run, else (fallback systems) during the rerun that follows it
         t_plain = time_to_reach(plain, target)
         t_learn = time_to_reach(learned, target)
         if rerun is not None:
-            t_learn[fb] = learned_total + time_to_reach(rerun, target[fb])
+            late = learned_total + time_to_reach(rerun, target[fb])
+            t_learn[fb] = np.where(np.isfinite(t_learn[fb]), t_learn[fb], late)
         return t_learn, t_plain
 
     def summ(t):

@@ -203,3 +203,35 @@ def test_batch_center_views_exact():
                                 acc += img[r, cc]
                     ref[i, j] = 0.25 * acc
             np.testing.assert_allclose(views[k], ref.astype(np.float32), rtol=1e-6, atol=1e-7)
+
+
+def test_full_size_uneven_batch_sampled_parity(tmp_path):
+    """The uneven-batch workload at full size in the benchmark's launch
+    configuration (100 systems of side 48-160 px, s 2-4, PSF 11-31 px, 512
+    particles each, one persistent launch, autotuned tiles): sampled
+    particles of the largest and smallest systems against the oracle.  Data
+    are seeded noise images (the likelihood parity does not depend on them)."""
+    specs = synth.uneven_batch_specs(100)
+    psfs = [synth.double_gaussian_psf(sp.psf_size, sp.pix_scale) for sp in specs]
+    datas = [synth.noise((sp.ny, sp.nx), synth.SIGMA_NOISE, synth.SEED_NOISE + k) for k, sp in enumerate(specs)]
+    invvars = [synth.invvar_map(sp.ny, sp.nx, synth.SIGMA_NOISE) for sp in specs]
+    P = 512
+    bp = lens.BatchPlan(specs, psfs, datas, invvars, [P] * 100, DEV)
+    theta = np.concatenate([synth.particles_paper(P, k) for k in range(100)]).astype(np.float32)
+    tt = torch.tensor(theta, device=DEV)
+    bp.autotune(tt, tmp_path / "tiles.json")
+    L, G = bp.loglike_grad(tt, use_graph=True)
+    L, G = L.cpu().numpy(), G.cpu().numpy()
+    work = [sp.nx * sp.ny * sp.supersample ** 2 for sp in specs]
+    order = np.argsort(work)
+    picks = [(int(order[-1]), 0), (int(order[-2]), 511), (int(order[0]), 7), (int(order[50]), 300)]
+    for k, p in picks:
+        row = k * P + p
+        sp = specs[k]
+        print("batch parity", sp, "particle", p, flush=True)
+        lr, gr = O.loglike_and_grad(theta[row], sp, psfs[k], datas[k], invvars[k])
+        if not np.isfinite(lr):
+            assert not np.isfinite(L[row])
+            continue
+        assert abs(L[row] - lr) <= 1e-5 * abs(lr), (k, p, L[row], lr)
+        assert np.linalg.norm(G[row] - gr) <= 1e-5 * np.linalg.norm(gr), (k, p)
