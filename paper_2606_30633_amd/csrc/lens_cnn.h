@@ -16,6 +16,13 @@ constexpr int CNN_NT = 14;       // regressed parameters
 constexpr int CNN_OUT = 2 * CNN_NT;   // means + log-variances
 constexpr int CNN_MAXD = 64;
 
+// K-splits of a weight-gradient GEMM over K output positions: about 64 K steps
+// of 32 per split (so that small outputs still fill the GPU), at most 1024.
+inline int wgrad_splits(long long K) {
+    const long long s = K / 2048;
+    return (int)(s < 1 ? 1 : (s > 1024 ? 1024 : s));
+}
+
 struct CnnLayer {
     int cin, cout, stride;
     long long w_off, b_off;   // offsets into the flat parameter vector

@@ -31,10 +31,17 @@ __device__ __forceinline__ bf16x8 zero8() {
 }
 
 // ---------------------------------------------------------------------------
-// Generic BF16 MFMA GEMM.  Op provides:
-//   bf16x8 loadA(int m, int k, int kend) : A(m, k..k+7), zero where m >= M or k >= kend
-//   bf16x8 loadB(int k, int n, int kend) : B(k..k+7, n), zero where n >= N or k >= kend
-//   void   store(int m, int n, float v, int split)
+// Generic BF16 MFMA GEMM.  Each operand is read either along K (row-major
+// A[m][k], column-major B[k][n]: 8 consecutive k per 16-byte load) or, in
+// "K-major" mode, along M (resp. N): 8 consecutive m at one k, transposed
+// into the LDS tile as they are stored.  Op provides, per operand:
+//   A along K: bf16x8 loadA(int m, int k, int kend)  -> A(m, k..k+7)
+//   A K-major: bf16x8 loadAT(int k, int m)           -> A(m..m+7, k)
+//   B along K: bf16x8 loadB(int k, int n, int kend)  -> B(k..k+7, n)
+//   B K-major: bf16x8 loadBT(int k, int n)           -> B(k, n..n+7)
+// (zero outside the matrix; K-major loads are called only for k < kend),
+// constexpr bool A_KMAJOR, B_KMAJOR, and void store(int m, int n, float v,
+// int split).
 // ---------------------------------------------------------------------------
 constexpr int GT = 64;    // output tile (M and N)
 constexpr int GK = 32;    // K step
@@ -54,13 +61,32 @@ __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // along-K loads: row t/4, k offset 8 (t%4); K-major loads: k t%32, rows 8 (t/32)
     const int lr = t >> 2, lk = (t & 3) * 8;
+    const int tk = t & 31, tr = (t >> 5) * 8;
     for (int k0 = kbeg; k0 < kend; k0 += GK) {
-        const bf16x8 av = (m0 + lr < M) ? op.loadA(m0 + lr, k0 + lk, kend) : zero8();
-        const bf16x8 bv = (n0 + lr < N) ? op.loadB(k0 + lk, n0 + lr, kend) : zero8();
+        bf16x8 av, bv;
+        if constexpr (Op::A_KMAJOR)
+            av = (k0 + tk < kend) ? op.loadAT(k0 + tk, m0 + tr) : zero8();
+        else
+            av = (m0 + lr < M) ? op.loadA(m0 + lr, k0 + lk, kend) : zero8();
+        if constexpr (Op::B_KMAJOR)
+            bv = (k0 + tk < kend) ? op.loadBT(k0 + tk, n0 + tr) : zero8();
+        else
+            bv = (n0 + lr < N) ? op.loadB(k0 + lk, n0 + lr, kend) : zero8();
         __syncthreads();
-        *reinterpret_cast<bf16x8*>(&As[lr][lk]) = av;
-        *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = bv;
+        if constexpr (Op::A_KMAJOR) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[tr + i][tk] = av[i];
+        } else {
+            *reinterpret_cast<bf16x8*>(&As[lr][lk]) = av;
+        }
+        if constexpr (Op::B_KMAJOR) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[tr + i][tk] = bv[i];
+        } else {
+            *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = bv;
+        }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -86,121 +112,135 @@ __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_
 
 // ---------------------------------------------------------------------------
 // Operand maps.  NHWC activations; conv weights W[co][ky][kx][ci] (row co of
-// length 9*Cin); fully connected W[out][in].
+// length 9*Cin); fully connected W[out][in].  Every spatial size and channel
+// count of the network is a power of two: index arithmetic uses shifts.
 // ---------------------------------------------------------------------------
 struct ConvShape {
     int B, H, W, Cin, Ho, Wo, Cout, stride;
+    int lW, lWo, lCin, lCout;   // log2 of W, Wo, Cin, Cout
 };
 
+__host__ __device__ inline int ilog2(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+
+inline ConvShape conv_shape(int B, int H, int Cin, int Ho, int Cout, int stride) {
+    return ConvShape{B, H, H, Cin, Ho, Ho, Cout, stride, ilog2(H), ilog2(Ho), ilog2(Cin), ilog2(Cout)};
+}
+
+__device__ __forceinline__ int div3(int tap) { return (tap * 11) >> 5; }   // tap in [0, 9)
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
 // forward: out[b,y,x,co] = relu(sum in[b, s y + ky - 1, s x + kx - 1, ci] W[co,ky,kx,ci] + bias)
+// A(m = (b, y, x), k = (tap, ci)) along K; B(k, n = co) = W[co][k] along K.
 struct OpConvFwd {
+    static constexpr bool A_KMAJOR = false, B_KMAJOR = false;
     ConvShape s;
     const __bf16* in;
     const __bf16* w;
     const float* bias;
     __bf16* out;
     __device__ bf16x8 loadA(int m, int k, int kend) const {
-        const int hw = s.Ho * s.Wo;
-        const int b = m / hw, r = m - b * hw, y = r / s.Wo, x = r - y * s.Wo;
+        const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
+        const int y = r >> s.lWo, x = r & (s.Wo - 1);
         bf16x8 v = zero8();
-        if (s.Cin % 8 == 0) {
+        if (s.Cin >= 8) {
             if (k >= kend) return v;
-            const int tap = k / s.Cin, ci = k - tap * s.Cin;
-            const int iy = y * s.stride + tap / 3 - 1, ix = x * s.stride + tap % 3 - 1;
+            const int tap = k >> s.lCin, ci = k & (s.Cin - 1), ky = div3(tap);
+            const int iy = y * s.stride + ky - 1, ix = x * s.stride + (tap - 3 * ky) - 1;
             if (iy < 0 || iy >= s.H || ix < 0 || ix >= s.W) return v;
-            return *reinterpret_cast<const bf16x8*>(in + ((size_t)(b * s.H + iy) * s.W + ix) * s.Cin + ci);
+            return ld8(in + ((((size_t)b << s.lW) + iy) << s.lW) * s.Cin + ((size_t)ix << s.lCin) + ci);
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int kk = k + q;
-            if (kk >= kend) break;
-            const int tap = kk / s.Cin, ci = kk - tap * s.Cin;
-            const int iy = y * s.stride + tap / 3 - 1, ix = x * s.stride + tap % 3 - 1;
-            if (iy >= 0 && iy < s.H && ix >= 0 && ix < s.W)
-                v[q] = in[((size_t)(b * s.H + iy) * s.W + ix) * s.Cin + ci];
+        for (int q = 0; q < 8; ++q) {   // Cin = 1 (first layer): k is the tap
+            const int tap = k + q;
+            if (tap >= kend) break;
+            const int ky = div3(tap);
+            const int iy = y * s.stride + ky - 1, ix = x * s.stride + (tap - 3 * ky) - 1;
+            if (iy >= 0 && iy < s.H && ix >= 0 && ix < s.W) v[q] = in[(((size_t)b << s.lW) + iy) * s.W + ix];
         }
         return v;
     }
     __device__ bf16x8 loadB(int k, int n, int kend) const {
         const int KK = 9 * s.Cin;
+        if (s.Cin >= 8) return k < kend ? ld8(w + (size_t)n * KK + k) : zero8();
         bf16x8 v = zero8();
-        if (KK % 8 == 0 && k + 8 <= kend) return *reinterpret_cast<const bf16x8*>(w + (size_t)n * KK + k);
 #pragma unroll
         for (int q = 0; q < 8; ++q)
             if (k + q < kend) v[q] = w[(size_t)n * KK + k + q];
         return v;
     }
     __device__ void store(int m, int n, float v, int) const {
-        out[(size_t)m * s.Cout + n] = to_bf16(fmaxf(v + bias[n], 0.0f));
+        out[((size_t)m << s.lCout) + n] = to_bf16(fmaxf(v + bias[n], 0.0f));
     }
 };
 
 // data gradient: dX[b,iy,ix,ci] = sum dZ[b,y,x,co] W[co,ky,kx,ci] over iy = s y + ky - 1,
-// then multiplied by the ReLU mask of the layer input (prev > 0) -> dZ of the previous layer
+// times the ReLU mask of the layer input (prev > 0) -> dZ of the previous layer.
+// A(m = (b, iy, ix), k = (tap, co)) = dZ[b, y, x, co] along K (Cout >= 8);
+// B(k = (tap, co), n = ci) = W[co][tap][ci]: K-major.
 struct OpConvDgrad {
+    static constexpr bool A_KMAJOR = false, B_KMAJOR = true;
     ConvShape s;
     const __bf16* dz;     // [B][Ho][Wo][Cout]
     const __bf16* w;
     const __bf16* prev;   // layer input (the previous layer's ReLU output)
     __bf16* dprev;        // [B][H][W][Cin]
     __device__ bf16x8 loadA(int m, int k, int kend) const {
-        const int hw = s.H * s.W;
-        const int b = m / hw, r = m - b * hw, iy = r / s.W, ix = r - iy * s.W;
-        bf16x8 v = zero8();
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int kk = k + q;
-            if (kk >= kend) break;
-            const int tap = kk / s.Cout, co = kk - tap * s.Cout;
-            const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
-            if (ty < 0 || tx < 0 || ty % s.stride || tx % s.stride) continue;
-            const int y = ty / s.stride, x = tx / s.stride;
-            if (y < s.Ho && x < s.Wo) v[q] = dz[((size_t)(b * s.Ho + y) * s.Wo + x) * s.Cout + co];
-        }
-        return v;
+        const int b = m >> (2 * s.lW), r = m & ((1 << (2 * s.lW)) - 1);
+        const int iy = r >> s.lW, ix = r & (s.W - 1);
+        if (k >= kend) return zero8();
+        const int tap = k >> s.lCout, co = k & (s.Cout - 1), ky = div3(tap);
+        const int ty = iy + 1 - ky, tx = ix + 1 - (tap - 3 * ky);
+        if (ty < 0 || tx < 0 || (ty & (s.stride - 1)) || (tx & (s.stride - 1))) return zero8();
+        const int y = ty >> (s.stride - 1), x = tx >> (s.stride - 1);   // stride 1 or 2
+        if (y >= s.Ho || x >= s.Wo) return zero8();
+        return ld8(dz + ((((size_t)b << s.lWo) + y) << s.lWo) * s.Cout + ((size_t)x << s.lCout) + co);
     }
-    __device__ bf16x8 loadB(int k, int n, int kend) const {
-        bf16x8 v = zero8();
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int kk = k + q;
-            if (kk >= kend) break;
-            const int tap = kk / s.Cout, co = kk - tap * s.Cout;
-            v[q] = w[(size_t)co * 9 * s.Cin + tap * s.Cin + n];
-        }
-        return v;
+    __device__ bf16x8 loadBT(int k, int n) const {
+        if (n >= s.Cin) return zero8();
+        const int tap = k >> s.lCout, co = k & (s.Cout - 1);
+        return ld8(w + (size_t)co * 9 * s.Cin + ((size_t)tap << s.lCin) + n);
     }
     __device__ void store(int m, int n, float v, int) const {
-        const size_t q = (size_t)m * s.Cin + n;
+        const size_t q = ((size_t)m << s.lCin) + n;
         dprev[q] = to_bf16(from_bf16(prev[q]) > 0.0f ? v : 0.0f);
     }
 };
 
-// weight gradient (split over K = B*Ho*Wo): dW[co][tap*Cin+ci] partial per split
+// weight gradient (split over K = B*Ho*Wo): dW[co][tap*Cin+ci] partial per split.
+// A(m = co, k = pos) = dZ[pos][co]: K-major; B(k = pos, n = (tap, ci)) =
+// in[b, s y + ky - 1, s x + kx - 1, ci]: K-major when Cin >= 8, else gathered.
 struct OpConvWgrad {
+    static constexpr bool A_KMAJOR = true, B_KMAJOR = true;
     ConvShape s;
     const __bf16* dz;   // [B*Ho*Wo][Cout]
     const __bf16* in;   // layer input [B][H][W][Cin]
     float* part;        // [splits][Cout][9*Cin]
-    __device__ bf16x8 loadA(int m, int k, int kend) const {
-        bf16x8 v = zero8();
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < kend) v[q] = dz[(size_t)(k + q) * s.Cout + m];
-        return v;
+    __device__ bf16x8 loadAT(int k, int m) const {
+        return m < s.Cout ? ld8(dz + ((size_t)k << s.lCout) + m) : zero8();
     }
-    __device__ bf16x8 loadB(int k, int n, int kend) const {
-        const int tap = n / s.Cin, ci = n - tap * s.Cin, ky = tap / 3, kx = tap % 3;
-        const int hw = s.Ho * s.Wo;
+    __device__ bf16x8 loadBT(int k, int n) const {
+        const int b = k >> (2 * s.lWo), r = k & ((1 << (2 * s.lWo)) - 1);
+        const int y = r >> s.lWo, x = r & (s.Wo - 1);
         bf16x8 v = zero8();
+        if (s.Cin >= 8) {
+            if (n >= 9 * s.Cin) return v;
+            const int tap = n >> s.lCin, ci = n & (s.Cin - 1), ky = div3(tap);
+            const int iy = y * s.stride + ky - 1, ix = x * s.stride + (tap - 3 * ky) - 1;
+            if (iy < 0 || iy >= s.H || ix < 0 || ix >= s.W) return v;
+            return ld8(in + ((((size_t)b << s.lW) + iy) << s.lW) * s.Cin + ((size_t)ix << s.lCin) + ci);
+        }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int kk = k + q;
-            if (kk >= kend) break;
-            const int b = kk / hw, r = kk - b * hw, y = r / s.Wo, x = r - y * s.Wo;
-            const int iy = y * s.stride + ky - 1, ix = x * s.stride + kx - 1;
-            if (iy >= 0 && iy < s.H && ix >= 0 && ix < s.W)
-                v[q] = in[((size_t)(b * s.H + iy) * s.W + ix) * s.Cin + ci];
+        for (int q = 0; q < 8; ++q) {   // Cin = 1: n is the tap
+            const int tap = n + q;
+            if (tap >= 9) break;
+            const int ky = div3(tap);
+            const int iy = y * s.stride + ky - 1, ix = x * s.stride + (tap - 3 * ky) - 1;
+            if (iy >= 0 && iy < s.H && ix >= 0 && ix < s.W) v[q] = in[(((size_t)b << s.lW) + iy) * s.W + ix];
         }
         return v;
     }
@@ -211,6 +251,7 @@ struct OpConvWgrad {
 
 // fully connected forward: y[b][n] = act(sum_k x[b][k] W[n][k] + bias[n])
 struct OpFcFwd {
+    static constexpr bool A_KMAJOR = false, B_KMAJOR = false;
     int In, Out, relu;
     const __bf16* x;
     const __bf16* w;
@@ -218,20 +259,10 @@ struct OpFcFwd {
     __bf16* ybf;     // bf16 output (hidden layer) or null
     float* yf;       // fp32 output (final layer) or null
     __device__ bf16x8 loadA(int m, int k, int kend) const {
-        bf16x8 v = zero8();
-        if (In % 8 == 0 && k + 8 <= kend) return *reinterpret_cast<const bf16x8*>(x + (size_t)m * In + k);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < kend) v[q] = x[(size_t)m * In + k + q];
-        return v;
+        return k < kend ? ld8(x + (size_t)m * In + k) : zero8();
     }
     __device__ bf16x8 loadB(int k, int n, int kend) const {
-        bf16x8 v = zero8();
-        if (In % 8 == 0 && k + 8 <= kend) return *reinterpret_cast<const bf16x8*>(w + (size_t)n * In + k);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < kend) v[q] = w[(size_t)n * In + k + q];
-        return v;
+        return k < kend ? ld8(w + (size_t)n * In + k) : zero8();
     }
     __device__ void store(int m, int n, float v, int) const {
         float y = v + bias[n];
@@ -242,8 +273,10 @@ struct OpFcFwd {
 };
 
 // fully connected data gradient: dx[b][k] = sum_n dy[b][n] W[n][k], masked by x > 0
-// (mask_src null: no mask, output fp32)
+// (mask_src null: no mask, output fp32).  A(m = b, k = out) = dy[b][out]
+// along K; B(k = out, n = in) = W[out][in]: K-major.
 struct OpFcDgrad {
+    static constexpr bool A_KMAJOR = false, B_KMAJOR = true;
     int In, Out;
     const __bf16* dy;     // [B][Out]
     const __bf16* w;      // [Out][In]
@@ -252,18 +285,13 @@ struct OpFcDgrad {
     float* dxf;
     __device__ bf16x8 loadA(int m, int k, int kend) const {
         bf16x8 v = zero8();
+        if ((Out & 7) == 0) return k < kend ? ld8(dy + (size_t)m * Out + k) : v;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
             if (k + q < kend) v[q] = dy[(size_t)m * Out + k + q];
         return v;
     }
-    __device__ bf16x8 loadB(int k, int n, int kend) const {
-        bf16x8 v = zero8();
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < kend) v[q] = w[(size_t)(k + q) * In + n];
-        return v;
-    }
+    __device__ bf16x8 loadBT(int k, int n) const { return n < In ? ld8(w + (size_t)k * In + n) : zero8(); }
     __device__ void store(int m, int n, float v, int) const {
         const size_t q = (size_t)m * In + n;
         if (mask_src && !(from_bf16(mask_src[q]) > 0.0f)) v = 0.0f;
@@ -272,26 +300,23 @@ struct OpFcDgrad {
     }
 };
 
-// fully connected weight gradient: dW[n][k] = sum_b dy[b][n] x[b][k]
+// fully connected weight gradient: dW[n][k] = sum_b dy[b][n] x[b][k].
+// A(m = out, k = b) = dy[b][out], B(k = b, n = in) = x[b][in]: both K-major.
 struct OpFcWgrad {
+    static constexpr bool A_KMAJOR = true, B_KMAJOR = true;
     int In, Out;
     const __bf16* dy;   // [B][Out]
     const __bf16* x;    // [B][In]
     float* dw;          // [Out][In]
-    __device__ bf16x8 loadA(int m, int k, int kend) const {
+    __device__ bf16x8 loadAT(int k, int m) const {
         bf16x8 v = zero8();
+        if ((Out & 7) == 0) return m < Out ? ld8(dy + (size_t)k * Out + m) : v;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            if (k + q < kend) v[q] = dy[(size_t)(k + q) * Out + m];
+            if (m + q < Out) v[q] = dy[(size_t)k * Out + m + q];
         return v;
     }
-    __device__ bf16x8 loadB(int k, int n, int kend) const {
-        bf16x8 v = zero8();
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k + q < kend) v[q] = x[(size_t)(k + q) * In + n];
-        return v;
-    }
+    __device__ bf16x8 loadBT(int k, int n) const { return n < In ? ld8(x + (size_t)k * In + n) : zero8(); }
     __device__ void store(int m, int n, float v, int) const { dw[(size_t)m * In + n] = v; }
 };
 
@@ -321,6 +346,20 @@ __global__ void k_sum_splits(int nz, long long n, const float* __restrict__ part
     out[i] = (float)s;
 }
 
+// The same with one wave per output (many splits, few outputs): lane l sums
+// splits l, l + 64, ...; the lanes are then combined by a fixed butterfly.
+__global__ __launch_bounds__(256) void k_sum_splits_wave(int nz, long long n, const float* __restrict__ part,
+                                                         float* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int z = lane; z < nz; z += 64) s += part[(size_t)z * n + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[i] = (float)s;
+}
+
 // column sums of a bf16 matrix [rows][cols] (bias gradients), fixed order:
 // stage 1 partial[chunk][col], stage 2 sums the chunks.
 __global__ void k_colsum_partial(int rows, int cols, int rows_per_chunk, const __bf16* __restrict__ x,
@@ -339,12 +378,48 @@ __global__ void k_colsum_partial(int rows, int cols, int rows_per_chunk, const _
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-__global__ void k_colsum_final(int chunks, int cols, const double* __restrict__ part, float* __restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// The same for cols a multiple of 8 (<= 2048), read row-major 16 bytes per
+// thread (coalesced): thread t sums column group t % (cols/8) over rows
+// t / (cols/8), + 256/(cols/8), ...; the per-thread sums are combined in LDS
+// in fixed order.
+__global__ __launch_bounds__(256) void k_colsum8_partial(int rows, int cols, int rows_per_chunk,
+                                                         const __bf16* __restrict__ x, double* __restrict__ part) {
+    __shared__ double red[2048];
+    const int g = cols >> 3, per = 256 / g;
+    const int t = threadIdx.x, cg = t % g, ro = t / g;
+    const int r0 = blockIdx.x * rows_per_chunk, r1 = min(rows, r0 + rows_per_chunk);
+    double acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+    if (ro < per)
+        for (int r = r0 + ro; r < r1; r += per) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(x + (size_t)r * cols + cg * 8);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] += (double)from_bf16(v[i]);
+        }
+    if (ro < per)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[ro * cols + cg * 8 + i] = acc[i];
+    __syncthreads();
+    for (int c = t; c < cols; c += 256) {
+        double sum = 0.0;
+        for (int q = 0; q < per; ++q) sum += red[q * cols + c];
+        part[(size_t)blockIdx.x * cols + c] = sum;
+    }
+}
+
+// out[c] = sum over chunks of part[chunk][c]: one wave per column, lane l
+// sums chunks l, l + 64, ..., then a fixed butterfly combines the lanes.
+__global__ __launch_bounds__(256) void k_colsum_final(int chunks, int cols, const double* __restrict__ part,
+                                                      float* __restrict__ out) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (c >= cols) return;
     double s = 0.0;
-    for (int z = 0; z < chunks; ++z) s += part[(size_t)z * cols + c];
-    out[c] = (float)s;
+    for (int z = lane; z < chunks; z += 64) s += part[(size_t)z * cols + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[c] = (float)s;
 }
 
 // global average pool over HxW of a [B][H][W][C] bf16 tensor -> bf16 [B][C]
@@ -533,7 +608,7 @@ hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st) {
     int H = CNN_IN;
     for (int l = 0; l < CNN_CONV; ++l) {
         const CnnLayer& L = net.conv[l];
-        ConvShape s{B, H, H, L.cin, H / L.stride, H / L.stride, L.cout, L.stride};
+        const ConvShape s = conv_shape(B, H, L.cin, H / L.stride, L.cout, L.stride);
         OpConvFwd op{s, x, net.wbf + L.w_off, net.params + L.b_off, net.act[l]};
         if (gemm(op, B * s.Ho * s.Wo, L.cout, 9 * L.cin, 1, st) != hipSuccess) return hipErrorLaunchFailure;
         x = net.act[l];
@@ -549,11 +624,15 @@ hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st) {
 
 // bias gradient = column sums of dz [rows][cols]
 static hipError_t bias_grad(CnnNet& net, int rows, int cols, const __bf16* dz, float* db, hipStream_t st) {
-    const int rpc = 4096;
+    // chunks of rows_per_chunk rows: about 1 KB of a column group per thread
+    const int rpc = (cols & 7) == 0 && cols <= 2048 ? 1024 : 4096;
     const int chunks = (rows + rpc - 1) / rpc;
-    hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 63) / 64, chunks), dim3(256), 0, st, rows, cols, rpc, dz,
-                       net.colpart);
-    hipLaunchKernelGGL(k_colsum_final, g1(cols, 128), dim3(128), 0, st, chunks, cols, net.colpart, db);
+    if ((cols & 7) == 0 && cols <= 2048)
+        hipLaunchKernelGGL(k_colsum8_partial, dim3(chunks), dim3(256), 0, st, rows, cols, rpc, dz, net.colpart);
+    else
+        hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 63) / 64, chunks), dim3(256), 0, st, rows, cols, rpc, dz,
+                           net.colpart);
+    hipLaunchKernelGGL(k_colsum_final, dim3((cols + 3) / 4), dim3(256), 0, st, chunks, cols, net.colpart, db);
     return hipGetLastError();
 }
 
@@ -581,14 +660,18 @@ hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* targ
     for (int l = CNN_CONV - 1; l >= 0; --l) {
         const CnnLayer& L = net.conv[l];
         const int H = Hout * L.stride;
-        ConvShape s{B, H, H, L.cin, Hout, Hout, L.cout, L.stride};
+        const ConvShape s = conv_shape(B, H, L.cin, Hout, L.cout, L.stride);
         const __bf16* in = l == 0 ? img : net.act[l - 1];
         const int K = B * Hout * Hout;
-        const int splits = gemm_splits(L.cout, 9 * L.cin, K, 32);
+        const int splits = gemm_splits(L.cout, 9 * L.cin, K, wgrad_splits(K));
         OpConvWgrad wg{s, net.dact[l], in, net.wpart};
-        if (gemm(wg, L.cout, 9 * L.cin, K, 32, st) != hipSuccess) return hipErrorLaunchFailure;
+        if (gemm(wg, L.cout, 9 * L.cin, K, wgrad_splits(K), st) != hipSuccess) return hipErrorLaunchFailure;
         const long long nw = (long long)L.cout * 9 * L.cin;
-        hipLaunchKernelGGL(k_sum_splits, g1(nw), dim3(256), 0, st, splits, nw, net.wpart, net.grads + L.w_off);
+        if (splits >= 64)
+            hipLaunchKernelGGL(k_sum_splits_wave, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, st, splits, nw,
+                               net.wpart, net.grads + L.w_off);
+        else
+            hipLaunchKernelGGL(k_sum_splits, g1(nw), dim3(256), 0, st, splits, nw, net.wpart, net.grads + L.w_off);
         if (bias_grad(net, K, L.cout, net.dact[l], net.grads + L.b_off, st) != hipSuccess) return hipErrorLaunchFailure;
         if (l > 0) {
             OpConvDgrad dg{s, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};

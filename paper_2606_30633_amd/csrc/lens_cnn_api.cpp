@@ -85,7 +85,7 @@ lens_status lens_cnn_create(int32_t max_batch, uint64_t seed, lens_cnn** out) {
         H /= kStrides[l];
         const size_t sz = B * H * H * kChannels[l];
         ok = alloc(&n.act[l], sz) && alloc(&n.dact[l], sz);
-        const size_t w = (size_t)32 * n.conv[l].cout * 9 * n.conv[l].cin;
+        const size_t w = (size_t)wgrad_splits((long long)B * H * H) * n.conv[l].cout * 9 * n.conv[l].cin;
         wpart = w > wpart ? w : wpart;
     }
     ok = ok && alloc(&n.pooled, B * CNN_C6) && alloc(&n.dpooled, B * CNN_C6) && alloc(&n.hidden, B * CNN_H1) &&

@@ -82,7 +82,10 @@ def test_prepare_transform_matches_oracle():
 def test_training_reduces_loss():
     """Targets are translation-invariant image statistics (offset and noise
     scale), which the pooled network can learn: the loss must fall well
-    below its starting value within 300 Adam steps."""
+    below its starting value within 300 Adam steps.  The learning rate
+    decays (1e-3 to 1e-5) so that the end point is a converged state: at a
+    constant rate the loss oscillates by several units and where it stops
+    depends on rounding order."""
     B, N = 64, 512
     rng = np.random.default_rng(4)
     m = rng.uniform(-1, 1, N)
@@ -95,10 +98,10 @@ def test_training_reduces_loss():
     first = net.loss_grad(x[:B], t[:B])[0].item()
     for it in range(300):
         i = (it * B) % N
-        loss = net.train_step(x[i:i + B], t[i:i + B], 1e-3)
+        loss = net.train_step(x[i:i + B], t[i:i + B], 1e-3 * 0.01 ** (it / 299))
         assert math.isfinite(loss.item())
     last = np.mean([net.loss_grad(x[i:i + B], t[i:i + B])[0].item() for i in range(0, N, B)])
-    assert last < first - 4.0, (first, last)
+    assert last < first - 6.0, (first, last)
 
 
 def _center_scale(row):
