@@ -44,9 +44,61 @@ __device__ __forceinline__ bf16x8 zero8() {
 // int split).
 // ---------------------------------------------------------------------------
 constexpr int GT = 64;    // output tile (M and N)
-constexpr int GK = 32;    // K step
-constexpr int LDSK = 40;  // padded LDS row (bf16)
+constexpr int GK = 64;    // K per stage (two MFMA K-steps of 32)
+constexpr int LDSK = 72;  // padded LDS row (bf16)
 
+// Loads of one stage into registers: along K, thread t covers row t/4 at
+// k offsets 8 (t%4) and 32 + 8 (t%4); K-major, k t%64 at rows 8 (t/64) and
+// 32 + 8 (t/64).
+template <class Op>
+struct StageRegs {
+    bf16x8 a[2], b[2];
+};
+
+template <class Op>
+__device__ __forceinline__ void load_stage(const Op& op, StageRegs<Op>& r, int m0, int n0, int k0, int kend, int M,
+                                           int N) {
+    const int t = threadIdx.x;
+    const int lr = t >> 2, lk = (t & 3) * 8;
+    const int tk = t & 63, tr = (t >> 6) * 8;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if constexpr (Op::A_KMAJOR)
+            r.a[h] = (k0 + tk < kend) ? op.loadAT(k0 + tk, m0 + tr + 32 * h) : zero8();
+        else
+            r.a[h] = (m0 + lr < M) ? op.loadA(m0 + lr, k0 + lk + 32 * h, kend) : zero8();
+        if constexpr (Op::B_KMAJOR)
+            r.b[h] = (k0 + tk < kend) ? op.loadBT(k0 + tk, n0 + tr + 32 * h) : zero8();
+        else
+            r.b[h] = (n0 + lr < N) ? op.loadB(k0 + lk + 32 * h, n0 + lr, kend) : zero8();
+    }
+}
+
+template <class Op>
+__device__ __forceinline__ void store_stage(const StageRegs<Op>& r, __bf16 (*As)[LDSK], __bf16 (*Bs)[LDSK]) {
+    const int t = threadIdx.x;
+    const int lr = t >> 2, lk = (t & 3) * 8;
+    const int tk = t & 63, tr = (t >> 6) * 8;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if constexpr (Op::A_KMAJOR) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[tr + 32 * h + i][tk] = r.a[h][i];
+        } else {
+            *reinterpret_cast<bf16x8*>(&As[lr][lk + 32 * h]) = r.a[h];
+        }
+        if constexpr (Op::B_KMAJOR) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[tr + 32 * h + i][tk] = r.b[h][i];
+        } else {
+            *reinterpret_cast<bf16x8*>(&Bs[lr][lk + 32 * h]) = r.b[h];
+        }
+    }
+}
+
+// C[M][N] over K in [blockIdx.z * k_per_split, ...): 64 x 64 tile per
+// 256-thread work-group, each wave 32 x 32 (2 x 2 MFMA 16x16x32 tiles).  The
+// next stage's global loads are issued before the current stage's MFMAs.
 template <class Op>
 __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_per_split) {
     __shared__ __attribute__((aligned(16))) __bf16 As[GT][LDSK];
@@ -61,40 +113,25 @@ __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // along-K loads: row t/4, k offset 8 (t%4); K-major loads: k t%32, rows 8 (t/32)
-    const int lr = t >> 2, lk = (t & 3) * 8;
-    const int tk = t & 31, tr = (t >> 5) * 8;
+    StageRegs<Op> r;
+    if (kbeg < kend) load_stage(op, r, m0, n0, kbeg, kend, M, N);
     for (int k0 = kbeg; k0 < kend; k0 += GK) {
-        bf16x8 av, bv;
-        if constexpr (Op::A_KMAJOR)
-            av = (k0 + tk < kend) ? op.loadAT(k0 + tk, m0 + tr) : zero8();
-        else
-            av = (m0 + lr < M) ? op.loadA(m0 + lr, k0 + lk, kend) : zero8();
-        if constexpr (Op::B_KMAJOR)
-            bv = (k0 + tk < kend) ? op.loadBT(k0 + tk, n0 + tr) : zero8();
-        else
-            bv = (n0 + lr < N) ? op.loadB(k0 + lk, n0 + lr, kend) : zero8();
         __syncthreads();
-        if constexpr (Op::A_KMAJOR) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) As[tr + i][tk] = av[i];
-        } else {
-            *reinterpret_cast<bf16x8*>(&As[lr][lk]) = av;
-        }
-        if constexpr (Op::B_KMAJOR) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) Bs[tr + i][tk] = bv[i];
-        } else {
-            *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = bv;
-        }
+        store_stage(r, As, Bs);
         __syncthreads();
+        if (k0 + GK < kend) load_stage(op, r, m0, n0, k0 + GK, kend, M, N);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[32 * wm + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+        for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[32 * wn + 16 * j + (lane & 15)][8 * (lane >> 4)]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 a =
+                    *reinterpret_cast<const bf16x8*>(&As[32 * wm + 16 * i + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+                        &Bs[32 * wn + 16 * j + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+                }
             }
         }
     }
@@ -103,10 +140,10 @@ __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + 32 * wm + 16 * i + 4 * (lane >> 4) + r;
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + 32 * wm + 16 * i + 4 * (lane >> 4) + q;
                 const int n = n0 + 32 * wn + 16 * j + (lane & 15);
-                if (m < M && n < N) op.store(m, n, acc[i][j][r], blockIdx.z);
+                if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
             }
 }
 
