@@ -682,7 +682,10 @@ __global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts
 }
 
 template <int MASS, int NL, int NS>
-__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ consts, Geo g, int ppb,
+// Four waves per SIMD (at most 128 VGPRs): measured faster than the three the
+// register demand would otherwise give, with the few spills left outside the
+// sub-pixel loops.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint(const float* __restrict__ consts, Geo g, int ppb,
                                                  const float* __restrict__ gimg,
                                                  double* __restrict__ partial) {
     constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
@@ -946,7 +949,10 @@ __global__ __launch_bounds__(256) void k_batch_render(const BatchSys* __restrict
 }
 
 template <int MASS, int NL, int NS>
-__global__ __launch_bounds__(256) void k_batch_adjoint(const BatchSys* __restrict__ sys,
+// Four waves per SIMD (at most 128 VGPRs): measured faster than the three the
+// register demand would otherwise give, with the few spills left outside the
+// sub-pixel loops.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_adjoint(const BatchSys* __restrict__ sys,
                                                        const WorkItem* __restrict__ items, int n_items,
                                                        int* __restrict__ counter,
                                                        const float* __restrict__ consts,
