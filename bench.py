@@ -75,7 +75,7 @@ def adjoint_flops_per_subpixel(K_s, K_a, NL, NS, epl=True):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload != "map":

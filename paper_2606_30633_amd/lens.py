@@ -96,7 +96,7 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is None:
         if not os.path.exists(path):
-            raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+            raise RuntimeError(f"{path} is not built: build it first (python -m paper_2606_30633_amd.build)")
         lib = ctypes.CDLL(path)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(lib, name, None)

@@ -9,8 +9,8 @@ arrays.
 
 Workload shapes follow the paper's simulated systems (Sec. 4.2, eq. sim-dist:
 EPL + external shear mass, Sersic lens light, Sersic source, supersampling,
-Table 100sysparams) and the five workload configurations documented in
-the design doc.  Every generator takes an explicit seed and uses
+Table 100sysparams): the parity system (60x60, SIE), the 100x100 EPL system
+with two sources, and the uneven batch of 100 systems.  Every generator takes an explicit seed and uses
 ``numpy.random.default_rng``; values are produced in float64 and rounded to
 float32 once, so every consumer sees identical bits.
 """

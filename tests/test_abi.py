@@ -26,7 +26,7 @@ def _declared():
 
 
 def test_library_is_built():
-    assert os.path.exists(lens.LIB_PATH), "run __graft_entry__.build()"
+    assert os.path.exists(lens.LIB_PATH), "liblens.so is not built (python -m paper_2606_30633_amd.build)"
 
 
 def test_every_declared_symbol_is_exported():

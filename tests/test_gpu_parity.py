@@ -1,6 +1,6 @@
 """GPU parity: liblens.so (through the C ABI) against the FP64 oracle.
 
-Tolerances (north-star "1e-5 relative", FP32 GPU vs FP64 oracle), per particle:
+Tolerances (1e-5 relative, FP32 GPU vs FP64 oracle), per particle:
   images   max|dm| <= 1e-5 max|m_ref|
   logL     |dL| <= 1e-5 |L_ref| + B, where B = 2 sum w |d - m| |m| 2^-23 bounds the
            effect of storing the model image in float32 (one ulp) on the
