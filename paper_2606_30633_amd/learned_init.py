@@ -447,7 +447,7 @@ def main(argv=None):
     ap.add_argument("--load", default=None)
     ap.add_argument("--train-images", type=int, default=200000)
     ap.add_argument("--val-images", type=int, default=4096)
-    ap.add_argument("--epochs", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--systems", type=int, default=100)
     ap.add_argument("--learned", type=int, default=512)
