@@ -240,6 +240,15 @@ def test_argument_errors():
     with pytest.raises(lens.LensError) as e:
         lens.lens_loglike(plan, big)
     assert e.value.status == lens.LENS_EINVAL
+    # empty input: zero particles is an argument error on every entry point
+    empty = torch.zeros((0, spec.n_params), device=DEV)
+    for fn in (lens.lens_forward, lens.lens_loglike, lens.lens_loglike_grad):
+        with pytest.raises(lens.LensError) as e:
+            fn(plan, empty)
+        assert e.value.status == lens.LENS_EINVAL
+    # a plan stays usable after rejected calls
+    L = lens.lens_loglike(plan, torch.tensor(th, device=DEV)).cpu().numpy()
+    check_loglike(spec, psf, data, sysm.invvar, th, L)
     big_spec = synth.ModelSpec(256, 256, 0.05, 2, 31, "EPL", 1, 1)
     with pytest.raises(lens.LensError) as e:
         lens.LensPlan(big_spec, np.ones((31, 31), np.float32), np.zeros((256, 256), np.float32),
