@@ -30,6 +30,10 @@
  *    NaN gradient.  A particle with an ellipticity |e| >= 1 on any
  *    component has no valid profile: logL = -inf and gradient 0.
  *  - Functions return a lens_status and never throw.
+ *  - Plans, batch plans and networks own scratch buffers that every call on
+ *    them uses: calls on one object must be ordered (one stream, or
+ *    synchronise between streams); distinct objects may run concurrently.
+ *    An object is used from one host thread at a time.
  *
  * Canonical parameter order (d = n_mass + 7 * (n_lens_light + n_source)):
  *   mass   : theta_E ["], [gamma (EPL only)], e1, e2, x ["], y ["]
