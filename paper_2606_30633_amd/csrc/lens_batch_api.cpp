@@ -31,6 +31,7 @@ struct PsfClass {
     int K = 0;
     int n = 0;
     size_t shm = 0;
+    int nt = 256;   // work-group size
     WorkItem* items = nullptr;
 };
 
@@ -131,16 +132,19 @@ static lens_status rebuild(lens_batch_plan* b) {
     free_classes(b);
     std::map<int, std::vector<WorkItem>> byK;
     std::map<int, size_t> shm;
+    std::map<int, int> strips;
     for (int k = 0; k < b->S; ++k) {
         for (int p = 0; p < b->P[k]; ++p) byK[sys[k].K].push_back({k, p, 0});
         const size_t bytes = (size_t)sys[k].stride * sys[k].rows * sizeof(float);
         shm[sys[k].K] = std::max(shm[sys[k].K], bytes);
+        strips[sys[k].K] = std::max(strips[sys[k].K], psf_strips(sys[k].g));
     }
     for (auto& kv : byK) {
         PsfClass c;
         c.K = kv.first;
         c.n = (int)kv.second.size();
         c.shm = shm[kv.first];
+        c.nt = psf_threads(c.shm, strips[kv.first]);
         if (hipMalloc(&c.items, sizeof(WorkItem) * c.n) != hipSuccess) return LENS_ENOMEM;
         b->classes.push_back(c);
         if (hipMemcpy(c.items, kv.second.data(), sizeof(WorkItem) * c.n, hipMemcpyHostToDevice) !=
@@ -159,7 +163,7 @@ static lens_status enqueue(lens_batch_plan* b, const float* theta, float* logl, 
                             b->consts, b->img, st) != hipSuccess)
         return LENS_EHIP;
     for (const auto& c : b->classes)
-        if (launch_batch_psf(c.K, c.n, b->d_sys, c.items, b->consts, b->img, logl, logl64, c.shm, st) !=
+        if (launch_batch_psf(c.K, c.n, b->d_sys, c.items, b->consts, b->img, logl, logl64, c.shm, c.nt, st) !=
             hipSuccess)
             return LENS_EHIP;
     if (launch_set_int_host(b->d_counter + 1, 0, st) != hipSuccess) return LENS_EHIP;

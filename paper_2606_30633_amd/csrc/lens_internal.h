@@ -131,8 +131,12 @@ hipError_t launch_batch_adjoint(const ModelInfo& mi, int grid, const BatchSys* s
                                 const float* consts, const float* gimg, double* partial,
                                 hipStream_t st);
 hipError_t launch_batch_psf(int K, int n_items, const BatchSys* sys, const WorkItem* items,
-                            const float* consts, float* img, float* logl, double* logl64, size_t shm,
+                            const float* consts, float* img, float* logl, double* logl64, size_t shm, int nt,
                             hipStream_t st);
+// Work-group size (256, 512 or 1024) of the PSF pass for an LDS tile of shm
+// bytes over nstrips row strips; psf_strips counts the strips of an image.
+int psf_threads(size_t shm, int nstrips);
+int psf_strips(const Geo& g);
 hipError_t launch_batch_finalize(const ModelInfo& mi, int N, const BatchSys* sys,
                                  const int* particle_sys, const float* theta, const float* consts,
                                  const double* partial, float* grad, hipStream_t st);

@@ -503,14 +503,18 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum over a 256-thread work-group (fixed order).  red: >= 4 doubles of LDS.
+// Sum over a work-group of NT threads (fixed order).  red: >= NT/64 doubles of LDS.
+template <int NT = 256>
 __device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) red[wv] = v;
     __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
+    double s = red[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) s += red[i];
+    return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -739,7 +743,7 @@ inline void psf_tile(const Geo& g, int K, int& stride, int& rows) {
 // loaded into an LDS tile with a zero halo; mode 0 writes the convolved
 // model to out, modes 1-2 compute chi^2 -> logL, mode 2 also replaces buf by
 // the adjoint image (correlation of the residual w (d - m) with the PSF).
-template <int K, int MODE>
+template <int K, int MODE, int NT>
 __device__ __forceinline__ void psf_body(float valid, const Geo& g, float* buf,
                                          const double* __restrict__ wflip,
                                          const float* __restrict__ wpsf,
@@ -759,16 +763,16 @@ __device__ __forceinline__ void psf_body(float valid, const Geo& g, float* buf,
         return;
     }
     const int total = rows * stride;
-    for (int q = tid; q < total; q += 256) lds[q] = 0.f;
+    for (int q = tid; q < total; q += NT) lds[q] = 0.f;
     __syncthreads();
-    for (int pix = tid; pix < g.npix; pix += 256) {
+    for (int pix = tid; pix < g.npix; pix += NT) {
         const int i = pix / g.nx, j = pix - i * g.nx;
         lds[(i + H) * stride + j + H] = buf[pix];
     }
     __syncthreads();
     const int nsx = (g.nx + RW - 1) / RW, nstrips = nsx * g.ny;
     double chi = 0.0;
-    for (int st = tid; st < nstrips; st += 256) {
+    for (int st = tid; st < nstrips; st += NT) {
         const int i = st / nsx, j0 = (st - i * nsx) * RW;
         double m[RW];
         correlate<K, RW, double>(lds, stride, i, j0, wflip, m);
@@ -792,19 +796,19 @@ __device__ __forceinline__ void psf_body(float valid, const Geo& g, float* buf,
         __syncthreads();
         return;
     }
-    chi = block_sum(chi, red);
+    chi = block_sum<NT>(chi, red);
     if (tid == 0) {
         *logl = (float)(-0.5 * chi);
         if (logl64) *logl64 = -0.5 * chi;
     }
     if (MODE == 2) {
         __syncthreads();
-        for (int pix = tid; pix < g.npix; pix += 256) {
+        for (int pix = tid; pix < g.npix; pix += NT) {
             const int i = pix / g.nx, j = pix - i * g.nx;
             lds[(i + H) * stride + j + H] = buf[pix];
         }
         __syncthreads();
-        for (int st = tid; st < nstrips; st += 256) {
+        for (int st = tid; st < nstrips; st += NT) {
             const int i = st / nsx, j0 = (st - i * nsx) * RW;
             float m[RW];
             correlate<K, RW, float>(lds, stride, i, j0, wpsf, m);
@@ -818,17 +822,17 @@ __device__ __forceinline__ void psf_body(float valid, const Geo& g, float* buf,
     __syncthreads();
 }
 
-template <int K, int MODE>
-__global__ __launch_bounds__(256) void k_psf(const float* __restrict__ consts, Geo g, float* img,
+template <int K, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_psf(const float* __restrict__ consts, Geo g, float* img,
                                              const double* __restrict__ wflip,
                                              const float* __restrict__ wpsf,
                                              const float* __restrict__ data,
                                              const float* __restrict__ invvar, float* out,
                                              float* logl, double* logl64, int stride, int rows) {
     extern __shared__ float4 lds4[];
-    __shared__ double red[4];
+    __shared__ double red[NT / 64];
     const int p = blockIdx.x;
-    psf_body<K, MODE>(consts[(size_t)p * CSTRIDE + C_VALID], g, img + (size_t)p * g.npix, wflip, wpsf,
+    psf_body<K, MODE, NT>(consts[(size_t)p * CSTRIDE + C_VALID], g, img + (size_t)p * g.npix, wflip, wpsf,
                       data, invvar, out ? out + (size_t)p * g.npix : nullptr, logl ? logl + p : nullptr,
                       logl64 ? logl64 + p : nullptr, stride, rows, reinterpret_cast<float*>(lds4), red);
 }
@@ -976,17 +980,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 }
 
 // One work-group per (system, particle) of one PSF size class.
-template <int K>
-__global__ __launch_bounds__(256) void k_batch_psf(const BatchSys* __restrict__ sys,
+template <int K, int NT>
+__global__ __launch_bounds__(NT) void k_batch_psf(const BatchSys* __restrict__ sys,
                                                    const WorkItem* __restrict__ items,
                                                    const float* __restrict__ consts, float* img,
                                                    float* logl, double* logl64) {
     extern __shared__ float4 lds4[];
-    __shared__ double red[4];
+    __shared__ double red[NT / 64];
     const WorkItem w = items[blockIdx.x];
     const BatchSys& S = sys[w.sys];
     const int gp = S.p0 + w.p;
-    psf_body<K, 2>(consts[(size_t)gp * CSTRIDE + C_VALID], S.g, img + S.img_off + (size_t)w.p * S.g.npix,
+    psf_body<K, 2, NT>(consts[(size_t)gp * CSTRIDE + C_VALID], S.g, img + S.img_off + (size_t)w.p * S.g.npix,
                    S.wflip, S.wpsf, S.data, S.invvar, nullptr, logl + gp, logl64 ? logl64 + gp : nullptr,
                    S.stride, S.rows,
                    reinterpret_cast<float*>(lds4), red);
@@ -1078,6 +1082,45 @@ hipError_t launch_adjoint(const ModelInfo& mi, const Geo& g, int P, int ppt, con
     return hipGetLastError();
 }
 
+// Work-group size of the PSF pass: the LDS tile limits the work-groups per
+// CU, so large images get more threads per work-group to keep the SIMDs fed;
+// the score counts resident waves per SIMD (up to 4) times the fraction of
+// threads busy over the image's row strips.
+int psf_threads(size_t shm, int nstrips) {
+    int best = 256;
+    double best_score = -1.0;
+    for (int nt : {256, 512, 1024}) {
+        const int by_lds = shm > 0 ? (int)((160 * 1024) / shm) : 64;
+        const int blocks = std::min(by_lds, 2048 / nt);
+        if (blocks < 1) continue;
+        const int waves = blocks * nt / 256;
+        const int rounds = (nstrips + nt - 1) / nt;
+        const double eff = rounds > 0 ? (double)nstrips / ((double)nt * rounds) : 1.0;
+        const double score = std::min(waves, 4) * eff;
+        if (score > best_score + 1e-9) {
+            best_score = score;
+            best = nt;
+        }
+    }
+    return best;
+}
+
+int psf_strips(const Geo& g) { return ((g.nx + PSF_RW - 1) / PSF_RW) * g.ny; }
+
+template <int K, int MODE, int NT>
+static void launch_psf_kernel(size_t shm, int P, const float* consts, const Geo& g, float* img, const double* wflip,
+                              const float* wpsf, const float* data, const float* invvar, float* out, float* logl,
+                              double* logl64, int stride, int rows, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_psf<K, MODE, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)MAX_LDS_BYTES);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_psf<K, MODE, NT>), dim3(P), dim3(NT), shm, st, consts, g, img, wflip, wpsf, data, invvar,
+                       out, logl, logl64, stride, rows);
+}
+
 template <int K>
 static hipError_t launch_psf_k(const Geo& g, int mode, int P, const float* consts, float* img,
                                const double* wflip, const float* wpsf, const float* data,
@@ -1086,19 +1129,24 @@ static hipError_t launch_psf_k(const Geo& g, int mode, int P, const float* const
     int stride, rows;
     psf_tile(g, K, stride, rows);
     const size_t shm = (size_t)stride * rows * sizeof(float);
-    static bool attr_set[3] = {false, false, false};
-    auto go = [&](auto kern) {
-        if (!attr_set[mode]) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)MAX_LDS_BYTES);
-            attr_set[mode] = true;
-        }
-        hipLaunchKernelGGL(kern, dim3(P), dim3(256), shm, st, consts, g, img, wflip, wpsf, data,
-                           invvar, out, logl, logl64, stride, rows);
-    };
-    if (mode == 0) go(k_psf<K, 0>);
-    else if (mode == 1) go(k_psf<K, 1>);
-    else go(k_psf<K, 2>);
+    if (mode == 0) {
+        launch_psf_kernel<K, 0, 256>(shm, P, consts, g, img, wflip, wpsf, data, invvar, out, logl, logl64, stride,
+                                     rows, st);
+    } else if (mode == 1) {
+        launch_psf_kernel<K, 1, 256>(shm, P, consts, g, img, wflip, wpsf, data, invvar, out, logl, logl64, stride,
+                                     rows, st);
+    } else {
+        const int nt = psf_threads(shm, psf_strips(g));
+        if (nt == 1024)
+            launch_psf_kernel<K, 2, 1024>(shm, P, consts, g, img, wflip, wpsf, data, invvar, out, logl, logl64,
+                                          stride, rows, st);
+        else if (nt == 512)
+            launch_psf_kernel<K, 2, 512>(shm, P, consts, g, img, wflip, wpsf, data, invvar, out, logl, logl64,
+                                         stride, rows, st);
+        else
+            launch_psf_kernel<K, 2, 256>(shm, P, consts, g, img, wflip, wpsf, data, invvar, out, logl, logl64,
+                                         stride, rows, st);
+    }
     return hipGetLastError();
 }
 
@@ -1152,27 +1200,38 @@ hipError_t launch_batch_adjoint(const ModelInfo& mi, int grid, const BatchSys* s
     return hipGetLastError();
 }
 
-template <int K>
-static hipError_t launch_batch_psf_k(int n_items, const BatchSys* sys, const WorkItem* items,
-                                     const float* consts, float* img, float* logl, double* logl64,
-                                     size_t shm, hipStream_t st) {
+template <int K, int NT>
+static void launch_batch_psf_kernel(int n_items, const BatchSys* sys, const WorkItem* items, const float* consts,
+                                    float* img, float* logl, double* logl64, size_t shm, hipStream_t st) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_psf<K>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch_psf<K, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)MAX_LDS_BYTES);
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_batch_psf<K>, dim3(n_items), dim3(256), shm, st, sys, items, consts, img, logl,
+    hipLaunchKernelGGL((k_batch_psf<K, NT>), dim3(n_items), dim3(NT), shm, st, sys, items, consts, img, logl,
                        logl64);
+}
+
+template <int K>
+static hipError_t launch_batch_psf_k(int n_items, const BatchSys* sys, const WorkItem* items,
+                                     const float* consts, float* img, float* logl, double* logl64,
+                                     size_t shm, int nt, hipStream_t st) {
+    if (nt == 1024)
+        launch_batch_psf_kernel<K, 1024>(n_items, sys, items, consts, img, logl, logl64, shm, st);
+    else if (nt == 512)
+        launch_batch_psf_kernel<K, 512>(n_items, sys, items, consts, img, logl, logl64, shm, st);
+    else
+        launch_batch_psf_kernel<K, 256>(n_items, sys, items, consts, img, logl, logl64, shm, st);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_psf(int K, int n_items, const BatchSys* sys, const WorkItem* items,
                             const float* consts, float* img, float* logl, double* logl64,
-                            size_t shm, hipStream_t st) {
+                            size_t shm, int nt, hipStream_t st) {
     switch (K) {
 #define LENS_BPSF_CASE(KK) \
-    case KK: return launch_batch_psf_k<KK>(n_items, sys, items, consts, img, logl, logl64, shm, st);
+    case KK: return launch_batch_psf_k<KK>(n_items, sys, items, consts, img, logl, logl64, shm, nt, st);
         LENS_BPSF_CASE(1) LENS_BPSF_CASE(3) LENS_BPSF_CASE(5) LENS_BPSF_CASE(7) LENS_BPSF_CASE(9)
         LENS_BPSF_CASE(11) LENS_BPSF_CASE(13) LENS_BPSF_CASE(15) LENS_BPSF_CASE(17) LENS_BPSF_CASE(19)
         LENS_BPSF_CASE(21) LENS_BPSF_CASE(23) LENS_BPSF_CASE(25) LENS_BPSF_CASE(27) LENS_BPSF_CASE(29)
