@@ -147,6 +147,113 @@ __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_
             }
 }
 
+// Tall tile for GEMMs with large M (convolution forward and data gradient):
+// 128 x 64 outputs per work-group, wave w computing rows 32 w .. 32 w + 31 of
+// all 64 columns (2 x 4 MFMA tiles), so each B stage feeds twice the rows.
+constexpr int GT2 = 128;
+
+template <class Op>
+struct StageRegs2 {
+    bf16x8 a[4], b[2];
+};
+
+template <class Op>
+__device__ __forceinline__ void load_stage2(const Op& op, StageRegs2<Op>& r, int m0, int n0, int k0, int kend, int M,
+                                            int N) {
+    const int t = threadIdx.x;
+    const int ar = t >> 1, ak = (t & 1) * 32;        // A along K: row t/2, k 32 (t%2) + 8 h
+    const int br = t >> 2, bk = (t & 3) * 8;         // B along K: row t/4, k 8 (t%4) + 32 h
+    const int tk = t & 63, tr = (t >> 6) * 8;        // K-major: k t%64, rows 8 (t/64) + 32 h
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        if constexpr (Op::A_KMAJOR)
+            r.a[h] = (k0 + tk < kend) ? op.loadAT(k0 + tk, m0 + tr + 32 * h) : zero8();
+        else
+            r.a[h] = (m0 + ar < M) ? op.loadA(m0 + ar, k0 + ak + 8 * h, kend) : zero8();
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if constexpr (Op::B_KMAJOR)
+            r.b[h] = (k0 + tk < kend) ? op.loadBT(k0 + tk, n0 + tr + 32 * h) : zero8();
+        else
+            r.b[h] = (n0 + br < N) ? op.loadB(k0 + bk + 32 * h, n0 + br, kend) : zero8();
+    }
+}
+
+template <class Op>
+__device__ __forceinline__ void store_stage2(const StageRegs2<Op>& r, __bf16 (*As)[LDSK], __bf16 (*Bs)[LDSK]) {
+    const int t = threadIdx.x;
+    const int ar = t >> 1, ak = (t & 1) * 32;
+    const int br = t >> 2, bk = (t & 3) * 8;
+    const int tk = t & 63, tr = (t >> 6) * 8;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        if constexpr (Op::A_KMAJOR) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[tr + 32 * h + i][tk] = r.a[h][i];
+        } else {
+            *reinterpret_cast<bf16x8*>(&As[ar][ak + 8 * h]) = r.a[h];
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if constexpr (Op::B_KMAJOR) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[tr + 32 * h + i][tk] = r.b[h][i];
+        } else {
+            *reinterpret_cast<bf16x8*>(&Bs[br][bk + 32 * h]) = r.b[h];
+        }
+    }
+}
+
+template <class Op>
+__global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, int k_per_split) {
+    __shared__ __attribute__((aligned(16))) __bf16 As[GT2][LDSK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[GT][LDSK];
+    const int m0 = blockIdx.x * GT2, n0 = blockIdx.y * GT;
+    const int kbeg = blockIdx.z * k_per_split;
+    const int kend = min(K, kbeg + k_per_split);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    StageRegs2<Op> r;
+    if (kbeg < kend) load_stage2(op, r, m0, n0, kbeg, kend, M, N);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        __syncthreads();
+        store_stage2(r, As, Bs);
+        __syncthreads();
+        if (k0 + GK < kend) load_stage2(op, r, m0, n0, k0 + GK, kend, M, N);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            bf16x8 bv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bv[j] = *reinterpret_cast<const bf16x8*>(&Bs[16 * j + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 a =
+                    *reinterpret_cast<const bf16x8*>(&As[32 * w + 16 * i + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + 32 * w + 16 * i + 4 * (lane >> 4) + q;
+                const int n = n0 + 16 * j + (lane & 15);
+                if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
+            }
+}
+
 // ---------------------------------------------------------------------------
 // Operand maps.  NHWC activations; conv weights W[co][ky][kx][ci] (row co of
 // length 9*Cin); fully connected W[out][in].  Every spatial size and channel
@@ -363,6 +470,14 @@ static hipError_t gemm(const Op& op, int M, int N, int K, int splits, hipStream_
     const int nz = (K + kps - 1) / kps;
     hipLaunchKernelGGL(k_gemm<Op>, dim3((M + GT - 1) / GT, (N + GT - 1) / GT, nz), dim3(256), 0, st, op,
                        M, N, K, kps);
+    return hipGetLastError();
+}
+
+// Large-M GEMM (no K split): the 128 x 64 tile.
+template <class Op>
+static hipError_t gemm_tall(const Op& op, int M, int N, int K, hipStream_t st) {
+    hipLaunchKernelGGL(k_gemm_tall<Op>, dim3((M + GT2 - 1) / GT2, (N + GT - 1) / GT, 1), dim3(256), 0, st, op, M,
+                       N, K, K);
     return hipGetLastError();
 }
 
@@ -647,7 +762,7 @@ hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st) {
         const CnnLayer& L = net.conv[l];
         const ConvShape s = conv_shape(B, H, L.cin, H / L.stride, L.cout, L.stride);
         OpConvFwd op{s, x, net.wbf + L.w_off, net.params + L.b_off, net.act[l]};
-        if (gemm(op, B * s.Ho * s.Wo, L.cout, 9 * L.cin, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+        if (gemm_tall(op, B * s.Ho * s.Wo, L.cout, 9 * L.cin, st) != hipSuccess) return hipErrorLaunchFailure;
         x = net.act[l];
         H = s.Ho;
     }
@@ -712,7 +827,7 @@ hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* targ
         if (bias_grad(net, K, L.cout, net.dact[l], net.grads + L.b_off, st) != hipSuccess) return hipErrorLaunchFailure;
         if (l > 0) {
             OpConvDgrad dg{s, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};
-            if (gemm(dg, B * H * H, L.cin, 9 * L.cout, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+            if (gemm_tall(dg, B * H * H, L.cin, 9 * L.cout, st) != hipSuccess) return hipErrorLaunchFailure;
         }
         Hout = H;
     }
