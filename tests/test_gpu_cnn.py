@@ -179,3 +179,42 @@ def test_init_propose_clips_to_support_and_flags():
     net2 = _fixed_output_net(table, mean, std, n=8)
     th2, _ = lens.init_propose(net2, torch.zeros((5, 64, 64), device=DEV), 100, 3)
     assert torch.equal(th, th2)
+
+
+def test_trained_network_beats_prior_draws():
+    """What the learned initializer gains over the plain method: on held-out
+    systems (64x64 px, truths from the simulation distribution, data = oracle
+    model + noise), the best of 64 network proposals has a higher
+    log-posterior than the best of 64 prior draws."""
+    from oracle import lens_oracle as O
+    from paper_2606_30633_amd import learned_init as LI
+    dev = torch.device(DEV, 0)
+    theta, images = LI.simulate(100000, synth.SEED_CNN_TRAIN, dev)
+    mean, std = LI.target_standardization(theta)
+    net = lens.Cnn(256, 1, dev)
+    LI.train(net, images, theta, mean, std, 5, 256, lr=2e-3, lr_final=1e-4, log=lambda *_: None)
+    del images
+    table = LI.configure(net, mean, std)
+    spec = LI.train_spec()
+    S, n = 8, 64
+    psf = synth.double_gaussian_psf(spec.psf_size, spec.pix_scale)
+    truths = synth.draw_params(synth.paper_sim_dists(), S, synth.SEED_CNN_VAL + 777)
+    datas = [(O.model_image(truths[k], spec, psf).numpy()
+              + synth.noise((spec.ny, spec.nx), synth.SIGMA_NOISE, synth.SEED_NOISE + 900 + k)).astype(np.float32)
+             for k in range(S)]
+    inv = synth.invvar_map(spec.ny, spec.nx, synth.SIGMA_NOISE)
+    bp = lens.BatchPlan([spec] * S, [psf] * S, datas, [inv] * S, [n] * S, DEV)
+    bp.set_prior(table)
+    learned, _ = lens.init_propose(net, torch.tensor(np.stack(datas), device=DEV), n, 11)
+    prior = lens.lens_prior_sample(table, S, n, 12, DEV)
+
+    def best(th):
+        u = bp.to_unconstrained(th.reshape(S * n, -1).contiguous())
+        lp, _ = bp.logpost_grad(u, False)
+        b, _ = bp.argmin((-lp).float().contiguous())
+        return -b.double().cpu().numpy()
+
+    bl, bpr = best(learned), best(prior)
+    gain = bl - bpr
+    print("best logp learned", np.round(bl, 1).tolist(), "prior", np.round(bpr, 1).tolist(), flush=True)
+    assert np.median(gain) > 0 and np.sum(gain > 0) >= 6, gain
