@@ -235,3 +235,30 @@ def test_full_size_uneven_batch_sampled_parity(tmp_path):
             continue
         assert abs(L[row] - lr) <= 1e-5 * abs(lr), (k, p, L[row], lr)
         assert np.linalg.norm(G[row] - gr) <= 1e-5 * np.linalg.norm(gr), (k, p)
+
+
+@pytest.mark.parametrize("mass,nl,ns", [("SIE", 0, 2), ("EPL", 2, 3), ("SIE", 1, 1)])
+def test_batch_other_models_equal_single_plans_and_oracle(mass, nl, ns):
+    """Other compositions (other instances of the batch kernels): batch ==
+    per-system plans bitwise, sampled particles against the oracle."""
+    rng = np.random.default_rng(40 + nl + 3 * ns)
+    specs, cases = [], []
+    for k in range(4):
+        spec = synth.ModelSpec(int(rng.integers(16, 40)), int(rng.integers(16, 40)), 0.1, int(rng.integers(1, 4)),
+                               int(2 * rng.integers(0, 6) + 1), mass, nl, ns)
+        specs.append(spec)
+        cases.append(make_case(spec, 60 + k, 3, psf="asym"))
+    print("batch models", mass, nl, ns, specs, flush=True)
+    bp = lens.BatchPlan(specs, [c[1] for c in cases], [c[2] for c in cases], [c[0].invvar for c in cases],
+                        [3] * 4, DEV)
+    theta = np.concatenate([c[3] for c in cases])
+    L, G = bp.loglike_grad(torch.tensor(theta, device=DEV))
+    L, G = L.cpu().numpy(), G.cpu().numpy()
+    for k, (spec, (sysm, psf, data, th)) in enumerate(zip(specs, cases)):
+        plan = lens.LensPlan(spec, psf, data, sysm.invvar, 3, DEV)
+        Ls, Gs = lens.lens_loglike_grad(plan, torch.tensor(th, device=DEV))
+        assert np.array_equal(L[3 * k:3 * k + 3], Ls.cpu().numpy())
+        assert np.array_equal(G[3 * k:3 * k + 3], Gs.cpu().numpy())
+        lr, gr = O.loglike_and_grad(th[1], spec, psf, data, sysm.invvar)
+        assert abs(L[3 * k + 1] - lr) <= 1e-5 * abs(lr)
+        assert np.linalg.norm(G[3 * k + 1] - gr) <= 1e-5 * np.linalg.norm(gr)

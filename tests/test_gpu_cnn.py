@@ -44,7 +44,7 @@ def test_exact_arithmetic_forward_and_gradients_match_oracle():
         assert err <= 1e-6 * max(1.0, np.abs(r).max()), (name, err, np.abs(r).max())
 
 
-@pytest.mark.parametrize("B", [16, 64])
+@pytest.mark.parametrize("B", [5, 16, 64])
 def test_random_network_close_to_oracle(B):
     """B = 64 gives the first layer's weight gradient 128 K-splits (the
     wave-parallel split sum)."""
