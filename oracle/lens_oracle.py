@@ -31,11 +31,16 @@ formula below is a published lensing result, restated:
   downsample  mean over the s x s sub-pixels of each pixel
   PSF         zero-padded 'same' 2-D convolution with an odd K x K kernel
   logL        -1/2 sum w (d - m)^2  (Gaussian, w = inverse variance)
+  stages      prior and bijection, Adam, HMC with Philox draws, and SVI: a
+              full-covariance Gaussian surrogate, its Monte-Carlo ELBO with
+              the pathwise gradient, Adam or AdaBelief updates
 
 Pins: tests/test_oracle_*.py check these functions against closed forms,
 invariants, library routines and brute force (SIS, EPL->SIE at gamma = 2,
 Poisson equation, Keeton's 1-D integral, Sersic flux via the incomplete
-gamma function, delta-PSF, chi-square statistics, finite differences).
+gamma function, delta-PSF, chi-square statistics, finite differences; for
+SVI the closed-form KL of a Gaussian target and the AdaBelief closed form
+under a constant gradient).
 """
 from __future__ import annotations
 
@@ -544,19 +549,22 @@ def box_muller(a: float, b: float) -> Tuple[float, float]:
     return r * math.cos(2.0 * math.pi * b), r * math.sin(2.0 * math.pi * b)
 
 
-def hmc_momenta(d: int, seed: int, chain: int, t: int) -> np.ndarray:
-    """Standard normals for one chain and transition.
-
-    Philox4x32-10 with key (seed low word, seed high word) and counter
-    (chain, t, block, 0); each block's four words give two Box-Muller pairs.
-    """
+def philox_normals(d: int, seed: int, w0: int, w1: int, tag: int) -> np.ndarray:
+    """d standard normals from Philox4x32-10 with key (seed low word, seed
+    high word) and counters (w0, w1, block, tag); each block's four words give
+    two Box-Muller pairs."""
     key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
     z = []
     for blk in range((d + 3) // 4):
-        w = philox4x32([chain, t, blk, 0], key)
+        w = philox4x32([w0, w1, blk, tag], key)
         z += list(box_muller(uniform_from_bits(w[0]), uniform_from_bits(w[1])))
         z += list(box_muller(uniform_from_bits(w[2]), uniform_from_bits(w[3])))
     return np.array(z[:d])
+
+
+def hmc_momenta(d: int, seed: int, chain: int, t: int) -> np.ndarray:
+    """Standard normals for one chain and transition: counters (chain, t, block, 0)."""
+    return philox_normals(d, seed, chain, t, 0)
 
 
 def hmc_accept_uniform(d: int, seed: int, chain: int, t: int) -> float:
@@ -583,3 +591,140 @@ def hmc_transition(u, logp_grad_fn, inv_mass, eps: float, L: int, seed: int, cha
     lu = math.log(hmc_accept_uniform(d, seed, chain, t))
     acc = bool(np.isfinite(H1) and lu < H0 - H1)
     return (u1 if acc else u), (lp1 if acc else lp0), acc, H0, H1, lu
+
+
+# ---------------------------------------------------------------------------
+# Stochastic variational inference (Sec. 3: the SVI stage, eq. vi, eq. elbo,
+# eq. elbo-grad; Sec. 3.2: AdaBelief for SVI)
+#
+# Surrogate: q(u) = N(u; mu, L L^T) in the unconstrained space, L lower
+# triangular with a positive diagonal.  Parameter vector phi, length
+# d + d(d+1)/2: mu, then the lower triangle of L row by row; each diagonal
+# entry is stored as rho with L_ii = softplus(rho) + SVI_DIAG_SHIFT.
+# Samples u_i = mu + L eps_i, eps_i standard normal.  The target is the
+# log posterior in the unconstrained space with the bijection's Jacobian
+# (the density of u).
+# ---------------------------------------------------------------------------
+SVI_DIAG_SHIFT = 1e-5
+SVI_RNG_TAG = 1          # counter word 3 of the surrogate draws (HMC's is 0)
+
+
+def svi_n_params(d: int) -> int:
+    return d + d * (d + 1) // 2
+
+
+def svi_unpack(phi: torch.Tensor, d: int) -> Tuple[torch.Tensor, torch.Tensor]:
+    """phi -> (mu [d], L [d, d]) as float64 tensors (differentiable)."""
+    mu = phi[:d]
+    rows, cols = torch.tril_indices(d, d)
+    vals = phi[d:]
+    diag = rows == cols
+    vals = torch.where(diag, torch.nn.functional.softplus(vals) + SVI_DIAG_SHIFT, vals)
+    L = torch.zeros(d, d, dtype=phi.dtype).index_put((rows, cols), vals)
+    return mu, L
+
+
+def svi_pack(mu, L) -> np.ndarray:
+    """(mu, L) -> phi: the inverse of svi_unpack (diagonal through the inverse softplus)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    d = mu.shape[0]
+    r, c = np.tril_indices(d)
+    vals = L[r, c].copy()
+    dg = r == c
+    x = vals[dg] - SVI_DIAG_SHIFT
+    vals[dg] = x + np.log(-np.expm1(-x))       # softplus^-1(x) = log(e^x - 1)
+    return np.concatenate([mu, vals])
+
+
+def svi_normals(d: int, seed: int, sample: int, step: int) -> np.ndarray:
+    """The standard normals of surrogate sample `sample` at SVI step `step`
+    (0-based): Philox counters (sample, step, block, SVI_RNG_TAG)."""
+    return philox_normals(d, seed, sample, step, SVI_RNG_TAG)
+
+
+def svi_elbo_grad(phi, eps, logp_grad_fn, round_u: bool = True):
+    """Monte-Carlo ELBO of eq. elbo over the samples u_i = mu + L eps_i, and its
+    gradient with respect to phi.
+
+    eps [n, d]; logp_grad_fn(u [n, d]) -> (logp [n], dlogp/du [n, d]).  With
+    round_u the target is evaluated at u rounded to float32 (the points a
+    float32 interface receives).  ELBO = mean_i [log q(u_i) - logp(u_i)] with
+    log q(u_i) = -|eps_i|^2/2 - sum log L_jj - (d/2) log 2 pi.
+
+    The gradient is the reparameterised (pathwise) estimator: the derivative
+    of that sample mean with the eps_i held fixed; the target enters only
+    through its gradient at u_i.  Its expectation is the gradient of eq.
+    elbo-grad.  Returns (elbo, grad [len(phi)], u [n, d]).
+    """
+    eps = np.asarray(eps, dtype=np.float64)
+    n, d = eps.shape
+    ph = torch.tensor(np.asarray(phi, dtype=np.float64), requires_grad=True)
+    mu, L = svi_unpack(ph, d)
+    E = torch.tensor(eps)
+    u = mu[None, :] + E @ L.T
+    u_eval = u.detach().numpy()
+    if round_u:
+        u_eval = u_eval.astype(np.float32).astype(np.float64)
+    lp, g = logp_grad_fn(u_eval)
+    lp = np.asarray(lp, dtype=np.float64)
+    g = torch.tensor(np.asarray(g, dtype=np.float64))
+    logq = -0.5 * (E * E).sum(1) - torch.log(torch.diagonal(L)).sum() - 0.5 * d * math.log(2 * math.pi)
+    elbo = float((logq.detach() - torch.tensor(lp)).mean())
+    # d(-logp(u_i))/dphi = -dlogp/du . du/dphi, with du/dphi from autograd
+    obj = logq.mean() - (g * u).sum(1).mean()
+    (gr,) = torch.autograd.grad(obj, ph)
+    return elbo, gr.numpy(), u_eval
+
+
+def adabelief_step(x, g, m, s, k: int, lr: float, b1=0.9, b2=0.999, eps=1e-16):
+    """One AdaBelief update (Zhuang et al. 2020) minimising a loss with gradient g.
+
+    Like Adam, but the second moment follows the squared deviation of the
+    gradient from its moving average, (g - m)^2, plus eps; both moments are
+    bias-corrected with the 1-based step number k.
+    """
+    m = b1 * m + (1 - b1) * g
+    s = b2 * s + (1 - b2) * (g - m) ** 2 + eps
+    mh = m / (1 - b1 ** k)
+    sh = s / (1 - b2 ** k)
+    return x - lr * mh / (np.sqrt(sh) + eps), m, s
+
+
+SVI_ADAM, SVI_ADABELIEF = 0, 1
+
+
+def svi_run(phi0, n: int, n_steps: int, seed: int, logp_grad_fn, optimizer: int = SVI_ADABELIEF,
+            lr: float = 1e-4, b1: float = 0.95, b2: float = 0.99, eps: float = 1e-16, step0: int = 0,
+            round_u: bool = True):
+    """n_steps SVI iterations from phi0 with n surrogate samples per step.
+
+    Step t (0-based, counted from step0 for the draws and the bias correction)
+    draws eps with svi_normals(d, seed, i, step0 + t), evaluates the ELBO and
+    its gradient, and applies one Adam or AdaBelief update (moments start at
+    zero).  Returns (phi, elbo per step [n_steps], gradient of the last step).
+    """
+    phi = np.asarray(phi0, dtype=np.float64).copy()
+    npar = phi.shape[0]
+    d = int(round((math.sqrt(9 + 8 * npar) - 3) / 2))
+    assert svi_n_params(d) == npar
+    m = np.zeros(npar)
+    s = np.zeros(npar)
+    elbos = []
+    g = None
+    for t in range(n_steps):
+        k = step0 + t
+        E = np.stack([svi_normals(d, seed, i, k) for i in range(n)])
+        elbo, g, _ = svi_elbo_grad(phi, E, logp_grad_fn, round_u)
+        elbos.append(elbo)
+        if optimizer == SVI_ADABELIEF:
+            phi, m, s = adabelief_step(phi, g, m, s, k + 1, lr, b1, b2, eps)
+        else:
+            phi, m, s = adam_step(phi, g, m, s, k + 1, lr, b1, b2, eps)
+    return phi, np.array(elbos), g
+
+
+def svi_moments(phi, d: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Mean and covariance L L^T of the surrogate."""
+    mu, L = svi_unpack(torch.tensor(np.asarray(phi, dtype=np.float64)), d)
+    return mu.numpy(), (L @ L.T).numpy()
