@@ -199,6 +199,69 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
                          float* d_samples, int32_t* d_accepts, int32_t use_graph, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Stochastic variational inference (Sec. 3: eq. vi, eq. elbo, eq. elbo-grad;
+ * Sec. 3.2: AdaBelief as the SVI optimizer).  The surrogate is a Gaussian
+ * q(u) = N(mu, L L^T) over the unconstrained parameters u, fitted to the
+ * HMC target logp(u) (with the bijection's Jacobian) by minimising the
+ * Monte-Carlo ELBO = mean_i [log q(u_i) - logp(u_i)] over n draws
+ * u_i = mu + L eps_i.
+ *
+ * Surrogate parameters phi (float32, length lens_svi_num_params(d) =
+ * d + d(d+1)/2): mu, then the lower triangle of L row by row; a diagonal
+ * entry holds rho with L_jj = softplus(rho) + 1e-5.
+ *
+ * eps_i: Philox4x32-10 with key = seed and counters (i, step, block, 1),
+ * Box-Muller in float64 (the HMC draws use counter word 3 = 0, so the two
+ * streams never meet).  The ELBO gradient is the reparameterised (pathwise)
+ * estimator: the derivative of the sample mean with the eps_i held fixed,
+ * reduced over the draws in float64 in a fixed order (deterministic).
+ * A draw whose target is not finite (an ellipticity |e| >= 1) contributes a
+ * zero gradient and makes the ELBO +inf.
+ *
+ * Plan scratch: draws, their normals and log q for up to max_particles draws;
+ * the target reuses the plan's posterior buffers.  Requires
+ * lens_plan_set_prior and d <= 50.
+ * ------------------------------------------------------------------------- */
+#define LENS_OPT_ADAM      0   /* Kingma & Ba 2015 */
+#define LENS_OPT_ADABELIEF 1   /* Zhuang et al. 2020 */
+
+/* d + d(d+1)/2, or -1 for d outside [1, 50]. */
+int32_t lens_svi_num_params(int32_t d);
+
+/* Restart the plan's SVI step counter (draws and bias correction) at 0. */
+lens_status lens_svi_reset(lens_plan* plan);
+
+/* ELBO estimate and its gradient at phi, draws of step `step`, no update.
+ *   d_phi [np] in; d_elbo [1] out (float64); d_grad_phi [np] out, optional;
+ *   d_u [n][d] out, optional: the draws u_i (float32, the points at which
+ *   the target is evaluated). */
+lens_status lens_svi_elbo_grad(lens_plan* plan, int32_t n, const float* d_phi, uint64_t seed,
+                               int32_t step, double* d_elbo, float* d_grad_phi, float* d_u,
+                               void* stream);
+
+/* n_steps SVI iterations with n draws each.  Step k (the plan's counter,
+ * from lens_svi_reset) draws with counter word 1 = k and applies one Adam
+ * or AdaBelief update with bias corrections 1 - beta^(k+1):
+ *   Adam:      m = b1 m + (1-b1) g;  s = b2 s + (1-b2) g^2
+ *   AdaBelief: m = b1 m + (1-b1) g;  s = b2 s + (1-b2) (g-m)^2 + eps
+ *   phi -= lr m^ / (sqrt(s^) + eps)
+ *   d_phi, d_m, d_s [np] in/out (moments zero to start); d_elbo [n_steps]
+ *   out, optional: the ELBO of each step, at phi before its update.
+ *   The paper's SVI setting: AdaBelief, lr 1e-4, beta1 0.95, beta2 0.99;
+ *   eps must be > 0 (1e-16 is AdaBelief's usual value).
+ *   use_graph as for lens_map_adam.
+ * Errors: LENS_EINVAL for an unknown optimizer or hyper-parameters out of
+ * range. */
+lens_status lens_svi_run(lens_plan* plan, int32_t n, float* d_phi, float* d_m, float* d_s,
+                         int32_t n_steps, int32_t optimizer, float lr, float beta1, float beta2,
+                         float eps, uint64_t seed, double* d_elbo, int32_t use_graph, void* stream);
+
+/* Surrogate moments: d_mean [d] = mu, d_cov [d][d] = L L^T, d_var [d] its
+ * diagonal (e.g. the inverse mass matrix of HMC); each optional. */
+lens_status lens_svi_moments(int32_t d, const float* d_phi, float* d_mean, float* d_cov, float* d_var,
+                             void* stream);
+
+/* ---------------------------------------------------------------------------
  * Uneven batch: many lens systems of different image size, supersampling and
  * PSF size, each with its own particles, evaluated together (the paper models
  * samples of many systems, Sec. 4.2; this is the one-GPU form of that

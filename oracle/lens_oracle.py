@@ -702,7 +702,7 @@ def svi_run(phi0, n: int, n_steps: int, seed: int, logp_grad_fn, optimizer: int 
     Step t (0-based, counted from step0 for the draws and the bias correction)
     draws eps with svi_normals(d, seed, i, step0 + t), evaluates the ELBO and
     its gradient, and applies one Adam or AdaBelief update (moments start at
-    zero).  Returns (phi, elbo per step [n_steps], gradient of the last step).
+    zero).  Returns (phi, elbo per step [n_steps], gradient per step [n_steps, len(phi)]).
     """
     phi = np.asarray(phi0, dtype=np.float64).copy()
     npar = phi.shape[0]
@@ -710,18 +710,18 @@ def svi_run(phi0, n: int, n_steps: int, seed: int, logp_grad_fn, optimizer: int 
     assert svi_n_params(d) == npar
     m = np.zeros(npar)
     s = np.zeros(npar)
-    elbos = []
-    g = None
+    elbos, grads = [], []
     for t in range(n_steps):
         k = step0 + t
         E = np.stack([svi_normals(d, seed, i, k) for i in range(n)])
         elbo, g, _ = svi_elbo_grad(phi, E, logp_grad_fn, round_u)
         elbos.append(elbo)
+        grads.append(g)
         if optimizer == SVI_ADABELIEF:
             phi, m, s = adabelief_step(phi, g, m, s, k + 1, lr, b1, b2, eps)
         else:
             phi, m, s = adam_step(phi, g, m, s, k + 1, lr, b1, b2, eps)
-    return phi, np.array(elbos), g
+    return phi, np.array(elbos), np.array(grads)
 
 
 def svi_moments(phi, d: int) -> Tuple[np.ndarray, np.ndarray]:

@@ -96,9 +96,13 @@ struct lens_plan {
     float* hmc_p;             // [maxP][d]
     double* hmc_logp0;        // [maxP]
     double* hmc_h0;           // [maxP]
-    int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC base
+    float* svi_u;             // [maxP][d] surrogate samples
+    double* svi_eps;          // [d][maxP] their standard normals
+    double* svi_logq;         // [maxP]
+    int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC base,
+                              // [4] SVI step, [5] SVI steps in this run, [6] step of lens_svi_elbo_grad
     hipStream_t cap_stream;
-    GraphCache map_graph, hmc_graph;
+    GraphCache map_graph, hmc_graph, svi_graph;
 };
 
 namespace {
@@ -187,9 +191,10 @@ lens_status lens_plan_destroy(lens_plan* plan) {
     if (plan->partial) (void)hipFree(plan->partial);
     plan->map_graph.reset();
     plan->hmc_graph.reset();
+    plan->svi_graph.reset();
     void* bufs[] = {plan->prior, plan->theta, plan->gtheta, plan->logl, plan->logl64, plan->logp,
                     plan->gradu, plan->hmc_u0, plan->hmc_g0, plan->hmc_p, plan->hmc_logp0,
-                    plan->hmc_h0, plan->counters};
+                    plan->hmc_h0, plan->svi_u, plan->svi_eps, plan->svi_logq, plan->counters};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
@@ -244,6 +249,9 @@ lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf, co
         hipMalloc(&p->hmc_p, sizeof(float) * Pd) != hipSuccess ||
         hipMalloc(&p->hmc_logp0, sizeof(double) * Pn) != hipSuccess ||
         hipMalloc(&p->hmc_h0, sizeof(double) * Pn) != hipSuccess ||
+        hipMalloc(&p->svi_u, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&p->svi_eps, sizeof(double) * Pd) != hipSuccess ||
+        hipMalloc(&p->svi_logq, sizeof(double) * Pn) != hipSuccess ||
         hipMalloc(&p->counters, sizeof(int) * 8) != hipSuccess) {
         lens_plan_destroy(p);
         return LENS_ENOMEM;
@@ -254,6 +262,7 @@ lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf, co
     }
     if (launch_set_int(p->counters, 0, nullptr) != hipSuccess ||
         launch_set_int(p->counters + 1, 0, nullptr) != hipSuccess ||
+        launch_set_int(p->counters + 4, 0, nullptr) != hipSuccess ||
         launch_flip(K, d_psf, p->psf_flip, nullptr) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         lens_plan_destroy(p);
@@ -368,6 +377,7 @@ lens_status lens_plan_set_prior(lens_plan* plan, const float* h_table) {
         return LENS_EHIP;
     plan->map_graph.reset();
     plan->hmc_graph.reset();
+    plan->svi_graph.reset();
     return LENS_OK;
 }
 
@@ -515,6 +525,102 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
                                        (uint64_t)(uintptr_t)d_samples, (uint64_t)(uintptr_t)d_accepts,
                                        (uint64_t)plan->ppt};
     return run_maybe_graph(plan, plan->hmc_graph, key, use_graph != 0, n_transitions, st, transition);
+}
+
+int32_t lens_svi_num_params(int32_t d) {
+    return (d < 1 || d > SVI_MAX_D) ? -1 : svi_num_params(d);
+}
+
+lens_status lens_svi_reset(lens_plan* plan) {
+    if (!plan) return LENS_EINVAL;
+    if (launch_set_int(plan->counters + 4, 0, nullptr) != hipSuccess) return LENS_EHIP;
+    return hip_status(hipDeviceSynchronize());
+}
+
+// Shared part of the SVI calls: draws, target at the draws, reduction (+ update).
+static lens_status svi_step_enqueue(lens_plan* plan, const SviArgs& a, hipStream_t s) {
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+        if (launch_svi_draw(a, s) != hipSuccess) return LENS_EHIP;
+    }
+    lens_status r = logpost_enqueue(plan, a.n, a.u, 1, nullptr, plan->logp, plan->gradu, s);
+    if (r != LENS_OK) return r;
+    TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+    return hip_status(launch_svi_reduce(a, s));
+}
+
+static SviArgs svi_args(lens_plan* plan, int32_t n, float* d_phi, uint64_t seed) {
+    SviArgs a{};
+    a.phi = d_phi;
+    a.u = plan->svi_u;
+    a.eps = plan->svi_eps;
+    a.logq = plan->svi_logq;
+    a.logp = plan->logp;
+    a.grad_u = plan->gradu;
+    a.seed = seed;
+    a.n = n;
+    a.d = plan->mi.d;
+    return a;
+}
+
+lens_status lens_svi_elbo_grad(lens_plan* plan, int32_t n, const float* d_phi, uint64_t seed,
+                               int32_t step, double* d_elbo, float* d_grad_phi, float* d_u,
+                               void* stream) {
+    if (!plan || !d_phi || !d_elbo || n < 1 || n > plan->max_particles || step < 0) return LENS_EINVAL;
+    if (!plan->prior || plan->mi.d > SVI_MAX_D) return LENS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    SviArgs a = svi_args(plan, n, const_cast<float*>(d_phi), seed);
+    if (d_u) a.u = d_u;
+    a.grad_phi = d_grad_phi;
+    a.elbo = d_elbo;
+    a.step = plan->counters + 6;
+    a.call_step = nullptr;
+    a.update = 0;
+    if (launch_set_int(plan->counters + 6, step, st) != hipSuccess) return LENS_EHIP;
+    return svi_step_enqueue(plan, a, st);
+}
+
+lens_status lens_svi_run(lens_plan* plan, int32_t n, float* d_phi, float* d_m, float* d_s,
+                         int32_t n_steps, int32_t optimizer, float lr, float beta1, float beta2,
+                         float eps, uint64_t seed, double* d_elbo, int32_t use_graph, void* stream) {
+    if (!plan || !d_phi || !d_m || !d_s || n < 1 || n > plan->max_particles || n_steps < 0)
+        return LENS_EINVAL;
+    if (!plan->prior || plan->mi.d > SVI_MAX_D) return LENS_EINVAL;
+    if ((optimizer != LENS_OPT_ADAM && optimizer != LENS_OPT_ADABELIEF) || !(lr > 0.0f) ||
+        !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return LENS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    SviArgs a = svi_args(plan, n, d_phi, seed);
+    a.m = d_m;
+    a.s = d_s;
+    a.elbo = d_elbo;
+    a.step = plan->counters + 4;
+    a.call_step = plan->counters + 5;
+    a.update = 1;
+    a.optimizer = optimizer == LENS_OPT_ADABELIEF ? SVI_OPT_ADABELIEF : SVI_OPT_ADAM;
+    a.lr = lr;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps_opt = eps;
+    auto step = [&](hipStream_t s) -> lens_status {
+        lens_status r = svi_step_enqueue(plan, a, s);
+        if (r != LENS_OK) return r;
+        if (launch_add_int(plan->counters + 4, 1, s) != hipSuccess) return LENS_EHIP;
+        return hip_status(launch_add_int(plan->counters + 5, 1, s));
+    };
+    // steps of this run are counted from zero (outside any graph): the ELBO index
+    if (launch_set_int(plan->counters + 5, 0, st) != hipSuccess) return LENS_EHIP;
+    const std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)(uintptr_t)d_phi, (uint64_t)(uintptr_t)d_m,
+                                       (uint64_t)(uintptr_t)d_s, (uint64_t)(uintptr_t)d_elbo,
+                                       (uint64_t)optimizer, fbits(lr), fbits(beta1), fbits(beta2),
+                                       fbits(eps), seed, (uint64_t)plan->ppt};
+    return run_maybe_graph(plan, plan->svi_graph, key, use_graph != 0, n_steps, st, step);
+}
+
+lens_status lens_svi_moments(int32_t d, const float* d_phi, float* d_mean, float* d_cov, float* d_var,
+                             void* stream) {
+    if (d < 1 || d > SVI_MAX_D || !d_phi) return LENS_EINVAL;
+    return hip_status(launch_svi_moments(d, d_phi, d_mean, d_cov, d_var, (hipStream_t)stream));
 }
 
 lens_status lens_plan_enable_timing(lens_plan* plan, int32_t enable) {

@@ -35,6 +35,33 @@ struct HmcArgs {
     float eps;
 };
 
+// SVI: surrogate draws, ELBO + pathwise gradient, optimizer step.
+constexpr int SVI_MAX_D = 50;                 // 8 + 7 * (3 lens-light + 3 source components)
+constexpr double SVI_DIAG_SHIFT = 1e-5;
+constexpr uint32_t SVI_RNG_TAG = 1u;          // counter word 3 (HMC draws use 0)
+constexpr int SVI_OPT_ADAM = 0, SVI_OPT_ADABELIEF = 1;
+
+inline int svi_num_params(int d) { return d + d * (d + 1) / 2; }
+
+struct SviArgs {
+    float* phi;            // [np] surrogate parameters (updated in place if update)
+    float* m;              // [np] first moment
+    float* s;              // [np] second moment
+    float* u;              // [n][d] sample points
+    double* eps;           // [d][n] standard normals
+    double* logq;          // [n]
+    const double* logp;    // [n] target at u
+    const float* grad_u;   // [n][d] dlogp/du at u
+    float* grad_phi;       // [np] or null
+    double* elbo;          // ELBO output (indexed by *call_step) or null
+    const int* step;       // SVI step: Philox counter word 1; bias correction uses step + 1
+    const int* call_step;  // index into elbo, or null for index 0
+    uint64_t seed;
+    int n, d;
+    int update, optimizer;
+    float lr, beta1, beta2, eps_opt;
+};
+
 // Observed image of one system of a batch (device pointer) for k_center_views.
 struct ViewSrc {
     const float* data;
@@ -58,6 +85,10 @@ hipError_t launch_set_int(int* c, int val, hipStream_t st);
 hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_kick_drift(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_end(int C, int d, const HmcArgs& a, hipStream_t st);
+
+hipError_t launch_svi_draw(const SviArgs& a, hipStream_t st);
+hipError_t launch_svi_reduce(const SviArgs& a, hipStream_t st);
+hipError_t launch_svi_moments(int d, const float* phi, float* mean, float* cov, float* var, hipStream_t st);
 
 hipError_t launch_inverse_bijection(int P, int d, const PriorRow* table, const float* theta, float* u,
                                     hipStream_t st);

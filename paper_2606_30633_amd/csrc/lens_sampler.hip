@@ -388,4 +388,160 @@ hipError_t launch_center_views(int S, int side, const ViewSrc* src, float* out, 
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// SVI (Sec. 3: eq. vi, eq. elbo, eq. elbo-grad; Sec. 3.2: AdaBelief).
+// Surrogate N(mu, L L^T) over the unconstrained parameters; phi = mu, then
+// the lower triangle of L row by row, diagonal entries stored as rho with
+// L_jj = softplus(rho) + SVI_DIAG_SHIFT.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sigmoid_d(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+// One work-group of 256 threads draws 256 samples: eps by Philox4x32-10 with
+// counters (sample, step, block, SVI_RNG_TAG) and Box-Muller, u = mu + L eps,
+// log q(u) = -|eps|^2/2 - log det L - (d/2) log 2 pi.  eps is stored [d][n].
+__global__ __launch_bounds__(256) void k_svi_draw(SviArgs a) {
+    __shared__ double Lp[SVI_MAX_D * (SVI_MAX_D + 1) / 2];
+    __shared__ double mu[SVI_MAX_D];
+    __shared__ double logdet;
+    const int d = a.d, n = a.n;
+    const int r = threadIdx.x;
+    if (r < d) {
+        const int t0 = r * (r + 1) / 2;
+        mu[r] = (double)a.phi[r];
+        for (int c = 0; c < r; ++c) Lp[t0 + c] = (double)a.phi[d + t0 + c];
+        Lp[t0 + r] = softplus_d((double)a.phi[d + t0 + r]) + SVI_DIAG_SHIFT;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sl = 0.0;
+        for (int j = 0; j < d; ++j) sl += log(Lp[j * (j + 3) / 2]);
+        logdet = sl;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t step = (uint32_t)*a.step;
+    const uint2 key = make_uint2((uint32_t)(a.seed & 0xffffffffu), (uint32_t)(a.seed >> 32));
+    double* eps = a.eps;
+    double ss = 0.0;
+    for (int b = 0; 4 * b < d; ++b) {
+        const uint4 w = philox(make_uint4((uint32_t)i, step, (uint32_t)b, SVI_RNG_TAG), key);
+        double z[4];
+        box_muller(w.x, w.y, z[0], z[1]);
+        box_muller(w.z, w.w, z[2], z[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b + q;
+            if (j < d) {
+                eps[(size_t)j * n + i] = z[q];
+                ss += z[q] * z[q];
+            }
+        }
+    }
+    a.logq[i] = -0.5 * ss - logdet - 0.5 * (double)d * 1.8378770664093454836;   // log 2 pi
+    for (int j = 0; j < d; ++j) {
+        const double* Lr = Lp + j * (j + 1) / 2;
+        double acc = mu[j];
+        for (int c = 0; c <= j; ++c) acc = fma(Lr[c], eps[(size_t)c * n + i], acc);
+        a.u[(size_t)i * d + j] = (float)acc;
+    }
+}
+
+// Work-group 0: the ELBO estimate mean(log q - logp).  Work-group 1 + e: the
+// pathwise gradient of entry e of phi,
+//   mu_j:      -mean_i g_ij
+//   L_rc:      -mean_i g_ir eps_ic                      (c < r)
+//   rho_r:     (-mean_i g_ir eps_ir - 1/L_rr) sigmoid(rho_r)
+// with g = dlogp/du, each a fixed-order float64 sum; then (if update) one
+// Adam or AdaBelief step of that entry.  Every work-group reads and writes
+// only its own entry of phi, m and s.
+__global__ __launch_bounds__(256) void k_svi_reduce(SviArgs a) {
+    __shared__ double red[256];
+    const int n = a.n, d = a.d, tid = threadIdx.x;
+    const int e = (int)blockIdx.x - 1;
+    int r = 0, c = 0;
+    double acc = 0.0;
+    if (e < 0) {
+        for (int i = tid; i < n; i += 256) acc += a.logq[i] - a.logp[i];
+    } else if (e < d) {
+        for (int i = tid; i < n; i += 256) acc -= (double)a.grad_u[(size_t)i * d + e];
+    } else {
+        const int t = e - d;
+        while ((r + 1) * (r + 2) / 2 <= t) ++r;
+        c = t - r * (r + 1) / 2;
+        const double* ec = a.eps + (size_t)c * n;
+        for (int i = tid; i < n; i += 256) acc -= (double)a.grad_u[(size_t)i * d + r] * ec[i];
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    double v = red[0] / (double)n;
+    if (e < 0) {
+        if (a.elbo) a.elbo[a.call_step ? *a.call_step : 0] = v;
+        return;
+    }
+    if (e >= d && r == c) {
+        const double rho = (double)a.phi[e];
+        v = (v - 1.0 / (softplus_d(rho) + SVI_DIAG_SHIFT)) * sigmoid_d(rho);
+    }
+    if (a.grad_phi) a.grad_phi[e] = (float)v;
+    if (!a.update) return;
+    const int k = *a.step + 1;
+    const double b1 = (double)a.beta1, b2 = (double)a.beta2, ep = (double)a.eps_opt;
+    const double m = b1 * (double)a.m[e] + (1.0 - b1) * v;
+    double s;
+    if (a.optimizer == SVI_OPT_ADABELIEF) {
+        const double dv = v - m;
+        s = b2 * (double)a.s[e] + (1.0 - b2) * dv * dv + ep;
+    } else {
+        s = b2 * (double)a.s[e] + (1.0 - b2) * v * v;
+    }
+    a.m[e] = (float)m;
+    a.s[e] = (float)s;
+    const double mh = m / (1.0 - pow(b1, (double)k));
+    const double sh = s / (1.0 - pow(b2, (double)k));
+    a.phi[e] = (float)((double)a.phi[e] - (double)a.lr * mh / (sqrt(sh) + ep));
+}
+
+// mean, covariance L L^T [d][d] and its diagonal, each optional.
+__global__ void k_svi_moments(int d, const float* __restrict__ phi, float* __restrict__ mean,
+                              float* __restrict__ cov, float* __restrict__ var) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d * d) return;
+    const int i = q / d, j = q - (q / d) * d;
+    auto Lat = [&](int r, int c) -> double {
+        const int t = r * (r + 1) / 2 + c;
+        const double x = (double)phi[d + t];
+        return r == c ? softplus_d(x) + SVI_DIAG_SHIFT : x;
+    };
+    double acc = 0.0;
+    const int kmax = i < j ? i : j;
+    for (int k = 0; k <= kmax; ++k) acc = fma(Lat(i, k), Lat(j, k), acc);
+    if (cov) cov[q] = (float)acc;
+    if (i == j) {
+        if (var) var[i] = (float)acc;
+        if (mean) mean[i] = phi[i];
+    }
+}
+
+hipError_t launch_svi_draw(const SviArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_svi_draw, blocks_for(a.n, 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_svi_reduce(const SviArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_svi_reduce, dim3((unsigned)(1 + svi_num_params(a.d))), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_svi_moments(int d, const float* phi, float* mean, float* cov, float* var, hipStream_t st) {
+    hipLaunchKernelGGL(k_svi_moments, blocks_for((long)d * d, 256), dim3(256), 0, st, d, phi, mean, cov, var);
+    return hipGetLastError();
+}
+
 }  // namespace lens

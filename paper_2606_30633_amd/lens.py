@@ -55,6 +55,12 @@ _SIGNATURES = {
                            ctypes.c_float, ctypes.c_float, _P, _I, _P]),
     "lens_hmc_run": (_I, [_P, _I, _P, _P, _P, _P, ctypes.c_float, _I, _I, ctypes.c_uint64,
                           ctypes.c_uint64, _P, _P, _I, _P]),
+    "lens_svi_num_params": (_I, [_I]),
+    "lens_svi_reset": (_I, [_P]),
+    "lens_svi_elbo_grad": (_I, [_P, _I, _P, ctypes.c_uint64, _I, _P, _P, _P, _P]),
+    "lens_svi_run": (_I, [_P, _I, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                          ctypes.c_float, ctypes.c_uint64, _P, _I, _P]),
+    "lens_svi_moments": (_I, [_I, _P, _P, _P, _P, _P]),
     "lens_batch_plan_create": (_I, [_I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "lens_batch_plan_destroy": (_I, [_P]),
     "lens_batch_total_particles": (ctypes.c_int64, [_P]),
@@ -339,6 +345,67 @@ def lens_hmc_run(plan: LensPlan, u: torch.Tensor, grad: torch.Tensor, logp: torc
                              inv_mass.data_ptr(), eps, int(n_leapfrog), int(n_transitions), int(seed),
                              int(transition0), _ptr(samples), _ptr(accepts), 1 if use_graph else 0,
                              _stream(stream)), "lens_hmc_run")
+
+
+SVI_OPTIMIZERS = {"adam": 0, "adabelief": 1}
+
+
+def lens_svi_num_params(d: int) -> int:
+    n = _lib.lens_svi_num_params(int(d))
+    if n < 0:
+        raise ValueError(f"SVI supports 1 <= d <= 50, got {d}")
+    return n
+
+
+def _svi_phi(plan: LensPlan, phi: torch.Tensor, name: str = "phi") -> torch.Tensor:
+    n = lens_svi_num_params(plan.d)
+    if phi.dtype != torch.float32 or phi.shape != (n,) or not phi.is_contiguous() or phi.device != plan.device:
+        raise ValueError(f"{name} must be a contiguous float32 [{n}] tensor on {plan.device}")
+    return phi
+
+
+def lens_svi_reset(plan: LensPlan):
+    _check(_lib.lens_svi_reset(plan.handle), "lens_svi_reset")
+
+
+def lens_svi_elbo_grad(plan: LensPlan, phi: torch.Tensor, n: int, seed: int, step: int = 0,
+                       want_u: bool = False, stream=None):
+    """ELBO estimate (float64 [1]) and its gradient w.r.t. phi at the draws of `step`."""
+    _svi_phi(plan, phi)
+    elbo = torch.empty(1, dtype=torch.float64, device=plan.device)
+    grad = torch.empty_like(phi)
+    u = torch.empty((n, plan.d), dtype=torch.float32, device=plan.device) if want_u else None
+    _check(_lib.lens_svi_elbo_grad(plan.handle, int(n), phi.data_ptr(), int(seed), int(step), elbo.data_ptr(),
+                                   grad.data_ptr(), _ptr(u), _stream(stream)), "lens_svi_elbo_grad")
+    return (elbo, grad, u) if want_u else (elbo, grad)
+
+
+def lens_svi_run(plan: LensPlan, phi: torch.Tensor, m: torch.Tensor, s: torch.Tensor, n: int, n_steps: int,
+                 optimizer: str = "adabelief", lr: float = 1e-4, beta1: float = 0.95, beta2: float = 0.99,
+                 eps: float = 1e-16, seed: int = 0, elbo: Optional[torch.Tensor] = None,
+                 use_graph: bool = False, stream=None):
+    """n_steps SVI iterations of phi (in place) with n draws each; moments m, s in place."""
+    _svi_phi(plan, phi)
+    _svi_phi(plan, m, "m")
+    _svi_phi(plan, s, "s")
+    if elbo is not None:
+        _check_out(elbo, (n_steps,), torch.float64, plan.device)
+    _check(_lib.lens_svi_run(plan.handle, int(n), phi.data_ptr(), m.data_ptr(), s.data_ptr(), int(n_steps),
+                             SVI_OPTIMIZERS[optimizer], lr, beta1, beta2, eps, int(seed), _ptr(elbo),
+                             1 if use_graph else 0, _stream(stream)), "lens_svi_run")
+    return elbo
+
+
+def lens_svi_moments(plan: LensPlan, phi: torch.Tensor, stream=None):
+    """(mean [d], covariance [d, d], variances [d]) of the surrogate, float32."""
+    _svi_phi(plan, phi)
+    d = plan.d
+    mean = torch.empty(d, dtype=torch.float32, device=plan.device)
+    cov = torch.empty((d, d), dtype=torch.float32, device=plan.device)
+    var = torch.empty(d, dtype=torch.float32, device=plan.device)
+    _check(_lib.lens_svi_moments(d, phi.data_ptr(), mean.data_ptr(), cov.data_ptr(), var.data_ptr(),
+                                 _stream(stream)), "lens_svi_moments")
+    return mean, cov, var
 
 
 class BatchPlan:

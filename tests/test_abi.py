@@ -60,3 +60,13 @@ def test_cnn_parameter_count_matches_oracle_layout():
     lib = lens.load_library()
     lib.lens_cnn_num_params.restype = ctypes.c_int64
     assert lib.lens_cnn_num_params() == cnn_oracle.n_params()
+
+
+def test_svi_parameter_count_matches_oracle_layout():
+    from oracle import lens_oracle as O
+    lens.load_library()
+    for d in (1, 21, 22, 29, 50):
+        assert lens.lens_svi_num_params(d) == O.svi_n_params(d)
+    for bad in (0, -3, 51):
+        with pytest.raises(ValueError):
+            lens.lens_svi_num_params(bad)

@@ -1,0 +1,219 @@
+"""GPU parity of the SVI stage (lens_svi_*) against the oracle.
+
+The oracle (oracle.svi_elbo_grad / adabelief_step / svi_run) draws the same
+Philox4x32-10 normals from its own implementation, evaluates the target
+(the log posterior with the bijection's Jacobian) at the draws rounded to
+float32 with the likelihood at T(u) rounded to float32, and reduces in
+float64.  Tolerance: 1e-5 relative, as for the likelihood; parameters are
+float32 on the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lens_oracle as O
+from paper_2606_30633_amd import synth
+from tests.cases import make_case
+
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2606_30633_amd import lens  # noqa: E402
+
+DEV = "cuda"
+RTOL = 1e-5
+B1, B2 = float(np.float32(0.95)), float(np.float32(0.99))   # the float32 values the library receives
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _target_fn(spec, psf, data, invvar, table):
+    def f(U):
+        out = [O.log_posterior_unconstrained(np.asarray(u, np.float32), spec, psf, data, invvar, table, True,
+                                             theta_float32=True) for u in U]
+        return np.array([o[0] for o in out]), np.stack([o[1] for o in out])
+    return f
+
+
+def _setup(spec, k, max_n, scale=0.01, seed=0):
+    sysm, psf, data, _ = make_case(spec, k, 1, psf="asym")
+    table = synth.prior_table(sysm.prior)
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, max_n, DEV)
+    plan.set_prior(table)
+    d = spec.n_params
+    rng = np.random.default_rng(100 + seed)
+    mu = O.to_unconstrained(torch.tensor(sysm.truth, dtype=torch.float64), table).numpy()
+    L = np.diag(scale * (1 + 0.5 * rng.uniform(size=d))) + np.tril(0.2 * scale * rng.standard_normal((d, d)), -1)
+    phi = O.svi_pack(mu, L).astype(np.float32)
+    return sysm, psf, data, table, plan, phi, _target_fn(spec, psf, data, sysm.invvar, table)
+
+
+SPECS = [synth.ModelSpec(24, 20, 0.12, 2, 5, "EPL", 1, 2), synth.ModelSpec(30, 26, 0.1, 3, 7, "SIE", 1, 1)]
+
+
+@pytest.mark.parametrize("spec", SPECS, ids=["EPL-1-2", "SIE-1-1"])
+def test_svi_elbo_grad_matches_oracle(spec):
+    _log(f"svi elbo_grad {spec}")
+    n, seed, step = 24, 11, 3
+    sysm, psf, data, table, plan, phi, f = _setup(spec, 1, 64)
+    elbo, g, u = lens.lens_svi_elbo_grad(plan, torch.tensor(phi, device=DEV), n, seed, step, want_u=True)
+    elbo, g, u = float(elbo.item()), g.cpu().numpy(), u.cpu().numpy()
+    E = np.stack([O.svi_normals(spec.n_params, seed, i, step) for i in range(n)])
+    eo, go, uo = O.svi_elbo_grad(phi.astype(np.float64), E, f)
+    np.testing.assert_allclose(u, uo, rtol=2.4e-7, atol=1e-7)
+    assert abs(elbo - eo) <= RTOL * abs(eo), (elbo, eo)
+    assert np.linalg.norm(g - go) <= RTOL * np.linalg.norm(go)
+    mu_part = slice(0, spec.n_params)
+    assert np.linalg.norm(g[mu_part] - go[mu_part]) <= RTOL * np.linalg.norm(go[mu_part])
+
+
+def _compare_phi(phi_gpu, phi_o, lr):
+    """Every entry agrees to float32 rounding plus 1 % of a step: a wrong
+    sign, moment or bias correction is off by O(lr).  (Measured on these
+    inputs: at most 6e-4 of a step, entries whose gradient is 1e-5 of the
+    largest included, since the gradient agrees per entry to ~1e-5.)"""
+    err = np.abs(phi_gpu - phi_o)
+    lim = 4 * np.spacing(np.abs(phi_o).astype(np.float32)).astype(np.float64) + 1e-2 * lr
+    assert np.all(err <= lim), (np.nonzero(err > lim), (err / lr).max())
+
+
+@pytest.mark.parametrize("optimizer", ["adabelief", "adam"])
+def test_svi_run_matches_oracle_eager_graph_and_split(optimizer):
+    spec = SPECS[0]
+    _log(f"svi run {optimizer}")
+    n, seed, steps, lr = 16, 5, 3, 1e-3
+    sysm, psf, data, table, plan, phi, f = _setup(spec, 2, 32)
+    eps = 1e-16 if optimizer == "adabelief" else float(np.float32(1e-8))
+    npar = phi.shape[0]
+    runs = {}
+    for mode in ("eager", "graph", "split"):
+        lens.lens_svi_reset(plan)
+        x = torch.tensor(phi, device=DEV)
+        m = torch.zeros(npar, device=DEV)
+        s = torch.zeros(npar, device=DEV)
+        if mode == "split":
+            e1 = torch.empty(2, dtype=torch.float64, device=DEV)
+            e2 = torch.empty(1, dtype=torch.float64, device=DEV)
+            lens.lens_svi_run(plan, x, m, s, n, 2, optimizer, lr, B1, B2, eps, seed, elbo=e1, use_graph=True)
+            lens.lens_svi_run(plan, x, m, s, n, 1, optimizer, lr, B1, B2, eps, seed, elbo=e2, use_graph=True)
+            el = torch.cat([e1, e2])
+        else:
+            el = torch.empty(steps, dtype=torch.float64, device=DEV)
+            lens.lens_svi_run(plan, x, m, s, n, steps, optimizer, lr, B1, B2, eps, seed, elbo=el,
+                              use_graph=(mode == "graph"))
+        runs[mode] = (x.cpu().numpy(), el.cpu().numpy())
+    for mode in ("graph", "split"):
+        assert np.array_equal(runs[mode][0], runs["eager"][0]), mode
+        assert np.array_equal(runs[mode][1], runs["eager"][1]), mode
+    opt = O.SVI_ADABELIEF if optimizer == "adabelief" else O.SVI_ADAM
+    phi_o, elbo_o, _ = O.svi_run(phi.astype(np.float64), n, steps, seed, f, opt, lr, B1, B2, eps)
+    np.testing.assert_allclose(runs["eager"][1], elbo_o, rtol=RTOL)
+    _compare_phi(runs["eager"][0].astype(np.float64), phi_o, lr)
+
+
+def test_svi_full_size_sampled():
+    """The benchmarked configuration: 100x100 px EPL system (d = 29), 4096
+    draws, one graph-replayed AdaBelief step.  Draws at sampled indices match
+    the oracle's Philox normals; the target at sampled draws matches the
+    oracle one by one; the ELBO, its gradient and the update equal the
+    float64 reductions of the per-draw values (a property at any size)."""
+    spec = synth.config2_spec()
+    n, seed, lr = 4096, 0xABCDE, 1e-4
+    d = spec.n_params
+    _log("svi full size: 4096 draws, config-2 system")
+    sysm, psf, data, _ = make_case(spec, 0, 1, psf="double")
+    table = synth.prior_table(sysm.prior)
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, n, DEV)
+    plan.set_prior(table)
+    mu = O.to_unconstrained(torch.tensor(sysm.truth, dtype=torch.float64), table).numpy()
+    rng = np.random.default_rng(8)
+    L = np.diag(np.full(d, 3e-3)) + np.tril(5e-4 * rng.standard_normal((d, d)), -1)
+    phi = O.svi_pack(mu, L).astype(np.float32)
+    x = torch.tensor(phi, device=DEV)
+    elbo0, g_gpu, u = lens.lens_svi_elbo_grad(plan, x, n, seed, 0, want_u=True)
+    E = np.stack([O.svi_normals(d, seed, i, 0) for i in range(n)])
+    mu64, L64 = (t.numpy() for t in O.svi_unpack(torch.tensor(phi.astype(np.float64)), d))
+    u_ref = (mu64[None, :] + E @ L64.T)
+    u_np = u.cpu().numpy()
+    np.testing.assert_allclose(u_np, u_ref.astype(np.float32), rtol=2.4e-7, atol=1e-7)
+    lp, gu = lens.lens_logpost_grad(plan, u, True)
+    lp, gu = lp.cpu().numpy(), gu.cpu().numpy().astype(np.float64)
+    f = _target_fn(spec, psf, data, sysm.invvar, table)
+    for i in (0, 2047, 4095):
+        lo, go = f(u_np[i:i + 1])
+        assert abs(lp[i] - lo[0]) <= RTOL * abs(lo[0])
+        assert np.linalg.norm(gu[i] - go[0]) <= RTOL * np.linalg.norm(go[0])
+    logq = -0.5 * (E * E).sum(1) - np.log(np.diag(L64)).sum() - 0.5 * d * math.log(2 * math.pi)
+    elbo_ref = np.mean(logq - lp)
+    assert abs(float(elbo0.item()) - elbo_ref) <= 1e-9 * abs(elbo_ref)
+    gL = -(gu.T @ E) / n
+    r, c = np.tril_indices(d)
+    gtri = gL[r, c]
+    rho = phi.astype(np.float64)[d:][r == c]
+    gtri[r == c] = (gtri[r == c] - 1 / np.diag(L64)) / (1 + np.exp(-rho))
+    g_ref = np.concatenate([-gu.mean(0), gtri])
+    g_gpu = g_gpu.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(g_gpu, g_ref, rtol=1e-6, atol=1e-6 * np.abs(g_ref).max())
+    lens.lens_svi_reset(plan)
+    m = torch.zeros_like(x)
+    s = torch.zeros_like(x)
+    el = torch.empty(1, dtype=torch.float64, device=DEV)
+    lens.lens_svi_run(plan, x, m, s, n, 1, "adabelief", lr, B1, B2, 1e-16, seed, elbo=el, use_graph=True)
+    assert el.item() == elbo0.item()
+    phi1, _, _ = O.adabelief_step(phi.astype(np.float64), g_gpu, np.zeros_like(g_ref), np.zeros_like(g_ref), 1,
+                                  lr, B1, B2, 1e-16)
+    err = np.abs(x.cpu().numpy().astype(np.float64) - phi1)
+    assert np.all(err <= 2 * np.spacing(np.abs(phi1).astype(np.float32)).astype(np.float64) + 1e-6 * lr)
+
+
+def test_svi_moments_match_oracle():
+    spec = SPECS[1]
+    sysm, psf, data, table, plan, phi, f = _setup(spec, 0, 8, scale=0.3)
+    mean, cov, var = lens.lens_svi_moments(plan, torch.tensor(phi, device=DEV))
+    mo, co = O.svi_moments(phi.astype(np.float64), spec.n_params)
+    np.testing.assert_allclose(mean.cpu().numpy(), mo, rtol=0, atol=0)
+    np.testing.assert_allclose(cov.cpu().numpy(), co, rtol=1e-6, atol=1e-7 * np.abs(co).max())
+    np.testing.assert_allclose(var.cpu().numpy(), np.diag(co), rtol=1e-6)
+
+
+def test_svi_adabelief_lowers_the_elbo():
+    """From a broad surrogate at the truth, a short AdaBelief run shrinks the
+    ELBO (what SVI minimises) by a wide margin and keeps every step finite."""
+    spec = SPECS[0]
+    sysm, psf, data, table, plan, phi, f = _setup(spec, 3, 512, scale=0.05)
+    x = torch.tensor(phi, device=DEV)
+    m = torch.zeros_like(x)
+    s = torch.zeros_like(x)
+    el = torch.empty(400, dtype=torch.float64, device=DEV)
+    lens.lens_svi_reset(plan)
+    lens.lens_svi_run(plan, x, m, s, 512, 400, "adabelief", 3e-3, B1, B2, 1e-16, 9, elbo=el, use_graph=True)
+    el = el.cpu().numpy()
+    assert np.all(np.isfinite(el))
+    assert el[-20:].mean() < el[:5].mean() - 0.5 * abs(el[:5].mean() - el[-20:].min())
+    assert el[-20:].mean() < el[0] - 10
+
+
+def test_svi_argument_errors():
+    spec = SPECS[1]
+    sysm, psf, data, table, plan, phi, f = _setup(spec, 0, 8)
+    x = torch.tensor(phi, device=DEV)
+    m = torch.zeros_like(x)
+    s = torch.zeros_like(x)
+    with pytest.raises(lens.LensError):
+        lens.lens_svi_run(plan, x, m, s, 9, 1)                     # more draws than the plan holds
+    with pytest.raises(lens.LensError):
+        lens.lens_svi_run(plan, x, m, s, 4, 1, eps=0.0)
+    with pytest.raises(lens.LensError):
+        lens.lens_svi_run(plan, x, m, s, 4, 1, beta1=1.0)
+    with pytest.raises(ValueError):
+        lens.lens_svi_run(plan, x[:-1].contiguous(), m, s, 4, 1)
+    fresh = lens.LensPlan(spec, psf, data, sysm.invvar, 8, DEV)
+    with pytest.raises(lens.LensError):
+        lens.lens_svi_elbo_grad(fresh, x, 4, 0)                   # no prior set
