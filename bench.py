@@ -41,9 +41,10 @@ def parse():
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
-    ap.add_argument("--workload", choices=["map", "hmc", "batch", "cnn"], default="map",
+    ap.add_argument("--workload", choices=["map", "hmc", "svi", "batch", "cnn"], default="map",
                     help="map: the headline MAP step (default); hmc: 8192 chains x 10 leapfrog on the same "
-                         "system; batch: 100 uneven systems x 512 particles; cnn: network training")
+                         "system; svi: AdaBelief SVI steps with 4096 surrogate draws on the same system; "
+                         "batch: 100 uneven systems x 512 particles; cnn: network training")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB (plain copy kernel, "
                          "for scaling HBM byte counters)")
@@ -79,7 +80,7 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload != "map":
-        return {"hmc": run_hmc, "batch": run_batch, "cnn": run_cnn}[args.workload](args)
+        return {"hmc": run_hmc, "svi": run_svi, "batch": run_batch, "cnn": run_cnn}[args.workload](args)
     import torch
     from paper_2606_30633_amd import lens, synth
 
@@ -288,6 +289,73 @@ def run_hmc(args):
           "HMC: 100x100 px EPL system, 8192 chains x 10 leapfrog per transition, hipGraph transitions",
           {"chains": C, "leapfrog": L, "transitions_per_s": round(1.0 / dt, 3), "acceptance": round(rate, 4),
            "eps": eps}, roof)
+
+
+def run_svi(args):
+    """SVI on the headline system: 4096 surrogate draws per step, AdaBelief (lr 1e-4,
+    betas 0.95 / 0.99), graph-replayed steps; value = logL+grad evals/s (draws x steps/s)."""
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    dev = torch.device("cuda", 0)
+    spec, sysm = synth.config2_spec(), synth.config2_system()
+    n = 4096
+    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
+    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
+            + torch.tensor(sysm.noise, device=dev)).contiguous()
+    plan = lens.LensPlan(spec, torch.tensor(sysm.psf, device=dev), data, torch.tensor(sysm.invvar, device=dev),
+                         n, dev)
+    plan.set_prior(synth.prior_table(sysm.prior))
+    d = spec.n_params
+    ut = lens.lens_to_unconstrained(plan, torch.tensor(sysm.truth[None, :], device=dev))
+    # surrogate start: mean at the truth, diagonal scale half the inverse-Hessian-diagonal width
+    h = 1e-3
+    probe = ut.repeat(2 * d, 1)
+    for j in range(d):
+        probe[2 * j, j] += h
+        probe[2 * j + 1, j] -= h
+    _, g = lens.lens_logpost_grad(plan, probe.contiguous(), True)
+    hd = torch.stack([(g[2 * j, j] - g[2 * j + 1, j]) / (2 * h) for j in range(d)]).abs().clamp_min(1e-6)
+    sig = (0.5 / hd.sqrt()).double().cpu().numpy()
+    rho = np.log(np.expm1(sig - 1e-10))
+    phi = np.concatenate([ut[0].double().cpu().numpy(), np.zeros(d * (d + 1) // 2)])
+    phi[d + np.arange(d) * (np.arange(d) + 3) // 2] = rho
+    x = torch.tensor(phi, dtype=torch.float32, device=dev)
+    m = torch.zeros_like(x)
+    s = torch.zeros_like(x)
+    seed, lr = synth.SEED_HMC + 1, 1e-4
+    lens.lens_svi_reset(plan)
+    # warm-up and timed calls pass prefixes of one buffer: same pointer, so the captured graph is reused
+    ebuf = torch.empty(max(args.warmup, args.steps), dtype=torch.float64, device=dev)
+    lens.lens_svi_run(plan, x, m, s, n, args.warmup, "adabelief", lr, 0.95, 0.99, 1e-16, seed,
+                      elbo=ebuf[:args.warmup], use_graph=True)
+    torch.cuda.synchronize()
+    el = ebuf[:args.steps]
+    t0 = time.perf_counter()
+    lens.lens_svi_run(plan, x, m, s, n, args.steps, "adabelief", lr, 0.95, 0.99, 1e-16, seed, elbo=el,
+                      use_graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    elbos = el.cpu().numpy()
+    # one eager step with per-kernel events for the adjoint's roofline; series lengths of these draws
+    plan.enable_timing(True)
+    lens.lens_svi_run(plan, x, m, s, n, 1, "adabelief", lr, 0.95, 0.99, 1e-16, seed, use_graph=False)
+    torch.cuda.synchronize()
+    plan.enable_timing(False)
+    tim = plan.read_timing()
+    adj_ms = tim["adjoint"][0] / max(tim["adjoint"][1], 1)
+    _, _, u = lens.lens_svi_elbo_grad(plan, x, n, seed, 0, want_u=True)
+    _, _, th = lens.lens_logpost_grad(plan, u[:256].contiguous(), True, want_theta=True)
+    steps_k = _series_terms(th.cpu().numpy(), spec).mean(axis=0)
+    fl = adjoint_flops_per_subpixel(steps_k[0], steps_k[1], spec.n_lens_light, spec.n_source, True)
+    achieved = fl * (spec.nx * spec.supersample) ** 2 * n / (adj_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None, "kernel": "k_adjoint",
+            "avg_ms": round(adj_ms, 4), "note": "series lengths from 256 of the step's draws"}
+    _line(args, n / dt, "evals/s", dt * 1e3,
+          "SVI: 100x100 px EPL system, full-covariance Gaussian surrogate (d = 29), 4096 draws per step, "
+          "AdaBelief lr 1e-4, hipGraph steps",
+          {"draws": n, "svi_steps_per_s": round(1.0 / dt, 3), "elbo_first": round(float(elbos[0]), 3),
+           "elbo_last": round(float(elbos[-1]), 3)}, roof)
 
 
 def run_batch(args):

@@ -208,7 +208,8 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
  *
  * Surrogate parameters phi (float32, length lens_svi_num_params(d) =
  * d + d(d+1)/2): mu, then the lower triangle of L row by row; a diagonal
- * entry holds rho with L_jj = softplus(rho) + 1e-5.
+ * entry holds rho with L_jj = softplus(rho) + 1e-10 (a guard against underflow
+ * only: conditional posterior widths reach ~4e-6 on a 100x100 system).
  *
  * eps_i: Philox4x32-10 with key = seed and counters (i, step, block, 1),
  * Box-Muller in float64 (the HMC draws use counter word 3 = 0, so the two

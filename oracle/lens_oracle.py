@@ -605,7 +605,7 @@ def hmc_transition(u, logp_grad_fn, inv_mass, eps: float, L: int, seed: int, cha
 # log posterior in the unconstrained space with the bijection's Jacobian
 # (the density of u).
 # ---------------------------------------------------------------------------
-SVI_DIAG_SHIFT = 1e-5
+SVI_DIAG_SHIFT = 1e-10
 SVI_RNG_TAG = 1          # counter word 3 of the surrogate draws (HMC's is 0)
 
 

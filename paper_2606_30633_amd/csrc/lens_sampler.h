@@ -37,7 +37,7 @@ struct HmcArgs {
 
 // SVI: surrogate draws, ELBO + pathwise gradient, optimizer step.
 constexpr int SVI_MAX_D = 50;                 // 8 + 7 * (3 lens-light + 3 source components)
-constexpr double SVI_DIAG_SHIFT = 1e-5;
+constexpr double SVI_DIAG_SHIFT = 1e-10;
 constexpr uint32_t SVI_RNG_TAG = 1u;          // counter word 3 (HMC draws use 0)
 constexpr int SVI_OPT_ADAM = 0, SVI_OPT_ADABELIEF = 1;
 
