@@ -217,3 +217,24 @@ def test_svi_argument_errors():
     fresh = lens.LensPlan(spec, psf, data, sysm.invvar, 8, DEV)
     with pytest.raises(lens.LensError):
         lens.lens_svi_elbo_grad(fresh, x, 4, 0)                   # no prior set
+
+
+def test_svi_study_miniature():
+    """The MAP -> SVI (Adam and AdaBelief) -> HMC study on one small system
+    with short runs (too short for the MAP to find the global mode): every
+    stage runs, the ELBO stays finite and drops from its start, and the HMC
+    stage returns finite samples and diagnostics."""
+    from paper_2606_30633_amd.svi_study import StudyConfig, run_study
+    cfg = StudyConfig(systems=1, n_map=1024, steps_map=600, n_vi=256, steps_vi=300, lr_vi=1e-4, chains=64,
+                      burn=60, n_hmc=60, mass_burn_factor=2)
+    res = run_study(cfg, log=_log)
+    r = res["per_system"][0]
+    assert np.isfinite(r["map_logp"]) and np.isfinite(r["truth_logp"])
+    for opt in ("adam", "adabelief"):
+        assert r[opt]["finite"]
+        assert r[opt]["elbo_last100"] < r[opt]["elbo_first"]
+        assert np.isfinite(r[opt]["vs_hmc"]["std_ratio_median"])
+    h = r["hmc"]
+    assert 0.0 <= h["acceptance"] <= 1.0 and h["eps"] > 0
+    assert np.isfinite(h["rhat_max"]) and np.isfinite(h["ess_min"])
+    assert set(res["summary"]) >= {"adabelief_lower_final_elbo", "hmc_converged"}
