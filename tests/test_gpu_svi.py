@@ -238,3 +238,40 @@ def test_svi_study_miniature():
     assert 0.0 <= h["acceptance"] <= 1.0 and h["eps"] > 0
     assert np.isfinite(h["rhat_max"]) and np.isfinite(h["ess_min"])
     assert set(res["summary"]) >= {"adabelief_lower_final_elbo", "hmc_converged"}
+
+
+@pytest.mark.parametrize("n", [1, 300])
+def test_svi_largest_model_and_ragged_draw_counts(n):
+    """d = 50 (EPL + 3 lens-light + 3 source components: the largest model,
+    which fills the draw kernel's packed-L table) with a single draw and with
+    a draw count that leaves a partial work-group."""
+    spec = synth.ModelSpec(16, 14, 0.15, 2, 3, "EPL", 3, 3)
+    assert spec.n_params == 50
+    _log(f"svi d=50 n={n}")
+    sysm, psf, data, table, plan, phi, f = _setup(spec, 4, 320, scale=0.02)
+    elbo, g, u = lens.lens_svi_elbo_grad(plan, torch.tensor(phi, device=DEV), n, 21, 2, want_u=True)
+    elbo, g, u = float(elbo.item()), g.cpu().numpy(), u.cpu().numpy()
+    picks = list(range(n)) if n <= 4 else [0, 255, 256, n - 1]
+    E = np.stack([O.svi_normals(50, 21, i, 2) for i in range(n)])
+    mu64, L64 = (t.numpy() for t in O.svi_unpack(torch.tensor(phi.astype(np.float64)), 50))
+    np.testing.assert_allclose(u, (mu64[None, :] + E @ L64.T).astype(np.float32), rtol=2.4e-7, atol=1e-7)
+    if n == 1:
+        eo, go, _ = O.svi_elbo_grad(phi.astype(np.float64), E, f)
+        assert abs(elbo - eo) <= RTOL * abs(eo)
+        assert np.linalg.norm(g - go) <= RTOL * np.linalg.norm(go)
+    else:
+        lp, gu = lens.lens_logpost_grad(plan, torch.tensor(u, device=DEV), True)
+        lp, gu = lp.cpu().numpy(), gu.cpu().numpy().astype(np.float64)
+        for i in picks:
+            lo, go = f(u[i:i + 1])
+            assert abs(lp[i] - lo[0]) <= RTOL * abs(lo[0])
+            assert np.linalg.norm(gu[i] - go[0]) <= RTOL * np.linalg.norm(go[0])
+        logq = -0.5 * (E * E).sum(1) - np.log(np.diag(L64)).sum() - 25 * math.log(2 * math.pi)
+        assert abs(elbo - np.mean(logq - lp)) <= 1e-9 * abs(elbo)
+        r, c = np.tril_indices(50)
+        gL = -(gu.T @ E) / n
+        gt = gL[r, c]
+        rho = phi.astype(np.float64)[50:][r == c]
+        gt[r == c] = (gt[r == c] - 1 / np.diag(L64)) / (1 + np.exp(-rho))
+        g_ref = np.concatenate([-gu.mean(0), gt])
+        np.testing.assert_allclose(g, g_ref, rtol=1e-6, atol=1e-6 * np.abs(g_ref).max())
