@@ -728,3 +728,87 @@ def svi_moments(phi, d: int) -> Tuple[np.ndarray, np.ndarray]:
     """Mean and covariance L L^T of the surrogate."""
     mu, L = svi_unpack(torch.tensor(np.asarray(phi, dtype=np.float64)), d)
     return mu.numpy(), (L @ L.T).numpy()
+
+
+# ---------------------------------------------------------------------------
+# "Backward" modelling (Sec. 3: the lens and source intensities solved by
+# linear inversion instead of being parameters).  For fixed nonlinear
+# parameters the model is linear in the intensities A_k of the K light
+# components: m = sum_k A_k B_k with B_k the model image of component k at
+# unit intensity.  A = argmin_A sum w (d - m)^2 solves the weighted normal
+# equations M A = b, M_kl = sum w B_k B_l, b_k = sum w B_k d.  The intensity
+# entries of the parameter vector are ignored.
+# ---------------------------------------------------------------------------
+BACKWARD_PIVOT_REL = 1e-12
+
+
+def intensity_slots(spec) -> List[int]:
+    """Indices of the Sersic intensities I_e in the parameter vector."""
+    base = 8 if spec.mass_model == "EPL" else 7
+    return [base + 7 * k + 6 for k in range(spec.n_lens_light + spec.n_source)]
+
+
+def component_images(theta, spec, psf) -> torch.Tensor:
+    """[K, ny, nx]: the model image of each light component at unit intensity
+    (the others at zero)."""
+    th = _t(theta)
+    slots = intensity_slots(spec)
+    keep = torch.ones(th.shape[0], dtype=DT)
+    keep[slots] = 0.0
+    out = []
+    for s in slots:
+        e = torch.zeros(th.shape[0], dtype=DT)
+        e[s] = 1.0
+        out.append(model_image(th * keep + e, spec, psf))
+    return torch.stack(out)
+
+
+def solve_normal_equations(M: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """Solve M A = b (M symmetric positive semi-definite) by Cholesky in index
+    order.  A component whose pivot is not above BACKWARD_PIVOT_REL x the
+    largest diagonal entry of M (its image is zero, or a combination of the
+    earlier components' images) is left out with A_k = 0."""
+    K = M.shape[0]
+    tol = BACKWARD_PIVOT_REL * float(torch.max(torch.diagonal(M)).detach())
+    Lc = [[None] * K for _ in range(K)]
+    active: List[int] = []
+    for j in range(K):
+        s = M[j, j] - sum((Lc[j][i] * Lc[j][i] for i in active), torch.zeros((), dtype=M.dtype))
+        if not float(s.detach()) > tol:
+            continue
+        Lc[j][j] = torch.sqrt(s)
+        for r in range(j + 1, K):
+            Lc[r][j] = (M[r, j] - sum((Lc[r][i] * Lc[j][i] for i in active), torch.zeros((), dtype=M.dtype))) / Lc[j][j]
+        active.append(j)
+    y = {}
+    for j in active:                       # L y = b
+        y[j] = (b[j] - sum((Lc[j][i] * y[i] for i in active if i < j), torch.zeros((), dtype=M.dtype))) / Lc[j][j]
+    x = {}
+    for j in reversed(active):             # L^T x = y
+        x[j] = (y[j] - sum((Lc[r][j] * x[r] for r in active if r > j), torch.zeros((), dtype=M.dtype))) / Lc[j][j]
+    return torch.stack([x[j] if j in x else torch.zeros((), dtype=M.dtype) for j in range(K)])
+
+
+def loglike_backward(theta, spec, psf, data, invvar, with_grad: bool = True):
+    """logL at the solved intensities, its gradient with respect to the
+    parameter vector (zero in the intensity entries) and the intensities.
+
+    Returns (logL, grad [d] or None, A [K]); (-inf, zeros, nan) when a
+    component's ellipticity is invalid."""
+    th = _t(theta).clone().requires_grad_(with_grad)
+    K = spec.n_lens_light + spec.n_source
+    if not ellipticity_valid(th, spec):
+        return -math.inf, (np.zeros(th.shape[0]) if with_grad else None), np.full(K, np.nan)
+    B = component_images(th, spec, psf).reshape(K, -1)
+    w = _t(invvar).reshape(-1)
+    dd = _t(data).reshape(-1)
+    M = (B * w) @ B.T
+    b = (B * w) @ dd
+    A = solve_normal_equations(M, b)
+    m = (A[:, None] * B).sum(0)
+    L = -0.5 * (w * (dd - m) ** 2).sum()
+    g = None
+    if with_grad:
+        (g,) = torch.autograd.grad(L, th)
+        g = g.numpy()
+    return float(L.detach()), g, A.detach().numpy()
