@@ -124,6 +124,27 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
                               float* d_logl, float* d_grad, double* d_logl64,
                               void* stream);
 
+/* Backward modelling (Sec. 3: the lens and source intensities solved by
+ * linear inversion instead of sampled).  For each particle the K =
+ * n_lens_light + n_source Sersic intensities are set to the weighted
+ * least-squares solution A of the normal equations M A = b,
+ * M_kl = sum w B_k B_l, b_k = sum w B_k d, with B_k the model image of
+ * component k at unit intensity (Cholesky in component order; a component
+ * whose pivot is <= 1e-12 x max_k M_kk, i.e. no flux in the cutout or an
+ * image that is a combination of the earlier components', gets A_k = 0).
+ * logL and its gradient are those at the solved intensities; the gradient is
+ * with respect to the nonlinear parameters (envelope theorem), its intensity
+ * entries are 0.
+ *   d_theta [P][d] in (intensity entries ignored); d_logl [P], d_grad [P][d]
+ *   out; d_amp [P][K] out, optional: the solved intensities (NaN for a
+ *   particle with an invalid ellipticity, whose logL is -inf).
+ * Requires P * K <= max_particles (the K unit-intensity copies of every
+ * particle are rendered together).  Allocates its scratch (two parameter
+ * arrays and one model-image array of max_particles rows) on first use.
+ * Errors: LENS_EINVAL for P * K above max_particles. */
+lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
+                                       float* d_grad, float* d_amp, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Prior and bijection to the unconstrained space (Sec. 3.1: the tilde
  * quantities are the parameters mapped to an unconstrained space; Sec. 4.2,

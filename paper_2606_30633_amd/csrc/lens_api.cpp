@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "lens_internal.h"
+#include "lens_backward.h"
 #include "lens_sampler.h"
 
 using namespace lens;
@@ -99,6 +100,9 @@ struct lens_plan {
     float* svi_u;             // [maxP][d] surrogate samples
     double* svi_eps;          // [d][maxP] their standard normals
     double* svi_logq;         // [maxP]
+    float* bwd_thx;           // [maxP][d] unit-intensity copies (backward likelihood; on first use)
+    float* bwd_img;           // [maxP][npix] their model images
+    float* bwd_theta;         // [maxP][d] parameters with the solved intensities
     int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC base,
                               // [4] SVI step, [5] SVI steps in this run, [6] step of lens_svi_elbo_grad
     hipStream_t cap_stream;
@@ -194,7 +198,8 @@ lens_status lens_plan_destroy(lens_plan* plan) {
     plan->svi_graph.reset();
     void* bufs[] = {plan->prior, plan->theta, plan->gtheta, plan->logl, plan->logl64, plan->logp,
                     plan->gradu, plan->hmc_u0, plan->hmc_g0, plan->hmc_p, plan->hmc_logp0,
-                    plan->hmc_h0, plan->svi_u, plan->svi_eps, plan->svi_logq, plan->counters};
+                    plan->hmc_h0, plan->svi_u, plan->svi_eps, plan->svi_logq, plan->bwd_thx,
+                    plan->bwd_img, plan->bwd_theta, plan->counters};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
@@ -347,6 +352,57 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta, 
     if (!plan || !d_theta || !d_logl || !d_grad || P < 1 || P > plan->max_particles)
         return LENS_EINVAL;
     return loglike_grad_enqueue(plan, P, d_theta, d_logl, d_grad, d_logl64, (hipStream_t)stream);
+}
+
+static BwdSlots bwd_slots(const lens_plan* plan) {
+    BwdSlots s{};
+    s.K = plan->desc.n_lens_light + plan->desc.n_source;
+    s.d = plan->mi.d;
+    const int base = plan->desc.mass_model == LENS_MASS_EPL ? 8 : 7;
+    for (int k = 0; k < s.K; ++k) s.slot[k] = base + 7 * k + 6;
+    return s;
+}
+
+lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
+                                       float* d_grad, float* d_amp, void* stream) {
+    if (!plan || !d_theta || !d_logl || !d_grad || P < 1) return LENS_EINVAL;
+    const BwdSlots s = bwd_slots(plan);
+    if (s.K < 1 || s.K > BWD_MAX_K || (long)P * s.K > plan->max_particles) return LENS_EINVAL;
+    const size_t Pd = (size_t)plan->max_particles * s.d;
+    const size_t npix = (size_t)plan->geo.npix;
+    if (!plan->bwd_thx) {
+        if (hipMalloc(&plan->bwd_thx, sizeof(float) * Pd) != hipSuccess ||
+            hipMalloc(&plan->bwd_img, sizeof(float) * npix * plan->max_particles) != hipSuccess ||
+            hipMalloc(&plan->bwd_theta, sizeof(float) * Pd) != hipSuccess) {
+            for (float** b : {&plan->bwd_thx, &plan->bwd_img, &plan->bwd_theta})
+                if (*b) {
+                    (void)hipFree(*b);
+                    *b = nullptr;
+                }
+            return LENS_ENOMEM;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int PK = P * s.K;
+    if (launch_bwd_expand(P, s, d_theta, plan->bwd_thx, st) != hipSuccess) return LENS_EHIP;
+    lens_status r = front(plan, PK, plan->bwd_thx, st);
+    if (r != LENS_OK) return r;
+    hipError_t e;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
+        e = launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 0, PK, plan->consts, plan->imgbuf,
+                       plan->psf_flip, plan->psf, plan->data, plan->invvar, plan->bwd_img, nullptr, nullptr, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_FINALIZE, st);
+        e = launch_bwd_normal(P, s, (int)npix, plan->bwd_img, plan->data, plan->invvar, plan->consts, d_theta,
+                              plan->bwd_theta, d_amp, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
+    r = loglike_grad_enqueue(plan, P, plan->bwd_theta, d_logl, d_grad, nullptr, st);
+    if (r != LENS_OK) return r;
+    return hip_status(launch_bwd_zero_slots(P, s, d_grad, st));
 }
 
 // Enqueues logp(u) and dlogp/du (no argument checks).  theta_out may be null.

@@ -1,0 +1,185 @@
+// Backward ("linear inversion") likelihood: the Sersic intensities are solved
+// for, not sampled (Sec. 3: forward vs backward modelling of the surface
+// brightness).  For fixed nonlinear parameters the model image is
+// m = sum_k A_k B_k, with B_k the PSF-convolved, downsampled image of light
+// component k at unit intensity; the intensities minimise
+// chi^2 = sum w (d - m)^2, i.e. solve M A = b with M_kl = sum w B_k B_l and
+// b_k = sum w B_k d.  The component images come from the ordinary render and
+// PSF kernels run on K copies of each particle (unit intensity one at a time);
+// the kernels here expand the parameters, reduce and solve the normal
+// equations per particle in float64, and clear the intensity entries of the
+// gradient (which, by the envelope theorem, is the forward gradient at the
+// solved intensities).
+#include <math.h>
+#include <stdint.h>
+
+#include "lens_backward.h"
+#include "lens_internal.h"
+
+namespace lens {
+
+__global__ void k_bwd_expand(int P, BwdSlots s, const float* __restrict__ theta, float* __restrict__ thx) {
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = (long)P * s.K * s.d;
+    if (q >= total) return;
+    const int j = (int)(q % s.d);
+    const long row = q / s.d;
+    const int k = (int)(row % s.K);
+    const long p = row / s.K;
+    float v = theta[p * s.d + j];
+    for (int c = 0; c < s.K; ++c)
+        if (s.slot[c] == j) v = (c == k) ? 1.0f : 0.0f;
+    thx[q] = v;
+}
+
+// Solve M x = b (K x K, symmetric positive semi-definite) by Cholesky in
+// index order; a component whose pivot is not above BWD_PIVOT_REL x max diag
+// is left out (x_k = 0).
+template <int K>
+__device__ void solve_skip(const double (&M)[K][K], const double (&b)[K], double (&x)[K]) {
+    double Lc[K][K];
+    bool on[K];
+    double dmax = 0.0;
+    for (int j = 0; j < K; ++j) dmax = fmax(dmax, M[j][j]);
+    const double tol = BWD_PIVOT_REL * dmax;
+    for (int j = 0; j < K; ++j) {
+        double s = M[j][j];
+        for (int i = 0; i < j; ++i)
+            if (on[i]) s -= Lc[j][i] * Lc[j][i];
+        on[j] = s > tol;
+        if (!on[j]) continue;
+        Lc[j][j] = sqrt(s);
+        for (int r = j + 1; r < K; ++r) {
+            double t = M[r][j];
+            for (int i = 0; i < j; ++i)
+                if (on[i]) t -= Lc[r][i] * Lc[j][i];
+            Lc[r][j] = t / Lc[j][j];
+        }
+    }
+    double y[K];
+    for (int j = 0; j < K; ++j) {
+        if (!on[j]) continue;
+        double t = b[j];
+        for (int i = 0; i < j; ++i)
+            if (on[i]) t -= Lc[j][i] * y[i];
+        y[j] = t / Lc[j][j];
+    }
+    for (int j = K - 1; j >= 0; --j) {
+        if (!on[j]) {
+            x[j] = 0.0;
+            continue;
+        }
+        double t = y[j];
+        for (int r = j + 1; r < K; ++r)
+            if (on[r]) t -= Lc[r][j] * x[r];
+        x[j] = t / Lc[j][j];
+    }
+}
+
+// One work-group of 256 threads per particle: fixed-order float64 sums of
+// the K(K+1)/2 + K normal-equation entries over the pixels, then one thread
+// solves.
+template <int K>
+__global__ __launch_bounds__(256) void k_bwd_normal(int P, BwdSlots s, int npix, const float* __restrict__ B,
+                                                    const float* __restrict__ data,
+                                                    const float* __restrict__ invvar,
+                                                    const float* __restrict__ consts_x,
+                                                    const float* __restrict__ theta, float* __restrict__ theta_full,
+                                                    float* __restrict__ amp) {
+    constexpr int NM = K * (K + 1) / 2;
+    constexpr int NV = NM + K;
+    __shared__ double red[NV][256];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const float* Bp = B + (size_t)p * K * npix;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int pix = tid; pix < npix; pix += 256) {
+        const double w = (double)invvar[pix], dd = (double)data[pix];
+        double bk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) bk[k] = (double)Bp[(size_t)k * npix + pix];
+        int v = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double wb = w * bk[k];
+#pragma unroll
+            for (int l = 0; l <= k; ++l) {
+                acc[v] = fma(wb, bk[l], acc[v]);
+                ++v;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[NM + k] = fma(w * bk[k], dd, acc[NM + k]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) red[v][tid] = acc[v];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) red[v][tid] += red[v][tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const int d = s.d;
+    const bool valid = consts_x[(size_t)p * K * CSTRIDE + C_VALID] == 1.0f;
+    double M[K][K], b[K], x[K];
+    int v = 0;
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l <= k; ++l) {
+            M[k][l] = red[v][0];
+            M[l][k] = red[v][0];
+            ++v;
+        }
+    for (int k = 0; k < K; ++k) b[k] = red[NM + k][0];
+    if (valid) {
+        solve_skip<K>(M, b, x);
+    } else {
+        for (int k = 0; k < K; ++k) x[k] = __builtin_nan("");
+    }
+    const float* tp = theta + (size_t)p * d;
+    float* tf = theta_full + (size_t)p * d;
+    for (int j = 0; j < d; ++j) tf[j] = tp[j];
+    for (int k = 0; k < K; ++k) {
+        tf[s.slot[k]] = valid ? (float)x[k] : 0.0f;
+        if (amp) amp[(size_t)p * K + k] = (float)x[k];
+    }
+}
+
+__global__ void k_bwd_zero_slots(int P, BwdSlots s, float* __restrict__ grad) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P * s.K) return;
+    const int p = q / s.K, k = q - (q / s.K) * s.K;
+    grad[(size_t)p * s.d + s.slot[k]] = 0.0f;
+}
+
+hipError_t launch_bwd_expand(int P, const BwdSlots& s, const float* theta, float* thx, hipStream_t st) {
+    const long total = (long)P * s.K * s.d;
+    hipLaunchKernelGGL(k_bwd_expand, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, P, s, theta, thx);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_normal(int P, const BwdSlots& s, int npix, const float* B, const float* data,
+                             const float* invvar, const float* consts_x, const float* theta, float* theta_full,
+                             float* amp, hipStream_t st) {
+    switch (s.K) {
+#define LENS_BWD_CASE(KK)                                                                                  \
+    case KK:                                                                                               \
+        hipLaunchKernelGGL(k_bwd_normal<KK>, dim3(P), dim3(256), 0, st, P, s, npix, B, data, invvar, consts_x, \
+                           theta, theta_full, amp);                                                        \
+        break;
+        LENS_BWD_CASE(1) LENS_BWD_CASE(2) LENS_BWD_CASE(3) LENS_BWD_CASE(4) LENS_BWD_CASE(5) LENS_BWD_CASE(6)
+#undef LENS_BWD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_zero_slots(int P, const BwdSlots& s, float* grad, hipStream_t st) {
+    hipLaunchKernelGGL(k_bwd_zero_slots, dim3((unsigned)((P * s.K + 255) / 256)), dim3(256), 0, st, P, s, grad);
+    return hipGetLastError();
+}
+
+}  // namespace lens

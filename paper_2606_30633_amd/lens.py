@@ -48,6 +48,7 @@ _SIGNATURES = {
     "lens_forward": (_I, [_P, _I, _P, _P, _P]),
     "lens_loglike": (_I, [_P, _I, _P, _P, _P]),
     "lens_loglike_grad": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "lens_loglike_grad_backward": (_I, [_P, _I, _P, _P, _P, _P, _P]),
     "lens_plan_set_prior": (_I, [_P, _P]),
     "lens_logpost_grad": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
     "lens_map_reset": (_I, [_P]),
@@ -259,6 +260,20 @@ def lens_loglike_grad(plan: LensPlan, theta: torch.Tensor, logl: Optional[torch.
     if logl64 is not None:
         return logl, grad, logl64
     return logl, grad
+
+
+def lens_loglike_grad_backward(plan: LensPlan, theta: torch.Tensor, stream=None):
+    """Backward modelling: logL and dlogL/dtheta at the intensities solved by
+    linear inversion, and those intensities [P, K]."""
+    th = plan._theta(theta)
+    P = th.shape[0]
+    K = plan.spec.n_lens_light + plan.spec.n_source
+    logl = torch.empty(P, dtype=torch.float32, device=plan.device)
+    grad = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
+    amp = torch.empty((P, K), dtype=torch.float32, device=plan.device)
+    _check(_lib.lens_loglike_grad_backward(plan.handle, P, th.data_ptr(), logl.data_ptr(), grad.data_ptr(),
+                                           amp.data_ptr(), _stream(stream)), "lens_loglike_grad_backward")
+    return logl, grad, amp
 
 
 class LensLogLike(torch.autograd.Function):

@@ -1,0 +1,158 @@
+"""GPU parity of the backward (linear-inversion) likelihood against the oracle
+(oracle.loglike_backward: component images at unit intensity, weighted
+normal equations, Cholesky with left-out components, autograd through the
+solve).
+
+Tolerances: logL and the gradient as for the forward likelihood (1e-5
+relative; near the optimum the per-component scale-aware form); the solved
+intensities to 1e-5 relative plus 1e-3 of their statistical uncertainty
+sqrt(diag M^-1) (the float32 component images set how well the solve is
+determined; the measured difference is below 1.5e-6 relative and 2e-4 of
+that uncertainty).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lens_oracle as O
+from paper_2606_30633_amd import synth
+from tests.cases import make_case
+
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2606_30633_amd import lens  # noqa: E402
+
+DEV = "cuda"
+RTOL = 1e-5
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _with_amps(t, spec, A):
+    t = np.array(t, dtype=np.float64)
+    t[O.intensity_slots(spec)] = A
+    return t
+
+
+def _check(spec, psf, data, invvar, th, L, G, A, near=()):
+    K = spec.n_lens_light + spec.n_source
+    slots = O.intensity_slots(spec)
+    for p in range(th.shape[0]):
+        lo, go, ao = O.loglike_backward(th[p], spec, psf, data, invvar)
+        if not np.isfinite(lo):
+            assert L[p] == lo and np.all(G[p] == 0) and np.all(np.isnan(A[p]))
+            continue
+        full = _with_amps(th[p], spec, ao)
+        m = O.model_image(full, spec, psf).numpy()
+        fp32 = 2.0 * float(np.sum(invvar * np.abs(data - m) * np.abs(m))) * 2.0 ** -23
+        assert abs(float(L[p]) - lo) <= RTOL * abs(lo) + fp32, (p, L[p], lo)
+        B = O.component_images(th[p], spec, psf).numpy().reshape(K, -1)
+        Mo = (B * invvar.reshape(-1)) @ B.T
+        active = ao != 0
+        sig = np.zeros(K)
+        sig[active] = np.sqrt(np.diag(np.linalg.inv(Mo[np.ix_(active, active)])))
+        assert np.all(np.abs(A[p] - ao) <= RTOL * np.abs(ao) + 1e-3 * sig), (p, A[p], ao, sig)
+        dg = G[p].astype(np.float64) - go
+        assert np.all(G[p][slots] == 0)
+        if p in near:
+            # forward form, plus what the intensities' own tolerance carries
+            # into the gradient: g is quadratic in A, so a central difference
+            # in each intensity slot gives dg/dA_k exactly
+            S = O.gradient_scale(full, spec, psf, data, invvar)
+            tolA = RTOL * np.abs(ao) + 1e-3 * sig
+            prop = np.zeros_like(go)
+            for k, sl in enumerate(slots):
+                h = 1e-3 * max(abs(ao[k]), 1e-3)
+                e = np.zeros_like(full)
+                e[sl] = h
+                dgdA = (O.loglike_and_grad(full + e, spec, psf, data, invvar)[1]
+                        - O.loglike_and_grad(full - e, spec, psf, data, invvar)[1]) / (2 * h)
+                prop += np.abs(dgdA) * tolA[k]
+            prop[slots] = 0
+            assert np.all(np.abs(dg) <= RTOL * (np.abs(go) + S) + prop), p
+        else:
+            assert np.linalg.norm(dg) <= RTOL * np.linalg.norm(go), (p, np.linalg.norm(dg) / np.linalg.norm(go))
+
+
+SPECS = [synth.ModelSpec(24, 20, 0.12, 2, 5, "EPL", 1, 2), synth.ModelSpec(30, 26, 0.1, 3, 7, "SIE", 1, 1),
+         synth.ModelSpec(16, 14, 0.15, 2, 3, "EPL", 3, 3), synth.ModelSpec(21, 30, 0.12, 4, 3, "SIE", 0, 1)]
+
+
+@pytest.mark.parametrize("spec", SPECS, ids=["EPL-1-2", "SIE-1-1", "EPL-3-3", "SIE-0-1"])
+def test_backward_matches_oracle(spec):
+    _log(f"backward {spec}")
+    sysm, psf, data, th = make_case(spec, 1, 4, psf="asym", near_truth=2)
+    K = spec.n_lens_light + spec.n_source
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, th.shape[0] * K, DEV)
+    L, G, A = (t.cpu().numpy() for t in lens.lens_loglike_grad_backward(plan, torch.tensor(th, device=DEV)))
+    _check(spec, psf, data, sysm.invvar, th, L, G, A, near=(4, 5))
+
+
+def test_backward_noiseless_truth_recovers_intensities():
+    spec = SPECS[0]
+    sysm, psf, _, _ = make_case(spec, 2, 1, psf="asym")
+    data = O.model_image(sysm.truth, spec, psf).numpy().astype(np.float32)
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, 3, DEV)
+    L, G, A = (t.cpu().numpy() for t in
+               lens.lens_loglike_grad_backward(plan, torch.tensor(sysm.truth[None, :], device=DEV)))
+    np.testing.assert_allclose(A[0], sysm.truth[O.intensity_slots(spec)], rtol=1e-5)
+    # chi^2 at the truth is only the float32 rounding of the data
+    assert -float(L[0]) <= 1e-6 * float(np.sum(sysm.invvar * data.astype(np.float64) ** 2))
+
+
+def test_backward_degenerate_components():
+    """A duplicated source (dependent image) and a source outside the cutout
+    (no flux) are left out with intensity 0, as in the oracle."""
+    spec = SPECS[0]
+    sysm, psf, data, _ = make_case(spec, 3, 1, psf="asym")
+    s1, s2 = O.intensity_slots(spec)[1] - 6, O.intensity_slots(spec)[2] - 6
+    t1 = np.array(sysm.truth, dtype=np.float32)
+    t1[s2:s2 + 6] = t1[s1:s1 + 6]
+    t2 = np.array(sysm.truth, dtype=np.float32)
+    t2[s2 + 4], t2[s2 + 5], t2[s2] = 80.0, 80.0, 0.05
+    th = np.stack([t1, t2])
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, 6, DEV)
+    L, G, A = (t.cpu().numpy() for t in lens.lens_loglike_grad_backward(plan, torch.tensor(th, device=DEV)))
+    assert A[0, 2] == 0 and A[1, 2] == 0
+    assert np.all(np.isfinite(L)) and np.all(np.isfinite(G))
+    for p in range(2):
+        lo, go, ao = O.loglike_backward(th[p], spec, psf, data, sysm.invvar)
+        assert ao[2] == 0
+        assert abs(float(L[p]) - lo) <= RTOL * abs(lo)
+
+
+def test_backward_invalid_particle_and_errors():
+    spec = SPECS[1]
+    sysm, psf, data, th = make_case(spec, 0, 2, psf="asym")
+    bad = th.copy()
+    bad[1, 1], bad[1, 2] = 0.9, 0.9                  # |e| > 1 for the SIE mass (e1, e2 follow theta_E)
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, 4, DEV)
+    L, G, A = (t.cpu().numpy() for t in lens.lens_loglike_grad_backward(plan, torch.tensor(bad, device=DEV)))
+    assert np.isfinite(L[0]) and L[1] == -np.inf and np.all(G[1] == 0) and np.all(np.isnan(A[1]))
+    with pytest.raises(lens.LensError):
+        lens.lens_loglike_grad_backward(plan, torch.tensor(np.vstack([th, th, th]), device=DEV))   # 6 x 2 > 4
+
+
+def test_backward_full_size_sampled():
+    """The benchmarked configuration: 100x100 px EPL system, K = 3 components,
+    4096 particles (12288 unit-intensity renders per call); sampled particles
+    against the oracle."""
+    spec = synth.config2_spec()
+    sysm, psf, data, _ = make_case(spec, 0, 1, psf="double")
+    th = synth.particles_box(sysm, 4096, 0)
+    rng = np.random.default_rng(6)
+    th[-1] = (sysm.truth * (1 + 1e-3 * rng.standard_normal(spec.n_params))).astype(np.float32)
+    _log("backward full size: P=4096, K=3")
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, 3 * 4096, DEV)
+    L, G, A = (t.cpu().numpy() for t in lens.lens_loglike_grad_backward(plan, torch.tensor(th, device=DEV)))
+    sample = [0, 2047, 4095]
+    _check(spec, psf, data, sysm.invvar, th[sample], L[sample], G[sample], A[sample], near=(2,))
+    ok = np.isfinite(L)
+    assert ok.mean() > 0.5 and np.all(np.isfinite(G[ok])) and np.all(np.isfinite(A[ok]))
