@@ -41,9 +41,10 @@ def parse():
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
-    ap.add_argument("--workload", choices=["map", "hmc", "svi", "batch", "cnn"], default="map",
+    ap.add_argument("--workload", choices=["map", "hmc", "svi", "backward", "batch", "cnn"], default="map",
                     help="map: the headline MAP step (default); hmc: 8192 chains x 10 leapfrog on the same "
                          "system; svi: AdaBelief SVI steps with 4096 surrogate draws on the same system; "
+                         "backward: logL + gradient with the intensities solved by linear inversion; "
                          "batch: 100 uneven systems x 512 particles; cnn: network training")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB (plain copy kernel, "
@@ -73,6 +74,13 @@ def adjoint_flops_per_subpixel(K_s, K_a, NL, NS, epl=True):
             + (NL + NS) * (sersic_fwd + sersic_adj))
 
 
+def render_flops_per_subpixel(K_s, NL, NS, epl=True):
+    """Algorithmic flops of the render pass per sub-pixel (FMA = 2, other = 1):
+    the forward part of the adjoint count (float64 series and deflection,
+    shear and lens equation, Sersic values) plus the downsampling sum."""
+    return 4 * K_s + 40 + (60 if epl else 0) + 12 + (NL + NS) * 18 + 1
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -80,7 +88,8 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload != "map":
-        return {"hmc": run_hmc, "svi": run_svi, "batch": run_batch, "cnn": run_cnn}[args.workload](args)
+        return {"hmc": run_hmc, "svi": run_svi, "backward": run_backward, "batch": run_batch,
+                "cnn": run_cnn}[args.workload](args)
     import torch
     from paper_2606_30633_amd import lens, synth
 
@@ -356,6 +365,53 @@ def run_svi(args):
           "AdaBelief lr 1e-4, hipGraph steps",
           {"draws": n, "svi_steps_per_s": round(1.0 / dt, 3), "elbo_first": round(float(elbos[0]), 3),
            "elbo_last": round(float(elbos[-1]), 3)}, roof)
+
+
+def run_backward(args):
+    """Backward modelling on the headline system: logL + gradient with the three
+    Sersic intensities solved by linear inversion, 4096 particles per call
+    (12288 unit-intensity component renders + the logL/adjoint pass)."""
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    dev = torch.device("cuda", 0)
+    spec, sysm = synth.config2_spec(), synth.config2_system()
+    P = 4096
+    K = spec.n_lens_light + spec.n_source
+    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
+    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
+            + torch.tensor(sysm.noise, device=dev)).contiguous()
+    plan = lens.LensPlan(spec, torch.tensor(sysm.psf, device=dev), data, torch.tensor(sysm.invvar, device=dev),
+                         P * K, dev)
+    th_np = synth.particles_box(sysm, P, 0)
+    th = torch.tensor(th_np, device=dev)
+    for _ in range(args.warmup):
+        lens.lens_loglike_grad_backward(plan, th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lens.lens_loglike_grad_backward(plan, th)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    plan.enable_timing(True)
+    L, _, _ = lens.lens_loglike_grad_backward(plan, th)
+    torch.cuda.synchronize()
+    plan.enable_timing(False)
+    tim = plan.read_timing()
+    steps_k = _series_terms(th_np[:256], spec).mean(axis=0)
+    nsub = (spec.nx * spec.supersample) ** 2
+    ren_ms = tim["render"][0]
+    fl = render_flops_per_subpixel(steps_k[0], spec.n_lens_light, spec.n_source, True)
+    achieved = fl * nsub * P * (K + 1) / (ren_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None, "kernel": "k_render",
+            "avg_ms": round(ren_ms / max(tim["render"][1], 1), 4),
+            "kernel_ms_per_step": {k: round(v[0], 4) for k, v in tim.items() if v[1]},
+            "note": "render runs on the K unit-intensity copies and once more on the solved parameters"}
+    _line(args, P / dt, "evals/s", dt * 1e3,
+          "backward modelling: 100x100 px EPL system, 3 Sersic intensities solved by linear inversion per particle, "
+          "4096 particles",
+          {"particles": P, "components": K, "finite_fraction": round(float(torch.isfinite(L).float().mean()), 4)},
+          roof)
 
 
 def run_batch(args):
