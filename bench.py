@@ -30,7 +30,7 @@ PEAK_FP32_PACKED = 157.3
 # WRITE_SIZE passes, scaled by a plain 256 MiB copy (profiles/
 # map_step_100px_4096p_counters.txt).  Valid only for the kernel source it was
 # measured on; reported as null otherwise.
-TRAFFIC_MEASURED = {"kernel_src_sha256_16": "a177c522b91f6fdc", "bytes": 206941249}
+TRAFFIC_MEASURED = {"kernel_src_sha256_16": "bb7dec4797a99ba8", "bytes": 206062001}
 
 
 def parse():
@@ -370,7 +370,8 @@ def run_svi(args):
 def run_backward(args):
     """Backward modelling on the headline system: logL + gradient with the three
     Sersic intensities solved by linear inversion, 4096 particles per call
-    (12288 unit-intensity component renders + the logL/adjoint pass)."""
+    (one render pass writing the 3 unit-intensity component images of each
+    particle, their PSF, the normal equations, then the logL/adjoint pass)."""
     import torch
     from paper_2606_30633_amd import lens, synth
     dev = torch.device("cuda", 0)
@@ -401,12 +402,12 @@ def run_backward(args):
     nsub = (spec.nx * spec.supersample) ** 2
     ren_ms = tim["render"][0]
     fl = render_flops_per_subpixel(steps_k[0], spec.n_lens_light, spec.n_source, True)
-    achieved = fl * nsub * P * (K + 1) / (ren_ms * 1e-3) / 1e12
+    achieved = fl * nsub * P * 2 / (ren_ms * 1e-3) / 1e12          # two render passes per call
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None, "kernel": "k_render",
             "avg_ms": round(ren_ms / max(tim["render"][1], 1), 4),
             "kernel_ms_per_step": {k: round(v[0], 4) for k, v in tim.items() if v[1]},
-            "note": "render runs on the K unit-intensity copies and once more on the solved parameters"}
+            "note": "render: one pass writing the K unit-intensity component images, one on the solved parameters"}
     _line(args, P / dt, "evals/s", dt * 1e3,
           "backward modelling: 100x100 px EPL system, 3 Sersic intensities solved by linear inversion per particle, "
           "4096 particles",

@@ -138,8 +138,8 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
  *   d_theta [P][d] in (intensity entries ignored); d_logl [P], d_grad [P][d]
  *   out; d_amp [P][K] out, optional: the solved intensities (NaN for a
  *   particle with an invalid ellipticity, whose logL is -inf).
- * Requires P * K <= max_particles (the K unit-intensity copies of every
- * particle are rendered together).  Allocates its scratch (two parameter
+ * Requires P * K <= max_particles (the K component images of every particle
+ * are held together in the plan's image buffers).  Allocates its scratch (two parameter
  * arrays and one model-image array of max_particles rows) on first use.
  * Errors: LENS_EINVAL for P * K above max_particles. */
 lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,

@@ -100,8 +100,8 @@ struct lens_plan {
     float* svi_u;             // [maxP][d] surrogate samples
     double* svi_eps;          // [d][maxP] their standard normals
     double* svi_logq;         // [maxP]
-    float* bwd_thx;           // [maxP][d] unit-intensity copies (backward likelihood; on first use)
-    float* bwd_img;           // [maxP][npix] their model images
+    float* bwd_thx;           // [maxP][d] parameters with unit intensities (backward likelihood; on first use)
+    float* bwd_img;           // [maxP][npix] PSF-convolved component images, K per particle
     float* bwd_theta;         // [maxP][d] parameters with the solved intensities
     int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC base,
                               // [4] SVI step, [5] SVI steps in this run, [6] step of lens_svi_elbo_grad
@@ -384,10 +384,19 @@ lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* 
     }
     hipStream_t st = (hipStream_t)stream;
     const int PK = P * s.K;
+    // all intensities 1, one render pass writing each component's image
     if (launch_bwd_expand(P, s, d_theta, plan->bwd_thx, st) != hipSuccess) return LENS_EHIP;
-    lens_status r = front(plan, PK, plan->bwd_thx, st);
-    if (r != LENS_OK) return r;
     hipError_t e;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_PROLOGUE, st);
+        e = launch_prologue(plan->mi, P, plan->bwd_thx, plan->consts, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_RENDER, st);
+        e = launch_render_split(plan->mi, plan->geo, P, plan->ppt, plan->consts, plan->imgbuf, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
     {
         TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
         e = launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 0, PK, plan->consts, plan->imgbuf,
@@ -400,7 +409,7 @@ lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* 
                               plan->bwd_theta, d_amp, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
-    r = loglike_grad_enqueue(plan, P, plan->bwd_theta, d_logl, d_grad, nullptr, st);
+    lens_status r = loglike_grad_enqueue(plan, P, plan->bwd_theta, d_logl, d_grad, nullptr, st);
     if (r != LENS_OK) return r;
     return hip_status(launch_bwd_zero_slots(P, s, d_grad, st));
 }

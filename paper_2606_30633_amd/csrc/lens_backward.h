@@ -14,12 +14,13 @@ struct BwdSlots {
     int slot[BWD_MAX_K];
 };
 
-// thx[(p K + k)][j] = theta[p][j], with the intensities set to 1 for component k and 0 otherwise.
-hipError_t launch_bwd_expand(int P, const BwdSlots& s, const float* theta, float* thx, hipStream_t st);
+// th1[p][j] = theta[p][j], with every intensity set to 1.
+hipError_t launch_bwd_expand(int P, const BwdSlots& s, const float* theta, float* th1, hipStream_t st);
 // Per particle: normal equations from the K unit-intensity model images B [(p K + k)][npix], solve,
-// theta_full = theta with the intensities replaced by the solution; amp [P][K] (optional).
+// theta_full = theta with the intensities replaced by the solution; amp [P][K] (optional);
+// consts: the particles' constants (their validity flags).
 hipError_t launch_bwd_normal(int P, const BwdSlots& s, int npix, const float* B, const float* data,
-                             const float* invvar, const float* consts_expanded, const float* theta,
+                             const float* invvar, const float* consts, const float* theta,
                              float* theta_full, float* amp, hipStream_t st);
 // grad[p][slot] = 0 for every intensity slot.
 hipError_t launch_bwd_zero_slots(int P, const BwdSlots& s, float* grad, hipStream_t st);

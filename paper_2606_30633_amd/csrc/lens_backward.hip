@@ -4,9 +4,9 @@
 // m = sum_k A_k B_k, with B_k the PSF-convolved, downsampled image of light
 // component k at unit intensity; the intensities minimise
 // chi^2 = sum w (d - m)^2, i.e. solve M A = b with M_kl = sum w B_k B_l and
-// b_k = sum w B_k d.  The component images come from the ordinary render and
-// PSF kernels run on K copies of each particle (unit intensity one at a time);
-// the kernels here expand the parameters, reduce and solve the normal
+// b_k = sum w B_k d.  The component images come from a render pass that
+// writes each component's image separately and the ordinary PSF kernel;
+// the kernels here set the intensities to 1, reduce and solve the normal
 // equations per particle in float64, and clear the intensity entries of the
 // gradient (which, by the envelope theorem, is the forward gradient at the
 // solved intensities).
@@ -18,18 +18,14 @@
 
 namespace lens {
 
-__global__ void k_bwd_expand(int P, BwdSlots s, const float* __restrict__ theta, float* __restrict__ thx) {
+__global__ void k_bwd_expand(int P, BwdSlots s, const float* __restrict__ theta, float* __restrict__ th1) {
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long total = (long)P * s.K * s.d;
-    if (q >= total) return;
+    if (q >= (long)P * s.d) return;
     const int j = (int)(q % s.d);
-    const long row = q / s.d;
-    const int k = (int)(row % s.K);
-    const long p = row / s.K;
-    float v = theta[p * s.d + j];
+    float v = theta[q];
     for (int c = 0; c < s.K; ++c)
-        if (s.slot[c] == j) v = (c == k) ? 1.0f : 0.0f;
-    thx[q] = v;
+        if (s.slot[c] == j) v = 1.0f;
+    th1[q] = v;
 }
 
 // Solve M x = b (K x K, symmetric positive semi-definite) by Cholesky in
@@ -83,7 +79,7 @@ template <int K>
 __global__ __launch_bounds__(256) void k_bwd_normal(int P, BwdSlots s, int npix, const float* __restrict__ B,
                                                     const float* __restrict__ data,
                                                     const float* __restrict__ invvar,
-                                                    const float* __restrict__ consts_x,
+                                                    const float* __restrict__ consts,
                                                     const float* __restrict__ theta, float* __restrict__ theta_full,
                                                     float* __restrict__ amp) {
     constexpr int NM = K * (K + 1) / 2;
@@ -124,7 +120,7 @@ __global__ __launch_bounds__(256) void k_bwd_normal(int P, BwdSlots s, int npix,
     }
     if (tid != 0) return;
     const int d = s.d;
-    const bool valid = consts_x[(size_t)p * K * CSTRIDE + C_VALID] == 1.0f;
+    const bool valid = consts[(size_t)p * CSTRIDE + C_VALID] == 1.0f;
     double M[K][K], b[K], x[K];
     int v = 0;
     for (int k = 0; k < K; ++k)
@@ -155,19 +151,19 @@ __global__ void k_bwd_zero_slots(int P, BwdSlots s, float* __restrict__ grad) {
     grad[(size_t)p * s.d + s.slot[k]] = 0.0f;
 }
 
-hipError_t launch_bwd_expand(int P, const BwdSlots& s, const float* theta, float* thx, hipStream_t st) {
-    const long total = (long)P * s.K * s.d;
-    hipLaunchKernelGGL(k_bwd_expand, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, P, s, theta, thx);
+hipError_t launch_bwd_expand(int P, const BwdSlots& s, const float* theta, float* th1, hipStream_t st) {
+    const long total = (long)P * s.d;
+    hipLaunchKernelGGL(k_bwd_expand, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, P, s, theta, th1);
     return hipGetLastError();
 }
 
 hipError_t launch_bwd_normal(int P, const BwdSlots& s, int npix, const float* B, const float* data,
-                             const float* invvar, const float* consts_x, const float* theta, float* theta_full,
+                             const float* invvar, const float* consts, const float* theta, float* theta_full,
                              float* amp, hipStream_t st) {
     switch (s.K) {
 #define LENS_BWD_CASE(KK)                                                                                  \
     case KK:                                                                                               \
-        hipLaunchKernelGGL(k_bwd_normal<KK>, dim3(P), dim3(256), 0, st, P, s, npix, B, data, invvar, consts_x, \
+        hipLaunchKernelGGL(k_bwd_normal<KK>, dim3(P), dim3(256), 0, st, P, s, npix, B, data, invvar, consts,   \
                            theta, theta_full, amp);                                                        \
         break;
         LENS_BWD_CASE(1) LENS_BWD_CASE(2) LENS_BWD_CASE(3) LENS_BWD_CASE(4) LENS_BWD_CASE(5) LENS_BWD_CASE(6)

@@ -96,6 +96,9 @@ hipError_t launch_psf(const ModelInfo& mi, const Geo& g, int K, int mode, int P,
                       const float* consts, float* img, const double* wflip, const float* wpsf,
                       const float* data, const float* invvar, float* out, float* logl,
                       double* logl64, hipStream_t st);
+// img [(p K + c)][npix]: each of the K light components' images of particle p.
+hipError_t launch_render_split(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
+                               float* img, hipStream_t st);
 hipError_t launch_adjoint(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
                           const float* gimg, double* partial, hipStream_t st);
 hipError_t launch_finalize(const ModelInfo& mi, int P, int nchunks, const float* theta,

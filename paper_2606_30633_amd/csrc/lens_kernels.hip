@@ -685,6 +685,56 @@ __global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts
                                img + (size_t)p * g.npix);
 }
 
+// Backward modelling: the image of each light component at the intensity in
+// its constants (the unit-intensity images when every intensity is 1), in
+// one pass, so the deflection is evaluated once per sub-pixel.
+// img [(p (NL + NS) + c)][npix]; lens-light components first, then sources.
+template <int MASS, int NL, int NS>
+__global__ __launch_bounds__(256) void k_render_split(const float* __restrict__ consts, Geo g, int ppb,
+                                                      float* __restrict__ img) {
+    constexpr int NC = NL + NS;
+    init_math_tab();
+    const int p = blockIdx.x;
+    const int pix0 = blockIdx.y * ppb, pix1 = min(pix0 + ppb, g.npix);
+    const float* C = consts + (size_t)p * CSTRIDE;
+    float* out = img + (size_t)p * NC * g.npix;
+    if (C[C_VALID] != 1.0f) {
+        for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x)
+            for (int c = 0; c < NC; ++c) out[(size_t)c * g.npix + pix] = __builtin_nanf("");
+        return;
+    }
+    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) {
+        const int i = pix / g.nx, j = pix - i * g.nx;
+        double acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        for (int a = 0; a < g.s; ++a) {
+            const double y = ((double)(g.s * i + a) - g.cy) * g.h;
+            for (int b = 0; b < g.s; ++b) {
+                const double x = ((double)(g.s * j + b) - g.cx) * g.h;
+#pragma unroll
+                for (int c = 0; c < NL; ++c) {
+                    const SersicK sk = load_sersic(opaque(C + C_SERS + c * SERS_STRIDE));
+                    acc[c] += sersic_val(x - sk.xc, y - sk.yc, sk);
+                }
+                const float* Cm = opaque(C);
+                const PK<0> k = load_pk<0>(Cm);
+                double ax, ay;
+                deflect<MASS, false, 0>(x, y, k, Cm, ax, ay, nullptr);
+                const double bx = x - ax - fma(k.g1, x, k.g2 * y);
+                const double by = y - ay - fma(k.g2, x, -k.g1 * y);
+#pragma unroll
+                for (int c = 0; c < NS; ++c) {
+                    const SersicK sk = load_sersic(opaque(C + C_SERS + (NL + c) * SERS_STRIDE));
+                    acc[NL + c] += sersic_val(bx - sk.xc, by - sk.yc, sk);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[(size_t)c * g.npix + pix] = (float)(acc[c] * (double)g.inv_s2);
+    }
+}
+
 template <int MASS, int NL, int NS>
 // Four waves per SIMD (at most 128 VGPRs): measured faster than the three the
 // register demand would otherwise give, with the few spills left outside the
@@ -1063,6 +1113,19 @@ hipError_t launch_render(const ModelInfo& mi, const Geo& g, int P, int ppt, cons
     const int ppb = 256 * ppt;
     const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
         hipLaunchKernelGGL((k_render<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
+                           grid, dim3(256), 0, st, consts, g, ppb, img);
+    });
+    if (!done) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_render_split(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
+                               float* img, hipStream_t st) {
+    const int nch = chunks_for(g.npix, ppt);
+    const dim3 grid(P, nch);
+    const int ppb = 256 * ppt;
+    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
+        hipLaunchKernelGGL((k_render_split<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
                            grid, dim3(256), 0, st, consts, g, ppb, img);
     });
     if (!done) return hipErrorInvalidValue;
