@@ -812,3 +812,71 @@ def loglike_backward(theta, spec, psf, data, invvar, with_grad: bool = True):
         (g,) = torch.autograd.grad(L, th)
         g = g.numpy()
     return float(L.detach()), g, A.detach().numpy()
+
+
+# ---------------------------------------------------------------------------
+# HMC adaptation during burn-in (Sec. 3.3: the mass matrix fitted to burn-in
+# samples; the step size by dual averaging, Hoffman & Gelman 2014, "The
+# No-U-Turn Sampler", Sec. 3.2.1, with their constants gamma, t0, kappa).
+# All chains share one step size; the adaptation statistic of a transition is
+# the chain mean of min(1, exp(H0 - H1)) (0 for a non-finite energy).
+# ---------------------------------------------------------------------------
+DA_GAMMA, DA_T0, DA_KAPPA = 0.05, 10.0, 0.75
+
+
+def dual_averaging_init(eps0: float) -> Dict[str, float]:
+    """State before the first update: mu = log(10 eps0), log eps = log eps0,
+    log eps_bar = 0, H_bar = 0, m = 0."""
+    return {"mu": math.log(10.0 * eps0), "log_eps": math.log(eps0), "log_eps_bar": 0.0, "H_bar": 0.0, "m": 0}
+
+
+def dual_averaging_update(st: Dict[str, float], alpha: float, delta: float) -> Dict[str, float]:
+    """One update after a transition with adaptation statistic alpha, target delta."""
+    m = st["m"] + 1
+    eta = 1.0 / (m + DA_T0)
+    H_bar = (1.0 - eta) * st["H_bar"] + eta * (delta - alpha)
+    log_eps = st["mu"] - math.sqrt(m) / DA_GAMMA * H_bar
+    w = m ** (-DA_KAPPA)
+    log_eps_bar = w * log_eps + (1.0 - w) * st["log_eps_bar"]
+    return {"mu": st["mu"], "log_eps": log_eps, "log_eps_bar": log_eps_bar, "H_bar": H_bar, "m": m}
+
+
+def accept_prob(H0: float, H1: float) -> float:
+    if not (math.isfinite(H0) and math.isfinite(H1)):
+        return 0.0
+    return min(1.0, math.exp(H0 - H1))
+
+
+def hmc_adapt(U0, logp_grad_fn, inv_mass, eps0: float, delta: float, L: int, n_transitions: int,
+              window_start: int, seed: int, transition0: int = 0, eps_float32: bool = True):
+    """Burn-in of C chains with a shared, dual-averaged step size.
+
+    Transition t (0-based) uses eps_t = exp(log eps) (rounded to float32 with
+    eps_float32: the step size a float32 interface receives) and the Philox
+    counters of transition transition0 + t; after it the step size is
+    updated.  Positions after transitions t >= window_start are collected
+    and their variance per coordinate (over chains and transitions, ddof 1)
+    is returned as the fitted inverse mass matrix.
+    Returns (U [C, d], eps per transition [T], adapted eps = exp(log eps_bar),
+    variance [d] or None, chain-mean acceptance statistic per transition [T]).
+    """
+    U = np.array(U0, dtype=np.float64)
+    C, d = U.shape
+    st = dual_averaging_init(eps0)
+    eps_trace, alphas, window = [], [], []
+    for t in range(n_transitions):
+        eps = math.exp(st["log_eps"])
+        if eps_float32:
+            eps = float(np.float32(eps))
+        eps_trace.append(eps)
+        al = []
+        for c in range(C):
+            U[c], _, _, H0, H1, _ = hmc_transition(U[c], logp_grad_fn, inv_mass, eps, L, seed, c, transition0 + t)
+            al.append(accept_prob(H0, H1))
+        alpha = float(np.mean(al))
+        alphas.append(alpha)
+        st = dual_averaging_update(st, alpha, delta)
+        if t >= window_start:
+            window.append(U.copy())
+    var = np.concatenate(window).var(axis=0, ddof=1) if len(window) * C > 1 else None
+    return U, np.array(eps_trace), math.exp(st["log_eps_bar"]), var, np.array(alphas)
