@@ -219,6 +219,31 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
                          int32_t n_transitions, uint64_t seed, uint64_t transition0,
                          float* d_samples, int32_t* d_accepts, int32_t use_graph, void* stream);
 
+/* HMC burn-in with adaptation: the transitions of lens_hmc_run, with
+ *  - one step size shared by all chains, adapted after every transition by
+ *    dual averaging (Hoffman & Gelman 2014, Sec. 3.2.1: mu = log(10 eps0),
+ *    gamma 0.05, t0 10, kappa 0.75) towards a chain-mean acceptance
+ *    statistic min(1, exp(H0 - H1)) of target_accept;
+ *  - the mass-matrix fit of Sec. 3.3: the variance of the positions over
+ *    the transitions t >= window_start (all chains, ddof 1), from per-chain
+ *    Welford sums combined in a fixed order.
+ * Transition t (0-based in this call) uses Philox counter word 1 =
+ * transition0 + t, like lens_hmc_run.  The step-size state, the window sums
+ * and the counters restart at every call.
+ *   d_u, d_grad, d_logp: chain state in/out as for lens_hmc_run;
+ *   d_inv_mass [d]: the inverse mass matrix used during this burn-in;
+ *   d_eps_trace [n_transitions] out, optional: the step size of each transition;
+ *   d_eps_final [1] out, optional: the adapted step size exp(log eps_bar);
+ *   d_var [d] out, optional: the window variances (the next inverse mass
+ *   matrix; NaN if the window holds fewer than 2 samples).
+ * use_graph as for lens_map_adam (eps0 is not part of the captured graph).
+ * Allocates its state (2 x max_particles x d doubles) on first use.
+ * Errors: LENS_EINVAL for target_accept outside (0, 1) or eps0 <= 0. */
+lens_status lens_hmc_adapt(lens_plan* plan, int32_t C, float* d_u, float* d_grad, double* d_logp,
+                           const float* d_inv_mass, float eps0, float target_accept, int32_t n_leapfrog,
+                           int32_t n_transitions, int32_t window_start, uint64_t seed, uint64_t transition0,
+                           float* d_eps_trace, float* d_eps_final, float* d_var, int32_t use_graph, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Stochastic variational inference (Sec. 3: eq. vi, eq. elbo, eq. elbo-grad;
  * Sec. 3.2: AdaBelief as the SVI optimizer).  The surrogate is a Gaussian

@@ -858,12 +858,14 @@ def hmc_adapt(U0, logp_grad_fn, inv_mass, eps0: float, delta: float, L: int, n_t
     and their variance per coordinate (over chains and transitions, ddof 1)
     is returned as the fitted inverse mass matrix.
     Returns (U [C, d], eps per transition [T], adapted eps = exp(log eps_bar),
-    variance [d] or None, chain-mean acceptance statistic per transition [T]).
+    variance [d] or None, chain-mean acceptance statistic per transition [T],
+    the smallest |log u - (H0 - H1)| of any accept decision).
     """
     U = np.array(U0, dtype=np.float64)
     C, d = U.shape
     st = dual_averaging_init(eps0)
     eps_trace, alphas, window = [], [], []
+    margin = math.inf
     for t in range(n_transitions):
         eps = math.exp(st["log_eps"])
         if eps_float32:
@@ -871,12 +873,14 @@ def hmc_adapt(U0, logp_grad_fn, inv_mass, eps0: float, delta: float, L: int, n_t
         eps_trace.append(eps)
         al = []
         for c in range(C):
-            U[c], _, _, H0, H1, _ = hmc_transition(U[c], logp_grad_fn, inv_mass, eps, L, seed, c, transition0 + t)
+            U[c], _, _, H0, H1, lu = hmc_transition(U[c], logp_grad_fn, inv_mass, eps, L, seed, c, transition0 + t)
             al.append(accept_prob(H0, H1))
+            if math.isfinite(H1):
+                margin = min(margin, abs(lu - (H0 - H1)))
         alpha = float(np.mean(al))
         alphas.append(alpha)
         st = dual_averaging_update(st, alpha, delta)
         if t >= window_start:
             window.append(U.copy())
     var = np.concatenate(window).var(axis=0, ddof=1) if len(window) * C > 1 else None
-    return U, np.array(eps_trace), math.exp(st["log_eps_bar"]), var, np.array(alphas)
+    return U, np.array(eps_trace), math.exp(st["log_eps_bar"]), var, np.array(alphas), margin

@@ -100,13 +100,19 @@ struct lens_plan {
     float* svi_u;             // [maxP][d] surrogate samples
     double* svi_eps;          // [d][maxP] their standard normals
     double* svi_logq;         // [maxP]
+    double* hmc_accprob;      // [maxP] adaptation statistic (lens_hmc_adapt; on first use)
+    double* hmc_state;        // [8] dual-averaging state
+    float* hmc_eps;           // [1] device step size
+    double* hmc_wmean;        // [maxP][d] window means (Welford)
+    double* hmc_wm2;          // [maxP][d] window sums of squared deviations
     float* bwd_thx;           // [maxP][d] parameters with unit intensities (backward likelihood; on first use)
     float* bwd_img;           // [maxP][npix] PSF-convolved component images, K per particle
     float* bwd_theta;         // [maxP][d] parameters with the solved intensities
     int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC base,
-                              // [4] SVI step, [5] SVI steps in this run, [6] step of lens_svi_elbo_grad
+                              // [4] SVI step, [5] SVI steps in this run, [6] step of lens_svi_elbo_grad,
+                              // [7] window samples of lens_hmc_adapt
     hipStream_t cap_stream;
-    GraphCache map_graph, hmc_graph, svi_graph;
+    GraphCache map_graph, hmc_graph, svi_graph, adapt_graph;
 };
 
 namespace {
@@ -196,9 +202,11 @@ lens_status lens_plan_destroy(lens_plan* plan) {
     plan->map_graph.reset();
     plan->hmc_graph.reset();
     plan->svi_graph.reset();
+    plan->adapt_graph.reset();
     void* bufs[] = {plan->prior, plan->theta, plan->gtheta, plan->logl, plan->logl64, plan->logp,
                     plan->gradu, plan->hmc_u0, plan->hmc_g0, plan->hmc_p, plan->hmc_logp0,
-                    plan->hmc_h0, plan->svi_u, plan->svi_eps, plan->svi_logq, plan->bwd_thx,
+                    plan->hmc_h0, plan->svi_u, plan->svi_eps, plan->svi_logq, plan->hmc_accprob,
+                    plan->hmc_state, plan->hmc_eps, plan->hmc_wmean, plan->hmc_wm2, plan->bwd_thx,
                     plan->bwd_img, plan->bwd_theta, plan->counters};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -443,6 +451,7 @@ lens_status lens_plan_set_prior(lens_plan* plan, const float* h_table) {
     plan->map_graph.reset();
     plan->hmc_graph.reset();
     plan->svi_graph.reset();
+    plan->adapt_graph.reset();
     return LENS_OK;
 }
 
@@ -554,7 +563,7 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
     if (!plan->prior) return LENS_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const int d = plan->mi.d;
-    HmcArgs a;
+    HmcArgs a{};
     a.u = d_u; a.grad = d_grad; a.logp = d_logp;
     a.u0 = plan->hmc_u0; a.g0 = plan->hmc_g0; a.logp0 = plan->hmc_logp0;
     a.p = plan->hmc_p; a.h0 = plan->hmc_h0; a.inv_mass = d_inv_mass;
@@ -686,6 +695,90 @@ lens_status lens_svi_moments(int32_t d, const float* d_phi, float* d_mean, float
                              void* stream) {
     if (d < 1 || d > SVI_MAX_D || !d_phi) return LENS_EINVAL;
     return hip_status(launch_svi_moments(d, d_phi, d_mean, d_cov, d_var, (hipStream_t)stream));
+}
+
+lens_status lens_hmc_adapt(lens_plan* plan, int32_t C, float* d_u, float* d_grad, double* d_logp,
+                           const float* d_inv_mass, float eps0, float target_accept, int32_t n_leapfrog,
+                           int32_t n_transitions, int32_t window_start, uint64_t seed, uint64_t transition0,
+                           float* d_eps_trace, float* d_eps_final, float* d_var, int32_t use_graph, void* stream) {
+    if (!plan || !d_u || !d_grad || !d_logp || !d_inv_mass || C < 1 || C > plan->max_particles ||
+        n_leapfrog < 1 || n_transitions < 0 || window_start < 0 || !(eps0 > 0.0f) ||
+        !(target_accept > 0.0f && target_accept < 1.0f))
+        return LENS_EINVAL;
+    if (!plan->prior) return LENS_EINVAL;
+    const int d = plan->mi.d;
+    const size_t Pd = (size_t)plan->max_particles * d;
+    if (!plan->hmc_accprob) {
+        if (hipMalloc(&plan->hmc_accprob, sizeof(double) * plan->max_particles) != hipSuccess ||
+            hipMalloc(&plan->hmc_state, sizeof(double) * 8) != hipSuccess ||
+            hipMalloc(&plan->hmc_eps, sizeof(float) * 2) != hipSuccess ||
+            hipMalloc(&plan->hmc_wmean, sizeof(double) * Pd) != hipSuccess ||
+            hipMalloc(&plan->hmc_wm2, sizeof(double) * Pd) != hipSuccess) {
+            void** bs[] = {(void**)&plan->hmc_accprob, (void**)&plan->hmc_state, (void**)&plan->hmc_eps,
+                           (void**)&plan->hmc_wmean, (void**)&plan->hmc_wm2};
+            for (void** b : bs)
+                if (*b) {
+                    (void)hipFree(*b);
+                    *b = nullptr;
+                }
+            return LENS_ENOMEM;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HmcArgs a{};
+    a.u = d_u; a.grad = d_grad; a.logp = d_logp;
+    a.u0 = plan->hmc_u0; a.g0 = plan->hmc_g0; a.logp0 = plan->hmc_logp0;
+    a.p = plan->hmc_p; a.h0 = plan->hmc_h0; a.inv_mass = d_inv_mass;
+    a.tcount = plan->counters + 1;
+    a.seed = seed;
+    a.transition0 = transition0;
+    a.eps = eps0;
+    a.eps_dev = plan->hmc_eps;
+    a.accprob = plan->hmc_accprob;
+    AdaptArgs ad{};
+    ad.state = plan->hmc_state;
+    ad.accprob = plan->hmc_accprob;
+    ad.eps_dev = plan->hmc_eps;
+    ad.eps_trace = d_eps_trace;
+    ad.eps_final = d_eps_final;
+    ad.tcount = plan->counters + 1;
+    ad.delta = target_accept;
+    int* wcount = plan->counters + 7;
+    auto transition = [&](hipStream_t s) -> lens_status {
+        {
+            TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+            if (launch_hmc_begin(C, d, a, s) != hipSuccess) return LENS_EHIP;
+        }
+        for (int l = 0; l < n_leapfrog; ++l) {
+            if (l > 0) {
+                TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+                if (launch_hmc_kick_drift(C, d, a, s) != hipSuccess) return LENS_EHIP;
+            }
+            lens_status r = logpost_enqueue(plan, C, d_u, 1, nullptr, d_logp, d_grad, s);
+            if (r != LENS_OK) return r;
+        }
+        TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, s);
+        if (launch_hmc_end(C, d, a, s) != hipSuccess || launch_hmc_adapt(C, ad, s) != hipSuccess ||
+            launch_hmc_welford(C, d, d_u, plan->counters + 1, window_start, plan->hmc_wmean, plan->hmc_wm2,
+                               wcount, s) != hipSuccess)
+            return LENS_EHIP;
+        return hip_status(launch_add_int(plan->counters + 1, 1, s));
+    };
+    // state, step size, window sums and counters start afresh (outside any graph)
+    if (launch_hmc_adapt_init(C, d, plan->hmc_state, plan->hmc_eps, eps0, plan->hmc_wmean, plan->hmc_wm2, wcount,
+                              st) != hipSuccess ||
+        launch_set_int(plan->counters + 1, 0, st) != hipSuccess)
+        return LENS_EHIP;
+    const std::vector<uint64_t> key = {(uint64_t)C, (uint64_t)(uintptr_t)d_u, (uint64_t)(uintptr_t)d_grad,
+                                       (uint64_t)(uintptr_t)d_logp, (uint64_t)(uintptr_t)d_inv_mass,
+                                       (uint64_t)n_leapfrog, seed, transition0, (uint64_t)window_start,
+                                       fbits(target_accept), (uint64_t)(uintptr_t)d_eps_trace,
+                                       (uint64_t)(uintptr_t)d_eps_final, (uint64_t)plan->ppt};
+    lens_status r = run_maybe_graph(plan, plan->adapt_graph, key, use_graph != 0, n_transitions, st, transition);
+    if (r != LENS_OK) return r;
+    if (d_var)
+        return hip_status(launch_hmc_window_var(C, d, plan->hmc_wmean, plan->hmc_wm2, wcount, d_var, st));
+    return LENS_OK;
 }
 
 lens_status lens_plan_enable_timing(lens_plan* plan, int32_t enable) {

@@ -33,6 +33,20 @@ struct HmcArgs {
     uint64_t seed;
     uint64_t transition0;
     float eps;
+    const float* eps_dev;   // if set: the step size, read on the device (adaptive runs)
+    double* accprob;        // [C] or null: min(1, exp(H0 - H1)) of each chain's transition
+};
+
+// Burn-in adaptation: dual-averaged shared step size (Hoffman & Gelman 2014)
+// and per-chain Welford sums of the positions over a window of transitions.
+struct AdaptArgs {
+    double* state;          // [0] mu, [1] log eps, [2] log eps_bar, [3] H_bar, [4] m
+    const double* accprob;  // [C]
+    float* eps_dev;         // the step size of the next transition
+    float* eps_trace;       // [T] or null: the step size each transition used
+    float* eps_final;       // or null: exp(log eps_bar) after the last update
+    const int* tcount;      // transitions done in this run
+    float delta;            // target acceptance
 };
 
 // SVI: surrogate draws, ELBO + pathwise gradient, optimizer step.
@@ -85,6 +99,13 @@ hipError_t launch_set_int(int* c, int val, hipStream_t st);
 hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_kick_drift(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_end(int C, int d, const HmcArgs& a, hipStream_t st);
+hipError_t launch_hmc_adapt_init(int C, int d, double* state, float* eps_dev, float eps0, double* wmean, double* wm2,
+                                 int* wcount, hipStream_t st);
+hipError_t launch_hmc_adapt(int C, const AdaptArgs& a, hipStream_t st);
+hipError_t launch_hmc_welford(int C, int d, const float* u, const int* tcount, int window_start, double* wmean,
+                              double* wm2, int* wcount, hipStream_t st);
+hipError_t launch_hmc_window_var(int C, int d, const double* wmean, const double* wm2, const int* wcount, float* var,
+                                 hipStream_t st);
 
 hipError_t launch_svi_draw(const SviArgs& a, hipStream_t st);
 hipError_t launch_svi_reduce(const SviArgs& a, hipStream_t st);

@@ -196,6 +196,7 @@ __global__ void k_hmc_begin(int C, int d, HmcArgs a) {
     float* u0 = a.u0 + (size_t)c * d;
     float* g0 = a.g0 + (size_t)c * d;
     float* p = a.p + (size_t)c * d;
+    const float eps = a.eps_dev ? *a.eps_dev : a.eps;
     double kin = 0.0;
     for (int j = 0; j < d; ++j) {
         const double im = (double)a.inv_mass[j];
@@ -203,9 +204,9 @@ __global__ void k_hmc_begin(int C, int d, HmcArgs a) {
         kin += pj * pj * im;
         u0[j] = u[j];
         g0[j] = g[j];
-        const float ph = (float)(pj + 0.5 * (double)a.eps * (double)g[j]);
+        const float ph = (float)(pj + 0.5 * (double)eps * (double)g[j]);
         p[j] = ph;
-        u[j] = fmaf(a.eps * a.inv_mass[j], ph, u[j]);
+        u[j] = fmaf(eps * a.inv_mass[j], ph, u[j]);
     }
     a.logp0[c] = a.logp[c];
     a.h0[c] = -a.logp[c] + 0.5 * kin;
@@ -216,9 +217,10 @@ __global__ void k_hmc_kick_drift(int C, int d, HmcArgs a) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= C * d) return;
     const int j = q % d;
-    const float ph = fmaf(a.eps, a.grad[q], a.p[q]);
+    const float eps = a.eps_dev ? *a.eps_dev : a.eps;
+    const float ph = fmaf(eps, a.grad[q], a.p[q]);
     a.p[q] = ph;
-    a.u[q] = fmaf(a.eps * a.inv_mass[j], ph, a.u[q]);
+    a.u[q] = fmaf(eps * a.inv_mass[j], ph, a.u[q]);
 }
 
 // End: last half kick, H1, Metropolis accept (float64 energies), sample.
@@ -231,12 +233,17 @@ __global__ void k_hmc_end(int C, int d, HmcArgs a) {
     float* u = a.u + (size_t)c * d;
     float* g = a.grad + (size_t)c * d;
     float* p = a.p + (size_t)c * d;
+    const float eps = a.eps_dev ? *a.eps_dev : a.eps;
     double kin = 0.0;
     for (int j = 0; j < d; ++j) {
-        const double pj = (double)p[j] + 0.5 * (double)a.eps * (double)g[j];
+        const double pj = (double)p[j] + 0.5 * (double)eps * (double)g[j];
         kin += pj * pj * (double)a.inv_mass[j];
     }
     const double h1 = -a.logp[c] + 0.5 * kin;
+    if (a.accprob) {
+        const double h0 = a.h0[c];
+        a.accprob[c] = (isfinite(h0) && isfinite(h1)) ? fmin(1.0, exp(h0 - h1)) : 0.0;
+    }
     const uint4 w = philox(make_uint4((uint32_t)c, t, (uint32_t)((d + 3) / 4), 0u), key);
     const double lu = log(uniform01(w.x));
     const bool accept = isfinite(h1) && (lu < a.h0[c] - h1);
@@ -254,9 +261,145 @@ __global__ void k_hmc_end(int C, int d, HmcArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Burn-in adaptation.  Step size: dual averaging (Hoffman & Gelman 2014,
+// Sec. 3.2.1; gamma 0.05, t0 10, kappa 0.75) on the chain mean of the
+// acceptance statistic, one shared step size.  Mass matrix (Sec. 3.3): the
+// variance of the positions over a window of transitions, from per-chain
+// Welford sums combined across chains.
+// ---------------------------------------------------------------------------
+__global__ void k_hmc_adapt_init(int n, double* state, float* eps_dev, float eps0, double* wmean, double* wm2,
+                                 int* wcount) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) {
+        wmean[q] = 0.0;
+        wm2[q] = 0.0;
+    }
+    if (q == 0) {
+        state[0] = log(10.0 * (double)eps0);
+        state[1] = log((double)eps0);
+        state[2] = 0.0;
+        state[3] = 0.0;
+        state[4] = 0.0;
+        *eps_dev = eps0;
+        *wcount = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_hmc_adapt(int C, AdaptArgs a) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int c = tid; c < C; c += 256) s += a.accprob[c];
+    red[tid] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const double alpha = red[0] / (double)C;
+    if (a.eps_trace) a.eps_trace[*a.tcount] = *a.eps_dev;
+    constexpr double GAMMA = 0.05, T0 = 10.0, KAPPA = 0.75;
+    double* st = a.state;
+    const double m = st[4] + 1.0;
+    const double eta = 1.0 / (m + T0);
+    const double hb = (1.0 - eta) * st[3] + eta * ((double)a.delta - alpha);
+    const double le = st[0] - sqrt(m) / GAMMA * hb;
+    const double w = pow(m, -KAPPA);
+    const double leb = w * le + (1.0 - w) * st[2];
+    st[1] = le;
+    st[2] = leb;
+    st[3] = hb;
+    st[4] = m;
+    *a.eps_dev = (float)exp(le);
+    if (a.eps_final) *a.eps_final = (float)exp(leb);
+}
+
+// After transition t of the run (t = *tcount): positions of transitions
+// t >= window_start enter each chain's running mean and sum of squared
+// deviations (Welford); k_hmc_wcount then counts the window sample.
+__global__ void k_hmc_welford(int C, int d, const float* __restrict__ u, const int* __restrict__ tcount,
+                              int window_start, double* __restrict__ wmean, double* __restrict__ wm2,
+                              const int* __restrict__ wcount) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= C * d || *tcount < window_start) return;
+    const double n = (double)(*wcount + 1);
+    const double x = (double)u[q];
+    const double dl = x - wmean[q];
+    const double mn = wmean[q] + dl / n;
+    wmean[q] = mn;
+    wm2[q] = fma(dl, x - mn, wm2[q]);
+}
+
+__global__ void k_hmc_wcount(const int* tcount, int window_start, int* wcount) {
+    if (*tcount >= window_start) *wcount += 1;
+}
+
+// Variance over chains and window transitions of coordinate j (work-group j):
+// grand mean of the chain means, then sum_c M2_c + n sum_c (mean_c - grand)^2
+// over n C - 1; fixed-order sums.
+__global__ __launch_bounds__(256) void k_hmc_window_var(int C, int d, const double* __restrict__ wmean,
+                                                        const double* __restrict__ wm2,
+                                                        const int* __restrict__ wcount, float* __restrict__ var) {
+    __shared__ double red[256];
+    const int j = blockIdx.x, tid = threadIdx.x;
+    double s = 0.0;
+    for (int c = tid; c < C; c += 256) s += wmean[(size_t)c * d + j];
+    red[tid] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    const double gm = red[0] / (double)C;
+    __syncthreads();
+    const double n = (double)(*wcount);
+    s = 0.0;
+    for (int c = tid; c < C; c += 256) {
+        const double dm = wmean[(size_t)c * d + j] - gm;
+        s += wm2[(size_t)c * d + j] + n * dm * dm;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) var[j] = (n * C > 1.0) ? (float)(red[0] / (n * C - 1.0)) : __builtin_nanf("");
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static inline dim3 blocks_for(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+hipError_t launch_hmc_adapt_init(int C, int d, double* state, float* eps_dev, float eps0, double* wmean, double* wm2,
+                                 int* wcount, hipStream_t st) {
+    const long n = (long)C * d;
+    hipLaunchKernelGGL(k_hmc_adapt_init, blocks_for(n > 0 ? n : 1, 256), dim3(256), 0, st, (int)n, state, eps_dev,
+                       eps0, wmean, wm2, wcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmc_adapt(int C, const AdaptArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_hmc_adapt, dim3(1), dim3(256), 0, st, C, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmc_welford(int C, int d, const float* u, const int* tcount, int window_start, double* wmean,
+                              double* wm2, int* wcount, hipStream_t st) {
+    hipLaunchKernelGGL(k_hmc_welford, blocks_for((long)C * d, 256), dim3(256), 0, st, C, d, u, tcount, window_start,
+                       wmean, wm2, wcount);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_hmc_wcount, dim3(1), dim3(1), 0, st, tcount, window_start, wcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmc_window_var(int C, int d, const double* wmean, const double* wm2, const int* wcount, float* var,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_hmc_window_var, dim3(d), dim3(256), 0, st, C, d, wmean, wm2, wcount, var);
+    return hipGetLastError();
+}
 
 hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u, float* theta,
                             hipStream_t st) {

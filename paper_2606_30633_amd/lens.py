@@ -62,6 +62,8 @@ _SIGNATURES = {
     "lens_svi_run": (_I, [_P, _I, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           ctypes.c_float, ctypes.c_uint64, _P, _I, _P]),
     "lens_svi_moments": (_I, [_I, _P, _P, _P, _P, _P]),
+    "lens_hmc_adapt": (_I, [_P, _I, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, _I, _I, _I, ctypes.c_uint64,
+                            ctypes.c_uint64, _P, _P, _P, _I, _P]),
     "lens_batch_plan_create": (_I, [_I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "lens_batch_plan_destroy": (_I, [_P]),
     "lens_batch_total_particles": (ctypes.c_int64, [_P]),
@@ -360,6 +362,29 @@ def lens_hmc_run(plan: LensPlan, u: torch.Tensor, grad: torch.Tensor, logp: torc
                              inv_mass.data_ptr(), eps, int(n_leapfrog), int(n_transitions), int(seed),
                              int(transition0), _ptr(samples), _ptr(accepts), 1 if use_graph else 0,
                              _stream(stream)), "lens_hmc_run")
+
+
+def lens_hmc_adapt(plan: LensPlan, u: torch.Tensor, grad: torch.Tensor, logp: torch.Tensor,
+                   inv_mass: torch.Tensor, eps0: float, target_accept: float, n_leapfrog: int, n_transitions: int,
+                   window_start: int, seed: int, transition0: int = 0, use_graph: bool = False, stream=None):
+    """HMC burn-in of C chains in place with a dual-averaged step size and a
+    windowed variance fit; returns (step size per transition [T], adapted step
+    size [1], window variances [d])."""
+    uu = plan._theta(u)
+    plan._theta(grad)
+    C = uu.shape[0]
+    if logp.dtype != torch.float64 or logp.shape != (C,):
+        raise ValueError("logp must be float64 [C]")
+    if inv_mass.dtype != torch.float32 or inv_mass.shape != (plan.d,) or not inv_mass.is_contiguous():
+        raise ValueError("inv_mass must be a contiguous float32 [d] tensor")
+    trace = torch.empty(max(int(n_transitions), 1), dtype=torch.float32, device=plan.device)
+    final = torch.empty(1, dtype=torch.float32, device=plan.device)
+    var = torch.empty(plan.d, dtype=torch.float32, device=plan.device)
+    _check(_lib.lens_hmc_adapt(plan.handle, C, uu.data_ptr(), grad.data_ptr(), logp.data_ptr(), inv_mass.data_ptr(),
+                               eps0, target_accept, int(n_leapfrog), int(n_transitions), int(window_start), int(seed),
+                               int(transition0), trace.data_ptr(), final.data_ptr(), var.data_ptr(),
+                               1 if use_graph else 0, _stream(stream)), "lens_hmc_adapt")
+    return trace[:n_transitions], final, var
 
 
 SVI_OPTIMIZERS = {"adam": 0, "adabelief": 1}

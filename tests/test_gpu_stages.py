@@ -319,3 +319,76 @@ def test_hmc_full_size_sampled(L, tol):
         assert np.all(err <= tol * scale + 2 * ulp), (c, (err / scale).max())
         checked += 1
     assert checked >= 2
+
+
+def _adapt_case():
+    spec = synth.ModelSpec(24, 20, 0.12, 2, 5, "SIE", 1, 1)
+    sysm, psf, data, table, u, plan = _setup(spec, 4, 64)
+    d = spec.n_params
+    f = _oracle_grad_fn(spec, psf, data, sysm.invvar, table, True)
+    ut = O.to_unconstrained(torch.tensor(sysm.truth, dtype=torch.float64), table).numpy()
+    h = 1e-4
+    hd = np.array([(f(ut + h * np.eye(d)[j])[1][j] - f(ut - h * np.eye(d)[j])[1][j]) / (2 * h) for j in range(d)])
+    inv_mass = (1.0 / np.maximum(np.abs(hd), 1e-6)).astype(np.float32)
+    return spec, plan, f, ut, inv_mass
+
+
+def test_hmc_adapt_matches_oracle():
+    """Burn-in with a dual-averaged step size and a windowed variance fit
+    (lens_hmc_adapt, graph replay) against the oracle's hmc_adapt on the same
+    Philox momenta, over three transitions: the step size of each transition,
+    the adapted one, the final positions and the window variances.  The
+    oracle reports the smallest accept-decision margin, which must be clear
+    of rounding (every decision the same on both sides).  The step sizes
+    agree to 1e-2: a transition's acceptance statistic carries the float32 /
+    float64 trajectory difference (measured ~1e-3 at step size 0.7) and dual
+    averaging scales it into log eps by sqrt(m) / (gamma (m + t0)) <= 3.2; a
+    wrong sign or constant in the recursion is off by factors."""
+    spec, plan, f, ut, inv_mass = _adapt_case()
+    d = spec.n_params
+    C, T, L, W, seed, eps0 = 8, 3, 3, 1, 0xADA97, 0.05
+    rng = np.random.default_rng(12)
+    U0 = (ut[None, :] + 0.3 * np.sqrt(inv_mass)[None, :] * rng.standard_normal((C, d))).astype(np.float32)
+    _log("hmc adapt: 8 chains x 3 transitions")
+    x = torch.tensor(U0, device=DEV)
+    lp, g = lens.lens_logpost_grad(plan, x, True)
+    tr, fin, var = lens.lens_hmc_adapt(plan, x, g, lp, torch.tensor(inv_mass, device=DEV), eps0, 0.8, L, T, W, seed,
+                                       use_graph=True)
+    tr, fin, var, xg = tr.cpu().numpy(), float(fin.item()), var.cpu().numpy(), x.cpu().numpy()
+    Uo, tr_o, fin_o, var_o, al_o, margin = O.hmc_adapt(U0.astype(np.float64), f, inv_mass.astype(np.float64),
+                                                       float(np.float32(eps0)), float(np.float32(0.8)), L, T, W, seed)
+    _log(f"margin {margin:.3g}; eps {tr} vs {tr_o}; final {fin} vs {fin_o}")
+    assert margin > 1e-3
+    assert tr[0] == np.float32(eps0)
+    np.testing.assert_allclose(tr, tr_o, rtol=1e-2)
+    assert abs(fin / fin_o - 1) < 1e-2
+    scale = np.sqrt(inv_mass.astype(np.float64))
+    err = np.abs(xg - Uo) / scale
+    _log(f"positions: max error {err.max():.3g} posterior sd; variances rel err {np.max(np.abs(var / var_o - 1)):.3g}")
+    assert err.max() < 2e-2
+    np.testing.assert_allclose(var, var_o, rtol=5e-2)
+
+
+def test_hmc_adapt_reaches_target_acceptance():
+    """A 100-transition burn-in: with the adapted step size fixed, 50 further
+    transitions accept at a rate near the 0.8 target; the window variances are
+    finite and positive, and a second call restarts the adaptation."""
+    spec, plan, f, ut, inv_mass = _adapt_case()
+    d = spec.n_params
+    C = 64
+    rng = np.random.default_rng(13)
+    x = torch.tensor((ut[None, :] + 0.3 * np.sqrt(inv_mass)[None, :] * rng.standard_normal((C, d))).astype(np.float32),
+                     device=DEV)
+    lp, g = lens.lens_logpost_grad(plan, x, True)
+    im = torch.tensor(inv_mass, device=DEV)
+    tr, fin, var = lens.lens_hmc_adapt(plan, x, g, lp, im, 0.05, 0.8, 5, 100, 50, 77, use_graph=True)
+    eps = float(fin.item())
+    v = var.cpu().numpy()
+    assert np.all(np.isfinite(v)) and np.all(v > 0) and eps > 0
+    acc = torch.zeros(C, dtype=torch.int32, device=DEV)
+    lens.lens_hmc_run(plan, x, g, lp, im, eps, 5, 50, 77, 1000, accepts=acc, use_graph=True)
+    rate = float(acc.sum().item()) / (50 * C)
+    _log(f"adapted eps {eps:.3g}, acceptance {rate:.3f}")
+    assert 0.6 < rate < 0.95
+    tr2, _, _ = lens.lens_hmc_adapt(plan, x, g, lp, im, 0.05, 0.8, 5, 2, 0, 78)
+    assert float(tr2[0].item()) == np.float32(0.05)

@@ -38,7 +38,7 @@ def test_hmc_adapt_on_gaussian_target():
     f = lambda u: (-0.5 * u @ P @ u, -(P @ u))
     rng = np.random.default_rng(1)
     U0 = rng.standard_normal((16, 2)) * 0.3
-    U, eps_t, eps_bar, var, alphas = O.hmc_adapt(U0, f, np.ones(2), 0.05, 0.8, 4, 300, 100, 7, eps_float32=False)
+    U, eps_t, eps_bar, var, alphas, _ = O.hmc_adapt(U0, f, np.ones(2), 0.05, 0.8, 4, 300, 100, 7, eps_float32=False)
     assert abs(eps_t[0] - 0.05) < 1e-15 and np.all(np.isfinite(eps_t))
     assert 0.6 < np.mean(alphas[-100:]) < 0.95
     np.testing.assert_allclose(var, np.diag(cov), rtol=0.2)
