@@ -18,9 +18,9 @@ the paper's prior, eq. sim-dist):
    the ELBO of every step.
 4. HMC: chains started at draws of the AdaBelief surrogate
    (lens_svi_elbo_grad), inverse mass matrix = the surrogate's variances
-   (lens_svi_moments), the step size adapted during burn-in towards an
-   acceptance of 0.8, then n_hmc transitions of L leapfrog steps
-   (lens_hmc_run); split-R-hat and effective sample size of the samples.
+   (lens_svi_moments), the step size dual-averaged during burn-in towards an
+   acceptance of 0.8 (lens_hmc_adapt), then n_hmc transitions of L leapfrog
+   steps (lens_hmc_run); split-R-hat and effective sample size of the samples.
    A system with split-R-hat >= 1.1 gets the mass-matrix adaptation of
    Sec. 3.3 (plus a short step-size retune) and is sampled again.  Defaults follow the paper's settings for
    its 100 simulated systems (MAP 1000 steps; SVI 5000 steps of 1000 draws;
@@ -181,46 +181,41 @@ def study_system(sy, k, table, cfg: StudyConfig, dev, u_map, lp_map, log=print) 
     inv_mass = var.contiguous()
     acc = torch.zeros(C, dtype=torch.int32, device=dev)
     hseed = cfg.seed + 900 + k
-    st = {"eps": 0.5, "t": 0}
+    st = {"t": 0}
 
-    def adapt(n, mass, out=None):
-        """n transitions in rounds of 10; after each round the step size moves
-        towards an acceptance of 0.8 (cut tenfold below 5 %)."""
-        for r in range(n // 10):
-            acc.zero_()
-            lens.lens_hmc_run(plan, u, grad, logp, mass, st["eps"], cfg.leapfrog, 10, hseed, st["t"], accepts=acc,
-                              samples=None if out is None else out[10 * r:10 * r + 10], use_graph=True)
-            st["t"] += 10
-            a = float(acc.sum().item()) / (10 * C)
-            st["eps"] *= math.exp(2.0 * (a - 0.8)) if a >= 0.05 else 0.1
+    def adapt(n, mass, eps0, window_start):
+        """n burn-in transitions with the library's dual-averaged step size
+        (target acceptance 0.8) and window variances."""
+        _, fin, wv = lens.lens_hmc_adapt(plan, u, grad, logp, mass, eps0, 0.8, cfg.leapfrog, n, window_start, hseed,
+                                         st["t"], use_graph=True)
+        st["t"] += n
+        return float(fin.item()), wv
 
-    def sample(mass):
+    def sample(mass, eps):
         acc.zero_()
-        lens.lens_hmc_run(plan, u, grad, logp, mass, st["eps"], cfg.leapfrog, cfg.n_hmc, hseed, st["t"],
+        lens.lens_hmc_run(plan, u, grad, logp, mass, eps, cfg.leapfrog, cfg.n_hmc, hseed, st["t"],
                           samples=samples, accepts=acc, use_graph=True)
         st["t"] += cfg.n_hmc
         smp = samples.cpu().numpy()
         return smp, split_rhat(smp), ess(smp), float(acc.sum().item()) / (cfg.n_hmc * C)
 
-    adapt(cfg.burn, inv_mass)
+    eps_h, _ = adapt(cfg.burn, inv_mass, 0.1, cfg.burn)
     samples = torch.empty((cfg.n_hmc, C, d), device=dev)
-    smp, rh, es, a = sample(inv_mass)
-    res["hmc"] = {"eps": st["eps"], "acceptance": a, "rhat_max": float(rh.max()), "ess_min": float(es.min()),
+    smp, rh, es, a = sample(inv_mass, eps_h)
+    res["hmc"] = {"eps": eps_h, "acceptance": a, "rhat_max": float(rh.max()), "ess_min": float(es.min()),
                   "mass_adapted": False}
     if rh.max() >= 1.1 and cfg.mass_burn_factor > 0:
         # mass-matrix adaptation (Sec. 3.3): a burn-in mass_burn_factor times
-        # longer; a Gaussian fitted to its last 90 % sets the inverse mass (its
-        # variances); the chains continue from where they are.  The step size
-        # is then retuned over burn/5 transitions (the second burn-in phase the
-        # paper names as a possible improvement), and the chains are sampled.
+        # longer whose last 90 % give the variances of the new inverse mass;
+        # the chains continue from where they are.  The step size is then
+        # retuned over burn/5 transitions (the second burn-in phase the paper
+        # names as a possible improvement), and the chains are sampled.
         nb = cfg.mass_burn_factor * cfg.burn
-        burn = torch.empty((nb, C, d), device=dev)
-        adapt(nb, inv_mass, burn)
-        inv_mass = burn[nb // 10:].reshape(-1, d).var(dim=0).clamp_min(1e-30).contiguous()
-        del burn
-        adapt(max(cfg.burn // 5, 10), inv_mass)
-        smp, rh, es, a = sample(inv_mass)
-        res["hmc"].update({"eps": st["eps"], "acceptance": a, "rhat_max": float(rh.max()), "ess_min": float(es.min()),
+        eps_h, wv = adapt(nb, inv_mass, eps_h, nb // 10)
+        inv_mass = wv.clamp_min(1e-30).contiguous()
+        eps_h, _ = adapt(max(cfg.burn // 5, 10), inv_mass, eps_h, cfg.burn)
+        smp, rh, es, a = sample(inv_mass, eps_h)
+        res["hmc"].update({"eps": eps_h, "acceptance": a, "rhat_max": float(rh.max()), "ess_min": float(es.min()),
                            "mass_adapted": True, "rhat_max_before_adaptation": res["hmc"]["rhat_max"]})
     res["hmc"]["converged"] = bool(rh.max() < 1.1)
     for opt in ("adam", "adabelief"):
