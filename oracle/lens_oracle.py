@@ -582,7 +582,9 @@ def hmc_transition(u, logp_grad_fn, inv_mass, eps: float, L: int, seed: int, cha
     u = np.asarray(u, dtype=np.float64)
     inv_mass = np.asarray(inv_mass, dtype=np.float64)
     d = u.shape[0]
-    p = hmc_momenta(d, seed, chain, t) / np.sqrt(inv_mass)
+    # a coordinate with zero inverse mass is frozen: no momentum, no motion
+    z = hmc_momenta(d, seed, chain, t)
+    p = np.where(inv_mass > 0, z / np.sqrt(np.where(inv_mass > 0, inv_mass, 1.0)), 0.0)
     lp0, _ = logp_grad_fn(u)
     H0 = hamiltonian(lp0, p, inv_mass)
     u1, p1 = leapfrog(u, p, lambda z: logp_grad_fn(z)[1], eps, L, inv_mass)
@@ -884,3 +886,35 @@ def hmc_adapt(U0, logp_grad_fn, inv_mass, eps0: float, delta: float, L: int, n_t
             window.append(U.copy())
     var = np.concatenate(window).var(axis=0, ddof=1) if len(window) * C > 1 else None
     return U, np.array(eps_trace), math.exp(st["log_eps_bar"]), var, np.array(alphas), margin
+
+
+def log_posterior_backward(u, spec, psf, data, invvar, table, with_jacobian: bool,
+                           theta_float32: bool = False):
+    """Backward-modelling posterior in the unconstrained space: logL at the
+    solved intensities (loglike_backward) of T(u), plus the log prior and,
+    optionally, the log-Jacobian of the nonlinear parameters only (the
+    intensities are not parameters); gradient w.r.t. u, zero in the intensity
+    entries.  With theta_float32 the likelihood sees T(u) rounded to float32.
+    """
+    tab = np.asarray(_t(table).numpy())
+    d = tab.shape[0]
+    slots = intensity_slots(spec)
+    keep = [j for j in range(d) if j not in slots]
+    uu = _t(u).clone().requires_grad_(True)
+    th, _ = to_constrained(uu, tab)
+    thk, logj = to_constrained(uu[keep], tab[keep])
+    if not ellipticity_valid(th.detach(), spec):
+        return -math.inf, np.zeros(d)
+    rest = log_prior(thk, tab[keep]) + (logj if with_jacobian else 0.0)
+    th_eval = th.detach()
+    if theta_float32:
+        th_eval = th_eval.to(torch.float32).to(DT)
+    L, gL, _ = loglike_backward(th_eval, spec, psf, data, invvar)
+    (dth,) = torch.autograd.grad(th.sum(), uu, retain_graph=True)
+    gr = None
+    if torch.is_tensor(rest) and rest.requires_grad:
+        (gr,) = torch.autograd.grad(rest, uu, allow_unused=True)
+    gr = torch.zeros_like(uu) if gr is None else gr
+    g = torch.tensor(gL) * dth.detach() + gr
+    g[slots] = 0.0
+    return float(L) + float(rest.detach()), g.numpy()

@@ -104,3 +104,37 @@ def test_degenerate_components_are_left_out():
     t2[s2 + 4], t2[s2 + 5], t2[s2] = 80.0, 80.0, 0.05
     L2, g2, A2 = O.loglike_backward(t2, spec, psf, data, sysm.invvar)
     assert A2[2] == 0 and np.isfinite(L2) and np.all(np.isfinite(g2))
+
+
+def test_backward_posterior_gradient_and_frozen_intensities():
+    """The backward posterior in the unconstrained space: its gradient matches
+    central differences and is zero in the intensity entries, whose values do
+    not change it."""
+    sysm, psf, data = _case(6)
+    table = synth.prior_table(sysm.prior)
+    t = synth.particles_box(sysm, 1, 6)[0].astype(np.float64)
+    u = O.to_unconstrained(torch.tensor(t), table).numpy()
+    for jac in (False, True):
+        lp, g = O.log_posterior_backward(u, SPEC, psf, data, sysm.invvar, table, jac)
+        slots = O.intensity_slots(SPEC)
+        assert np.all(g[slots] == 0)
+        u2 = u.copy()
+        u2[slots] += 0.7
+        assert abs(O.log_posterior_backward(u2, SPEC, psf, data, sysm.invvar, table, jac)[0] - lp) <= 1e-9 * abs(lp)
+        for j in (0, 2, 9, 10):
+            h = 1e-6
+            e = np.zeros_like(u)
+            e[j] = h
+            fd = (O.log_posterior_backward(u + e, SPEC, psf, data, sysm.invvar, table, jac)[0]
+                  - O.log_posterior_backward(u - e, SPEC, psf, data, sysm.invvar, table, jac)[0]) / (2 * h)
+            assert abs(fd - g[j]) <= 1e-5 * np.abs(g).max(), (jac, j, fd, g[j])
+
+
+def test_hmc_zero_inverse_mass_freezes_a_coordinate():
+    cov = np.array([[1.0, 0.3], [0.3, 0.5]])
+    P = np.linalg.inv(cov)
+    f = lambda u: (-0.5 * u[:2] @ P @ u[:2], np.concatenate([-(P @ u[:2]), [0.0]]))
+    u = np.array([0.1, -0.2, 3.0])
+    for t in range(20):
+        u, *_ = O.hmc_transition(u, f, np.array([1.0, 1.0, 0.0]), 0.3, 4, 5, 0, t)
+        assert u[2] == 3.0 and np.all(np.isfinite(u))
