@@ -100,6 +100,7 @@ struct lens_plan {
     float* svi_u;             // [maxP][d] surrogate samples
     double* svi_eps;          // [d][maxP] their standard normals
     double* svi_logq;         // [maxP]
+    int backward;             // posterior path uses the backward likelihood (lens_plan_set_backward)
     double* hmc_accprob;      // [maxP] adaptation statistic (lens_hmc_adapt; on first use)
     double* hmc_state;        // [8] dual-averaging state
     float* hmc_eps;           // [1] device step size
@@ -371,27 +372,29 @@ static BwdSlots bwd_slots(const lens_plan* plan) {
     return s;
 }
 
-lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
-                                       float* d_grad, float* d_amp, void* stream) {
-    if (!plan || !d_theta || !d_logl || !d_grad || P < 1) return LENS_EINVAL;
-    const BwdSlots s = bwd_slots(plan);
-    if (s.K < 1 || s.K > BWD_MAX_K || (long)P * s.K > plan->max_particles) return LENS_EINVAL;
-    const size_t Pd = (size_t)plan->max_particles * s.d;
+static lens_status bwd_alloc(lens_plan* plan) {
+    if (plan->bwd_thx) return LENS_OK;
+    const size_t Pd = (size_t)plan->max_particles * plan->mi.d;
     const size_t npix = (size_t)plan->geo.npix;
-    if (!plan->bwd_thx) {
-        if (hipMalloc(&plan->bwd_thx, sizeof(float) * Pd) != hipSuccess ||
-            hipMalloc(&plan->bwd_img, sizeof(float) * npix * plan->max_particles) != hipSuccess ||
-            hipMalloc(&plan->bwd_theta, sizeof(float) * Pd) != hipSuccess) {
-            for (float** b : {&plan->bwd_thx, &plan->bwd_img, &plan->bwd_theta})
-                if (*b) {
-                    (void)hipFree(*b);
-                    *b = nullptr;
-                }
-            return LENS_ENOMEM;
-        }
+    if (hipMalloc(&plan->bwd_thx, sizeof(float) * Pd) != hipSuccess ||
+        hipMalloc(&plan->bwd_img, sizeof(float) * npix * plan->max_particles) != hipSuccess ||
+        hipMalloc(&plan->bwd_theta, sizeof(float) * Pd) != hipSuccess) {
+        for (float** b : {&plan->bwd_thx, &plan->bwd_img, &plan->bwd_theta})
+            if (*b) {
+                (void)hipFree(*b);
+                *b = nullptr;
+            }
+        return LENS_ENOMEM;
     }
-    hipStream_t st = (hipStream_t)stream;
+    return LENS_OK;
+}
+
+// Enqueues the backward likelihood (scratch allocated; P K <= max_particles checked).
+static lens_status backward_enqueue(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
+                                    float* d_grad, float* d_amp, double* d_logl64, hipStream_t st) {
+    const BwdSlots s = bwd_slots(plan);
     const int PK = P * s.K;
+    const size_t npix = (size_t)plan->geo.npix;
     // all intensities 1, one render pass writing each component's image
     if (launch_bwd_expand(P, s, d_theta, plan->bwd_thx, st) != hipSuccess) return LENS_EHIP;
     hipError_t e;
@@ -417,9 +420,41 @@ lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* 
                               plan->bwd_theta, d_amp, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
-    lens_status r = loglike_grad_enqueue(plan, P, plan->bwd_theta, d_logl, d_grad, nullptr, st);
+    lens_status r = loglike_grad_enqueue(plan, P, plan->bwd_theta, d_logl, d_grad, d_logl64, st);
     if (r != LENS_OK) return r;
     return hip_status(launch_bwd_zero_slots(P, s, d_grad, st));
+}
+
+// The posterior path can take P particles (the backward likelihood holds K images per particle).
+static bool posterior_fits(const lens_plan* plan, int32_t P) {
+    if (P < 1 || P > plan->max_particles) return false;
+    return !plan->backward || (long)P * bwd_slots(plan).K <= plan->max_particles;
+}
+
+lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
+                                       float* d_grad, float* d_amp, void* stream) {
+    if (!plan || !d_theta || !d_logl || !d_grad || P < 1) return LENS_EINVAL;
+    const BwdSlots s = bwd_slots(plan);
+    if (s.K < 1 || s.K > BWD_MAX_K || (long)P * s.K > plan->max_particles) return LENS_EINVAL;
+    lens_status r = bwd_alloc(plan);
+    if (r != LENS_OK) return r;
+    return backward_enqueue(plan, P, d_theta, d_logl, d_grad, d_amp, nullptr, (hipStream_t)stream);
+}
+
+lens_status lens_plan_set_backward(lens_plan* plan, int32_t enable) {
+    if (!plan) return LENS_EINVAL;
+    if (enable) {
+        const int K = bwd_slots(plan).K;
+        if (K < 1 || K > BWD_MAX_K) return LENS_EINVAL;
+        lens_status r = bwd_alloc(plan);
+        if (r != LENS_OK) return r;
+    }
+    plan->backward = enable ? 1 : 0;
+    plan->map_graph.reset();
+    plan->hmc_graph.reset();
+    plan->svi_graph.reset();
+    plan->adapt_graph.reset();
+    return LENS_OK;
 }
 
 // Enqueues logp(u) and dlogp/du (no argument checks).  theta_out may be null.
@@ -432,11 +467,19 @@ static lens_status logpost_enqueue(lens_plan* plan, int32_t P, const float* d_u,
         TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, st);
         if (launch_bijection(P, d, plan->prior, d_u, th, st) != hipSuccess) return LENS_EHIP;
     }
-    lens_status s = loglike_grad_enqueue(plan, P, th, plan->logl, plan->gtheta, plan->logl64, st);
+    uint64_t skip = 0;
+    lens_status s;
+    if (plan->backward) {
+        const BwdSlots bs = bwd_slots(plan);
+        for (int k = 0; k < bs.K; ++k) skip |= (uint64_t)1 << bs.slot[k];
+        s = backward_enqueue(plan, P, th, plan->logl, plan->gtheta, nullptr, plan->logl64, st);
+    } else {
+        s = loglike_grad_enqueue(plan, P, th, plan->logl, plan->gtheta, plan->logl64, st);
+    }
     if (s != LENS_OK) return s;
     TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, st);
     return hip_status(launch_posterior(P, d, plan->prior, d_u, plan->logl64, plan->gtheta,
-                                       with_jac, d_logp, d_grad, st));
+                                       with_jac, d_logp, d_grad, st, skip));
 }
 
 lens_status lens_plan_set_prior(lens_plan* plan, const float* h_table) {
@@ -463,7 +506,7 @@ lens_status lens_to_unconstrained(lens_plan* plan, int32_t P, const float* d_the
 
 lens_status lens_logpost_grad(lens_plan* plan, int32_t P, const float* d_u, int32_t with_jacobian,
                               float* d_theta, double* d_logp, float* d_grad, void* stream) {
-    if (!plan || !d_u || !d_logp || !d_grad || P < 1 || P > plan->max_particles) return LENS_EINVAL;
+    if (!plan || !d_u || !d_logp || !d_grad || !posterior_fits(plan, P)) return LENS_EINVAL;
     if (!plan->prior) return LENS_EINVAL;
     return logpost_enqueue(plan, P, d_u, with_jacobian != 0, d_theta, d_logp, d_grad,
                            (hipStream_t)stream);
@@ -529,7 +572,7 @@ lens_status lens_map_reset(lens_plan* plan) {
 lens_status lens_map_adam(lens_plan* plan, int32_t P, float* d_u, float* d_m, float* d_v,
                           int32_t n_steps, float lr, float decay, float beta1, float beta2,
                           float eps, float* d_loss, int32_t use_graph, void* stream) {
-    if (!plan || !d_u || !d_m || !d_v || P < 1 || P > plan->max_particles || n_steps < 0)
+    if (!plan || !d_u || !d_m || !d_v || !posterior_fits(plan, P) || n_steps < 0)
         return LENS_EINVAL;
     if (!plan->prior || !(lr > 0.0f) || !(decay > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
         !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
@@ -557,7 +600,7 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
                          const float* d_inv_mass, float eps, int32_t n_leapfrog,
                          int32_t n_transitions, uint64_t seed, uint64_t transition0,
                          float* d_samples, int32_t* d_accepts, int32_t use_graph, void* stream) {
-    if (!plan || !d_u || !d_grad || !d_logp || !d_inv_mass || C < 1 || C > plan->max_particles ||
+    if (!plan || !d_u || !d_grad || !d_logp || !d_inv_mass || !posterior_fits(plan, C) ||
         n_leapfrog < 1 || n_transitions < 0 || !(eps > 0.0f))
         return LENS_EINVAL;
     if (!plan->prior) return LENS_EINVAL;
@@ -642,6 +685,7 @@ lens_status lens_svi_elbo_grad(lens_plan* plan, int32_t n, const float* d_phi, u
                                void* stream) {
     if (!plan || !d_phi || !d_elbo || n < 1 || n > plan->max_particles || step < 0) return LENS_EINVAL;
     if (!plan->prior || plan->mi.d > SVI_MAX_D) return LENS_EINVAL;
+    if (plan->backward) return LENS_EUNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     SviArgs a = svi_args(plan, n, const_cast<float*>(d_phi), seed);
     if (d_u) a.u = d_u;
@@ -660,6 +704,7 @@ lens_status lens_svi_run(lens_plan* plan, int32_t n, float* d_phi, float* d_m, f
     if (!plan || !d_phi || !d_m || !d_s || n < 1 || n > plan->max_particles || n_steps < 0)
         return LENS_EINVAL;
     if (!plan->prior || plan->mi.d > SVI_MAX_D) return LENS_EINVAL;
+    if (plan->backward) return LENS_EUNSUPPORTED;
     if ((optimizer != LENS_OPT_ADAM && optimizer != LENS_OPT_ADABELIEF) || !(lr > 0.0f) ||
         !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
         return LENS_EINVAL;
@@ -701,7 +746,7 @@ lens_status lens_hmc_adapt(lens_plan* plan, int32_t C, float* d_u, float* d_grad
                            const float* d_inv_mass, float eps0, float target_accept, int32_t n_leapfrog,
                            int32_t n_transitions, int32_t window_start, uint64_t seed, uint64_t transition0,
                            float* d_eps_trace, float* d_eps_final, float* d_var, int32_t use_graph, void* stream) {
-    if (!plan || !d_u || !d_grad || !d_logp || !d_inv_mass || C < 1 || C > plan->max_particles ||
+    if (!plan || !d_u || !d_grad || !d_logp || !d_inv_mass || !posterior_fits(plan, C) ||
         n_leapfrog < 1 || n_transitions < 0 || window_start < 0 || !(eps0 > 0.0f) ||
         !(target_accept > 0.0f && target_accept < 1.0f))
         return LENS_EINVAL;

@@ -88,9 +88,10 @@ bool build_prior_rows(int d, const float* h_table, PriorRow* rows);
 
 hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u, float* theta,
                             hipStream_t st);
+// skip: bit j set -> entry j is not a parameter (no prior or Jacobian term, gradient 0).
 hipError_t launch_posterior(int P, int d, const PriorRow* table, const float* u, const double* logl,
                             const float* gtheta, int with_jac, double* logp, float* grad_u,
-                            hipStream_t st);
+                            hipStream_t st, uint64_t skip = 0);
 hipError_t launch_adam(int P, int d, const float* grad_u, const double* logp, float* u, float* m,
                        float* v, const int* step, const AdamHyper& hp, float* loss,
                        hipStream_t st);

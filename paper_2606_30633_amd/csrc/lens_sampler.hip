@@ -95,7 +95,7 @@ __global__ void k_bijection(int P, int d, const PriorRow* __restrict__ table,
 // logp = logL(theta) + log prior(theta) [+ log J]; grad_u = (g_theta + dlp) dth [+ dlogJ]
 __global__ void k_posterior(int P, int d, const PriorRow* __restrict__ table,
                             const float* __restrict__ u, const double* __restrict__ logl,
-                            const float* __restrict__ gtheta, int with_jac,
+                            const float* __restrict__ gtheta, int with_jac, uint64_t skip,
                             double* __restrict__ logp, float* __restrict__ grad_u) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
@@ -111,6 +111,10 @@ __global__ void k_posterior(int P, int d, const PriorRow* __restrict__ table,
     }
     double lp_sum = 0.0, lj_sum = 0.0;
     for (int j = 0; j < d; ++j) {
+        if ((skip >> j) & 1u) {          // not a parameter (backward-modelled intensity)
+            go[j] = 0.0f;
+            continue;
+        }
         double th, dth, lj, dlj, lp, dlp;
         bijection(table[j], (double)up[j], th, dth, lj, dlj);
         log_prior(table[j], th, lp, dlp);
@@ -200,7 +204,8 @@ __global__ void k_hmc_begin(int C, int d, HmcArgs a) {
     double kin = 0.0;
     for (int j = 0; j < d; ++j) {
         const double im = (double)a.inv_mass[j];
-        const double pj = momentum(key, (uint32_t)c, t, j) / sqrt(im);
+        // a zero inverse mass freezes the coordinate (no momentum, no motion)
+        const double pj = im > 0.0 ? momentum(key, (uint32_t)c, t, j) / sqrt(im) : 0.0;
         kin += pj * pj * im;
         u0[j] = u[j];
         g0[j] = g[j];
@@ -410,9 +415,9 @@ hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u,
 
 hipError_t launch_posterior(int P, int d, const PriorRow* table, const float* u, const double* logl,
                             const float* gtheta, int with_jac, double* logp, float* grad_u,
-                            hipStream_t st) {
+                            hipStream_t st, uint64_t skip) {
     hipLaunchKernelGGL(k_posterior, blocks_for(P, 64), dim3(64), 0, st, P, d, table, u, logl,
-                       gtheta, with_jac, logp, grad_u);
+                       gtheta, with_jac, skip, logp, grad_u);
     return hipGetLastError();
 }
 

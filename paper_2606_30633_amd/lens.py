@@ -49,6 +49,7 @@ _SIGNATURES = {
     "lens_loglike": (_I, [_P, _I, _P, _P, _P]),
     "lens_loglike_grad": (_I, [_P, _I, _P, _P, _P, _P, _P]),
     "lens_loglike_grad_backward": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "lens_plan_set_backward": (_I, [_P, _I]),
     "lens_plan_set_prior": (_I, [_P, _P]),
     "lens_logpost_grad": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
     "lens_map_reset": (_I, [_P]),
@@ -184,6 +185,10 @@ class LensPlan:
             raise ValueError(f"prior table must be [{self.d}, 5]")
         _check(_lib.lens_plan_set_prior(self.handle, t.ctypes.data_as(ctypes.c_void_p)), "lens_plan_set_prior")
         self._prior = t
+
+    def set_backward(self, enable: bool = True):
+        """Posterior path with the intensities solved by linear inversion (lens_plan_set_backward)."""
+        _check(_lib.lens_plan_set_backward(self.handle, 1 if enable else 0), "lens_plan_set_backward")
 
     def enable_timing(self, on: bool = True):
         _check(_lib.lens_plan_enable_timing(self.handle, 1 if on else 0), "lens_plan_enable_timing")

@@ -156,3 +156,98 @@ def test_backward_full_size_sampled():
     _check(spec, psf, data, sysm.invvar, th[sample], L[sample], G[sample], A[sample], near=(2,))
     ok = np.isfinite(L)
     assert ok.mean() > 0.5 and np.all(np.isfinite(G[ok])) and np.all(np.isfinite(A[ok]))
+
+
+# ---------------------------------------------------------------------------
+# Backward modelling inside the inference stages (lens_plan_set_backward)
+# ---------------------------------------------------------------------------
+def _stage_case(n=4):
+    spec = SPECS[0]
+    sysm, psf, data, th = make_case(spec, 7, n, psf="asym")
+    table = synth.prior_table(synth.uniform_box_dists(spec))
+    u = np.stack([O.to_unconstrained(torch.tensor(t, dtype=torch.float64), table).numpy() for t in th])
+    K = spec.n_lens_light + spec.n_source
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, max(n, 8) * K, DEV)
+    plan.set_prior(table)
+    plan.set_backward(True)
+    f = lambda jac: (lambda uu: O.log_posterior_backward(np.asarray(uu, np.float32), spec, psf, data, sysm.invvar,
+                                                         table, jac, theta_float32=True))
+    return spec, sysm, table, u.astype(np.float32), plan, f
+
+
+@pytest.mark.parametrize("jac", [False, True])
+def test_backward_posterior_matches_oracle(jac):
+    spec, sysm, table, u, plan, f = _stage_case()
+    lp, g = (t.cpu().numpy() for t in lens.lens_logpost_grad(plan, torch.tensor(u, device=DEV), jac))
+    slots = O.intensity_slots(spec)
+    for p in range(u.shape[0]):
+        lo, go = f(jac)(u[p])
+        assert abs(lp[p] - lo) <= RTOL * abs(lo), (p, lp[p], lo)
+        assert np.all(g[p][slots] == 0)
+        assert np.linalg.norm(g[p] - go) <= RTOL * np.linalg.norm(go), p
+
+
+def test_backward_map_steps_match_oracle():
+    spec, sysm, table, u, plan, f = _stage_case()
+    ut = torch.tensor(u, device=DEV)
+    m = torch.zeros_like(ut)
+    v = torch.zeros_like(ut)
+    lens.lens_map_reset(plan)
+    lr = 1e-2
+    uo, mo, vo = u.astype(np.float64), np.zeros(u.shape), np.zeros(u.shape)
+    fo = f(False)
+    for k in range(1, 4):
+        lens.lens_map_adam(plan, ut, m, v, 1, lr, 1.0)
+        for p in range(u.shape[0]):
+            _, g = fo(uo[p])
+            uo[p], mo[p], vo[p] = O.adam_step(uo[p], -g, mo[p], vo[p], k, lr)
+        np.testing.assert_allclose(ut.cpu().numpy(), uo, atol=2e-4 * lr * k, rtol=0)
+    slots = O.intensity_slots(spec)
+    assert np.array_equal(ut.cpu().numpy()[:, slots], u[:, slots])
+
+
+def test_backward_hmc_with_frozen_intensities():
+    spec, sysm, table, u, plan, f = _stage_case()
+    d = spec.n_params
+    slots = O.intensity_slots(spec)
+    fj = f(True)
+    ut = O.to_unconstrained(torch.tensor(sysm.truth, dtype=torch.float64), table).numpy().astype(np.float32)
+    h = 1e-4
+    hd = np.array([(fj(ut + h * np.eye(d, dtype=np.float32)[j])[1][j] - fj(ut - h * np.eye(d, dtype=np.float32)[j])[1][j])
+                   / (2 * h) if j not in slots else 1.0 for j in range(d)])
+    inv_mass = (1.0 / np.maximum(np.abs(hd), 1e-6)).astype(np.float32)
+    inv_mass[slots] = 0.0
+    C, L, eps, seed = 4, 3, 0.2, 0xB4C
+    rng = np.random.default_rng(3)
+    U0 = (ut[None, :] + 0.3 * np.sqrt(inv_mass)[None, :] * rng.standard_normal((C, d))).astype(np.float32)
+    x = torch.tensor(U0, device=DEV)
+    lp, g = lens.lens_logpost_grad(plan, x, True)
+    samples = torch.empty((1, C, d), device=DEV)
+    acc = torch.zeros(C, dtype=torch.int32, device=DEV)
+    lens.lens_hmc_run(plan, x, g, lp, torch.tensor(inv_mass, device=DEV), eps, L, 1, seed, 0, samples=samples,
+                      accepts=acc, use_graph=True)
+    s = samples.cpu().numpy()[0]
+    assert np.array_equal(s[:, slots], U0[:, slots])
+    scale = np.sqrt(np.where(inv_mass > 0, inv_mass, 1.0).astype(np.float64))
+    checked = 0
+    for c in range(C):
+        uc, _, accepted, H0, H1, lu = O.hmc_transition(U0[c].astype(np.float64), fj, inv_mass, eps, L, seed, c, 0)
+        if abs(lu - (H0 - H1)) < 1e-2:
+            continue
+        assert bool(acc[c].item()) == bool(accepted), c
+        assert np.all(np.abs(s[c] - uc) <= 1e-3 * scale + 2 * np.spacing(np.abs(uc).astype(np.float32))), c
+        checked += 1
+    assert checked >= 2
+
+
+def test_backward_mode_refuses_svi_and_switches_off():
+    spec, sysm, table, u, plan, f = _stage_case()
+    phi = torch.zeros(lens.lens_svi_num_params(spec.n_params), device=DEV)
+    with pytest.raises(lens.LensError):
+        lens.lens_svi_elbo_grad(plan, phi, 4, 0)
+    with pytest.raises(lens.LensError):
+        lens.lens_logpost_grad(plan, torch.zeros((plan.max_particles, spec.n_params), device=DEV), True)  # P K > max
+    plan.set_backward(False)
+    lp, _ = lens.lens_logpost_grad(plan, torch.tensor(u, device=DEV), False)
+    assert torch.isfinite(lp).all()
+    lens.lens_svi_elbo_grad(plan, phi, 4, 0)          # accepted again
