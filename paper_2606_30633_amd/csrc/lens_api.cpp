@@ -420,8 +420,36 @@ static lens_status backward_enqueue(lens_plan* plan, int32_t P, const float* d_t
                               plan->bwd_theta, d_amp, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
-    lens_status r = loglike_grad_enqueue(plan, P, plan->bwd_theta, d_logl, d_grad, d_logl64, st);
-    if (r != LENS_OK) return r;
+    // logL and gradient at the solved intensities: constants of those
+    // parameters, the model image assembled from the component images (no
+    // second render), then the PSF / logL / adjoint pass of the forward path
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_PROLOGUE, st);
+        e = launch_prologue(plan->mi, P, plan->bwd_theta, plan->consts, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_FINALIZE, st);
+        e = launch_bwd_assemble(P, s, (int)npix, plan->imgbuf, plan->bwd_theta, plan->bwd_img, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
+        e = launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 2, P, plan->consts, plan->bwd_img, plan->psf_flip,
+                       plan->psf, plan->data, plan->invvar, nullptr, d_logl, d_logl64, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
+    {
+        TimedLaunch tl(&plan->timer, LENS_K_ADJOINT, st);
+        e = launch_adjoint(plan->mi, plan->geo, P, plan->ppt, plan->consts, plan->bwd_img, plan->partial, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
+    {
+        const int nch = chunks_for(plan->geo.npix, plan->ppt);
+        TimedLaunch tl(&plan->timer, LENS_K_FINALIZE, st);
+        e = launch_finalize(plan->mi, P, nch, plan->bwd_theta, plan->consts, plan->partial, d_grad, st);
+    }
+    if (e != hipSuccess) return LENS_EHIP;
     return hip_status(launch_bwd_zero_slots(P, s, d_grad, st));
 }
 

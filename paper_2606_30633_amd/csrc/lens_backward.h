@@ -22,6 +22,9 @@ hipError_t launch_bwd_expand(int P, const BwdSlots& s, const float* theta, float
 hipError_t launch_bwd_normal(int P, const BwdSlots& s, int npix, const float* B, const float* data,
                              const float* invvar, const float* consts, const float* theta,
                              float* theta_full, float* amp, hipStream_t st);
+// out [P][npix] = sum_k A_k comp[(p K + k)] with A_k read from theta_full's intensity slots.
+hipError_t launch_bwd_assemble(int P, const BwdSlots& s, int npix, const float* comp, const float* theta_full,
+                               float* out, hipStream_t st);
 // grad[p][slot] = 0 for every intensity slot.
 hipError_t launch_bwd_zero_slots(int P, const BwdSlots& s, float* grad, hipStream_t st);
 

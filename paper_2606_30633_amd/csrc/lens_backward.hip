@@ -7,9 +7,10 @@
 // b_k = sum w B_k d.  The component images come from a render pass that
 // writes each component's image separately and the ordinary PSF kernel;
 // the kernels here set the intensities to 1, reduce and solve the normal
-// equations per particle in float64, and clear the intensity entries of the
-// gradient (which, by the envelope theorem, is the forward gradient at the
-// solved intensities).
+// equations per particle in float64, assemble the model image at the solved
+// intensities from the component images, and clear the intensity entries of
+// the gradient (which, by the envelope theorem, is the forward gradient at
+// the solved intensities).
 #include <math.h>
 #include <stdint.h>
 
@@ -144,6 +145,22 @@ __global__ __launch_bounds__(256) void k_bwd_normal(int P, BwdSlots s, int npix,
     }
 }
 
+// Pre-PSF model image at the solved intensities, sum_k A_k b_k, from the
+// component images b_k of the split render (the PSF is linear, so this is
+// the image the render would produce at those intensities; NaN images of an
+// invalid particle stay NaN).
+__global__ void k_bwd_assemble(int P, BwdSlots s, int npix, const float* __restrict__ comp,
+                               const float* __restrict__ theta_full, float* __restrict__ out) {
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)P * npix) return;
+    const long p = q / npix;
+    const long pix = q - p * npix;
+    double acc = 0.0;
+    for (int k = 0; k < s.K; ++k)
+        acc = fma((double)theta_full[p * s.d + s.slot[k]], (double)comp[(p * s.K + k) * npix + pix], acc);
+    out[q] = (float)acc;
+}
+
 __global__ void k_bwd_zero_slots(int P, BwdSlots s, float* __restrict__ grad) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= P * s.K) return;
@@ -170,6 +187,14 @@ hipError_t launch_bwd_normal(int P, const BwdSlots& s, int npix, const float* B,
 #undef LENS_BWD_CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_assemble(int P, const BwdSlots& s, int npix, const float* comp, const float* theta_full,
+                               float* out, hipStream_t st) {
+    const long total = (long)P * npix;
+    hipLaunchKernelGGL(k_bwd_assemble, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, P, s, npix, comp,
+                       theta_full, out);
     return hipGetLastError();
 }
 
