@@ -70,3 +70,19 @@ def test_svi_parameter_count_matches_oracle_layout():
     for bad in (0, -3, 51):
         with pytest.raises(ValueError):
             lens.lens_svi_num_params(bad)
+
+
+def test_new_entry_points_reject_null_and_bad_arguments_on_the_host():
+    """SVI, HMC adaptation and backward modelling return LENS_EINVAL for a null
+    plan or invalid sizes before any GPU call."""
+    lib = lens.load_library()
+    EINVAL = -1
+    P = None
+    assert lib.lens_svi_reset(P) == EINVAL
+    assert lib.lens_svi_elbo_grad(P, 4, P, 0, 0, P, P, P, P) == EINVAL
+    assert lib.lens_svi_run(P, 4, P, P, P, 1, 1, 1e-4, 0.95, 0.99, 1e-16, 0, P, 0, P) == EINVAL
+    assert lib.lens_svi_moments(0, P, P, P, P, P) == EINVAL
+    assert lib.lens_svi_moments(29, P, P, P, P, P) == EINVAL
+    assert lib.lens_hmc_adapt(P, 4, P, P, P, P, 0.1, 0.8, 3, 10, 0, 0, 0, P, P, P, 0, P) == EINVAL
+    assert lib.lens_loglike_grad_backward(P, 4, P, P, P, P, P) == EINVAL
+    assert lib.lens_plan_set_backward(P, 1) == EINVAL
