@@ -147,14 +147,15 @@ lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* 
 
 /* Backward modelling in the inference stages (the paper models its real
  * system this way, App. B).  With enable != 0 the plan's posterior path
- * (lens_logpost_grad, lens_map_adam, lens_hmc_run, lens_hmc_adapt) uses the
- * backward likelihood above; the intensity entries of u are not parameters:
- * they add no prior or Jacobian term and their gradient is 0 (Adam leaves
- * them where they are; for HMC give them a zero inverse mass, which freezes a
- * coordinate).  Those calls then require P * K <= max_particles.  The SVI
- * calls return LENS_EUNSUPPORTED while it is on (nothing would bound the
- * surrogate's width along the intensities).  Allocates the backward scratch
- * when enabled; captured graphs are dropped.  Not callable during capture.
+ * (lens_logpost_grad, lens_map_adam, lens_hmc_run, lens_hmc_adapt and the
+ * SVI calls) uses the backward likelihood above; the intensity entries of u
+ * are not parameters: they add no prior or Jacobian term and their gradient
+ * is 0 (Adam leaves them where they are; for HMC give them a zero inverse
+ * mass, which freezes a coordinate; SVI holds mu_j and the whole row and
+ * column j of L fixed for them, since nothing would bound the surrogate's
+ * width there).  Those calls then require P * K <= max_particles (n draws
+ * for SVI).  Allocates the backward scratch when enabled; captured graphs
+ * are dropped.  Not callable during capture.
  * Errors: LENS_EINVAL for a model without light components. */
 lens_status lens_plan_set_backward(lens_plan* plan, int32_t enable);
 

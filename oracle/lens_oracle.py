@@ -645,7 +645,17 @@ def svi_normals(d: int, seed: int, sample: int, step: int) -> np.ndarray:
     return philox_normals(d, seed, sample, step, SVI_RNG_TAG)
 
 
-def svi_elbo_grad(phi, eps, logp_grad_fn, round_u: bool = True):
+def svi_frozen_mask(d: int, frozen) -> np.ndarray:
+    """Entries of phi held fixed when the coordinates in `frozen` are not
+    parameters (backward modelling): mu_j and every entry of L in row or
+    column j, for j in frozen."""
+    fz = set(int(j) for j in frozen)
+    r, c = np.tril_indices(d)
+    tri = np.array([(a in fz) or (b in fz) for a, b in zip(r, c)], dtype=bool)
+    return np.concatenate([np.array([j in fz for j in range(d)], dtype=bool), tri])
+
+
+def svi_elbo_grad(phi, eps, logp_grad_fn, round_u: bool = True, frozen=()):
     """Monte-Carlo ELBO of eq. elbo over the samples u_i = mu + L eps_i, and its
     gradient with respect to phi.
 
@@ -657,7 +667,9 @@ def svi_elbo_grad(phi, eps, logp_grad_fn, round_u: bool = True):
     The gradient is the reparameterised (pathwise) estimator: the derivative
     of that sample mean with the eps_i held fixed; the target enters only
     through its gradient at u_i.  Its expectation is the gradient of eq.
-    elbo-grad.  Returns (elbo, grad [len(phi)], u [n, d]).
+    elbo-grad.  With `frozen` coordinates (not parameters of the target) the
+    gradient entries of svi_frozen_mask are 0.  Returns (elbo, grad
+    [len(phi)], u [n, d]).
     """
     eps = np.asarray(eps, dtype=np.float64)
     n, d = eps.shape
@@ -676,7 +688,10 @@ def svi_elbo_grad(phi, eps, logp_grad_fn, round_u: bool = True):
     # d(-logp(u_i))/dphi = -dlogp/du . du/dphi, with du/dphi from autograd
     obj = logq.mean() - (g * u).sum(1).mean()
     (gr,) = torch.autograd.grad(obj, ph)
-    return elbo, gr.numpy(), u_eval
+    gr = gr.numpy()
+    if len(frozen):
+        gr = np.where(svi_frozen_mask(d, frozen), 0.0, gr)
+    return elbo, gr, u_eval
 
 
 def adabelief_step(x, g, m, s, k: int, lr: float, b1=0.9, b2=0.999, eps=1e-16):
@@ -698,7 +713,7 @@ SVI_ADAM, SVI_ADABELIEF = 0, 1
 
 def svi_run(phi0, n: int, n_steps: int, seed: int, logp_grad_fn, optimizer: int = SVI_ADABELIEF,
             lr: float = 1e-4, b1: float = 0.95, b2: float = 0.99, eps: float = 1e-16, step0: int = 0,
-            round_u: bool = True):
+            round_u: bool = True, frozen=()):
     """n_steps SVI iterations from phi0 with n surrogate samples per step.
 
     Step t (0-based, counted from step0 for the draws and the bias correction)
@@ -716,7 +731,7 @@ def svi_run(phi0, n: int, n_steps: int, seed: int, logp_grad_fn, optimizer: int 
     for t in range(n_steps):
         k = step0 + t
         E = np.stack([svi_normals(d, seed, i, k) for i in range(n)])
-        elbo, g, _ = svi_elbo_grad(phi, E, logp_grad_fn, round_u)
+        elbo, g, _ = svi_elbo_grad(phi, E, logp_grad_fn, round_u, frozen)
         elbos.append(elbo)
         grads.append(g)
         if optimizer == SVI_ADABELIEF:

@@ -705,15 +705,18 @@ static SviArgs svi_args(lens_plan* plan, int32_t n, float* d_phi, uint64_t seed)
     a.seed = seed;
     a.n = n;
     a.d = plan->mi.d;
+    if (plan->backward) {
+        const BwdSlots bs = bwd_slots(plan);
+        for (int k = 0; k < bs.K; ++k) a.frozen |= (uint64_t)1 << bs.slot[k];
+    }
     return a;
 }
 
 lens_status lens_svi_elbo_grad(lens_plan* plan, int32_t n, const float* d_phi, uint64_t seed,
                                int32_t step, double* d_elbo, float* d_grad_phi, float* d_u,
                                void* stream) {
-    if (!plan || !d_phi || !d_elbo || n < 1 || n > plan->max_particles || step < 0) return LENS_EINVAL;
+    if (!plan || !d_phi || !d_elbo || !posterior_fits(plan, n) || step < 0) return LENS_EINVAL;
     if (!plan->prior || plan->mi.d > SVI_MAX_D) return LENS_EINVAL;
-    if (plan->backward) return LENS_EUNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     SviArgs a = svi_args(plan, n, const_cast<float*>(d_phi), seed);
     if (d_u) a.u = d_u;
@@ -729,10 +732,9 @@ lens_status lens_svi_elbo_grad(lens_plan* plan, int32_t n, const float* d_phi, u
 lens_status lens_svi_run(lens_plan* plan, int32_t n, float* d_phi, float* d_m, float* d_s,
                          int32_t n_steps, int32_t optimizer, float lr, float beta1, float beta2,
                          float eps, uint64_t seed, double* d_elbo, int32_t use_graph, void* stream) {
-    if (!plan || !d_phi || !d_m || !d_s || n < 1 || n > plan->max_particles || n_steps < 0)
+    if (!plan || !d_phi || !d_m || !d_s || !posterior_fits(plan, n) || n_steps < 0)
         return LENS_EINVAL;
     if (!plan->prior || plan->mi.d > SVI_MAX_D) return LENS_EINVAL;
-    if (plan->backward) return LENS_EUNSUPPORTED;
     if ((optimizer != LENS_OPT_ADAM && optimizer != LENS_OPT_ADABELIEF) || !(lr > 0.0f) ||
         !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
         return LENS_EINVAL;

@@ -71,6 +71,7 @@ struct SviArgs {
     const int* step;       // SVI step: Philox counter word 1; bias correction uses step + 1
     const int* call_step;  // index into elbo, or null for index 0
     uint64_t seed;
+    uint64_t frozen;       // bit j: coordinate j is not a parameter; mu_j and L's row and column j stay fixed
     int n, d;
     int update, optimizer;
     float lr, beta1, beta2, eps_opt;

@@ -610,14 +610,22 @@ __global__ __launch_bounds__(256) void k_svi_reduce(SviArgs a) {
     const int e = (int)blockIdx.x - 1;
     int r = 0, c = 0;
     double acc = 0.0;
-    if (e < 0) {
-        for (int i = tid; i < n; i += 256) acc += a.logq[i] - a.logp[i];
-    } else if (e < d) {
-        for (int i = tid; i < n; i += 256) acc -= (double)a.grad_u[(size_t)i * d + e];
-    } else {
+    bool frozen = false;
+    if (e >= d) {
         const int t = e - d;
         while ((r + 1) * (r + 2) / 2 <= t) ++r;
         c = t - r * (r + 1) / 2;
+        frozen = ((a.frozen >> r) & 1u) || ((a.frozen >> c) & 1u);
+    } else if (e >= 0) {
+        frozen = (a.frozen >> e) & 1u;
+    }
+    if (e < 0) {
+        for (int i = tid; i < n; i += 256) acc += a.logq[i] - a.logp[i];
+    } else if (frozen) {
+        acc = 0.0;
+    } else if (e < d) {
+        for (int i = tid; i < n; i += 256) acc -= (double)a.grad_u[(size_t)i * d + e];
+    } else {
         const double* ec = a.eps + (size_t)c * n;
         for (int i = tid; i < n; i += 256) acc -= (double)a.grad_u[(size_t)i * d + r] * ec[i];
     }
@@ -633,12 +641,12 @@ __global__ __launch_bounds__(256) void k_svi_reduce(SviArgs a) {
         if (a.elbo) a.elbo[a.call_step ? *a.call_step : 0] = v;
         return;
     }
-    if (e >= d && r == c) {
+    if (e >= d && r == c && !frozen) {
         const double rho = (double)a.phi[e];
         v = (v - 1.0 / (softplus_d(rho) + SVI_DIAG_SHIFT)) * sigmoid_d(rho);
     }
     if (a.grad_phi) a.grad_phi[e] = (float)v;
-    if (!a.update) return;
+    if (!a.update || frozen) return;
     const int k = *a.step + 1;
     const double b1 = (double)a.beta1, b2 = (double)a.beta2, ep = (double)a.eps_opt;
     const double m = b1 * (double)a.m[e] + (1.0 - b1) * v;

@@ -240,14 +240,45 @@ def test_backward_hmc_with_frozen_intensities():
     assert checked >= 2
 
 
-def test_backward_mode_refuses_svi_and_switches_off():
+def test_backward_svi_matches_oracle_with_frozen_intensities():
+    """SVI in backward mode: the intensity coordinates are frozen in the
+    surrogate (mu_j and L's row and column j get a zero gradient and are not
+    updated); ELBO and gradient against the oracle, the frozen entries
+    unchanged bit for bit after AdaBelief steps; the P K limit; switching
+    backward mode off."""
     spec, sysm, table, u, plan, f = _stage_case()
-    phi = torch.zeros(lens.lens_svi_num_params(spec.n_params), device=DEV)
+    d = spec.n_params
+    slots = O.intensity_slots(spec)
+    fj = f(True)
+
+    def fb(U):
+        out = [fj(x) for x in U]
+        return np.array([o[0] for o in out]), np.stack([o[1] for o in out])
+
+    mu = O.to_unconstrained(torch.tensor(sysm.truth, dtype=torch.float64), table).numpy()
+    rng = np.random.default_rng(4)
+    L = np.diag(np.full(d, 0.01)) + np.tril(0.002 * rng.standard_normal((d, d)), -1)
+    phi = O.svi_pack(mu, L).astype(np.float32)
+    n, seed = 8, 17
+    x = torch.tensor(phi, device=DEV)
+    elbo, g = lens.lens_svi_elbo_grad(plan, x, n, seed, 1)
+    elbo, g = float(elbo.item()), g.cpu().numpy()
+    E = np.stack([O.svi_normals(d, seed, i, 1) for i in range(n)])
+    eo, go, _ = O.svi_elbo_grad(phi.astype(np.float64), E, fb, frozen=slots)
+    mask = O.svi_frozen_mask(d, slots)
+    assert np.all(g[mask] == 0)
+    assert abs(elbo - eo) <= RTOL * abs(eo), (elbo, eo)
+    assert np.linalg.norm(g - go) <= RTOL * np.linalg.norm(go)
+    m = torch.zeros_like(x)
+    s2 = torch.zeros_like(x)
+    lens.lens_svi_reset(plan)
+    lens.lens_svi_run(plan, x, m, s2, n, 2, "adabelief", 1e-3, 0.95, 0.99, 1e-16, seed, use_graph=True)
+    xn = x.cpu().numpy()
+    assert np.array_equal(xn[mask], phi[mask]) and not np.array_equal(xn[~mask], phi[~mask])
     with pytest.raises(lens.LensError):
-        lens.lens_svi_elbo_grad(plan, phi, 4, 0)
+        lens.lens_svi_elbo_grad(plan, x, plan.max_particles, 0)          # n K > max_particles
     with pytest.raises(lens.LensError):
-        lens.lens_logpost_grad(plan, torch.zeros((plan.max_particles, spec.n_params), device=DEV), True)  # P K > max
+        lens.lens_logpost_grad(plan, torch.zeros((plan.max_particles, d), device=DEV), True)
     plan.set_backward(False)
     lp, _ = lens.lens_logpost_grad(plan, torch.tensor(u, device=DEV), False)
     assert torch.isfinite(lp).all()
-    lens.lens_svi_elbo_grad(plan, phi, 4, 0)          # accepted again

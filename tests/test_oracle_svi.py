@@ -167,3 +167,47 @@ def test_svi_gradient_matches_finite_differences_on_lens_posterior():
         fm = O.svi_elbo_grad(phi - e, E, f, round_u=False)[0]
         fd = (fp - fm) / (2 * h)
         assert abs(fd - g[k]) <= 2e-5 * max(1.0, np.abs(g).max()), (k, fd, g[k])
+
+
+def test_frozen_coordinates_stay_put_and_leave_the_rest_exact():
+    """A coordinate that the target ignores (a backward-modelled intensity)
+    is held fixed with every surrogate entry in its row and column; on a
+    Gaussian target over the other coordinates the rest of the gradient is
+    still the closed-form KL gradient, and the frozen entries never move."""
+    rng = np.random.default_rng(9)
+    d, fz = 4, [2]
+    keep = [0, 1, 3]
+    S = _spd(rng, 3)
+    m = rng.normal(size=3)
+    base = _gauss_fn(m, S)
+
+    def f(U):
+        lp, g = base(U[:, keep])
+        G = np.zeros_like(U)
+        G[:, keep] = g
+        return lp, G
+
+    mu = rng.normal(size=d)
+    L = np.tril(0.2 * rng.normal(size=(d, d)))
+    np.fill_diagonal(L, 0.5 + rng.uniform(size=d))
+    L[2, :2] = 0.0
+    L[3, 2] = 0.0
+    phi = O.svi_pack(mu, L)
+    E = 2.0 * np.vstack([np.eye(d), -np.eye(d)])          # mean 0, second moment I (sqrt(d) = 2)
+    _, g, _ = O.svi_elbo_grad(phi, E, f, round_u=False, frozen=fz)
+    mask = O.svi_frozen_mask(d, fz)
+    assert np.all(g[mask] == 0)
+    Lk = L[np.ix_(keep, keep)]
+    P = np.linalg.inv(S)
+    g_mu = P @ (mu[keep] - m)
+    g_L = np.tril(P @ Lk) - np.diag(1.0 / np.diag(Lk))
+    r, c = np.tril_indices(d)
+    full = np.zeros((d, d))
+    full[np.ix_(keep, keep)] = g_L
+    want = full[r, c].copy()
+    rho = phi[d:][r == c]
+    want[r == c] *= 1.0 / (1.0 + np.exp(-rho))
+    np.testing.assert_allclose(g[:d][keep], g_mu, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(g[d:][~mask[d:]], want[~mask[d:]], rtol=1e-11, atol=1e-12)
+    phi2, _, _ = O.svi_run(phi, 16, 30, 3, f, O.SVI_ADABELIEF, lr=1e-2, round_u=False, frozen=fz)
+    assert np.array_equal(phi2[mask], phi[mask])
