@@ -446,12 +446,39 @@ def run_batch(args):
         bp.loglike_grad(theta, logl, grad, use_graph=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # the same work as 100 single-system plans (each with the tile the autotuner chose for its
+    # system), launched one after another on the stream
+    plans = []
+    for k, sp in enumerate(sy.specs):
+        pl = lens.LensPlan(sp, sy.psfs[k], sy.datas[k], sy.invvars[k], P, dev)
+        pl.set_pixels_per_thread(int(tiles[k]))
+        plans.append(pl)
+    l2 = torch.empty_like(logl)
+    g2 = torch.empty_like(grad)
+
+    def per_system():
+        for k, pl in enumerate(plans):
+            r = slice(k * P, (k + 1) * P)
+            lens.lens_loglike_grad(pl, theta[r], l2[r], g2[r])
+
+    per_system()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        per_system()
+    torch.cuda.synchronize()
+    dt_sep = (time.perf_counter() - t0) / args.steps
+    same = bool(torch.equal(l2, logl)) and bool(torch.equal(g2, grad))
+    for pl in plans:
+        pl.close()
     sub = sum(sp.nx * sp.ny * sp.supersample ** 2 for sp in sy.specs) * P
     _line(args, bp.N / dt, "evals/s", dt * 1e3,
           "uneven batch: 100 systems (side 48-160 px, s 2-4, PSF 11-31), 512 particles each, "
           "one persistent render + adjoint launch per step, autotuned tiles",
           {"particles": bp.N, "sub_pixel_evals_per_s": round(sub / dt, 1), "autotune_s": round(t_tune, 2),
-           "tiles": {str(t): tiles.count(t) for t in sorted(set(tiles))}})
+           "tiles": {str(t): tiles.count(t) for t in sorted(set(tiles))},
+           "per_system_plans_evals_per_s": round(bp.N / dt_sep, 1),
+           "persistent_gain": round(dt_sep / dt, 3), "per_system_results_identical": same})
 
 
 def run_cnn(args):
