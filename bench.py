@@ -216,7 +216,9 @@ def _series_terms(th, spec):
 
 
 def cpu_baseline(spec, sysm, th_sample):
-    """The FP64 oracle timed on the host cores on a bounded sample."""
+    """The FP64 oracle timed on the host cores on a bounded sample: logL +
+    gradient (the reported value), logL alone on 64 particles, and logL +
+    gradient on one thread (8 particles)."""
     import torch
     from oracle import lens_oracle as O
     model = O.model_image(sysm.truth, spec, sysm.psf).numpy()
@@ -226,9 +228,24 @@ def cpu_baseline(spec, sysm, th_sample):
     for t in th_sample:
         O.loglike_and_grad(t, spec, sysm.psf, data, sysm.invvar)
     dt = time.perf_counter() - t0
-    return {"value": round(len(th_sample) / dt, 3), "unit": "evals/s", "cores": torch.get_num_threads(),
+    cores = torch.get_num_threads()
+    t0 = time.perf_counter()
+    for t in th_sample[:64]:
+        O.loglike(t, spec, sysm.psf, data, sysm.invvar)
+    dt_l = time.perf_counter() - t0
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        for t in th_sample[:8]:
+            O.loglike_and_grad(t, spec, sysm.psf, data, sysm.invvar)
+        dt_1 = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(cores)
+    return {"value": round(len(th_sample) / dt, 3), "unit": "evals/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{len(th_sample)} particles of the same workload, logL+grad (FP64 autograd)"}
+            "sample": f"{len(th_sample)} particles of the same workload, logL+grad (FP64 autograd)",
+            "logl_only_evals_per_s": round(min(64, len(th_sample)) / dt_l, 3),
+            "one_thread_evals_per_s": round(min(8, len(th_sample)) / dt_1, 3)}
 
 
 def _line(args, value, unit, ms_step, workload, extra, roofline=None, dtype="f32+f64"):
