@@ -138,9 +138,10 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
  *   d_theta [P][d] in (intensity entries ignored); d_logl [P], d_grad [P][d]
  *   out; d_amp [P][K] out, optional: the solved intensities (NaN for a
  *   particle with an invalid ellipticity, whose logL is -inf).
- * Requires P * K <= max_particles (the K component images of every particle
- * are held together in the plan's image buffers).  Allocates its scratch (two parameter
- * arrays and one model-image array of max_particles rows) on first use.
+ * Requires P * K <= max_particles (the K component images of every
+ * particle are held together in the plan's image buffers).  Allocates its
+ * scratch (two parameter arrays and one model-image array of max_particles
+ * rows) on first use.
  * Errors: LENS_EINVAL for P * K above max_particles. */
 lens_status lens_loglike_grad_backward(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
                                        float* d_grad, float* d_amp, void* stream);
@@ -223,7 +224,8 @@ lens_status lens_map_adam(lens_plan* plan, int32_t P, float* d_u, float* d_m, fl
  * uniform from counter block ceil(d/4).
  *   d_u [C][d], d_grad [C][d] (= dlogp/du), d_logp [C] (float64): the chain
  *   state, in/out; must be consistent on entry (lens_logpost_grad with
- *   with_jacobian = 1).  d_inv_mass [d]: M^-1 diagonal.
+ *   with_jacobian = 1).  d_inv_mass [d]: M^-1 diagonal (an entry of 0
+ *   freezes that coordinate: no momentum, no motion).
  *   d_samples [n_transitions][C][d] out, optional; d_accepts [C] in/out,
  *   optional: incremented on every accepted transition.
  *   transition0: index of the first transition (counter word 1); successive
