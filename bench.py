@@ -41,11 +41,12 @@ def parse():
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
-    ap.add_argument("--workload", choices=["map", "hmc", "svi", "backward", "batch", "cnn"], default="map",
+    ap.add_argument("--workload", choices=["map", "hmc", "svi", "backward", "batch", "cnn", "parity"], default="map",
                     help="map: the headline MAP step (default); hmc: 8192 chains x 10 leapfrog on the same "
                          "system; svi: AdaBelief SVI steps with 4096 surrogate draws on the same system; "
                          "backward: logL + gradient with the intensities solved by linear inversion; "
-                         "batch: 100 uneven systems x 512 particles; cnn: network training")
+                         "batch: 100 uneven systems x 512 particles; cnn: network training; parity: the small "
+                         "60x60 parity system (64 particles), GPU and oracle rates for information")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB (plain copy kernel, "
                          "for scaling HBM byte counters)")
@@ -89,7 +90,7 @@ def main():
         sys.exit(2)
     if args.workload != "map":
         return {"hmc": run_hmc, "svi": run_svi, "backward": run_backward, "batch": run_batch,
-                "cnn": run_cnn}[args.workload](args)
+                "cnn": run_cnn, "parity": run_parity}[args.workload](args)
     import torch
     from paper_2606_30633_amd import lens, synth
 
@@ -435,6 +436,70 @@ def run_backward(args):
           "4096 particles",
           {"particles": P, "components": K, "finite_fraction": round(float(torch.isfinite(L).float().mean()), 4)},
           roof)
+
+
+def run_parity(args):
+    """The 60x60 parity system (SIE + shear, Sersic lens + source, s = 2, 11x11
+    PSF), 64 particles: GPU logL and logL + gradient rates (a small, launch-bound
+    call) and the oracle on all 64 particles, all host threads and one thread."""
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    dev = torch.device("cuda", 0)
+    spec, sysm = synth.config1_spec(), synth.config1_system()
+    psf = sysm.psf
+    plan0 = lens.LensPlan(spec, psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
+    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
+            + torch.tensor(sysm.noise, device=dev)).contiguous()
+    th = synth.particles_box(sysm, 64, 0)
+    plan = lens.LensPlan(spec, torch.tensor(psf, device=dev), data, torch.tensor(sysm.invvar, device=dev), 64, dev)
+    t = torch.tensor(th, device=dev)
+    for _ in range(args.warmup):
+        lens.lens_loglike_grad(plan, t)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 1) * 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lens.lens_loglike_grad(plan, t)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lens.lens_loglike(plan, t)
+    torch.cuda.synchronize()
+    dt_l = (time.perf_counter() - t0) / reps
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the host cores, with the data rendered by the oracle itself
+        from oracle import lens_oracle as O
+        data = (O.model_image(sysm.truth, spec, psf).numpy() + sysm.noise).astype(np.float32)
+        cores = torch.get_num_threads()
+        t0 = time.perf_counter()
+        for x in th:
+            O.loglike(x, spec, psf, data, sysm.invvar)
+        c_l = len(th) / (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for x in th:
+            O.loglike_and_grad(x, spec, psf, data, sysm.invvar)
+        c_g = len(th) / (time.perf_counter() - t0)
+        torch.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            for x in th[:16]:
+                O.loglike_and_grad(x, spec, psf, data, sysm.invvar)
+            c_1 = 16 / (time.perf_counter() - t0)
+        finally:
+            torch.set_num_threads(cores)
+        cpu = {"value": round(c_g, 3), "unit": "evals/s", "cores": cores, "kind": "oracle",
+               "sample": "the 64 particles, logL+grad (FP64 autograd)", "logl_only_evals_per_s": round(c_l, 3),
+               "one_thread_evals_per_s": round(c_1, 3)}
+    out = {"metric": METRIC, "value": round(64 / dt, 1), "unit": "evals/s", "n_gpus": 1, "steps": reps,
+           "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "parity system: 60x60 px, s=2, SIE+shear, Sersic lens + source, 11x11 Gaussian "
+                                  "PSF, 64 particles (information only: a launch-bound call)",
+                      "particles": 64, "logl_only_evals_per_s": round(64 / dt_l, 1)},
+           "roofline": None, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
 
 
 def run_batch(args):
