@@ -392,3 +392,23 @@ def test_hmc_adapt_reaches_target_acceptance():
     assert 0.6 < rate < 0.95
     tr2, _, _ = lens.lens_hmc_adapt(plan, x, g, lp, im, 0.05, 0.8, 5, 2, 0, 78)
     assert float(tr2[0].item()) == np.float32(0.05)
+
+
+def test_hmc_adapt_graph_equals_eager():
+    """The adaptive burn-in replayed from a captured graph equals the eager
+    run bit for bit (step-size state, window sums and counters live on the
+    device and restart at every call)."""
+    spec, plan, f, ut, inv_mass = _adapt_case()
+    d = spec.n_params
+    rng = np.random.default_rng(21)
+    U0 = (ut[None, :] + 0.3 * np.sqrt(inv_mass)[None, :] * rng.standard_normal((16, d))).astype(np.float32)
+    im = torch.tensor(inv_mass, device=DEV)
+    outs = []
+    for graph in (False, True, True):
+        x = torch.tensor(U0, device=DEV)
+        lp, g = lens.lens_logpost_grad(plan, x, True)
+        tr, fin, var = lens.lens_hmc_adapt(plan, x, g, lp, im, 0.05, 0.8, 3, 6, 2, 99, use_graph=graph)
+        outs.append([t.cpu().numpy() for t in (x, lp, tr, fin, var)])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
