@@ -302,3 +302,22 @@ def test_float32_theta_posterior_close_to_float64():
                                                   theta_float32=True)
             assert abs(a - b) <= 1e-6 * abs(a)
             assert np.linalg.norm(ga - gb) <= 1e-5 * np.linalg.norm(ga)
+
+
+def test_hmc_rejects_non_finite_energy():
+    """A proposal whose log density is -inf (outside the support) is never
+    accepted: the chain stays put and its log density stays finite."""
+    def f(u):
+        if u[0] > 0.5:                                   # hard wall: no density beyond it
+            return -math.inf, np.zeros(2)
+        return -0.5 * float(u @ u), -u
+    u = np.array([0.45, 0.0])
+    moved_out = 0
+    for t in range(200):
+        u1, lp, acc, H0, H1, lu = O.hmc_transition(u, f, np.ones(2), 0.4, 3, 11, 0, t)
+        if not math.isfinite(H1):
+            assert not acc and np.array_equal(u1, u)
+            moved_out += 1
+        assert u1[0] <= 0.5 and math.isfinite(lp)
+        u = u1
+    assert moved_out > 0
