@@ -82,6 +82,22 @@ def render_flops_per_subpixel(K_s, NL, NS, epl=True):
     return 4 * K_s + 40 + (60 if epl else 0) + 12 + (NL + NS) * 18 + 1
 
 
+def system_plan(spec, sysm, max_particles, dev, with_prior=True):
+    """A plan on the system's observed image: the forward model at the truth
+    (GPU) plus the system's seeded noise.  Returns (plan, data)."""
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
+    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
+            + torch.tensor(sysm.noise, device=dev)).contiguous()
+    plan0.close()
+    plan = lens.LensPlan(spec, torch.tensor(sysm.psf, device=dev), data, torch.tensor(sysm.invvar, device=dev),
+                         max_particles, dev)
+    if with_prior:
+        plan.set_prior(synth.prior_table(sysm.prior))
+    return plan, data
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -99,16 +115,9 @@ def main():
     sysm = synth.config2_system()
     P = args.particles
     th = synth.particles_box(sysm, P, 0)
-    psf_t = torch.tensor(sysm.psf, device=dev)
-    inv_t = torch.tensor(sysm.invvar, device=dev)
     # observed image: forward model at the truth (GPU) + seeded noise
-    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
-    model = lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
-    data = (model + torch.tensor(sysm.noise, device=dev)).contiguous()
-    plan0.close()
-    plan = lens.LensPlan(spec, psf_t, data, inv_t, P, dev)
+    plan, data = system_plan(spec, sysm, P, dev)
     table = synth.prior_table(sysm.prior)
-    plan.set_prior(table)
     u = torch.tensor(_to_unconstrained_box(th, table), device=dev)
     m = torch.zeros_like(u)
     v = torch.zeros_like(u)
@@ -265,12 +274,7 @@ def run_hmc(args):
     dev = torch.device("cuda", 0)
     spec, sysm = synth.config2_spec(), synth.config2_system()
     C, L = 8192, 10
-    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
-    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
-            + torch.tensor(sysm.noise, device=dev)).contiguous()
-    plan = lens.LensPlan(spec, torch.tensor(sysm.psf, device=dev), data, torch.tensor(sysm.invvar, device=dev),
-                         C, dev)
-    plan.set_prior(synth.prior_table(sysm.prior))
+    plan, _ = system_plan(spec, sysm, C, dev)
     d = spec.n_params
     ut = lens.lens_to_unconstrained(plan, torch.tensor(sysm.truth[None, :], device=dev))
     # diagonal of the Hessian at the truth by central differences of the gradient -> mass matrix
@@ -326,12 +330,7 @@ def run_svi(args):
     dev = torch.device("cuda", 0)
     spec, sysm = synth.config2_spec(), synth.config2_system()
     n = 4096
-    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
-    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
-            + torch.tensor(sysm.noise, device=dev)).contiguous()
-    plan = lens.LensPlan(spec, torch.tensor(sysm.psf, device=dev), data, torch.tensor(sysm.invvar, device=dev),
-                         n, dev)
-    plan.set_prior(synth.prior_table(sysm.prior))
+    plan, _ = system_plan(spec, sysm, n, dev)
     d = spec.n_params
     ut = lens.lens_to_unconstrained(plan, torch.tensor(sysm.truth[None, :], device=dev))
     # surrogate start: mean at the truth, diagonal scale half the inverse-Hessian-diagonal width
@@ -397,11 +396,7 @@ def run_backward(args):
     spec, sysm = synth.config2_spec(), synth.config2_system()
     P = 4096
     K = spec.n_lens_light + spec.n_source
-    plan0 = lens.LensPlan(spec, sysm.psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
-    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
-            + torch.tensor(sysm.noise, device=dev)).contiguous()
-    plan = lens.LensPlan(spec, torch.tensor(sysm.psf, device=dev), data, torch.tensor(sysm.invvar, device=dev),
-                         P * K, dev)
+    plan, _ = system_plan(spec, sysm, P * K, dev, with_prior=False)
     th_np = synth.particles_box(sysm, P, 0)
     th = torch.tensor(th_np, device=dev)
     for _ in range(args.warmup):
@@ -447,11 +442,8 @@ def run_parity(args):
     dev = torch.device("cuda", 0)
     spec, sysm = synth.config1_spec(), synth.config1_system()
     psf = sysm.psf
-    plan0 = lens.LensPlan(spec, psf, np.zeros((spec.ny, spec.nx), np.float32), sysm.invvar, 1, dev)
-    data = (lens.lens_forward(plan0, torch.tensor(sysm.truth[None, :], device=dev))[0]
-            + torch.tensor(sysm.noise, device=dev)).contiguous()
+    plan, _ = system_plan(spec, sysm, 64, dev, with_prior=False)
     th = synth.particles_box(sysm, 64, 0)
-    plan = lens.LensPlan(spec, torch.tensor(psf, device=dev), data, torch.tensor(sysm.invvar, device=dev), 64, dev)
     t = torch.tensor(th, device=dev)
     for _ in range(args.warmup):
         lens.lens_loglike_grad(plan, t)
