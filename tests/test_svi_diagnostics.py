@@ -40,3 +40,21 @@ def test_chains_stuck_apart_have_large_rhat():
     assert np.all(split_rhat(x) > 1.3)
     drift = rng.standard_normal((500, 4, 1)) + np.linspace(0, 4, 500)[:, None, None]
     assert split_rhat(drift)[0] > 1.3
+
+
+def test_elbo_summary_and_hmc_comparison_helpers():
+    from paper_2606_30633_amd.svi_study import compare_to_hmc, elbo_summary
+    el = np.concatenate([np.linspace(100.0, 10.0, 150), [30.0], np.full(149, 10.0)])
+    s = elbo_summary(el)
+    assert s["elbo_first"] == 100.0 and s["elbo_last100"] == 10.0 and s["elbo_min"] == 10.0
+    assert s["steps_above_start_after_100"] == 0
+    assert abs(s["max_rise_above_running_min"] - 20.0) < 1e-12
+    el2 = el.copy()
+    el2[200:205] = 150.0                       # five steps above the start after step 100
+    assert elbo_summary(el2)["steps_above_start_after_100"] == 5
+    rng = np.random.default_rng(0)
+    smp = rng.standard_normal((400, 8, 3)) * np.array([1.0, 2.0, 0.5]) + np.array([0.0, 1.0, -1.0])
+    c = compare_to_hmc(np.array([0.0, 1.0, -1.0]), np.array([1.0, 4.0, 0.25]), smp)
+    assert c["mean_offset_sd_max"] < 0.1 and abs(c["std_ratio_median"] - 1) < 0.05
+    c2 = compare_to_hmc(np.array([1.0, 1.0, -1.0]), np.array([0.25, 1.0, 0.0625]), smp)
+    assert abs(c2["std_ratio_median"] - 0.5) < 0.05 and c2["mean_offset_sd_max"] > 0.9
