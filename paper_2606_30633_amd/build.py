@@ -10,7 +10,8 @@ LIB = os.path.join(HERE, "liblens.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 instructions stay off (see the design notes)
+    # packed FP32 instructions stay off: some of their forms have given wrong
+    # results on this hardware without any error, and the kernels do not need them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

@@ -86,3 +86,14 @@ def test_new_entry_points_reject_null_and_bad_arguments_on_the_host():
     assert lib.lens_hmc_adapt(P, 4, P, P, P, P, 0.1, 0.8, 3, 10, 0, 0, 0, P, P, P, 0, P) == EINVAL
     assert lib.lens_loglike_grad_backward(P, 4, P, P, P, P, P) == EINVAL
     assert lib.lens_plan_set_backward(P, 1) == EINVAL
+
+
+def test_build_flags_target_gfx950_without_packed_fp32():
+    """Every HIP source is compiled for gfx950 with the packed-FP32 target
+    feature switched off (the code relies on scalar FP32 FMA only)."""
+    from paper_2606_30633_amd import build as B
+    flags = " ".join(B.HIPCC_FLAGS)
+    assert "--offload-arch=gfx950" in flags
+    assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in flags
+    srcs = B.sources()
+    assert any(s.endswith("lens_kernels.hip") for s in srcs) and any(s.endswith("lens_backward.hip") for s in srcs)
