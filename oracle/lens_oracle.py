@@ -933,3 +933,49 @@ def log_posterior_backward(u, spec, psf, data, invvar, table, with_jacobian: boo
     g = torch.tensor(gL) * dth.detach() + gr
     g[slots] = 0.0
     return float(L) + float(rest.detach()), g.numpy()
+
+
+# ---------------------------------------------------------------------------
+# Shapelet sources (Sec. 3 names shapelets beside Sersic profiles for the
+# source light; the basis is the Cartesian one of Refregier 2003, MNRAS 338,
+# 35, also used by Birrer et al. 2015).  Not on the GPU path: the oracle's
+# definition, pinned, for a source profile the kernels do not implement.
+#   phi_n(x; beta) = [2^n sqrt(pi) n! beta]^(-1/2) H_n(x / beta) exp(-x^2 / (2 beta^2)),
+#   H_n the physicists' Hermite polynomials; the 2-D basis is
+#   phi_n1(x) phi_n2(y) for n1 + n2 <= n_max, ordered by n = n1 + n2, then n2.
+# ---------------------------------------------------------------------------
+def hermite_phys(n: int, x: torch.Tensor) -> torch.Tensor:
+    """H_n(x) by the recurrence H_{k+1} = 2x H_k - 2k H_{k-1}."""
+    h0 = torch.ones_like(x)
+    if n == 0:
+        return h0
+    h1 = 2.0 * x
+    for k in range(1, n):
+        h0, h1 = h1, 2.0 * x * h1 - 2.0 * k * h0
+    return h1
+
+
+def shapelet_1d(n: int, x: torch.Tensor, beta) -> torch.Tensor:
+    norm = 1.0 / math.sqrt((2.0 ** n) * math.sqrt(math.pi) * math.factorial(n))
+    u = x / beta
+    return norm / torch.sqrt(torch.as_tensor(beta, dtype=DT)) * hermite_phys(n, u) * torch.exp(-0.5 * u * u)
+
+
+def shapelet_indices(n_max: int) -> List[Tuple[int, int]]:
+    return [(n - n2, n2) for n in range(n_max + 1) for n2 in range(n + 1)]
+
+
+def shapelet_basis(x: torch.Tensor, y: torch.Tensor, beta, n_max: int) -> torch.Tensor:
+    """[n_basis, *x.shape]: every 2-D basis function at (x, y)."""
+    return torch.stack([shapelet_1d(a, x, beta) * shapelet_1d(b, y, beta) for a, b in shapelet_indices(n_max)])
+
+
+def shapelet_source(x, y, xc, yc, beta, coeffs) -> torch.Tensor:
+    """Surface brightness sum_k c_k phi_k(x - xc, y - yc; beta); the number of
+    coefficients fixes n_max ((n_max + 1)(n_max + 2) / 2 of them)."""
+    c = _t(coeffs)
+    nb = c.shape[0]
+    n_max = int(round((math.sqrt(8 * nb + 1) - 3) / 2))
+    assert (n_max + 1) * (n_max + 2) // 2 == nb
+    B = shapelet_basis(x - xc, y - yc, beta, n_max)
+    return torch.einsum("k...,k->...", B, c)
