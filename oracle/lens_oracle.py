@@ -979,3 +979,21 @@ def shapelet_source(x, y, xc, yc, beta, coeffs) -> torch.Tensor:
     assert (n_max + 1) * (n_max + 2) // 2 == nb
     B = shapelet_basis(x - xc, y - yc, beta, n_max)
     return torch.einsum("k...,k->...", B, c)
+
+
+def lensed_shapelet_image(theta, spec, psf, xc, yc, beta, coeffs) -> torch.Tensor:
+    """Model image [ny, nx] of one shapelet source seen through the lens of
+    the parameter vector theta (its mass and shear entries; its light
+    components are not used): the source is evaluated at the lens-equation
+    positions of the sub-pixel grid, then downsampled and PSF-convolved like
+    the Sersic components."""
+    th = _t(theta)
+    X, Y = subpixel_grid(spec.nx, spec.ny, spec.pix_scale, spec.supersample)
+    p = unpack(th, spec)
+    if spec.mass_model == "EPL":
+        ax, ay = epl_deflection(X, Y, p["theta_E"], p["gamma"], p["m_e1"], p["m_e2"], p["m_x"], p["m_y"])
+    else:
+        ax, ay = sie_deflection(X, Y, p["theta_E"], p["m_e1"], p["m_e2"], p["m_x"], p["m_y"])
+    sx, sy = shear_deflection(X, Y, p["g1"], p["g2"])
+    v = shapelet_source(X - ax - sx, Y - ay - sy, xc, yc, beta, coeffs)
+    return convolve_psf(downsample(v, spec.supersample), psf)

@@ -2,7 +2,9 @@
 against numpy's, orthonormality of the 2-D basis by quadrature, the n = 0
 function is the unit-norm Gaussian, the odd functions integrate to zero and
 the even ones to their closed-form flux, and a source is the coefficient
-sum."""
+sum.  A lensed shapelet source without deflection is the unlensed one; the
+lensed image is linear in the coefficients, which a weighted least-squares
+solve recovers from noiseless data (the backward use of shapelets)."""
 import math
 
 import numpy as np
@@ -60,3 +62,39 @@ def test_source_is_the_coefficient_sum():
     s = O.shapelet_source(x, y, 0.05, -0.02, 0.2, c)
     B = O.shapelet_basis(x - 0.05, y + 0.02, 0.2, 3)
     np.testing.assert_allclose(s.numpy(), (torch.tensor(c)[:, None] * B).sum(0).numpy(), rtol=1e-13)
+
+
+def _lens_case():
+    from paper_2606_30633_amd import synth
+    spec = synth.ModelSpec(20, 18, 0.12, 2, 5, synth.MASS_SIE, 1, 1)
+    psf = synth.asymmetric_psf(spec.psf_size, synth.SEED_TEST_PSF)
+    sysm = synth.make_system_box(spec, 0, psf=psf)
+    return spec, psf, sysm
+
+
+def test_lensed_shapelets_without_deflection_are_the_unlensed_source():
+    spec, psf, sysm = _lens_case()
+    th = np.array(sysm.truth, dtype=np.float64)
+    th[0] = 1e-12                                  # theta_E -> 0: no mass deflection
+    th[5], th[6] = 0.0, 0.0                        # no shear (SIE layout: theta_E, e1, e2, x, y, g1, g2)
+    c = np.random.default_rng(3).normal(size=6)    # n_max = 2
+    img = O.lensed_shapelet_image(th, spec, psf, 0.1, -0.05, 0.3, c)
+    X, Y = O.subpixel_grid(spec.nx, spec.ny, spec.pix_scale, spec.supersample)
+    want = O.convolve_psf(O.downsample(O.shapelet_source(X, Y, 0.1, -0.05, 0.3, c), spec.supersample), psf)
+    # theta_E = 1e-12 leaves a deflection of that order: agreement to 1e-9 of the image's scale
+    np.testing.assert_allclose(img.numpy(), want.numpy(), rtol=0, atol=1e-9 * float(want.abs().max()))
+
+
+def test_lensed_shapelets_are_linear_and_recoverable_by_least_squares():
+    spec, psf, sysm = _lens_case()
+    rng = np.random.default_rng(4)
+    th = np.array(sysm.truth, dtype=np.float64)
+    c1, c2 = rng.normal(size=10), rng.normal(size=10)          # n_max = 3
+    f = lambda c: O.lensed_shapelet_image(th, spec, psf, 0.02, 0.03, 0.15, c).numpy()
+    np.testing.assert_allclose(f(c1 + 2 * c2), f(c1) + 2 * f(c2), rtol=1e-10, atol=1e-12)
+    # backward use: the coefficients are the weighted least-squares solution on noiseless data
+    B = np.stack([f(e) for e in np.eye(10)]).reshape(10, -1)
+    w = sysm.invvar.reshape(-1).astype(np.float64)
+    d = f(c1).reshape(-1)
+    sol = np.linalg.solve((B * w) @ B.T, (B * w) @ d)
+    np.testing.assert_allclose(sol, c1, rtol=1e-6, atol=1e-8)
