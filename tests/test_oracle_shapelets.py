@@ -98,3 +98,30 @@ def test_lensed_shapelets_are_linear_and_recoverable_by_least_squares():
     d = f(c1).reshape(-1)
     sol = np.linalg.solve((B * w) @ B.T, (B * w) @ d)
     np.testing.assert_allclose(sol, c1, rtol=1e-6, atol=1e-8)
+
+
+def test_lensed_shapelet_gradient_matches_finite_differences():
+    """Autograd through the lensed shapelet image (mass, shear, centre, scale)
+    against central differences of a chi^2 on it: the derivative a shapelet
+    adjoint would have to reproduce."""
+    spec, psf, sysm = _lens_case()
+    rng = np.random.default_rng(5)
+    c = rng.normal(size=6)
+    data = O.lensed_shapelet_image(sysm.truth, spec, psf, 0.02, 0.01, 0.2, c).numpy() + 0.01 * rng.normal(
+        size=(spec.ny, spec.nx))
+
+    def chi(v):
+        t = torch.tensor(sysm.truth, dtype=torch.float64)
+        t[:7] = v[:7]
+        m = O.lensed_shapelet_image(t, spec, psf, v[7], v[8], v[9], c)
+        return ((m - torch.tensor(data)) ** 2).sum()
+
+    v0 = torch.cat([torch.tensor(sysm.truth[:7], dtype=torch.float64) * 1.01,
+                    torch.tensor([0.025, 0.005, 0.21], dtype=torch.float64)]).requires_grad_(True)
+    (g,) = torch.autograd.grad(chi(v0), v0)
+    for j in range(10):
+        h = 1e-6
+        e = torch.zeros(10, dtype=torch.float64)
+        e[j] = h
+        fd = (float(chi(v0.detach() + e)) - float(chi(v0.detach() - e))) / (2 * h)
+        assert abs(fd - float(g[j])) <= 1e-5 * float(g.abs().max()), (j, fd, float(g[j]))
