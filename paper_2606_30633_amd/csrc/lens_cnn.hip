@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include "lens_cnn.h"
+#include "lens_philox.h"
 
 namespace lens {
 
@@ -651,22 +652,9 @@ __global__ void k_to_bf16(long long n, const float* __restrict__ x, __bf16* __re
     if (i < n) y[i] = to_bf16(x[i]);
 }
 
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al. 2011) for initial weights, noise and proposals
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox_c(uint4 c, uint2 k) {
-    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) { k.x += W0; k.y += W1; }
-        const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-        const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
-        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-    }
-    return c;
-}
-
-__device__ __forceinline__ double unif(uint32_t w) { return ((double)(w >> 8) + 0.5) * (1.0 / 16777216.0); }
+// Random numbers: Philox4x32-10 of lens_philox.h (initial weights, noise, proposals).
+__device__ __forceinline__ uint4 philox_c(uint4 c, uint2 k) { return philox4x32_10(c, k); }
+__device__ __forceinline__ double unif(uint32_t w) { return philox_uniform01(w); }
 
 // standard normal from counter (a, b, c): Box-Muller on words 0, 1
 __device__ __forceinline__ double normal_at(uint64_t seed, uint32_t a, uint32_t b, uint32_t c) {

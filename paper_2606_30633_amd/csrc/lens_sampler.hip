@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "lens_internal.h"
+#include "lens_philox.h"
 #include "lens_sampler.h"
 
 namespace lens {
@@ -150,34 +151,11 @@ __global__ void k_adam(int P, int d, const float* __restrict__ grad_u, const dou
 __global__ void k_add_int(int* c, int inc) { *c += inc; }
 __global__ void k_set_int(int* c, int val) { *c = val; }
 
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror & Shaw 2011): 10 rounds of two 32x32
-// multiplications whose high/low halves are mixed into the four words,
-// with a Weyl-sequence key schedule.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
-    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) { k.x += W0; k.y += W1; }
-        const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-        const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
-        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-    }
-    return c;
-}
-
-__device__ __forceinline__ double uniform01(uint32_t w) {
-    return ((double)(w >> 8) + 0.5) * (1.0 / 16777216.0);
-}
-
-// Box-Muller: two uniforms -> two standard normals (float64)
+// Philox4x32-10 and Box-Muller come from lens_philox.h.
+__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) { return philox4x32_10(c, k); }
+__device__ __forceinline__ double uniform01(uint32_t w) { return philox_uniform01(w); }
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1) {
-    const double r = sqrt(-2.0 * log(uniform01(a)));
-    const double ang = 6.283185307179586476925 * uniform01(b);
-    z0 = r * cos(ang);
-    z1 = r * sin(ang);
+    philox_box_muller(a, b, z0, z1);
 }
 
 // Momenta for one chain: words of counter blocks (chain, t, 0..), 4 normals per block.

@@ -152,16 +152,41 @@ def _dev_f32(x, device) -> torch.Tensor:
     return t.to(device).contiguous()
 
 
+def _shape(x):
+    return tuple(x.shape) if hasattr(x, "shape") else tuple(torch.as_tensor(x).shape)
+
+
+def _check_system_arrays(spec, psf, data, invvar, what="system"):
+    """The kernels read K*K PSF taps and nx*ny data and weight values through
+    raw device pointers: wrong shapes are rejected here, before any copy or
+    launch (the C layer cannot see the size of a device buffer)."""
+    K = int(spec.psf_size)
+    if _shape(psf) != (K, K):
+        raise ValueError(f"{what}: psf must be [{K}, {K}], got {list(_shape(psf))}")
+    for name, x in (("data", data), ("invvar", invvar)):
+        if _shape(x) != (spec.ny, spec.nx):
+            raise ValueError(f"{what}: {name} must be [{spec.ny}, {spec.nx}] (ny, nx), got {list(_shape(x))}")
+
+
+def _gpu_device(device) -> torch.device:
+    dev = torch.device(device)
+    if dev.type != "cuda":
+        raise ValueError(f"the library runs on the GPU: device must be cuda, got {dev}")
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    return dev
+
+
 class LensPlan:
     """One lens system on the GPU: owns the C plan and the system arrays."""
 
     def __init__(self, spec, psf, data, invvar, max_particles: int, device="cuda"):
+        _check_system_arrays(spec, psf, data, invvar)
+        if int(max_particles) < 1:
+            raise ValueError("max_particles must be >= 1")
+        self.device = _gpu_device(device)
         load_library()
         self.spec = spec
-        dev = torch.device(device)
-        if dev.type == "cuda" and dev.index is None:
-            dev = torch.device("cuda", torch.cuda.current_device())
-        self.device = dev
         self.psf = _dev_f32(psf, self.device)
         self.data = _dev_f32(data, self.device)
         self.invvar = _dev_f32(invvar, self.device)
@@ -221,7 +246,7 @@ class LensPlan:
 
 def _check_out(t: torch.Tensor, shape, dtype, device):
     if t.dtype != dtype or t.device != device or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
-        raise ValueError(f"output must be a contiguous {dtype} tensor of shape {tuple(shape)} on {device}")
+        raise ValueError(f"argument must be a contiguous {dtype} tensor of shape {tuple(shape)} on {device}")
 
 
 def lens_forward(plan: LensPlan, theta: torch.Tensor, out: Optional[torch.Tensor] = None,
@@ -313,6 +338,10 @@ def lens_logpost_grad(plan: LensPlan, u: torch.Tensor, with_jacobian: bool, logp
         grad = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
     if theta is None and want_theta:
         theta = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
+    _check_out(logp, (P,), torch.float64, plan.device)
+    _check_out(grad, (P, plan.d), torch.float32, plan.device)
+    if theta is not None:
+        _check_out(theta, (P, plan.d), torch.float32, plan.device)
     _check(_lib.lens_logpost_grad(plan.handle, P, uu.data_ptr(), 1 if with_jacobian else 0, _ptr(theta),
                                   logp.data_ptr(), grad.data_ptr(), _stream(stream)), "lens_logpost_grad")
     if theta is not None:
@@ -339,8 +368,10 @@ def lens_map_adam(plan: LensPlan, u: torch.Tensor, m: torch.Tensor, v: torch.Ten
                   stream=None):
     """n_steps Adam updates of u (in place) on -(logL + log prior)."""
     uu = plan._theta(u)
-    plan._theta(m)
-    plan._theta(v)
+    for x in (m, v):
+        _check_out(x, tuple(uu.shape), torch.float32, plan.device)
+    if loss is not None:
+        _check_out(loss, (uu.shape[0],), torch.float32, plan.device)
     _check(_lib.lens_map_adam(plan.handle, uu.shape[0], uu.data_ptr(), m.data_ptr(), v.data_ptr(),
                               int(n_steps), lr, decay, beta1, beta2, eps, _ptr(loss),
                               1 if use_graph else 0, _stream(stream)), "lens_map_adam")
@@ -353,16 +384,14 @@ def lens_hmc_run(plan: LensPlan, u: torch.Tensor, grad: torch.Tensor, logp: torc
                  accepts: Optional[torch.Tensor] = None, use_graph: bool = False, stream=None):
     """HMC transitions of C chains in place (state: u, grad = dlogp/du, logp float64)."""
     uu = plan._theta(u)
-    plan._theta(grad)
     C = uu.shape[0]
-    if logp.dtype != torch.float64 or logp.shape != (C,):
-        raise ValueError("logp must be float64 [C]")
-    if inv_mass.dtype != torch.float32 or inv_mass.shape != (plan.d,):
-        raise ValueError("inv_mass must be float32 [d]")
-    if samples is not None and samples.shape != (n_transitions, C, plan.d):
-        raise ValueError("samples must be [n_transitions, C, d]")
-    if accepts is not None and (accepts.dtype != torch.int32 or accepts.shape != (C,)):
-        raise ValueError("accepts must be int32 [C]")
+    _check_out(grad, (C, plan.d), torch.float32, plan.device)
+    _check_out(logp, (C,), torch.float64, plan.device)
+    _check_out(inv_mass, (plan.d,), torch.float32, plan.device)
+    if samples is not None:
+        _check_out(samples, (n_transitions, C, plan.d), torch.float32, plan.device)
+    if accepts is not None:
+        _check_out(accepts, (C,), torch.int32, plan.device)
     _check(_lib.lens_hmc_run(plan.handle, C, uu.data_ptr(), grad.data_ptr(), logp.data_ptr(),
                              inv_mass.data_ptr(), eps, int(n_leapfrog), int(n_transitions), int(seed),
                              int(transition0), _ptr(samples), _ptr(accepts), 1 if use_graph else 0,
@@ -376,12 +405,10 @@ def lens_hmc_adapt(plan: LensPlan, u: torch.Tensor, grad: torch.Tensor, logp: to
     windowed variance fit; returns (step size per transition [T], adapted step
     size [1], window variances [d])."""
     uu = plan._theta(u)
-    plan._theta(grad)
     C = uu.shape[0]
-    if logp.dtype != torch.float64 or logp.shape != (C,):
-        raise ValueError("logp must be float64 [C]")
-    if inv_mass.dtype != torch.float32 or inv_mass.shape != (plan.d,) or not inv_mass.is_contiguous():
-        raise ValueError("inv_mass must be a contiguous float32 [d] tensor")
+    _check_out(grad, (C, plan.d), torch.float32, plan.device)
+    _check_out(logp, (C,), torch.float64, plan.device)
+    _check_out(inv_mass, (plan.d,), torch.float32, plan.device)
     trace = torch.empty(max(int(n_transitions), 1), dtype=torch.float32, device=plan.device)
     final = torch.empty(1, dtype=torch.float32, device=plan.device)
     var = torch.empty(plan.d, dtype=torch.float32, device=plan.device)
@@ -457,13 +484,17 @@ class BatchPlan:
     """Many lens systems of uneven size evaluated together (lens_batch_*)."""
 
     def __init__(self, specs, psfs, datas, invvars, particles, device="cuda"):
-        load_library()
-        dev = torch.device(device)
-        if dev.type == "cuda" and dev.index is None:
-            dev = torch.device("cuda", torch.cuda.current_device())
-        self.device = dev
         self.specs = list(specs)
         S = len(self.specs)
+        if not (len(psfs) == len(datas) == len(invvars) == len(particles) == S) or S < 1:
+            raise ValueError("specs, psfs, datas, invvars and particles must be non-empty lists of one length")
+        for k in range(S):
+            _check_system_arrays(self.specs[k], psfs[k], datas[k], invvars[k], f"system {k}")
+            if int(particles[k]) < 1:
+                raise ValueError(f"system {k}: particles must be >= 1")
+        dev = _gpu_device(device)
+        load_library()
+        self.device = dev
         self.psfs = [_dev_f32(p, dev) for p in psfs]
         self.datas = [_dev_f32(x, dev) for x in datas]
         self.invvars = [_dev_f32(x, dev) for x in invvars]
@@ -499,6 +530,8 @@ class BatchPlan:
             logl = torch.empty(self.N, dtype=torch.float32, device=self.device)
         if grad is None:
             grad = torch.empty((self.N, self.d), dtype=torch.float32, device=self.device)
+        _check_out(logl, (self.N,), torch.float32, self.device)
+        _check_out(grad, (self.N, self.d), torch.float32, self.device)
         _check(_lib.lens_batch_loglike_grad(self.handle, theta.data_ptr(), logl.data_ptr(), grad.data_ptr(),
                                             1 if use_graph else 0, _stream(stream)), "lens_batch_loglike_grad")
         return logl, grad
@@ -513,6 +546,7 @@ class BatchPlan:
         _check(_lib.lens_batch_set_tiles(self.handle, arr), "lens_batch_set_tiles")
 
     def autotune(self, theta, cache_path=None, stream=None):
+        self._rows(theta, "theta")
         path = None if cache_path is None else str(cache_path).encode()
         _check(_lib.lens_batch_autotune(self.handle, theta.data_ptr(), path, _stream(stream)),
                "lens_batch_autotune")
@@ -550,6 +584,8 @@ class BatchPlan:
         """n_steps Adam updates of every packed particle (in place)."""
         for x, nm in ((u, "u"), (m, "m"), (v, "v")):
             self._rows(x, nm)
+        if loss is not None:
+            _check_out(loss, (self.N,), torch.float32, self.device)
         _check(_lib.lens_batch_map_adam(self.handle, u.data_ptr(), m.data_ptr(), v.data_ptr(), int(n_steps), lr,
                                         decay, beta1, beta2, eps, _ptr(loss), 1 if use_graph else 0,
                                         _stream(stream)), "lens_batch_map_adam")
@@ -564,8 +600,7 @@ class BatchPlan:
 
     def argmin(self, val, stream=None):
         """(min [S], global row [S]) of val [N] over each system's particles."""
-        if val.dtype != torch.float32 or val.shape != (self.N,) or not val.is_contiguous():
-            raise ValueError(f"val must be contiguous float32 [{self.N}]")
+        _check_out(val, (self.N,), torch.float32, self.device)
         best = torch.empty(self.S, dtype=torch.float32, device=self.device)
         arg = torch.empty(self.S, dtype=torch.int32, device=self.device)
         _check(_lib.lens_batch_argmin(self.handle, val.data_ptr(), best.data_ptr(), arg.data_ptr(),
@@ -586,11 +621,8 @@ class Cnn:
     """The learned initializer's network (lens_cnn_*)."""
 
     def __init__(self, max_batch: int, seed: int = 0, device="cuda"):
+        self.device = _gpu_device(device)
         load_library()
-        dev = torch.device(device)
-        if dev.type == "cuda" and dev.index is None:
-            dev = torch.device("cuda", torch.cuda.current_device())
-        self.device = dev
         self.max_batch = int(max_batch)
         handle = ctypes.c_void_p()
         _check(_lib.lens_cnn_create(self.max_batch, int(seed), ctypes.byref(handle)), "lens_cnn_create")
@@ -609,6 +641,14 @@ class Cnn:
         except Exception:
             pass
 
+    def _img(self, img: torch.Tensor) -> int:
+        """Batch size of a network input; rejects anything but contiguous bf16
+        [B, 64, 64] on the network's device with 1 <= B <= max_batch."""
+        if img.dim() != 3 or not (1 <= img.shape[0] <= self.max_batch):
+            raise ValueError(f"img must be [B, {CNN_SIDE}, {CNN_SIDE}] with 1 <= B <= {self.max_batch}")
+        _check_out(img, (img.shape[0], CNN_SIDE, CNN_SIDE), torch.bfloat16, self.device)
+        return int(img.shape[0])
+
     def get_params(self) -> torch.Tensor:
         out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
         _check(_lib.lens_cnn_get_params(self.handle, out.data_ptr(), _stream(None)), "lens_cnn_get_params")
@@ -623,25 +663,27 @@ class Cnn:
     def prepare(self, images: torch.Tensor, sigma: float, add_noise: bool = False, seed: int = 0,
                 counter0: int = 0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """float [n, 64, 64] -> bf16 [n, 64, 64] network input (noise, asinh, rounding in a kernel)."""
+        if images.dim() != 3 or tuple(images.shape[1:]) != (CNN_SIDE, CNN_SIDE):
+            raise ValueError(f"images must be [n, {CNN_SIDE}, {CNN_SIDE}]")
         x = images.to(self.device, torch.float32).contiguous()
         n = x.shape[0]
         if out is None:
             out = torch.empty((n, CNN_SIDE, CNN_SIDE), dtype=torch.bfloat16, device=self.device)
+        _check_out(out, (n, CNN_SIDE, CNN_SIDE), torch.bfloat16, self.device)
         _check(_lib.lens_cnn_prepare_images(n, x.data_ptr(), float(sigma), 1 if add_noise else 0, int(seed),
                                             int(counter0), out.data_ptr(), _stream(None)), "lens_cnn_prepare_images")
         return out
 
     def forward(self, img: torch.Tensor) -> torch.Tensor:
-        B = img.shape[0]
-        if img.dtype != torch.bfloat16 or not img.is_contiguous():
-            raise ValueError("img must be contiguous bfloat16 [B, 64, 64]")
+        B = self._img(img)
         out = torch.empty((B, CNN_OUTPUTS), dtype=torch.float32, device=self.device)
         _check(_lib.lens_cnn_forward(self.handle, B, img.data_ptr(), out.data_ptr(), _stream(None)), "lens_cnn_forward")
         return out
 
     def loss_grad(self, img: torch.Tensor, target: torch.Tensor):
-        B = img.shape[0]
+        B = self._img(img)
         t = target.to(self.device, torch.float32).contiguous()
+        _check_out(t, (B, CNN_TARGETS), torch.float32, self.device)
         loss = torch.empty(1, dtype=torch.float32, device=self.device)
         grads = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
         _check(_lib.lens_cnn_loss_grad(self.handle, B, img.data_ptr(), t.data_ptr(), loss.data_ptr(), grads.data_ptr(),
@@ -649,10 +691,12 @@ class Cnn:
         return loss, grads
 
     def train_step(self, img: torch.Tensor, target: torch.Tensor, lr: float, loss: Optional[torch.Tensor] = None):
-        B = img.shape[0]
-        t = target if (target.dtype == torch.float32 and target.is_contiguous()) else target.float().contiguous()
+        B = self._img(img)
+        t = target.to(self.device, torch.float32).contiguous()
+        _check_out(t, (B, CNN_TARGETS), torch.float32, self.device)
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check_out(loss, (1,), torch.float32, self.device)
         _check(_lib.lens_cnn_train_step(self.handle, B, img.data_ptr(), t.data_ptr(), float(lr), loss.data_ptr(),
                                         _stream(None)), "lens_cnn_train_step")
         return loss
@@ -673,6 +717,12 @@ class Cnn:
 
 def init_propose(net: Cnn, images64: torch.Tensor, n_per_system: int, seed: int, want_flags: bool = True):
     """Starting particles [S, n, d] (and clip flags [S]) from the network's proposals."""
+    if net.d is None:
+        raise ValueError("init_propose needs the network's target map (Cnn.set_target_map)")
+    if images64.dim() != 3 or tuple(images64.shape[1:]) != (CNN_SIDE, CNN_SIDE) or images64.shape[0] < 1:
+        raise ValueError(f"images64 must be [S, {CNN_SIDE}, {CNN_SIDE}] with S >= 1")
+    if int(n_per_system) < 1:
+        raise ValueError("n_per_system must be >= 1")
     x = images64.to(net.device, torch.float32).contiguous()
     S = x.shape[0]
     theta = torch.empty((S, n_per_system, net.d), dtype=torch.float32, device=net.device)
