@@ -20,12 +20,16 @@ from paper_2606_30633_amd import lens  # noqa: E402
 DEV = "cuda"
 
 
-def test_exact_arithmetic_forward_and_gradients_match_oracle():
-    """Quarter-integer images and sparse +-1 weights: every sum is exact in
-    fp32 (bound checked in the oracle tests), so the network output agrees
-    bit for bit and the gradients to fp32 rounding of the final sums."""
-    p, img, tgt = cnn_cases.exact_case()
-    B = img.shape[0]
+@pytest.mark.parametrize("B", [cnn_cases.EXACT_BATCH, 64])
+def test_exact_arithmetic_forward_and_gradients_match_oracle(B):
+    """Quarter-integer images and sparse +-1 weights: every forward and
+    data-gradient sum is exact in fp32 (bound checked in the oracle tests),
+    so the network output agrees bit for bit.  Every gradient entry agrees
+    to the float rounding of its own sum: |a - r| <= 2^-16 (|r| + S), S the
+    sum of |terms| of that entry (a chain of fp32 MFMA accumulations over a
+    K-split, then the fixed-order float64 sum of the splits).  B = 64 gives
+    the first layer's weight gradient 128 K-splits."""
+    p, img, tgt = cnn_cases.exact_case(B)
     net = lens.Cnn(B, 0, DEV)
     net.set_params(torch.tensor(p, dtype=torch.float32))
     x = torch.tensor(img, dtype=torch.bfloat16, device=DEV)
@@ -34,14 +38,15 @@ def test_exact_arithmetic_forward_and_gradients_match_oracle():
     np.testing.assert_array_equal(out, out_ref.astype(np.float32))
     loss, grads = net.loss_grad(x, torch.tensor(tgt, dtype=torch.float32))
     assert abs(loss.item() - L) <= 1e-6 * abs(L)
-    grads = grads.cpu().numpy()
+    grads = grads.cpu().numpy().astype(np.float64)
+    S = cnn_cases.gradient_term_scale(p, img, tgt)
     o = 0
     for name, shape in C.layout():
         n = int(np.prod(shape))
-        a, r = grads[o:o + n], g[o:o + n]
+        a, r, s = grads[o:o + n], g[o:o + n], S[o:o + n]
         o += n
-        err = np.abs(a - r).max()
-        assert err <= 1e-6 * max(1.0, np.abs(r).max()), (name, err, np.abs(r).max())
+        bad = np.abs(a - r) > 2.0 ** -16 * (np.abs(r) + s)
+        assert not bad.any(), (name, np.nonzero(bad)[0][:5], (a - r)[bad][:5], r[bad][:5], s[bad][:5])
 
 
 @pytest.mark.parametrize("B", [5, 16, 64])
@@ -68,6 +73,12 @@ def test_random_network_close_to_oracle(B):
         o += n
         cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r) + 1e-300))
         assert cos > 0.999, (name, cos)
+    # Entry by entry these random-network gradients are not comparable: a
+    # bf16 rounding that flips by one ulp (another summation order) changes
+    # the forward output by ~2^-8 of an activation, the loss gradient's
+    # sensitivity to the output carries that into every entry, and a ReLU
+    # whose input lies within rounding of zero switches a term on or off.
+    # The element-wise comparison runs on the exact fixture above.
 
 
 def test_prepare_transform_matches_oracle():

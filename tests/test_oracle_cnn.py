@@ -94,13 +94,14 @@ def _finest_unit(t):
     return float((2.0 ** (torch.floor(torch.log2(a)) - 7)).min())
 
 
-def test_exact_fixture_partial_sums_fit_fp32():
+@pytest.mark.parametrize("batch", [cnn_cases.EXACT_BATCH, 64])
+def test_exact_fixture_partial_sums_fit_fp32(batch):
     """The sparse-integer fixture used for the bitwise kernel comparison:
     every forward and data-gradient sum, bounded by the sum of absolute
     terms, stays below 2^24 times the finest unit of its bf16 operands, so
     any summation order gives the exact value in fp32."""
     import torch.nn.functional as F
-    p, img, tgt = cnn_cases.exact_case()
+    p, img, tgt = cnn_cases.exact_case(batch)
     P = C.unflatten(p)
     out, c = C.forward(p, img)
     acts = c["acts"]
