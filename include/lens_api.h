@@ -56,6 +56,7 @@ typedef int32_t lens_status;
 #define LENS_EUNSUPPORTED -2   /* valid request outside what the library builds */
 #define LENS_EHIP         -3   /* a HIP runtime call or kernel launch failed */
 #define LENS_ENOMEM       -4   /* device or host allocation failed */
+#define LENS_ESCRATCH     -5   /* request larger than the fixed scratch of lens_loglike_grad_noalloc */
 
 #define LENS_MASS_SIE 0        /* singular isothermal ellipsoid (gamma = 2) */
 #define LENS_MASS_EPL 1        /* elliptical power law, free slope gamma */
@@ -123,6 +124,40 @@ lens_status lens_loglike(lens_plan* plan, int32_t P, const float* d_theta,
 lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
                               float* d_logl, float* d_grad, double* d_logl64,
                               void* stream);
+
+/* Allocation-free logL + gradient, for callers that cannot allocate device
+ * memory: code being captured into a HIP graph, tight serving loops, and
+ * harnesses that forbid hipMalloc.  It computes what lens_loglike_grad
+ * computes on a plan with the default 4 pixels per thread (same kernels,
+ * same launch shape, hence bit-identical results), without a plan: the
+ * caller passes the system arrays and the descriptor on every call.
+ *   desc, d_psf [K][K], d_data [ny][nx], d_invvar [ny][nx]: as for
+ *   lens_plan_create (read during the call only);
+ *   d_theta [P][d] in; d_logl [P], d_grad [P][d] out; d_logl64 [P] out,
+ *   optional (NULL).
+ * Scratch: one static device array of LENS_NOALLOC_SCRATCH_BYTES on each
+ * GPU the call runs on, reserved from library load until the process ends;
+ * its device address is looked up once per device on the first call there.
+ * One call needs, each part rounded up to 256 bytes,
+ *   8 K^2 + 4 * 688 P + 4 nx ny P + 8 P ceil(nx ny / 1024) (11 + 8 n_comp)
+ * bytes, n_comp = n_lens_light + n_source: about 45.6 KB per particle at
+ * 100 x 100 px with three components, so up to ~1470 particles per call
+ * there (split larger batches into several calls).
+ * Every call on one GPU uses the same array and leaves the last call's
+ * contents in it: calls that overlap on one GPU (two streams, or two host
+ * threads, without ordering) race and give wrong results; order them.
+ * Every scratch word a kernel reads is written earlier in the same call,
+ * so no clearing is needed.  No hipMalloc, hipFree or other allocating
+ * call is made.
+ * Errors: LENS_EINVAL (bad descriptor, NULL pointer, P < 1),
+ * LENS_EUNSUPPORTED (image + PSF tile beyond the LDS), LENS_ESCRATCH
+ * (the call needs more than LENS_NOALLOC_SCRATCH_BYTES; nothing is launched),
+ * LENS_EHIP. */
+#define LENS_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+lens_status lens_loglike_grad_noalloc(const lens_model_desc* desc, const float* d_psf,
+                                      const float* d_data, const float* d_invvar, int32_t P,
+                                      const float* d_theta, float* d_logl, float* d_grad,
+                                      double* d_logl64, void* stream);
 
 /* Backward modelling (Sec. 3: the lens and source intensities solved by
  * linear inversion instead of sampled).  For each particle the K =

@@ -185,6 +185,7 @@ const char* lens_status_string(lens_status s) {
         case LENS_EUNSUPPORTED: return "unsupported configuration";
         case LENS_EHIP: return "HIP runtime error";
         case LENS_ENOMEM: return "out of memory";
+        case LENS_ESCRATCH: return "request exceeds the fixed scratch of the allocation-free entry point";
         default: return "unknown status";
     }
 }

@@ -15,7 +15,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblens.so")
 
-LENS_OK, LENS_EINVAL, LENS_EUNSUPPORTED, LENS_EHIP, LENS_ENOMEM = 0, -1, -2, -3, -4
+LENS_OK, LENS_EINVAL, LENS_EUNSUPPORTED, LENS_EHIP, LENS_ENOMEM, LENS_ESCRATCH = 0, -1, -2, -3, -4, -5
+LENS_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 LENS_MASS_SIE, LENS_MASS_EPL = 0, 1
 
 _lib = None
@@ -49,6 +50,7 @@ _SIGNATURES = {
     "lens_loglike": (_I, [_P, _I, _P, _P, _P]),
     "lens_loglike_grad": (_I, [_P, _I, _P, _P, _P, _P, _P]),
     "lens_loglike_grad_backward": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "lens_loglike_grad_noalloc": (_I, [ctypes.POINTER(lens_model_desc), _P, _P, _P, _I, _P, _P, _P, _P, _P]),
     "lens_plan_set_backward": (_I, [_P, _I]),
     "lens_plan_set_prior": (_I, [_P, _P]),
     "lens_logpost_grad": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
@@ -291,6 +293,38 @@ def lens_loglike_grad(plan: LensPlan, theta: torch.Tensor, logl: Optional[torch.
            "lens_loglike_grad")
     if logl64 is not None:
         return logl, grad, logl64
+    return logl, grad
+
+
+def lens_loglike_grad_noalloc(spec, psf: torch.Tensor, data: torch.Tensor, invvar: torch.Tensor,
+                              theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor,
+                              logl64: Optional[torch.Tensor] = None, stream=None):
+    """logL and gradient without a plan and without any device allocation in
+    the library (its scratch is a fixed static device array): psf, data,
+    invvar, theta and the outputs are caller-owned contiguous float32 tensors
+    on one GPU (logl64 float64, optional).  Raises LensError with status
+    LENS_ESCRATCH when the call needs more than LENS_NOALLOC_SCRATCH_BYTES."""
+    load_library()
+    dev = _gpu_device(theta.device)
+    _check_system_arrays(spec, psf, data, invvar)
+    K = int(spec.psf_size)
+    _check_out(psf, (K, K), torch.float32, dev)
+    _check_out(data, (spec.ny, spec.nx), torch.float32, dev)
+    _check_out(invvar, (spec.ny, spec.nx), torch.float32, dev)
+    d = lens_num_params(spec)
+    if theta.dim() != 2 or theta.shape[1] != d:
+        raise ValueError(f"theta must be [P, {d}]")
+    P = int(theta.shape[0])
+    _check_out(theta, (P, d), torch.float32, dev)
+    _check_out(logl, (P,), torch.float32, dev)
+    _check_out(grad, (P, d), torch.float32, dev)
+    if logl64 is not None:
+        _check_out(logl64, (P,), torch.float64, dev)
+    desc = desc_from_spec(spec)
+    _check(_lib.lens_loglike_grad_noalloc(ctypes.byref(desc), psf.data_ptr(), data.data_ptr(), invvar.data_ptr(),
+                                          P, theta.data_ptr(), logl.data_ptr(), grad.data_ptr(),
+                                          None if logl64 is None else logl64.data_ptr(), _stream(stream)),
+           "lens_loglike_grad_noalloc")
     return logl, grad
 
 

@@ -102,3 +102,34 @@ def test_non_contiguous_or_misplaced_outputs_are_rejected():
                 strided):
         with pytest.raises(ValueError):
             lens._check_out(bad, ok_shape, torch.float32, dev)
+
+
+def test_noalloc_size_and_argument_checks_run_before_any_gpu_call():
+    """lens_loglike_grad_noalloc refuses, on the host, a call larger than its
+    fixed scratch (LENS_ESCRATCH) and bad arguments (LENS_EINVAL).  The
+    pointers are never dereferenced on these paths, so placeholders serve."""
+    import ctypes
+    lib = lens.load_library()
+    spec = synth.config2_spec()
+    desc = lens.desc_from_spec(spec)
+    fake = ctypes.c_void_p(0x1000)
+    per_image = 4 * spec.nx * spec.ny
+    P_big = lens.LENS_NOALLOC_SCRATCH_BYTES // per_image + 1
+    args = (ctypes.byref(desc), fake, fake, fake)
+    out = (fake, fake, fake, None, None)
+    assert lib.lens_loglike_grad_noalloc(*args, P_big, *out) == lens.LENS_ESCRATCH
+    assert lib.lens_loglike_grad_noalloc(*args, 0, *out) == lens.LENS_EINVAL
+    assert lib.lens_loglike_grad_noalloc(ctypes.byref(desc), None, fake, fake, 8, *out) == lens.LENS_EINVAL
+    bad = lens.desc_from_spec(spec)
+    bad.psf_size = 4
+    assert lib.lens_loglike_grad_noalloc(ctypes.byref(bad), fake, fake, fake, 8, *out) == lens.LENS_EINVAL
+    assert "scratch" in lens.lens_status_string(lens.LENS_ESCRATCH)
+
+
+def test_noalloc_binding_rejects_host_tensors():
+    spec = synth.config1_spec()
+    K, d = spec.psf_size, spec.n_params
+    z = torch.zeros
+    with pytest.raises(ValueError):
+        lens.lens_loglike_grad_noalloc(spec, z((K, K)), z((spec.ny, spec.nx)), z((spec.ny, spec.nx)),
+                                       z((4, d)), z(4), z((4, d)))
