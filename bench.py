@@ -41,12 +41,14 @@ def parse():
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
-    ap.add_argument("--workload", choices=["map", "hmc", "svi", "backward", "batch", "cnn", "parity"], default="map",
+    ap.add_argument("--workload", choices=["map", "hmc", "svi", "backward", "batch", "cnn", "parity", "large"],
+                    default="map",
                     help="map: the headline MAP step (default); hmc: 8192 chains x 10 leapfrog on the same "
                          "system; svi: AdaBelief SVI steps with 4096 surrogate draws on the same system; "
                          "backward: logL + gradient with the intensities solved by linear inversion; "
                          "batch: 100 uneven systems x 512 particles; cnn: network training; parity: the small "
-                         "60x60 parity system (64 particles), GPU and oracle rates for information")
+                         "60x60 parity system (64 particles), GPU and oracle rates for information; large: "
+                         "one MAP step on a 1000x1000 px cutout (s=2, 21x21 PSF, tiled PSF stage), 128 particles")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB (plain copy kernel, "
                          "for scaling HBM byte counters)")
@@ -106,7 +108,7 @@ def main():
         sys.exit(2)
     if args.workload != "map":
         return {"hmc": run_hmc, "svi": run_svi, "backward": run_backward, "batch": run_batch,
-                "cnn": run_cnn, "parity": run_parity}[args.workload](args)
+                "cnn": run_cnn, "parity": run_parity, "large": run_large}[args.workload](args)
     import torch
     from paper_2606_30633_amd import lens, synth
 
@@ -382,6 +384,57 @@ def run_svi(args):
           "AdaBelief lr 1e-4, hipGraph steps",
           {"draws": n, "svi_steps_per_s": round(1.0 / dt, 3), "elbo_first": round(float(elbos[0]), 3),
            "elbo_last": round(float(elbos[-1]), 3)}, roof)
+
+
+def run_large(args):
+    """One multi-start MAP step (as in the headline workload) on a large cutout:
+    1000 x 1000 px (10^6 pixels, Sec. 2's cluster-scale cutout size), s = 2
+    (4 x 10^6 sub-pixels per particle), 21 x 21 PSF convolved by pixel tiles
+    with halos, headline model composition with the field-scaled ranges,
+    128 particles; value = logL+grad evals/s."""
+    import torch
+    from paper_2606_30633_amd import lens, synth
+    dev = torch.device("cuda", 0)
+    spec = synth.large_spec(1000, 2, 21)
+    sysm = synth.make_system_large(spec, 0)
+    P = 128
+    th = synth.draw_params(sysm.prior, P, synth.SEED_PARTICLES)
+    plan, _ = system_plan(spec, sysm, P, dev)
+    table = synth.prior_table(sysm.prior)
+    u = torch.tensor(_to_unconstrained_box(th, table), device=dev)
+    m, v = torch.zeros_like(u), torch.zeros_like(u)
+    loss = torch.empty(P, device=dev)
+    lens.lens_map_reset(plan)
+    for _ in range(args.warmup):
+        lens.lens_map_adam(plan, u, m, v, 1, 1e-2, 0.99, loss=loss)
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lens.lens_map_adam(plan, u, m, v, 1, 1e-2, 0.99, loss=loss)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    plan.enable_timing(False)
+    tim = plan.read_timing()
+    per = {k: t[0] / max(t[1], 1) for k, t in tim.items() if t[1]}
+    steps_k = _series_terms(th, spec).mean(axis=0)
+    nsub = (spec.nx * spec.supersample) * (spec.ny * spec.supersample)
+    fl_adj = adjoint_flops_per_subpixel(steps_k[0], steps_k[1], spec.n_lens_light, spec.n_source, True) * nsub * P
+    fl_ren = render_flops_per_subpixel(steps_k[0], spec.n_lens_light, spec.n_source, True) * nsub * P
+    fl_psf = 4.0 * spec.psf_size ** 2 * spec.nx * spec.ny * P     # model (float64) + adjoint (float32) correlation
+    ach = fl_adj / (per["adjoint"] * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_ALU_TFLOPS, 4), "traffic": None, "kernel": "k_adjoint",
+            "avg_ms": round(per["adjoint"], 4),
+            "kernel_ms_per_step": {k: round(x, 4) for k, x in per.items()},
+            "render_tflops": round(fl_ren / (per["render"] * 1e-3) / 1e12, 3),
+            "psf_tiled_tflops": round(fl_psf / (per["psf"] * 1e-3) / 1e12, 3),
+            "step_frac": round((fl_adj + fl_ren + fl_psf) / dt / 1e12 / PEAK_ALU_TFLOPS, 4)}
+    _line(args, P / dt, "evals/s", dt * 1e3,
+          "large cutout: 1000x1000 px, s=2, EPL+shear, 1 Sersic lens, 2 Sersic sources, 21x21 PSF by "
+          "32x128-pixel tiles; one multi-start MAP step over all particles",
+          {"particles": P, "sub_pixels_per_particle": nsub, "pixels": spec.nx * spec.ny,
+           "sub_pixel_evals_per_s": round(P * nsub / dt, 1)}, roof)
 
 
 def run_backward(args):

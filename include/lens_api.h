@@ -64,7 +64,7 @@ typedef int32_t lens_status;
 #define LENS_MAX_LENS_LIGHT 3
 #define LENS_MAX_SOURCE     3
 #define LENS_MAX_PSF       31
-#define LENS_MAX_SIDE     256
+#define LENS_MAX_SIDE    2048
 
 /* Geometry and composition of one lens system (Sec. 3 model components).
  * Sub-pixel (a, b) of pixel (i, j) sits at
@@ -96,6 +96,13 @@ int32_t lens_num_params(const lens_model_desc* desc);
  *   d_invvar [ny][nx] inverse variance w = 1/sigma^2 per pixel (>= 0).
  * The plan copies desc, allocates its device scratch (proportional to
  * max_particles * nx * ny) and keeps the three device pointers.
+ * Cutout size (Sec. 2: O(10^4) pixels for galaxy-scale HST cutouts, O(10^6)
+ * for a cluster-scale lens): when one particle's image with its (K-1)/2 halo
+ * fits a work-group's LDS (up to about 180 x 180 px) the PSF stage convolves
+ * whole images; larger images (up to LENS_MAX_SIDE per side) are convolved
+ * by 32 x 128-pixel tiles with halos, with chi^2 reduced per tile and then
+ * over the tiles in a fixed order; such plans hold two more buffers, the
+ * residual [max_particles][ny][nx] (float) and the tile partials.
  * Errors: LENS_EINVAL for a bad descriptor/pointer, LENS_ENOMEM. */
 lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf,
                              const float* d_data, const float* d_invvar,

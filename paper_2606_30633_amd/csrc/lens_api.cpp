@@ -82,6 +82,9 @@ struct lens_plan {
     float* consts;
     float* imgbuf;
     double* partial;
+    bool tiled;               // PSF stage by pixel tiles (the whole-image LDS tile does not fit)
+    float* resbuf;            // [maxP][npix] residual w (d - m) of the tiled PSF stage
+    double* chi_part;         // [maxP][tiles] chi^2 partials of the tiled PSF stage
     size_t partial_words;
     KernelTimer timer;
     // inference stages
@@ -201,6 +204,8 @@ lens_status lens_plan_destroy(lens_plan* plan) {
     if (plan->consts) (void)hipFree(plan->consts);
     if (plan->imgbuf) (void)hipFree(plan->imgbuf);
     if (plan->partial) (void)hipFree(plan->partial);
+    if (plan->resbuf) (void)hipFree(plan->resbuf);
+    if (plan->chi_part) (void)hipFree(plan->chi_part);
     plan->map_graph.reset();
     plan->hmc_graph.reset();
     plan->svi_graph.reset();
@@ -236,10 +241,7 @@ lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf, co
     p->psf = d_psf;
     p->data = d_data;
     p->invvar = d_invvar;
-    if (psf_lds_bytes(p->geo, desc->psf_size) > MAX_LDS_BYTES) {
-        delete p;
-        return LENS_EUNSUPPORTED;
-    }
+    p->tiled = psf_lds_bytes(p->geo, desc->psf_size) > MAX_LDS_BYTES;
     const size_t npix = (size_t)desc->nx * desc->ny;
     const int nacc = n_acc(desc->n_lens_light + desc->n_source);
     p->partial_words = (size_t)max_particles * chunks_for((int)npix, 1) * nacc;
@@ -248,6 +250,12 @@ lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf, co
         hipMalloc(&p->consts, sizeof(float) * CSTRIDE * (size_t)max_particles) != hipSuccess ||
         hipMalloc(&p->imgbuf, sizeof(float) * npix * (size_t)max_particles) != hipSuccess ||
         hipMalloc(&p->partial, sizeof(double) * p->partial_words) != hipSuccess) {
+        lens_plan_destroy(p);
+        return LENS_ENOMEM;
+    }
+    if (p->tiled &&
+        (hipMalloc(&p->resbuf, sizeof(float) * npix * (size_t)max_particles) != hipSuccess ||
+         hipMalloc(&p->chi_part, sizeof(double) * psf_num_tiles(p->geo) * (size_t)max_particles) != hipSuccess)) {
         lens_plan_destroy(p);
         return LENS_ENOMEM;
     }
@@ -307,6 +315,30 @@ static lens_status front(lens_plan* plan, int32_t P, const float* d_theta, hipSt
     return hip_status(e);
 }
 
+// PSF stage of a plan (modes of launch_psf): the whole image per work-group
+// when its tile fits the LDS, else by pixel tiles.
+static hipError_t plan_psf(lens_plan* plan, int mode, int P, float* img, float* out, float* logl,
+                           double* logl64, hipStream_t st) {
+    if (!plan->tiled)
+        return launch_psf(plan->mi, plan->geo, plan->desc.psf_size, mode, P, plan->consts, img, plan->psf_flip,
+                          plan->psf, plan->data, plan->invvar, out, logl, logl64, st);
+    return launch_psf_tiled(plan->geo, plan->desc.psf_size, mode, P, plan->consts, img, plan->resbuf,
+                            plan->psf_flip, plan->psf, plan->data, plan->invvar, out, logl, logl64,
+                            plan->chi_part, st);
+}
+
+// Chain rule from the adjoint partial rows; many rows per particle (large
+// images) are first summed in place in the same order.
+static hipError_t plan_finalize(lens_plan* plan, int P, const float* d_theta, float* d_grad, hipStream_t st) {
+    constexpr int kPreSumRows = 64;
+    const int nch = chunks_for(plan->geo.npix, plan->ppt);
+    if (nch <= kPreSumRows) return launch_finalize(plan->mi, P, nch, d_theta, plan->consts, plan->partial, d_grad, st);
+    const hipError_t e =
+        launch_partial_sum(P, nch, n_acc(plan->desc.n_lens_light + plan->desc.n_source), plan->partial, st);
+    if (e != hipSuccess) return e;
+    return launch_finalize(plan->mi, P, 1, d_theta, plan->consts, plan->partial, d_grad, st, nch);
+}
+
 lens_status lens_forward(lens_plan* plan, int32_t P, const float* d_theta, float* d_images,
                          void* stream) {
     if (!plan || !d_theta || !d_images || P < 1 || P > plan->max_particles) return LENS_EINVAL;
@@ -314,9 +346,7 @@ lens_status lens_forward(lens_plan* plan, int32_t P, const float* d_theta, float
     lens_status s = front(plan, P, d_theta, st);
     if (s != LENS_OK) return s;
     TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
-    return hip_status(launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 0, P, plan->consts,
-                                 plan->imgbuf, plan->psf_flip, plan->psf, plan->data,
-                                 plan->invvar, d_images, nullptr, nullptr, st));
+    return hip_status(plan_psf(plan, 0, P, plan->imgbuf, d_images, nullptr, nullptr, st));
 }
 
 lens_status lens_loglike(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
@@ -326,9 +356,7 @@ lens_status lens_loglike(lens_plan* plan, int32_t P, const float* d_theta, float
     lens_status s = front(plan, P, d_theta, st);
     if (s != LENS_OK) return s;
     TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
-    return hip_status(launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 1, P, plan->consts,
-                                 plan->imgbuf, plan->psf_flip, plan->psf, plan->data,
-                                 plan->invvar, nullptr, d_logl, nullptr, st));
+    return hip_status(plan_psf(plan, 1, P, plan->imgbuf, nullptr, d_logl, nullptr, st));
 }
 
 // Enqueues logL + gradient for theta (no argument checks).
@@ -340,9 +368,7 @@ static lens_status loglike_grad_enqueue(lens_plan* plan, int32_t P, const float*
     hipError_t e;
     {
         TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
-        e = launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 2, P, plan->consts, plan->imgbuf,
-                       plan->psf_flip, plan->psf, plan->data, plan->invvar, nullptr, d_logl,
-                       d_logl64, st);
+        e = plan_psf(plan, 2, P, plan->imgbuf, nullptr, d_logl, d_logl64, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
     {
@@ -351,10 +377,8 @@ static lens_status loglike_grad_enqueue(lens_plan* plan, int32_t P, const float*
                            plan->partial, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
-    const int nch = chunks_for(plan->geo.npix, plan->ppt);
     TimedLaunch tl(&plan->timer, LENS_K_FINALIZE, st);
-    return hip_status(launch_finalize(plan->mi, P, nch, d_theta, plan->consts, plan->partial,
-                                      d_grad, st));
+    return hip_status(plan_finalize(plan, P, d_theta, d_grad, st));
 }
 
 lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta, float* d_logl,
@@ -411,8 +435,7 @@ static lens_status backward_enqueue(lens_plan* plan, int32_t P, const float* d_t
     if (e != hipSuccess) return LENS_EHIP;
     {
         TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
-        e = launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 0, PK, plan->consts, plan->imgbuf,
-                       plan->psf_flip, plan->psf, plan->data, plan->invvar, plan->bwd_img, nullptr, nullptr, st);
+        e = plan_psf(plan, 0, PK, plan->imgbuf, plan->bwd_img, nullptr, nullptr, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
     {
@@ -436,8 +459,7 @@ static lens_status backward_enqueue(lens_plan* plan, int32_t P, const float* d_t
     if (e != hipSuccess) return LENS_EHIP;
     {
         TimedLaunch tl(&plan->timer, LENS_K_PSF, st);
-        e = launch_psf(plan->mi, plan->geo, plan->desc.psf_size, 2, P, plan->consts, plan->bwd_img, plan->psf_flip,
-                       plan->psf, plan->data, plan->invvar, nullptr, d_logl, d_logl64, st);
+        e = plan_psf(plan, 2, P, plan->bwd_img, nullptr, d_logl, d_logl64, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
     {
@@ -446,9 +468,8 @@ static lens_status backward_enqueue(lens_plan* plan, int32_t P, const float* d_t
     }
     if (e != hipSuccess) return LENS_EHIP;
     {
-        const int nch = chunks_for(plan->geo.npix, plan->ppt);
         TimedLaunch tl(&plan->timer, LENS_K_FINALIZE, st);
-        e = launch_finalize(plan->mi, P, nch, plan->bwd_theta, plan->consts, plan->partial, d_grad, st);
+        e = plan_finalize(plan, P, plan->bwd_theta, d_grad, st);
     }
     if (e != hipSuccess) return LENS_EHIP;
     return hip_status(launch_bwd_zero_slots(P, s, d_grad, st));

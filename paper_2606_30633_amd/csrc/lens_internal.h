@@ -101,10 +101,20 @@ hipError_t launch_render_split(const ModelInfo& mi, const Geo& g, int P, int ppt
                                float* img, hipStream_t st);
 hipError_t launch_adjoint(const ModelInfo& mi, const Geo& g, int P, int ppt, const float* consts,
                           const float* gimg, double* partial, hipStream_t st);
+// Particle p's partial rows start at row p * max(row_stride, nchunks).
 hipError_t launch_finalize(const ModelInfo& mi, int P, int nchunks, const float* theta,
                            const float* consts, const double* partial, float* grad,
-                           hipStream_t st);
+                           hipStream_t st, int row_stride = 0);
 hipError_t launch_flip(int K, const float* psf, double* flipped, hipStream_t st);
+// Tiled PSF stage (images whose whole LDS tile exceeds MAX_LDS_BYTES): modes as
+// launch_psf; res [P][npix] float scratch (modes 2), chi_part [P][psf_num_tiles]
+// float64 scratch (modes 1, 2).
+hipError_t launch_psf_tiled(const Geo& g, int K, int mode, int P, const float* consts, float* img, float* res,
+                            const double* wflip, const float* wpsf, const float* data, const float* invvar,
+                            float* out, float* logl, double* logl64, double* chi_part, hipStream_t st);
+int psf_num_tiles(const Geo& g);
+// Sums each particle's nch partial rows into its first row (k_finalize then takes nchunks = 1).
+hipError_t launch_partial_sum(int P, int nch, int nacc, double* partial, hipStream_t st);
 size_t psf_lds_bytes(const Geo& g, int K);
 constexpr size_t MAX_LDS_BYTES = 160 * 1024 - 256;   // dynamic part; statics need < 256 B
 

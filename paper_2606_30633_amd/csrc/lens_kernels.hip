@@ -960,14 +960,15 @@ __device__ void finalize_particle(const ModelInfo& mi, int nchunks, const float*
     }
 }
 
-__global__ void k_finalize(ModelInfo mi, int P, int nchunks, const float* __restrict__ theta,
+// Particle p's partial rows start at row p * row_stride; the first nchunks are summed.
+__global__ void k_finalize(ModelInfo mi, int P, int nchunks, int row_stride, const float* __restrict__ theta,
                            const float* __restrict__ consts, const double* __restrict__ partial,
                            float* __restrict__ grad) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const int nacc = A_SERS + A_SERS_STRIDE * (mi.n_lens_light + mi.n_source);
     finalize_particle(mi, nchunks, theta + (size_t)p * mi.d, consts[(size_t)p * CSTRIDE + C_VALID],
-                      partial + (size_t)p * nchunks * nacc, grad + (size_t)p * mi.d);
+                      partial + (size_t)p * row_stride * nacc, grad + (size_t)p * mi.d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,6 +1058,150 @@ __global__ void k_batch_finalize(ModelInfo mi, int N, const BatchSys* __restrict
     const int p = gp - S.p0;
     finalize_particle(mi, S.nch, theta + (size_t)gp * mi.d, consts[(size_t)gp * CSTRIDE + C_VALID],
                       partial + (S.part_off + (size_t)p * S.nch) * nacc, grad + (size_t)gp * mi.d);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled PSF stage for images whose whole tile does not fit the LDS (large
+// cutouts): grid (particle, pixel tile); each work-group stages a
+// PSF_TH x PSF_TW output tile plus its (K-1)/2 halo in LDS.
+//   pass 1 (MODE 0|1|2): model m = image (*) PSF in float64;
+//     MODE 0 writes m; MODE 1|2 write the tile's float64 chi^2 partial and
+//     MODE 2 the residual w (d - m) to res;
+//   pass 2: the adjoint image, correlation of res with the PSF (float32),
+//     into img (every tile reads only res, so img can be overwritten);
+//   k_chi_reduce sums each particle's tile partials in tile order.
+// ---------------------------------------------------------------------------
+constexpr int PSF_TH = 32, PSF_TW = 128;
+
+template <int K>
+struct TileDims {
+    static constexpr int NQ = (PSF_RW + K - 1 + 3) / 4;
+    static constexpr int STRIDE = PSF_TW - PSF_RW + 4 * NQ;   // floats, multiple of 4
+    static constexpr int ROWS = PSF_TH + K - 1;
+};
+
+// Loads the tile at (i0, j0) of src [ny][nx] with its halo into lds; zero
+// outside the image.
+template <int K>
+__device__ __forceinline__ void load_tile(const Geo& g, const float* __restrict__ src, int i0, int j0,
+                                          float* lds) {
+    constexpr int H = (K - 1) / 2, ST = TileDims<K>::STRIDE, R = TileDims<K>::ROWS;
+    for (int q = threadIdx.x; q < R * ST; q += 256) {
+        const int r = q / ST, c = q - r * ST;
+        const int gi = i0 + r - H, gj = j0 + c - H;
+        const bool in = c < PSF_TW + K - 1 && gi >= 0 && gi < g.ny && gj >= 0 && gj < g.nx;
+        lds[q] = in ? src[(size_t)gi * g.nx + gj] : 0.f;
+    }
+    __syncthreads();
+}
+
+template <int K, int MODE>
+__global__ __launch_bounds__(256) void k_psf_tile(const float* __restrict__ consts, Geo g, int tiles_x,
+                                                  const float* __restrict__ img, float* __restrict__ res,
+                                                  const double* __restrict__ wflip,
+                                                  const float* __restrict__ data,
+                                                  const float* __restrict__ invvar, float* __restrict__ out,
+                                                  double* __restrict__ chi_part) {
+    __shared__ float4 lds4[TileDims<K>::ROWS * TileDims<K>::STRIDE / 4];
+    __shared__ double red[4];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int p = blockIdx.x, tile = blockIdx.y;
+    const int i0 = (tile / tiles_x) * PSF_TH, j0 = (tile - (tile / tiles_x) * tiles_x) * PSF_TW;
+    const size_t base = (size_t)p * g.npix;
+    if (MODE != 0 && consts[(size_t)p * CSTRIDE + C_VALID] != 1.0f) {
+        // no valid profile: zero residual and partial (logL set by k_chi_reduce)
+        if (MODE == 2)
+            for (int q = threadIdx.x; q < PSF_TH * PSF_TW; q += 256) {
+                const int i = i0 + q / PSF_TW, j = j0 + q % PSF_TW;
+                if (i < g.ny && j < g.nx) res[base + (size_t)i * g.nx + j] = 0.f;
+            }
+        if (threadIdx.x == 0) chi_part[(size_t)p * gridDim.y + tile] = 0.0;
+        return;
+    }
+    load_tile<K>(g, img + base, i0, j0, lds);
+    constexpr int NS = PSF_TW / PSF_RW;   // strips per tile row
+    double chi = 0.0;
+    for (int st = threadIdx.x; st < PSF_TH * NS; st += 256) {
+        const int li = st / NS, lj = (st - li * NS) * PSF_RW;
+        const int i = i0 + li;
+        double m[PSF_RW];
+        correlate<K, PSF_RW, double>(lds, TileDims<K>::STRIDE, li, lj, wflip, m);
+#pragma unroll
+        for (int r = 0; r < PSF_RW; ++r) {
+            const int j = j0 + lj + r;
+            if (i < g.ny && j < g.nx) {
+                const size_t idx = (size_t)i * g.nx + j;
+                if (MODE == 0) {
+                    out[base + idx] = (float)m[r];
+                } else {
+                    const double dlt = (double)data[idx] - m[r];
+                    const double w = (double)invvar[idx];
+                    chi = fma(w * dlt, dlt, chi);
+                    if (MODE == 2) res[base + idx] = (float)(w * dlt);
+                }
+            }
+        }
+    }
+    if (MODE != 0) {
+        chi = block_sum<256>(chi, red);
+        if (threadIdx.x == 0) chi_part[(size_t)p * gridDim.y + tile] = chi;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_psf_tile_adj(Geo g, int tiles_x, const float* __restrict__ res,
+                                                      const float* __restrict__ wpsf, float* __restrict__ img) {
+    __shared__ float4 lds4[TileDims<K>::ROWS * TileDims<K>::STRIDE / 4];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int p = blockIdx.x, tile = blockIdx.y;
+    const int i0 = (tile / tiles_x) * PSF_TH, j0 = (tile - (tile / tiles_x) * tiles_x) * PSF_TW;
+    const size_t base = (size_t)p * g.npix;
+    load_tile<K>(g, res + base, i0, j0, lds);
+    constexpr int NS = PSF_TW / PSF_RW;
+    for (int st = threadIdx.x; st < PSF_TH * NS; st += 256) {
+        const int li = st / NS, lj = (st - li * NS) * PSF_RW;
+        const int i = i0 + li;
+        float m[PSF_RW];
+        correlate<K, PSF_RW, float>(lds, TileDims<K>::STRIDE, li, lj, wpsf, m);
+#pragma unroll
+        for (int r = 0; r < PSF_RW; ++r) {
+            const int j = j0 + lj + r;
+            if (i < g.ny && j < g.nx) img[base + (size_t)i * g.nx + j] = m[r];
+        }
+    }
+}
+
+// logL of every particle from its tile partials (fixed tile order).
+__global__ void k_chi_reduce(int P, int ntiles, const float* __restrict__ consts,
+                             const double* __restrict__ chi_part, float* __restrict__ logl,
+                             double* __restrict__ logl64) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const float valid = consts[(size_t)p * CSTRIDE + C_VALID];
+    double v;
+    if (valid != 1.0f) {
+        v = valid == 2.0f ? (double)__builtin_nanf("") : -(double)__builtin_inff();
+    } else {
+        double chi = 0.0;
+        for (int t = 0; t < ntiles; ++t) chi += chi_part[(size_t)p * ntiles + t];
+        v = -0.5 * chi;
+    }
+    logl[p] = (float)v;
+    if (logl64) logl64[p] = v;
+}
+
+// Sums the nch partial rows of every particle into its first row, so that
+// k_finalize can then run with one row per particle.  One wave per
+// (particle, accumulator): lane l sums rows l, l + 64, ... in order, then a
+// fixed butterfly over the lanes (deterministic; the rounding order differs
+// from k_finalize's serial sum over the rows).
+__global__ __launch_bounds__(64) void k_partial_sum(int nch, int nacc, double* __restrict__ partial) {
+    const int a = blockIdx.y, lane = threadIdx.x;
+    double* base = partial + (size_t)blockIdx.x * nch * nacc;
+    double s = 0.0;
+    for (int ch = lane; ch < nch; ch += 64) s += base[(size_t)ch * nacc + a];
+    s = wave_sum(s);
+    if (lane == 0) base[a] = s;
 }
 
 __global__ void k_flip(int K, const float* __restrict__ psf, double* __restrict__ flipped) {
@@ -1232,8 +1377,9 @@ hipError_t launch_psf(const ModelInfo& mi, const Geo& g, int K, int mode, int P,
 
 hipError_t launch_finalize(const ModelInfo& mi, int P, int nchunks, const float* theta,
                            const float* consts, const double* partial, float* grad,
-                           hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3((P + 63) / 64), dim3(64), 0, st, mi, P, nchunks, theta,
+                           hipStream_t st, int row_stride) {
+    if (row_stride < nchunks) row_stride = nchunks;
+    hipLaunchKernelGGL(k_finalize, dim3((P + 63) / 64), dim3(64), 0, st, mi, P, nchunks, row_stride, theta,
                        consts, partial, grad);
     return hipGetLastError();
 }
@@ -1326,6 +1472,60 @@ int batch_blocks_per_cu(const ModelInfo& mi, bool adjoint) {
 
 hipError_t launch_flip(int K, const float* psf, double* flipped, hipStream_t st) {
     hipLaunchKernelGGL(k_flip, dim3((K * K + 255) / 256), dim3(256), 0, st, K, psf, flipped);
+    return hipGetLastError();
+}
+
+int psf_num_tiles(const Geo& g) {
+    return ((g.nx + PSF_TW - 1) / PSF_TW) * ((g.ny + PSF_TH - 1) / PSF_TH);
+}
+
+template <int K>
+static hipError_t launch_psf_tiled_k(const Geo& g, int mode, int P, const float* consts, float* img, float* res,
+                                     const double* wflip, const float* wpsf, const float* data,
+                                     const float* invvar, float* out, float* logl, double* logl64,
+                                     double* chi_part, hipStream_t st) {
+    const int tiles_x = (g.nx + PSF_TW - 1) / PSF_TW;
+    const int nt = psf_num_tiles(g);
+    const dim3 grid(P, nt);
+    if (mode == 0) {
+        hipLaunchKernelGGL((k_psf_tile<K, 0>), grid, dim3(256), 0, st, consts, g, tiles_x, img, res, wflip, data,
+                           invvar, out, chi_part);
+        return hipGetLastError();
+    }
+    if (mode == 1)
+        hipLaunchKernelGGL((k_psf_tile<K, 1>), grid, dim3(256), 0, st, consts, g, tiles_x, img, res, wflip, data,
+                           invvar, out, chi_part);
+    else
+        hipLaunchKernelGGL((k_psf_tile<K, 2>), grid, dim3(256), 0, st, consts, g, tiles_x, img, res, wflip, data,
+                           invvar, out, chi_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chi_reduce, dim3((P + 63) / 64), dim3(64), 0, st, P, nt, consts, chi_part, logl, logl64);
+    e = hipGetLastError();
+    if (e != hipSuccess || mode != 2) return e;
+    hipLaunchKernelGGL((k_psf_tile_adj<K>), grid, dim3(256), 0, st, g, tiles_x, res, wpsf, img);
+    return hipGetLastError();
+}
+
+hipError_t launch_psf_tiled(const Geo& g, int K, int mode, int P, const float* consts, float* img, float* res,
+                            const double* wflip, const float* wpsf, const float* data, const float* invvar,
+                            float* out, float* logl, double* logl64, double* chi_part, hipStream_t st) {
+    switch (K) {
+#define LENS_TPSF_CASE(KK)                                                                                  \
+    case KK:                                                                                                \
+        return launch_psf_tiled_k<KK>(g, mode, P, consts, img, res, wflip, wpsf, data, invvar, out, logl,  \
+                                      logl64, chi_part, st);
+        LENS_TPSF_CASE(1) LENS_TPSF_CASE(3) LENS_TPSF_CASE(5) LENS_TPSF_CASE(7) LENS_TPSF_CASE(9)
+        LENS_TPSF_CASE(11) LENS_TPSF_CASE(13) LENS_TPSF_CASE(15) LENS_TPSF_CASE(17) LENS_TPSF_CASE(19)
+        LENS_TPSF_CASE(21) LENS_TPSF_CASE(23) LENS_TPSF_CASE(25) LENS_TPSF_CASE(27) LENS_TPSF_CASE(29)
+        LENS_TPSF_CASE(31)
+#undef LENS_TPSF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_partial_sum(int P, int nch, int nacc, double* partial, hipStream_t st) {
+    hipLaunchKernelGGL(k_partial_sum, dim3(P, nacc), dim3(64), 0, st, nch, nacc, partial);
     return hipGetLastError();
 }
 

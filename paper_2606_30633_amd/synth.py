@@ -301,6 +301,33 @@ def paper_spec(side: int, s: int, kpsf: int) -> ModelSpec:
     return ModelSpec(side, side, 0.05, s, kpsf, MASS_EPL, 1, 1)
 
 
+def large_spec(side: int, s: int = 2, kpsf: int = 21) -> ModelSpec:
+    """Large cutout (Sec. 2: O(10^6) pixels for a cluster-scale lens): the
+    headline model composition on a side x side grid at 0.05"/px."""
+    return ModelSpec(side, side, 0.05, s, kpsf, MASS_EPL, 1, 2)
+
+
+def large_box_dists(spec: ModelSpec) -> List[Dist]:
+    """The headline uniform ranges with every angle scaled by the field width
+    over the headline's 5" field: the same morphology resolved by more
+    pixels (theta_E 8-18" at 1000 px, a cluster-scale Einstein radius)."""
+    f = spec.nx * spec.pix_scale / 5.0
+    d = [U(0.8 * f, 1.8 * f), U(1.5, 2.5), U(-0.3, 0.3), U(-0.3, 0.3), U(-0.1 * f, 0.1 * f),
+         U(-0.1 * f, 0.1 * f), U(-0.1, 0.1), U(-0.1, 0.1)]
+    for k in range(spec.n_lens_light + spec.n_source):
+        c = 0.1 * f if k < spec.n_lens_light else 0.3 * f
+        d += [U(0.05 * f, 1.0 * f), U(0.5, 5.0), U(-0.3, 0.3), U(-0.3, 0.3), U(-c, c), U(-c, c), U(0.1, 1.0)]
+    return d
+
+
+def make_system_large(spec: ModelSpec, k: int = 0) -> System:
+    dists = large_box_dists(spec)
+    truth = draw_params(dists, 1, SEED_TRUTH + k)[0]
+    return System(spec, double_gaussian_psf(spec.psf_size, spec.pix_scale), truth,
+                  noise((spec.ny, spec.nx), SIGMA_NOISE, SEED_NOISE + k),
+                  invvar_map(spec.ny, spec.nx, SIGMA_NOISE), dists)
+
+
 def uneven_batch_specs(n_systems: int = 100, seed: int = SEED_TRUTH) -> List[ModelSpec]:
     """Image sides U{48..160}, supersampling U{2,3,4}, PSF sizes U{11,13,...,31}."""
     rng = np.random.default_rng(seed + 500000)

@@ -263,11 +263,11 @@ def test_argument_errors():
     # a plan stays usable after rejected calls
     L = lens.lens_loglike(plan, torch.tensor(th, device=DEV)).cpu().numpy()
     check_loglike(spec, psf, data, sysm.invvar, th, L)
-    big_spec = synth.ModelSpec(256, 256, 0.05, 2, 31, "EPL", 1, 1)
+    big_spec = synth.ModelSpec(2049, 16, 0.05, 1, 3, "EPL", 1, 1)    # side above LENS_MAX_SIDE
     with pytest.raises(lens.LensError) as e:
-        lens.LensPlan(big_spec, np.ones((31, 31), np.float32), np.zeros((256, 256), np.float32),
-                      np.ones((256, 256), np.float32), 1, DEV)
-    assert e.value.status == lens.LENS_EUNSUPPORTED
+        lens.LensPlan(big_spec, np.ones((3, 3), np.float32), np.zeros((16, 2049), np.float32),
+                      np.ones((16, 2049), np.float32), 1, DEV)
+    assert e.value.status == lens.LENS_EINVAL
 
 
 def test_autograd_function():
