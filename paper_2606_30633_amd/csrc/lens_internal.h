@@ -33,6 +33,7 @@ constexpr int SERS_STRIDE = 24;
 constexpr int S_XC = 0, S_YC = 2, S_A11 = 4, S_A12 = 6, S_A22 = 8, S_IE = 10,
               S_KU = 12, S_KU0 = 14, S_BL = 16;   // float64 (word offsets)
 constexpr int S_KAP2 = 18;                         // float32
+constexpr int S_A12X2 = 20;                        // float64: 2 a12
 constexpr int MAX_COMP = LENS_MAX_LENS_LIGHT + LENS_MAX_SOURCE;
 constexpr int KMAX_PAD = 128;            // entries per coefficient array
 constexpr int C_COEF_S = 176;            // float64 c_0..c_KP (2 words each)
