@@ -28,6 +28,8 @@ formula below is a published lensing result, restated:
   lens eq.    beta = theta - alpha_mass - alpha_shear
   Sersic      I_e exp(-b_n[(R/R_e)^(1/n) - 1]), R = sqrt(q x'^2 + y'^2/q),
               b_n = 1.9992 n - 0.3271; lens light at theta, sources at beta
+  shapelets   optional shapelet source at beta: sum_k c_k phi_k(x - xc, y - yc;
+              beta), the Cartesian basis of Refregier (2003) up to order n_max
   downsample  mean over the s x s sub-pixels of each pixel
   PSF         zero-padded 'same' 2-D convolution with an odd K x K kernel
   logL        -1/2 sum w (d - m)^2  (Gaussian, w = inverse variance)
@@ -40,7 +42,9 @@ invariants, library routines and brute force (SIS, EPL->SIE at gamma = 2,
 Poisson equation, Keeton's 1-D integral, Sersic flux via the incomplete
 gamma function, delta-PSF, chi-square statistics, finite differences; for
 SVI the closed-form KL of a Gaussian target and the AdaBelief closed form
-under a constant gradient).
+under a constant gradient; for shapelets numpy's Hermite polynomials, the
+basis's orthonormality and 1-D fluxes, superposition with the Sersic model,
+least-squares recovery of the coefficients).
 """
 from __future__ import annotations
 
@@ -67,8 +71,18 @@ def _t(x) -> torch.Tensor:
 # ---------------------------------------------------------------------------
 # Parameter layout (Sec. 3 lists the parameters of each component)
 # ---------------------------------------------------------------------------
+def n_shapelet_coeffs(spec) -> int:
+    """Coefficients of the shapelet source, (n_max + 1)(n_max + 2)/2, or 0."""
+    if not getattr(spec, "n_shapelet", 0):
+        return 0
+    n = spec.shapelet_nmax
+    return (n + 1) * (n + 2) // 2
+
+
 def n_params(spec) -> int:
-    return (8 if spec.mass_model == "EPL" else 7) + 7 * (spec.n_lens_light + spec.n_source)
+    nsh = n_shapelet_coeffs(spec)
+    return ((8 if spec.mass_model == "EPL" else 7) + 7 * (spec.n_lens_light + spec.n_source)
+            + (3 + nsh if getattr(spec, "n_shapelet", 0) else 0))
 
 
 def unpack(theta: torch.Tensor, spec) -> Dict[str, object]:
@@ -90,6 +104,13 @@ def unpack(theta: torch.Tensor, spec) -> Dict[str, object]:
     for _ in range(spec.n_source):
         sources.append(tuple(theta[i + k] for k in range(7))); i += 7
     out["lights"], out["sources"] = lights, sources
+    # optional shapelet source (Sec. 3: Sersic profiles and/or shapelets for
+    # the source light): (beta, x, y, coefficients in shapelet_indices order)
+    out["shapelet"] = None
+    if getattr(spec, "n_shapelet", 0):
+        nb = n_shapelet_coeffs(spec)
+        out["shapelet"] = (theta[i], theta[i + 1], theta[i + 2], theta[i + 3:i + 3 + nb])
+        i += 3 + nb
     return out
 
 
@@ -242,10 +263,14 @@ def sersic(x, y, R_e, n, e1, e2, xc, yc, I_e):
 # Steps 7-10: sub-pixel image, downsample, PSF, likelihood
 # ---------------------------------------------------------------------------
 def ellipticity_valid(theta: torch.Tensor, spec) -> bool:
-    """False if any component has |e| >= 1 (q <= 0: no valid profile)."""
+    """False if any component has |e| >= 1 (q <= 0: no valid profile), or a
+    shapelet source has a scale beta <= 0 (no valid basis)."""
     p = unpack(theta.detach(), spec)
     es = [(p["m_e1"], p["m_e2"])] + [(c[2], c[3]) for c in p["lights"] + p["sources"]]
-    return all(float(a * a + b * b) < 1.0 for a, b in es)
+    ok = all(float(a * a + b * b) < 1.0 for a, b in es)
+    if p["shapelet"] is not None:
+        ok = ok and float(p["shapelet"][0]) > 0.0
+    return ok
 
 
 def subpixel_image(theta: torch.Tensor, spec, n_terms: Optional[int] = None) -> torch.Tensor:
@@ -264,6 +289,9 @@ def subpixel_image(theta: torch.Tensor, spec, n_terms: Optional[int] = None) -> 
         v = v + sersic(X, Y, *c)
     for c in p["sources"]:
         v = v + sersic(bx, by, *c)
+    if p["shapelet"] is not None:
+        beta, xc, yc, coeffs = p["shapelet"]
+        v = v + shapelet_source(bx, by, xc, yc, beta, coeffs)
     return v
 
 
@@ -760,9 +788,14 @@ BACKWARD_PIVOT_REL = 1e-12
 
 
 def intensity_slots(spec) -> List[int]:
-    """Indices of the Sersic intensities I_e in the parameter vector."""
+    """Indices of the linear light amplitudes in the parameter vector: the
+    Sersic intensities I_e, then the shapelet coefficients (if any)."""
     base = 8 if spec.mass_model == "EPL" else 7
-    return [base + 7 * k + 6 for k in range(spec.n_lens_light + spec.n_source)]
+    slots = [base + 7 * k + 6 for k in range(spec.n_lens_light + spec.n_source)]
+    if getattr(spec, "n_shapelet", 0):
+        c0 = base + 7 * (spec.n_lens_light + spec.n_source) + 3
+        slots += list(range(c0, c0 + n_shapelet_coeffs(spec)))
+    return slots
 
 
 def component_images(theta, spec, psf) -> torch.Tensor:
@@ -813,7 +846,7 @@ def loglike_backward(theta, spec, psf, data, invvar, with_grad: bool = True):
     Returns (logL, grad [d] or None, A [K]); (-inf, zeros, nan) when a
     component's ellipticity is invalid."""
     th = _t(theta).clone().requires_grad_(with_grad)
-    K = spec.n_lens_light + spec.n_source
+    K = len(intensity_slots(spec))
     if not ellipticity_valid(th, spec):
         return -math.inf, (np.zeros(th.shape[0]) if with_grad else None), np.full(K, np.nan)
     B = component_images(th, spec, psf).reshape(K, -1)
@@ -938,8 +971,8 @@ def log_posterior_backward(u, spec, psf, data, invvar, table, with_jacobian: boo
 # ---------------------------------------------------------------------------
 # Shapelet sources (Sec. 3 names shapelets beside Sersic profiles for the
 # source light; the basis is the Cartesian one of Refregier 2003, MNRAS 338,
-# 35, also used by Birrer et al. 2015).  Not on the GPU path: the oracle's
-# definition, pinned, for a source profile the kernels do not implement.
+# 35, also used by Birrer et al. 2015).  A spec with n_shapelet = 1 carries
+# one such source after its Sersic sources (unpack, subpixel_image).
 #   phi_n(x; beta) = [2^n sqrt(pi) n! beta]^(-1/2) H_n(x / beta) exp(-x^2 / (2 beta^2)),
 #   H_n the physicists' Hermite polynomials; the 2-D basis is
 #   phi_n1(x) phi_n2(y) for n1 + n2 <= n_max, ordered by n = n1 + n2, then n2.

@@ -39,7 +39,9 @@ class ModelSpec:
     Canonical parameter order (Sec. 3 lists the parameters): mass block
     (theta_E, [gamma,] e1, e2, x, y), external shear (g1, g2), then the
     Sersic lens-light components, then the Sersic source components, each
-    (R_e, n, e1, e2, x, y, I_e).
+    (R_e, n, e1, e2, x, y, I_e), then an optional shapelet source
+    (beta, x, y, c_0 .. c_{nb-1}; Sec. 3: Sersic profiles and/or shapelets
+    for the source light).
     """
 
     nx: int
@@ -50,6 +52,8 @@ class ModelSpec:
     mass_model: str = MASS_EPL
     n_lens_light: int = 1
     n_source: int = 1
+    n_shapelet: int = 0          # 0 or 1 shapelet source (after the Sersic sources)
+    shapelet_nmax: int = 0       # its order: (n_max + 1)(n_max + 2)/2 coefficients
 
     def __post_init__(self):
         # the pixel scale is a float32 input of the GPU path: keep it float32-exact
@@ -60,8 +64,13 @@ class ModelSpec:
         return 8 if self.mass_model == MASS_EPL else 7
 
     @property
+    def n_shapelet_coeffs(self) -> int:
+        return (self.shapelet_nmax + 1) * (self.shapelet_nmax + 2) // 2 if self.n_shapelet else 0
+
+    @property
     def n_params(self) -> int:
-        return self.n_mass + 7 * (self.n_lens_light + self.n_source)
+        return self.n_mass + 7 * (self.n_lens_light + self.n_source) + (
+            3 + self.n_shapelet_coeffs if self.n_shapelet else 0)
 
     def param_names(self) -> List[str]:
         names = ["theta_E"]
@@ -72,6 +81,8 @@ class ModelSpec:
             names += [f"l{k}_{s}" for s in SERSIC_NAMES]
         for k in range(self.n_source):
             names += [f"s{k}_{s}" for s in SERSIC_NAMES]
+        if self.n_shapelet:
+            names += ["sh_beta", "sh_x", "sh_y"] + [f"sh_c{k}" for k in range(self.n_shapelet_coeffs)]
         return names
 
 

@@ -8,6 +8,7 @@ solve recovers from noiseless data (the backward use of shapelets)."""
 import math
 
 import numpy as np
+import pytest
 import torch
 from numpy.polynomial import hermite as nph
 
@@ -125,3 +126,79 @@ def test_lensed_shapelet_gradient_matches_finite_differences():
         e[j] = h
         fd = (float(chi(v0.detach() + e)) - float(chi(v0.detach() - e))) / (2 * h)
         assert abs(fd - float(g[j])) <= 1e-5 * float(g.abs().max()), (j, fd, float(g[j]))
+
+
+# ---------------------------------------------------------------------------
+# A shapelet source inside the parameter vector (spec.n_shapelet = 1): the
+# layout, superposition with the Sersic model, the likelihood gradient by
+# central differences, linear inversion of its coefficients, validity.
+# ---------------------------------------------------------------------------
+def _sh_case(nmax=3, mass="EPL", nl=1, ns=1):
+    import dataclasses
+    from paper_2606_30633_amd import synth
+    base = synth.ModelSpec(22, 20, 0.1, 2, 5, mass, nl, ns)
+    spec = dataclasses.replace(base, n_shapelet=1, shapelet_nmax=nmax)
+    psf = synth.asymmetric_psf(spec.psf_size, synth.SEED_TEST_PSF)
+    sysm = synth.make_system_box(base, 1, psf=psf)
+    rng = np.random.default_rng(11 + nmax)
+    nb = (nmax + 1) * (nmax + 2) // 2
+    block = np.concatenate([[0.18, 0.03, -0.04], 0.5 * rng.normal(size=nb)])
+    th = np.concatenate([np.asarray(sysm.truth, np.float64), block])
+    return base, spec, psf, sysm, th
+
+
+def test_shapelet_block_layout():
+    base, spec, psf, sysm, th = _sh_case(4)
+    assert O.n_params(spec) == O.n_params(base) + 3 + 15 == spec.n_params == len(spec.param_names())
+    slots = O.intensity_slots(spec)
+    assert slots[:2] == O.intensity_slots(base)
+    assert slots[2:] == list(range(O.n_params(base) + 3, O.n_params(spec)))
+    assert spec.param_names()[O.n_params(base)] == "sh_beta"
+
+
+@pytest.mark.parametrize("nmax", [0, 3])
+def test_model_is_the_sersic_model_plus_the_lensed_shapelet_source(nmax):
+    base, spec, psf, sysm, th = _sh_case(nmax)
+    d0 = O.n_params(base)
+    m = O.model_image(th, spec, psf).numpy()
+    m_base = O.model_image(th[:d0], base, psf).numpy()
+    m_sh = O.lensed_shapelet_image(th[:d0], base, psf, th[d0 + 1], th[d0 + 2], th[d0], th[d0 + 3:]).numpy()
+    np.testing.assert_allclose(m, m_base + m_sh, rtol=1e-12, atol=1e-14 * np.abs(m).max())
+    # zero coefficients leave the Sersic model
+    th0 = th.copy()
+    th0[d0 + 3:] = 0.0
+    np.testing.assert_allclose(O.model_image(th0, spec, psf).numpy(), m_base, rtol=1e-14, atol=0)
+
+
+def test_loglike_gradient_with_shapelets_matches_finite_differences():
+    base, spec, psf, sysm, th = _sh_case(3)
+    data = (O.model_image(th * (1 + 1e-3), spec, psf).numpy() + sysm.noise).astype(np.float32)
+    L, g = O.loglike_and_grad(th, spec, psf, data, sysm.invvar)
+    d0 = O.n_params(base)
+    for j in [0, 2, d0, d0 + 1, d0 + 2, d0 + 3, d0 + 7, d0 + 9]:
+        h = 1e-6 * max(abs(th[j]), 1e-2)
+        e = np.zeros_like(th)
+        e[j] = h
+        fd = (O.loglike(th + e, spec, psf, data, sysm.invvar) - O.loglike(th - e, spec, psf, data, sysm.invvar)) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-6 * (abs(g[j]) + np.abs(g).max()), (j, fd, g[j])
+
+
+def test_backward_solves_the_shapelet_coefficients_and_intensities():
+    base, spec, psf, sysm, th = _sh_case(3)
+    data = O.model_image(th, spec, psf).numpy()            # noiseless
+    L, g, A = O.loglike_backward(th, spec, psf, data, sysm.invvar)
+    slots = O.intensity_slots(spec)
+    assert A.shape == (len(slots),)
+    np.testing.assert_allclose(A, th[slots], rtol=1e-6, atol=1e-8)
+    assert -L < 1e-12 * float(np.sum(sysm.invvar * data ** 2))
+
+
+def test_nonpositive_shapelet_scale_is_invalid():
+    base, spec, psf, sysm, th = _sh_case(2)
+    d0 = O.n_params(base)
+    data = O.model_image(th, spec, psf).numpy()
+    bad = th.copy()
+    bad[d0] = 0.0
+    assert O.loglike(bad, spec, psf, data, sysm.invvar) == -math.inf
+    bad[d0] = -0.1
+    assert O.loglike(bad, spec, psf, data, sysm.invvar) == -math.inf
