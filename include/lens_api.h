@@ -35,11 +35,18 @@
  *    synchronise between streams); distinct objects may run concurrently.
  *    An object is used from one host thread at a time.
  *
- * Canonical parameter order (d = n_mass + 7 * (n_lens_light + n_source)):
+ * Canonical parameter order (d = n_mass + 7 * (n_lens_light + n_source)
+ * + n_shapelet * (3 + nb)):
  *   mass   : theta_E ["], [gamma (EPL only)], e1, e2, x ["], y ["]
  *   shear  : g1, g2                                      (n_mass = 7 | 8)
  *   Sersic : R_e ["], n, e1, e2, x ["], y ["], I_e       per component,
  *            lens-light components first, then sources.
+ *   shapelet source (optional): beta ["], x ["], y ["], c_0 .. c_{nb-1},
+ *            nb = (n_max + 1)(n_max + 2)/2 coefficients of the Cartesian
+ *            basis phi_{n1}(x - x_c; beta) phi_{n2}(y - y_c; beta),
+ *            phi_n(u; beta) = [2^n sqrt(pi) n! beta]^(-1/2) H_n(u/beta)
+ *            exp(-u^2 / (2 beta^2)) (Refregier 2003), ordered by
+ *            n = n1 + n2, then n2 (coefficient k <-> (n - n2, n2)).
  */
 #ifndef LENS_API_H
 #define LENS_API_H
@@ -63,6 +70,7 @@ typedef int32_t lens_status;
 
 #define LENS_MAX_LENS_LIGHT 3
 #define LENS_MAX_SOURCE     3
+#define LENS_MAX_SHAPELET_NMAX 8   /* shapelet order: up to 45 coefficients */
 #define LENS_MAX_PSF       31
 #define LENS_MAX_SIDE    2048
 
@@ -77,7 +85,13 @@ typedef struct lens_model_desc {
     int32_t psf_size;       /* odd K, 1..LENS_MAX_PSF; PSF centre at (K-1)/2 */
     int32_t mass_model;     /* LENS_MASS_SIE | LENS_MASS_EPL (+ external shear) */
     int32_t n_lens_light;   /* 0..LENS_MAX_LENS_LIGHT Sersic components at theta */
-    int32_t n_source;       /* 1..LENS_MAX_SOURCE Sersic components at beta */
+    int32_t n_source;       /* 0..LENS_MAX_SOURCE Sersic components at beta */
+    int32_t n_shapelet;     /* 0 or 1 shapelet source at beta (Sec. 3: Sersic profiles
+                               and/or shapelets for the source light); at least one
+                               source in all: n_source + n_shapelet >= 1.  With a
+                               shapelet source, n_lens_light and n_source are 0 or 1. */
+    int32_t shapelet_nmax;  /* its order n_max, 0..LENS_MAX_SHAPELET_NMAX (ignored
+                               without a shapelet source) */
 } lens_model_desc;
 
 typedef struct lens_plan lens_plan;   /* opaque; owns device scratch */
@@ -168,8 +182,9 @@ lens_status lens_loglike_grad_noalloc(const lens_model_desc* desc, const float* 
 
 /* Backward modelling (Sec. 3: the lens and source intensities solved by
  * linear inversion instead of sampled).  For each particle the K =
- * n_lens_light + n_source Sersic intensities are set to the weighted
- * least-squares solution A of the normal equations M A = b,
+ * n_lens_light + n_source + nb linear amplitudes (the Sersic intensities,
+ * then the nb shapelet coefficients, at most 51 in all) are set to the
+ * weighted least-squares solution A of the normal equations M A = b,
  * M_kl = sum w B_k B_l, b_k = sum w B_k d, with B_k the model image of
  * component k at unit intensity (Cholesky in component order; a component
  * whose pivot is <= 1e-12 x max_k M_kk, i.e. no flux in the cutout or an

@@ -121,21 +121,9 @@ struct lens_plan {
 
 namespace {
 
-bool desc_ok(const lens_model_desc* d) {
-    if (!d) return false;
-    if (d->nx < 1 || d->ny < 1 || d->nx > LENS_MAX_SIDE || d->ny > LENS_MAX_SIDE) return false;
-    if (!(d->pix_scale > 0.0f) || !std::isfinite(d->pix_scale)) return false;
-    if (d->supersample < 1 || d->supersample > 16) return false;
-    if (d->psf_size < 1 || d->psf_size > LENS_MAX_PSF || (d->psf_size % 2) == 0) return false;
-    if (d->mass_model != LENS_MASS_SIE && d->mass_model != LENS_MASS_EPL) return false;
-    if (d->n_lens_light < 0 || d->n_lens_light > LENS_MAX_LENS_LIGHT) return false;
-    if (d->n_source < 1 || d->n_source > LENS_MAX_SOURCE) return false;
-    return true;
-}
+bool desc_ok(const lens_model_desc* d) { return desc_valid(d); }
 
-int nparams(const lens_model_desc* d) {
-    return (d->mass_model == LENS_MASS_EPL ? 8 : 7) + 7 * (d->n_lens_light + d->n_source);
-}
+int nparams(const lens_model_desc* d) { return model_info(*d).d; }
 
 lens_status hip_status(hipError_t e) { return e == hipSuccess ? LENS_OK : LENS_EHIP; }
 
@@ -231,10 +219,7 @@ lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf, co
     lens_plan* p = new (std::nothrow) lens_plan();
     if (!p) return LENS_ENOMEM;
     p->desc = *desc;
-    p->mi.mass_model = desc->mass_model;
-    p->mi.n_lens_light = desc->n_lens_light;
-    p->mi.n_source = desc->n_source;
-    p->mi.d = nparams(desc);
+    p->mi = model_info(*desc);
     p->geo = make_geo(*desc);
     p->max_particles = max_particles;
     p->ppt = 4;
@@ -243,7 +228,7 @@ lens_status lens_plan_create(const lens_model_desc* desc, const float* d_psf, co
     p->invvar = d_invvar;
     p->tiled = psf_lds_bytes(p->geo, desc->psf_size) > MAX_LDS_BYTES;
     const size_t npix = (size_t)desc->nx * desc->ny;
-    const int nacc = n_acc(desc->n_lens_light + desc->n_source);
+    const int nacc = n_acc(p->mi);
     p->partial_words = (size_t)max_particles * chunks_for((int)npix, 1) * nacc;
     const int K = desc->psf_size;
     if (hipMalloc(&p->psf_flip, sizeof(double) * K * K) != hipSuccess ||
@@ -334,7 +319,7 @@ static hipError_t plan_finalize(lens_plan* plan, int P, const float* d_theta, fl
     const int nch = chunks_for(plan->geo.npix, plan->ppt);
     if (nch <= kPreSumRows) return launch_finalize(plan->mi, P, nch, d_theta, plan->consts, plan->partial, d_grad, st);
     const hipError_t e =
-        launch_partial_sum(P, nch, n_acc(plan->desc.n_lens_light + plan->desc.n_source), plan->partial, st);
+        launch_partial_sum(P, nch, n_acc(plan->mi), plan->partial, st);
     if (e != hipSuccess) return e;
     return launch_finalize(plan->mi, P, 1, d_theta, plan->consts, plan->partial, d_grad, st, nch);
 }
@@ -390,10 +375,14 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta, 
 
 static BwdSlots bwd_slots(const lens_plan* plan) {
     BwdSlots s{};
-    s.K = plan->desc.n_lens_light + plan->desc.n_source;
+    const int ns = plan->desc.n_lens_light + plan->desc.n_source;
     s.d = plan->mi.d;
     const int base = plan->desc.mass_model == LENS_MASS_EPL ? 8 : 7;
-    for (int k = 0; k < s.K; ++k) s.slot[k] = base + 7 * k + 6;
+    for (int k = 0; k < ns; ++k) s.slot[k] = base + 7 * k + 6;
+    // shapelet coefficients: linear amplitudes after the Sersic intensities
+    const int nb = plan->mi.n_shapelet ? (plan->mi.sh_nmax + 1) * (plan->mi.sh_nmax + 2) / 2 : 0;
+    for (int k = 0; k < nb; ++k) s.slot[ns + k] = base + 7 * ns + 3 + k;
+    s.K = ns + nb;
     return s;
 }
 

@@ -5,7 +5,8 @@
 
 namespace lens {
 
-constexpr int BWD_MAX_K = 6;                  // light components (3 lens light + 3 source)
+constexpr int BWD_SMALL_K = 6;                // light components solved in registers (Sersic only)
+constexpr int BWD_MAX_K = 51;                 // with a shapelet source: 1 + 1 Sersic + 45 coefficients
 constexpr double BWD_PIVOT_REL = 1e-12;       // pivot threshold, relative to the largest diagonal of M
 
 // Positions of the K intensities in a parameter vector of length d.

@@ -145,6 +145,136 @@ __global__ __launch_bounds__(256) void k_bwd_normal(int P, BwdSlots s, int npix,
     }
 }
 
+// K > BWD_SMALL_K (a shapelet source's coefficients are components too):
+// one work-group of 256 threads per particle.  Pixels are staged in tiles of
+// BWD_TILE through LDS as float64 w B_k and B_k; thread t owns entries t,
+// t + 256, ... of the packed list (the lower triangle of M row by row, then
+// b), each summed over the pixels in order.  Wave 0 then factors M in LDS by
+// the same pivot-skipping Cholesky as solve_skip (lanes over the rows of a
+// column) and lane 0 substitutes.
+constexpr int BWD_TILE = 32;
+constexpr int BWD_ENT = (BWD_MAX_K * (BWD_MAX_K + 1) / 2 + BWD_MAX_K + 255) / 256;
+
+__global__ __launch_bounds__(256) void k_bwd_normal_big(int P, BwdSlots s, int npix, const float* __restrict__ B,
+                                                       const float* __restrict__ data,
+                                                       const float* __restrict__ invvar,
+                                                       const float* __restrict__ consts,
+                                                       const float* __restrict__ theta,
+                                                       float* __restrict__ theta_full, float* __restrict__ amp) {
+    __shared__ double wb[BWD_MAX_K][BWD_TILE];
+    __shared__ double bt[BWD_MAX_K + 1][BWD_TILE];   // row K: the data
+    __shared__ double M[BWD_MAX_K][BWD_MAX_K];
+    __shared__ double rhs[BWD_MAX_K], xs[BWD_MAX_K];
+    __shared__ int on[BWD_MAX_K];
+    const int K = s.K, p = blockIdx.x, tid = threadIdx.x;
+    const int nm = K * (K + 1) / 2, ne = nm + K;
+    const float* Bp = B + (size_t)p * K * npix;
+    int ek[BWD_ENT], el[BWD_ENT];
+    double acc[BWD_ENT];
+#pragma unroll
+    for (int q = 0; q < BWD_ENT; ++q) {
+        const int e = tid + 256 * q;
+        ek[q] = -1;
+        el[q] = -1;
+        acc[q] = 0.0;
+        if (e < nm) {
+            int k = 0;
+            while ((k + 1) * (k + 2) / 2 <= e) ++k;
+            ek[q] = k;
+            el[q] = e - k * (k + 1) / 2;
+        } else if (e < ne) {
+            ek[q] = e - nm;
+            el[q] = K;   // the data row
+        }
+    }
+    for (int p0 = 0; p0 < npix; p0 += BWD_TILE) {
+        __syncthreads();
+        for (int q = tid; q < (K + 1) * BWD_TILE; q += 256) {
+            const int k = q / BWD_TILE, t = q - k * BWD_TILE, pix = p0 + t;
+            const bool in = pix < npix;
+            const double w = in ? (double)invvar[pix] : 0.0;
+            const double v = in ? (k < K ? (double)Bp[(size_t)k * npix + pix] : (double)data[pix]) : 0.0;
+            bt[k][t] = v;
+            if (k < K) wb[k][t] = w * v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < BWD_ENT; ++q) {
+            if (ek[q] < 0) continue;
+            const int k = ek[q], l = el[q];
+            double a = acc[q];
+            for (int t = 0; t < BWD_TILE; ++t) a = fma(wb[k][t], bt[l][t], a);
+            acc[q] = a;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < BWD_ENT; ++q) {
+        if (ek[q] < 0) continue;
+        if (el[q] < K) {
+            M[ek[q]][el[q]] = acc[q];
+        } else {
+            rhs[ek[q]] = acc[q];
+        }
+    }
+    __syncthreads();
+    // pivot threshold relative to the largest diagonal entry
+    double dmax = 0.0;
+    for (int j = 0; j < K; ++j) dmax = fmax(dmax, M[j][j]);
+    const double tol = BWD_PIVOT_REL * dmax;
+    // in-place Cholesky of the lower triangle, column by column: every thread
+    // evaluates the pivot (same value), the first wave the column below it;
+    // every thread reaches every barrier
+    for (int j = 0; j < K; ++j) {
+        double sj = M[j][j];
+        for (int i = 0; i < j; ++i)
+            if (on[i]) sj -= M[j][i] * M[j][i];
+        const bool onj = sj > tol;
+        const double ljj = onj ? sqrt(sj) : 1.0;
+        __syncthreads();
+        if (tid == 0) {
+            on[j] = onj ? 1 : 0;
+            M[j][j] = ljj;
+        }
+        if (onj && tid < 64) {
+            for (int r = j + 1 + tid; r < K; r += 64) {
+                double t = M[r][j];
+                for (int i = 0; i < j; ++i)
+                    if (on[i]) t -= M[r][i] * M[j][i];
+                M[r][j] = t / ljj;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const bool valid = consts[(size_t)p * CSTRIDE + C_VALID] == 1.0f;
+    for (int j = 0; j < K; ++j) {   // L y = b
+        if (!on[j]) continue;
+        double t = rhs[j];
+        for (int i = 0; i < j; ++i)
+            if (on[i]) t -= M[j][i] * xs[i];
+        xs[j] = t / M[j][j];
+    }
+    for (int j = K - 1; j >= 0; --j) {   // L^T x = y
+        if (!on[j]) {
+            xs[j] = 0.0;
+            continue;
+        }
+        double t = xs[j];
+        for (int r = j + 1; r < K; ++r)
+            if (on[r]) t -= M[r][j] * xs[r];
+        xs[j] = t / M[j][j];
+    }
+    const int d = s.d;
+    const float* tp = theta + (size_t)p * d;
+    float* tf = theta_full + (size_t)p * d;
+    for (int j = 0; j < d; ++j) tf[j] = tp[j];
+    for (int k = 0; k < K; ++k) {
+        const double x = valid ? xs[k] : (double)__builtin_nan("");
+        tf[s.slot[k]] = valid ? (float)x : 0.0f;
+        if (amp) amp[(size_t)p * K + k] = (float)x;
+    }
+}
+
 // Pre-PSF model image at the solved intensities, sum_k A_k b_k, from the
 // component images b_k of the split render (the PSF is linear, so this is
 // the image the render would produce at those intensities; NaN images of an
@@ -185,7 +315,10 @@ hipError_t launch_bwd_normal(int P, const BwdSlots& s, int npix, const float* B,
         break;
         LENS_BWD_CASE(1) LENS_BWD_CASE(2) LENS_BWD_CASE(3) LENS_BWD_CASE(4) LENS_BWD_CASE(5) LENS_BWD_CASE(6)
 #undef LENS_BWD_CASE
-        default: return hipErrorInvalidValue;
+        default:
+            if (s.K < 1 || s.K > BWD_MAX_K) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_bwd_normal_big, dim3(P), dim3(256), 0, st, P, s, npix, B, data, invvar, consts,
+                               theta, theta_full, amp);
     }
     return hipGetLastError();
 }

@@ -18,14 +18,7 @@ using namespace lens;
 
 namespace {
 
-bool desc_ok(const lens_model_desc& d) {
-    return d.nx >= 1 && d.ny >= 1 && d.nx <= LENS_MAX_SIDE && d.ny <= LENS_MAX_SIDE &&
-           d.pix_scale > 0.0f && std::isfinite(d.pix_scale) && d.supersample >= 1 &&
-           d.supersample <= 16 && d.psf_size >= 1 && d.psf_size <= LENS_MAX_PSF &&
-           (d.psf_size % 2) == 1 && (d.mass_model == LENS_MASS_SIE || d.mass_model == LENS_MASS_EPL) &&
-           d.n_lens_light >= 0 && d.n_lens_light <= LENS_MAX_LENS_LIGHT && d.n_source >= 1 &&
-           d.n_source <= LENS_MAX_SOURCE;
-}
+bool desc_ok(const lens_model_desc& d) { return desc_valid(&d); }
 
 struct PsfClass {
     int K = 0;
@@ -82,7 +75,7 @@ static void free_classes(lens_batch_plan* b) {
 
 // (Re)builds descriptors and work lists for the current tiles.
 static lens_status rebuild(lens_batch_plan* b) {
-    const int nacc = n_acc(b->mi.n_lens_light + b->mi.n_source);
+    const int nacc = n_acc(b->mi);
     std::vector<BatchSys> sys(b->S);
     std::vector<WorkItem> items;
     std::vector<long long> cost;
@@ -207,7 +200,7 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
             return LENS_EINVAL;
         if (h_descs[k].mass_model != h_descs[0].mass_model ||
             h_descs[k].n_lens_light != h_descs[0].n_lens_light ||
-            h_descs[k].n_source != h_descs[0].n_source)
+            h_descs[k].n_source != h_descs[0].n_source || h_descs[k].n_shapelet != 0)
             return LENS_EUNSUPPORTED;
         if (psf_lds_bytes(make_geo(h_descs[k]), h_descs[k].psf_size) > MAX_LDS_BYTES)
             return LENS_EUNSUPPORTED;
@@ -215,10 +208,7 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
     lens_batch_plan* b = new (std::nothrow) lens_batch_plan();
     if (!b) return LENS_ENOMEM;
     b->S = S;
-    b->mi.mass_model = h_descs[0].mass_model;
-    b->mi.n_lens_light = h_descs[0].n_lens_light;
-    b->mi.n_source = h_descs[0].n_source;
-    b->mi.d = (b->mi.mass_model == LENS_MASS_EPL ? 8 : 7) + 7 * (b->mi.n_lens_light + b->mi.n_source);
+    b->mi = model_info(h_descs[0]);
     long long N = 0, npix_tot = 0, rows_max = 0;
     for (int k = 0; k < S; ++k) {
         b->desc.push_back(h_descs[k]);
@@ -238,7 +228,7 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
         return LENS_EUNSUPPORTED;
     }
     b->N = (int)N;
-    const int nacc = n_acc(b->mi.n_lens_light + b->mi.n_source);
+    const int nacc = n_acc(b->mi);
     std::vector<int> psys(N);
     for (int k = 0; k < S; ++k)
         for (int p = 0; p < b->P[k]; ++p) psys[b->p0[k] + p] = k;

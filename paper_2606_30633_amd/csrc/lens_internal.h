@@ -39,8 +39,20 @@ constexpr int KMAX_PAD = 128;            // entries per coefficient array
 constexpr int C_COEF_S = 176;            // float64 c_0..c_KP (2 words each)
 constexpr int C_COEF_Z = C_COEF_S + 2 * KMAX_PAD;   // float (m+1) c_{m+1}: S'(z)
 constexpr int C_COEF_T = C_COEF_Z + KMAX_PAD;       // float dc_n/dt
-constexpr int CSTRIDE = C_COEF_T + KMAX_PAD;        // 688 words
+// Shapelet source block: float64 scalars, then the coefficients in the
+// kernels' layout: rows n2 = 0..SH_CAP, each n1 = 0..SH_CAP - n2 (zero where
+// n1 + n2 > n_max), as float64 and as float32.
+constexpr int SH_CAP = LENS_MAX_SHAPELET_NMAX;
+constexpr int SH_NB = (SH_CAP + 1) * (SH_CAP + 2) / 2;    // 45
+constexpr int C_SHAP = C_COEF_T + KMAX_PAD;                // 688
+constexpr int SH_XC = 0, SH_YC = 2, SH_IB = 4, SH_E0 = 6;   // centre, 1/beta, pi^(-1/2)/beta (float64)
+constexpr int SH_CD = 8;                                   // float64 coefficients (2 words each)
+constexpr int SH_CF = SH_CD + 2 * SH_NB;                   // float32 coefficients
+constexpr int CSTRIDE = C_SHAP + ((SH_CF + SH_NB + 3) / 4) * 4;   // 832 words
 constexpr int KMAX_TERMS = KMAX_PAD - 1;
+
+// First index of row n2 in the kernels' coefficient layout.
+__host__ __device__ constexpr int sh_row(int n2) { return n2 * (SH_CAP + 1) - n2 * (n2 - 1) / 2; }
 
 static_assert(C_SERS + MAX_COMP * SERS_STRIDE <= C_COEF_S, "constant layout");
 static_assert(C_COEF_S % 4 == 0 && C_COEF_Z % 4 == 0 && C_COEF_T % 4 == 0 && CSTRIDE % 4 == 0,
@@ -59,7 +71,15 @@ constexpr int A_SERS_STRIDE = 8;
 constexpr int AS_E = 0, AS_WU = 1, AS_WUL = 2, AS_QXX = 3, AS_QXY = 4, AS_QYY = 5,
               AS_QX = 6, AS_QY = 7;
 
-inline int n_acc(int ncomp) { return A_SERS + A_SERS_STRIDE * ncomp; }
+// Shapelet accumulators after the Sersic ones: sum W (V + u V_u + v V_v),
+// sum W V_u, sum W V_v, then one per coefficient (kernels' layout), with W
+// the adjoint of the sub-pixel value and V the source's value at beta.
+constexpr int AH_B = 0, AH_U = 1, AH_V = 2, AH_C = 3;
+constexpr int AH_SIZE = AH_C + SH_NB;
+
+__host__ __device__ inline int n_acc(int ncomp, int n_shapelet = 0) {
+    return A_SERS + A_SERS_STRIDE * ncomp + n_shapelet * AH_SIZE;
+}
 
 constexpr float RMIN2 = 1e-12f;   // radii are clamped to 1e-6 arcsec
 constexpr double RMIN2D = 1e-12;
@@ -83,8 +103,43 @@ inline Geo make_geo(const lens_model_desc& d) {
 }
 
 struct ModelInfo {
-    int mass_model, n_lens_light, n_source, d;
+    int mass_model, n_lens_light, n_source, n_shapelet, sh_nmax, d;
 };
+
+// Model layout of a descriptor (which must be valid: see desc_valid).
+inline ModelInfo model_info(const lens_model_desc& d) {
+    ModelInfo mi;
+    mi.mass_model = d.mass_model;
+    mi.n_lens_light = d.n_lens_light;
+    mi.n_source = d.n_source;
+    mi.n_shapelet = d.n_shapelet;
+    mi.sh_nmax = d.n_shapelet ? d.shapelet_nmax : 0;
+    const int nb = d.n_shapelet ? (mi.sh_nmax + 1) * (mi.sh_nmax + 2) / 2 : 0;
+    mi.d = (d.mass_model == LENS_MASS_EPL ? 8 : 7) + 7 * (d.n_lens_light + d.n_source) +
+           (d.n_shapelet ? 3 + nb : 0);
+    return mi;
+}
+
+__host__ __device__ inline int n_acc(const ModelInfo& mi) { return n_acc(mi.n_lens_light + mi.n_source, mi.n_shapelet); }
+
+// Descriptor checks shared by every entry point (single system).
+inline bool desc_valid(const lens_model_desc* d) {
+    if (!d) return false;
+    if (d->nx < 1 || d->ny < 1 || d->nx > LENS_MAX_SIDE || d->ny > LENS_MAX_SIDE) return false;
+    if (!(d->pix_scale > 0.0f) || !(d->pix_scale < 3.0e38f)) return false;
+    if (d->supersample < 1 || d->supersample > 16) return false;
+    if (d->psf_size < 1 || d->psf_size > LENS_MAX_PSF || (d->psf_size % 2) == 0) return false;
+    if (d->mass_model != LENS_MASS_SIE && d->mass_model != LENS_MASS_EPL) return false;
+    if (d->n_lens_light < 0 || d->n_lens_light > LENS_MAX_LENS_LIGHT) return false;
+    if (d->n_source < 0 || d->n_source > LENS_MAX_SOURCE) return false;
+    if (d->n_shapelet != 0 && d->n_shapelet != 1) return false;
+    if (d->n_source + d->n_shapelet < 1) return false;
+    if (d->n_shapelet) {
+        if (d->shapelet_nmax < 0 || d->shapelet_nmax > LENS_MAX_SHAPELET_NMAX) return false;
+        if (d->n_lens_light > 1 || d->n_source > 1) return false;
+    }
+    return true;
+}
 
 // Launchers (lens_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_prologue(const ModelInfo& mi, int P, const float* theta, float* consts,

@@ -225,6 +225,89 @@ __device__ __forceinline__ void sersic_adj(float dx, float dy, float gs, const S
 }
 
 // ---------------------------------------------------------------------------
+// Shapelet source (Cartesian basis of Refregier 2003).  With u = dx/beta,
+// v = dy/beta the basis function (n1, n2) is (1/beta) psi_n1(u) psi_n2(v),
+// psi_n = pi^(-1/4) h_n e^{-u^2/2} (Hermite functions), where h_0 = 1 and
+// h_{n+1} = sqrt(2/(n+1)) u h_n - sqrt(n/(n+1)) h_{n-1} (stable recurrence of
+// the normalised functions); psi_n' = sqrt(n/2) psi_{n-1} - sqrt((n+1)/2)
+// psi_{n+1}.  Coefficients are in the kernels' layout (sh_row).
+// ---------------------------------------------------------------------------
+__constant__ constexpr double SH_A[SH_CAP + 1] = {1.4142135623730951, 1.0, 0.816496580927726, 0.7071067811865476,
+                                                   0.6324555320336759, 0.5773502691896257, 0.5345224838248488, 0.5,
+                                                   0.4714045207910317};
+__constant__ constexpr double SH_B[SH_CAP + 1] = {0.0, 0.7071067811865476, 0.816496580927726, 0.8660254037844386,
+                                                   0.8944271909999159, 0.9128709291752769, 0.9258200997725514,
+                                                   0.9354143466934853, 0.9428090415820634};
+__constant__ constexpr float SH_D[SH_CAP + 2] = {0.0f, 0.70710678f, 1.0f, 1.22474487f, 1.41421356f,
+                                                 1.58113883f, 1.73205081f, 1.87082869f, 2.0f, 2.12132034f};
+
+template <typename T, int N>
+__device__ __forceinline__ void hermite_h(T u, T (&h)[N]) {
+    h[0] = (T)1;
+    if (N > 1) h[1] = (T)SH_A[0] * u;
+#pragma unroll
+    for (int n = 1; n + 1 < N; ++n) h[n + 1] = (T)SH_A[n] * u * h[n] - (T)SH_B[n] * h[n - 1];
+}
+
+// Value of the shapelet source at the source-plane point (bx, by), float64.
+__device__ __forceinline__ double shapelet_val(double bx, double by, const float* __restrict__ C) {
+    const float* H = C + C_SHAP;
+    const double ib = ldd(H, SH_IB);
+    const double u = (bx - ldd(H, SH_XC)) * ib, v = (by - ldd(H, SH_YC)) * ib;
+    double hu[SH_CAP + 1], hv[SH_CAP + 1];
+    hermite_h(u, hu);
+    hermite_h(v, hv);
+    double F = 0.0;
+#pragma unroll
+    for (int n2 = 0; n2 <= SH_CAP; ++n2) {
+        double t = 0.0;
+#pragma unroll
+        for (int n1 = 0; n1 <= SH_CAP - n2; ++n1) t = fma(ldd(H, SH_CD + 2 * (sh_row(n2) + n1)), hu[n1], t);
+        F = fma(t, hv[n2], F);
+    }
+    const double E = ldd(H, SH_E0) * exp2_d(fmax(-(u * u + v * v) * 0.7213475204444817, -1100.0));
+    return E * F;
+}
+
+// Adjoint of the shapelet value for the adjoint gs of the sub-pixel value at
+// the source-plane offset (dx, dy) from its centre: accumulates the sums of
+// the AH_* layout into a[] and adds the source-plane gradient to (gbx, gby).
+__device__ __forceinline__ void shapelet_adj(float dx, float dy, float gs, const float* __restrict__ C, float* a,
+                                             float& gbx, float& gby) {
+    const float* H = C + C_SHAP;
+    const float ib = (float)ldd(H, SH_IB);
+    const float u = dx * ib, v = dy * ib;
+    float hu[SH_CAP + 2], hv[SH_CAP + 2];
+    hermite_h(u, hu);
+    hermite_h(v, hv);
+    const float W = gs * (float)ldd(H, SH_E0) * fexp2(-(u * u + v * v) * 0.72134752f);
+    float F = 0.f, Fu = 0.f, Fv = 0.f;
+#pragma unroll
+    for (int n2 = 0; n2 <= SH_CAP; ++n2) {
+        float th = 0.f, tg = 0.f;
+#pragma unroll
+        for (int n1 = 0; n1 <= SH_CAP - n2; ++n1) {
+            const float c = ldf(H, SH_CF + sh_row(n2) + n1);
+            const float g1 = SH_D[n1] * (n1 > 0 ? hu[n1 > 0 ? n1 - 1 : 0] : 0.f) - SH_D[n1 + 1] * hu[n1 + 1];
+            th = fmaf(c, hu[n1], th);
+            tg = fmaf(c, g1, tg);
+        }
+        const float g2 = SH_D[n2] * (n2 > 0 ? hv[n2 > 0 ? n2 - 1 : 0] : 0.f) - SH_D[n2 + 1] * hv[n2 + 1];
+        F = fmaf(th, hv[n2], F);
+        Fu = fmaf(tg, hv[n2], Fu);
+        Fv = fmaf(th, g2, Fv);
+        const float wv = W * hv[n2];
+#pragma unroll
+        for (int n1 = 0; n1 <= SH_CAP - n2; ++n1) a[AH_C + sh_row(n2) + n1] = fmaf(wv, hu[n1], a[AH_C + sh_row(n2) + n1]);
+    }
+    a[AH_U] = fmaf(W, Fu, a[AH_U]);
+    a[AH_V] = fmaf(W, Fv, a[AH_V]);
+    a[AH_B] = fmaf(W, fmaf(u, Fu, fmaf(v, Fv, F)), a[AH_B]);
+    gbx = fmaf(W * Fu, ib, gbx);
+    gby = fmaf(W * Fv, ib, gby);
+}
+
+// ---------------------------------------------------------------------------
 // EPL series S(z) = sum a_n z^n with real coefficients at complex z.
 //
 // With r = 2 Re z and s = |z|^2, z is a root of w^2 - r w + s, so dividing
@@ -402,7 +485,7 @@ __device__ __forceinline__ void deflect(double x, double y, const PK<NC>& k,
 // The same value with each component's float64 constants loaded right
 // before the component is evaluated: the ~40 float64 constants of a particle
 // do not fit the scalar register file together.
-template <int MASS, int NL, int NS>
+template <int MASS, int NL, int NS, int SH>
 __device__ __forceinline__ double subpix_value_lean(double x, double y, const float* __restrict__ C) {
     double v = 0.0;
 #pragma unroll
@@ -421,11 +504,12 @@ __device__ __forceinline__ double subpix_value_lean(double x, double y, const fl
         const SersicK s = load_sersic(opaque(C + C_SERS + (NL + c) * SERS_STRIDE));
         v += sersic_val(bx - s.xc, by - s.yc, s);
     }
+    if (SH) v += shapelet_val(bx, by, opaque(C));
     return v;
 }
 
 // Reverse sweep of one sub-pixel: accumulates into acc[] (layout A_*).
-template <int MASS, int NL, int NS>
+template <int MASS, int NL, int NS, int SH>
 __device__ __forceinline__ void subpix_adjoint(double x, double y, float gs, const PK<NL + NS>& k,
                                                const float* __restrict__ C, float* acc) {
     float dummy0 = 0.f, dummy1 = 0.f;
@@ -448,6 +532,9 @@ __device__ __forceinline__ void subpix_adjoint(double x, double y, float gs, con
         sersic_adj<true>((float)(bx - sc.xc), (float)(by - sc.yc), gs, sc,
                          acc + A_SERS + A_SERS_STRIDE * (NL + c), gbx, gby);
     }
+    if (SH)
+        shapelet_adj((float)(bx - ldd(C + C_SHAP, SH_XC)), (float)(by - ldd(C + C_SHAP, SH_YC)), gs, C,
+                     acc + A_SERS + A_SERS_STRIDE * (NL + NS), gbx, gby);
 
     // G = dL/dalpha = -dL/dbeta (mass and shear deflections enter beta alike)
     const float xf = (float)x, yf = (float)y;
@@ -563,6 +650,29 @@ __global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
         Sd[S_BL / 2] = bn * 1.4426950408889634;
         S[S_KAP2] = (float)(-bn / n);
     }
+    if (mi.n_shapelet) {
+        // shapelet source: scale, centre, coefficients re-ordered into rows of n2
+        const double beta = th[o];
+        ok = ok && beta > 0.0;
+        float* H = C + C_SHAP;
+        double* Hd = reinterpret_cast<double*>(H);
+        const double ib = 1.0 / beta;
+        Hd[SH_XC / 2] = th[o + 1];
+        Hd[SH_YC / 2] = th[o + 2];
+        Hd[SH_IB / 2] = ib;
+        Hd[SH_E0 / 2] = 0.56418958354775628695 * ib;   // pi^(-1/2) / beta
+        for (int q = 0; q < SH_NB; ++q) {
+            Hd[SH_CD / 2 + q] = 0.0;
+            H[SH_CF + q] = 0.0f;
+        }
+        int k = 0;
+        for (int n = 0; n <= mi.sh_nmax; ++n)
+            for (int n2 = 0; n2 <= n; ++n2, ++k) {
+                const int q = sh_row(n2) + (n - n2);
+                Hd[SH_CD / 2 + q] = th[o + 3 + k];
+                H[SH_CF + q] = th[o + 3 + k];
+            }
+    }
     // Series coefficients c_n(t), (n+1) c_{n+1} for S'(z), and dc_n/dt = c_n D_n,
     // D_n = sum_{k<=n} [1/(2k-2+t) + 1/(2k+2-t)], |z| = c, c_n decreasing.
     // Truncation after z^K leaves at most c_{K+1} c^{K+1}/(1-c) in S (kept
@@ -608,7 +718,7 @@ __global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
 }
 
 // Renders pixels [pix0, pix1) of one particle (whole work-group).
-template <int MASS, int NL, int NS>
+template <int MASS, int NL, int NS, int SH>
 __device__ __forceinline__ void render_chunk(const float* __restrict__ C, const Geo& g, int pix0,
                                              int pix1, float* __restrict__ out) {
     if (C[C_VALID] != 1.0f) {
@@ -622,7 +732,7 @@ __device__ __forceinline__ void render_chunk(const float* __restrict__ C, const 
             const double y = ((double)(g.s * i + a) - g.cy) * g.h;
             for (int b = 0; b < g.s; ++b) {
                 const double x = ((double)(g.s * j + b) - g.cx) * g.h;
-                acc += subpix_value_lean<MASS, NL, NS>(x, y, C);
+                acc += subpix_value_lean<MASS, NL, NS, SH>(x, y, C);
             }
         }
         out[pix] = (float)(acc * (double)g.inv_s2);
@@ -632,11 +742,11 @@ __device__ __forceinline__ void render_chunk(const float* __restrict__ C, const 
 // Reverse sweep over pixels [pix0, pix1) of one particle; writes the
 // work-group's NACC float64 sums to outp.  red: LDS [NACC][4] doubles.
 // Ends with a barrier, so red can be reused by the caller.
-template <int MASS, int NL, int NS>
+template <int MASS, int NL, int NS, int SH>
 __device__ __forceinline__ void adjoint_chunk(const float* __restrict__ C, const Geo& g, int pix0,
                                               int pix1, const float* __restrict__ gp,
                                               double* __restrict__ outp, double (*red)[4]) {
-    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
+    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS) + SH * AH_SIZE;
     if (C[C_VALID] != 1.0f) {
         if (threadIdx.x < NACC) outp[threadIdx.x] = 0.0;
         return;
@@ -652,7 +762,7 @@ __device__ __forceinline__ void adjoint_chunk(const float* __restrict__ C, const
             const double y = ((double)(g.s * i + a) - g.cy) * g.h;
             for (int b = 0; b < g.s; ++b) {
                 const double x = ((double)(g.s * j + b) - g.cx) * g.h;
-                subpix_adjoint<MASS, NL, NS>(x, y, gs, k, C, acc);
+                subpix_adjoint<MASS, NL, NS, SH>(x, y, gs, k, C, acc);
             }
         }
     }
@@ -670,39 +780,44 @@ __device__ __forceinline__ void adjoint_chunk(const float* __restrict__ C, const
     __syncthreads();
 }
 
-template <int MASS, int NL, int NS>
+template <int MASS, int NL, int NS, int SH>
 __global__ __launch_bounds__(256) void k_render(const float* __restrict__ consts, Geo g, int ppb,
                                                 float* __restrict__ img) {
     init_math_tab();
     const int p = blockIdx.x;
     const int pix0 = blockIdx.y * ppb;
-    render_chunk<MASS, NL, NS>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
-                               img + (size_t)p * g.npix);
+    render_chunk<MASS, NL, NS, SH>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
+                                   img + (size_t)p * g.npix);
 }
 
 // Backward modelling: the image of each light component at the intensity in
 // its constants (the unit-intensity images when every intensity is 1), in
 // one pass, so the deflection is evaluated once per sub-pixel.
-// img [(p (NL + NS) + c)][npix]; lens-light components first, then sources.
-template <int MASS, int NL, int NS>
-__global__ __launch_bounds__(256) void k_render_split(const float* __restrict__ consts, Geo g, int ppb,
+// img [(p K + c)][npix], K = NL + NS + nb: lens-light components first, then
+// the Sersic sources, then the nb shapelet basis functions (coefficient order
+// of the parameter vector) at their coefficients.
+template <int MASS, int NL, int NS, int SH>
+__global__ __launch_bounds__(256) void k_render_split(const float* __restrict__ consts, Geo g, int ppb, int sh_nmax,
                                                       float* __restrict__ img) {
     constexpr int NC = NL + NS;
+    constexpr int NSH = SH ? SH_NB : 0;
     init_math_tab();
     const int p = blockIdx.x;
     const int pix0 = blockIdx.y * ppb, pix1 = min(pix0 + ppb, g.npix);
+    const int nb = SH ? (sh_nmax + 1) * (sh_nmax + 2) / 2 : 0;
+    const int K = NC + nb;
     const float* C = consts + (size_t)p * CSTRIDE;
-    float* out = img + (size_t)p * NC * g.npix;
+    float* out = img + (size_t)p * K * g.npix;
     if (C[C_VALID] != 1.0f) {
         for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x)
-            for (int c = 0; c < NC; ++c) out[(size_t)c * g.npix + pix] = __builtin_nanf("");
+            for (int c = 0; c < K; ++c) out[(size_t)c * g.npix + pix] = __builtin_nanf("");
         return;
     }
     for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) {
         const int i = pix / g.nx, j = pix - i * g.nx;
-        double acc[NC];
+        double acc[NC + NSH];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        for (int c = 0; c < NC + NSH; ++c) acc[c] = 0.0;
         for (int a = 0; a < g.s; ++a) {
             const double y = ((double)(g.s * i + a) - g.cy) * g.h;
             for (int b = 0; b < g.s; ++b) {
@@ -723,28 +838,73 @@ __global__ __launch_bounds__(256) void k_render_split(const float* __restrict__ 
                     const SersicK sk = load_sersic(opaque(C + C_SERS + (NL + c) * SERS_STRIDE));
                     acc[NL + c] += sersic_val(bx - sk.xc, by - sk.yc, sk);
                 }
+                if (SH) {
+                    // each basis function at its coefficient (kernels' layout)
+                    const float* H = opaque(C) + C_SHAP;
+                    const double ib = ldd(H, SH_IB);
+                    const double u = (bx - ldd(H, SH_XC)) * ib, v = (by - ldd(H, SH_YC)) * ib;
+                    double hu[SH_CAP + 1], hv[SH_CAP + 1];
+                    hermite_h(u, hu);
+                    hermite_h(v, hv);
+                    const double E = ldd(H, SH_E0) * exp2_d(fmax(-(u * u + v * v) * 0.7213475204444817, -1100.0));
+#pragma unroll
+                    for (int n2 = 0; n2 <= SH_CAP; ++n2) {
+                        const double ev = E * hv[n2];
+#pragma unroll
+                        for (int n1 = 0; n1 <= SH_CAP - n2; ++n1) {
+                            const int q = sh_row(n2) + n1;
+                            acc[NC + q] = fma(ev * ldd(H, SH_CD + 2 * q), hu[n1], acc[NC + q]);
+                        }
+                    }
+                }
             }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) out[(size_t)c * g.npix + pix] = (float)(acc[c] * (double)g.inv_s2);
+        if (SH) {
+            // basis (n1, n2) is coefficient n (n + 1)/2 + n2 of the parameter vector, n = n1 + n2
+#pragma unroll
+            for (int n2 = 0; n2 <= SH_CAP; ++n2)
+#pragma unroll
+                for (int n1 = 0; n1 <= SH_CAP - n2; ++n1) {
+                    const int n = n1 + n2;
+                    if (n <= sh_nmax)
+                        out[(size_t)(NC + n * (n + 1) / 2 + n2) * g.npix + pix] =
+                            (float)(acc[NC + sh_row(n2) + n1] * (double)g.inv_s2);
+                }
+        }
     }
 }
 
-template <int MASS, int NL, int NS>
 // Four waves per SIMD (at most 128 VGPRs): measured faster than the three the
 // register demand would otherwise give, with the few spills left outside the
 // sub-pixel loops.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint(const float* __restrict__ consts, Geo g, int ppb,
-                                                 const float* __restrict__ gimg,
-                                                 double* __restrict__ partial) {
-    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS);
+template <int MASS, int NL, int NS, int SH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint(
+    const float* __restrict__ consts, Geo g, int ppb, const float* __restrict__ gimg, double* __restrict__ partial) {
+    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS) + SH * AH_SIZE;
     __shared__ double red[NACC][4];
     init_math_tab();
     const int p = blockIdx.x;
     const int pix0 = blockIdx.y * ppb;
-    adjoint_chunk<MASS, NL, NS>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
-                                gimg + (size_t)p * g.npix,
-                                partial + ((size_t)p * gridDim.y + blockIdx.y) * NACC, red);
+    adjoint_chunk<MASS, NL, NS, SH>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
+                                    gimg + (size_t)p * g.npix,
+                                    partial + ((size_t)p * gridDim.y + blockIdx.y) * NACC, red);
+}
+
+// With a shapelet source (48 more accumulators): the same pass with no cap on
+// the registers.
+template <int MASS, int NL, int NS, int SH>
+__global__ __launch_bounds__(256) void k_adjoint_sh(const float* __restrict__ consts, Geo g, int ppb,
+                                                    const float* __restrict__ gimg, double* __restrict__ partial) {
+    constexpr int NACC = A_SERS + A_SERS_STRIDE * (NL + NS) + SH * AH_SIZE;
+    __shared__ double red[NACC][4];
+    init_math_tab();
+    const int p = blockIdx.x;
+    const int pix0 = blockIdx.y * ppb;
+    adjoint_chunk<MASS, NL, NS, SH>(consts + (size_t)p * CSTRIDE, g, pix0, min(pix0 + ppb, g.npix),
+                                    gimg + (size_t)p * g.npix,
+                                    partial + ((size_t)p * gridDim.y + blockIdx.y) * NACC, red);
 }
 
 // Register-blocked correlation of an LDS tile with a K x K kernel:
@@ -888,7 +1048,7 @@ __device__ void finalize_particle(const ModelInfo& mi, int nchunks, const float*
                                   float valid, const double* __restrict__ base,
                                   float* __restrict__ g) {
     const int nc = mi.n_lens_light + mi.n_source;
-    const int nacc = A_SERS + A_SERS_STRIDE * nc;
+    const int nacc = n_acc(mi);
     if (valid != 1.0f) {
         const float v = valid == 2.0f ? __builtin_nanf("") : 0.0f;
         for (int q = 0; q < mi.d; ++q) g[q] = v;
@@ -953,6 +1113,18 @@ __device__ void finalize_particle(const ModelInfo& mi, int nchunks, const float*
         g[o + 4] = (float)(-2.0 * kap * (a11 * qx + a12 * qy));
         g[o + 5] = (float)(-2.0 * kap * (a12 * qx + a22 * qy));
     }
+    if (mi.n_shapelet) {
+        // V = (1/beta) G((x - x_c)/beta, (y - y_c)/beta): dV/dbeta = -(V + u V_u + v V_v)/beta,
+        // dV/dx_c = -V_u/beta; the coefficients' sums are their derivatives
+        const int ab = A_SERS + A_SERS_STRIDE * nc;
+        const double ib = 1.0 / (double)th[o];
+        g[o] = (float)(-ib * acc(ab + AH_B));
+        g[o + 1] = (float)(-ib * acc(ab + AH_U));
+        g[o + 2] = (float)(-ib * acc(ab + AH_V));
+        int k = 0;
+        for (int n = 0; n <= mi.sh_nmax; ++n)
+            for (int n2 = 0; n2 <= n; ++n2, ++k) g[o + 3 + k] = (float)acc(ab + AH_C + sh_row(n2) + (n - n2));
+    }
 }
 
 // Particle p's partial rows start at row p * row_stride; the first nchunks are summed.
@@ -961,7 +1133,7 @@ __global__ void k_finalize(ModelInfo mi, int P, int nchunks, int row_stride, con
                            float* __restrict__ grad) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const int nacc = A_SERS + A_SERS_STRIDE * (mi.n_lens_light + mi.n_source);
+    const int nacc = n_acc(mi);
     finalize_particle(mi, nchunks, theta + (size_t)p * mi.d, consts[(size_t)p * CSTRIDE + C_VALID],
                       partial + (size_t)p * row_stride * nacc, grad + (size_t)p * mi.d);
 }
@@ -992,7 +1164,7 @@ __global__ __launch_bounds__(256) void k_batch_render(const BatchSys* __restrict
         const WorkItem w = items[it];
         const BatchSys& S = sys[w.sys];
         const int pix0 = w.chunk * S.ppb;
-        render_chunk<MASS, NL, NS>(consts + (size_t)(S.p0 + w.p) * CSTRIDE, S.g, pix0,
+        render_chunk<MASS, NL, NS, 0>(consts + (size_t)(S.p0 + w.p) * CSTRIDE, S.g, pix0,
                                    min(pix0 + S.ppb, S.g.npix),
                                    img + S.img_off + (size_t)w.p * S.g.npix);
     }
@@ -1018,7 +1190,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const WorkItem w = items[it];
         const BatchSys& S = sys[w.sys];
         const int pix0 = w.chunk * S.ppb;
-        adjoint_chunk<MASS, NL, NS>(consts + (size_t)(S.p0 + w.p) * CSTRIDE, S.g, pix0,
+        adjoint_chunk<MASS, NL, NS, 0>(consts + (size_t)(S.p0 + w.p) * CSTRIDE, S.g, pix0,
                                     min(pix0 + S.ppb, S.g.npix),
                                     gimg + S.img_off + (size_t)w.p * S.g.npix,
                                     partial + (S.part_off + (size_t)w.p * S.nch + w.chunk) * NACC, red);
@@ -1049,7 +1221,7 @@ __global__ void k_batch_finalize(ModelInfo mi, int N, const BatchSys* __restrict
     const int gp = blockIdx.x * blockDim.x + threadIdx.x;
     if (gp >= N) return;
     const BatchSys& S = sys[particle_sys[gp]];
-    const int nacc = A_SERS + A_SERS_STRIDE * (mi.n_lens_light + mi.n_source);
+    const int nacc = n_acc(mi);
     const int p = gp - S.p0;
     finalize_particle(mi, S.nch, theta + (size_t)gp * mi.d, consts[(size_t)gp * CSTRIDE + C_VALID],
                       partial + (S.part_off + (size_t)p * S.nch) * nacc, grad + (size_t)gp * mi.d);
@@ -1233,11 +1405,31 @@ bool dispatch_ls(int nl, int ns, F&& f) {
     }
 }
 
+// Models without a shapelet source (the uneven batch's kernels).
 template <class F>
 bool dispatch_model(const ModelInfo& mi, F&& f) {
+    if (mi.n_shapelet) return false;
     if (mi.mass_model == LENS_MASS_EPL)
         return dispatch_ls<LENS_MASS_EPL>(mi.n_lens_light, mi.n_source, f);
     return dispatch_ls<LENS_MASS_SIE>(mi.n_lens_light, mi.n_source, f);
+}
+
+// Calls f(IC<mass>, IC<n_lens_light>, IC<n_source>, IC<n_shapelet>); a
+// shapelet source is compiled with at most one lens light and one Sersic source.
+template <class F>
+bool dispatch_model_sh(const ModelInfo& mi, F&& f) {
+    if (!mi.n_shapelet) return dispatch_model(mi, [&](auto M, auto NL, auto NS) { f(M, NL, NS, IC<0>{}); });
+    if (mi.n_lens_light > 1 || mi.n_source > 1) return false;
+    auto g = [&](auto M) {
+        switch (mi.n_lens_light * 2 + mi.n_source) {
+            case 0: f(M, IC<0>{}, IC<0>{}, IC<1>{}); return true;
+            case 1: f(M, IC<0>{}, IC<1>{}, IC<1>{}); return true;
+            case 2: f(M, IC<1>{}, IC<0>{}, IC<1>{}); return true;
+            case 3: f(M, IC<1>{}, IC<1>{}, IC<1>{}); return true;
+            default: return false;
+        }
+    };
+    return mi.mass_model == LENS_MASS_EPL ? g(IC<LENS_MASS_EPL>{}) : g(IC<LENS_MASS_SIE>{});
 }
 
 hipError_t launch_prologue(const ModelInfo& mi, int P, const float* theta, float* consts,
@@ -1251,8 +1443,8 @@ hipError_t launch_render(const ModelInfo& mi, const Geo& g, int P, int ppt, cons
     const int nch = chunks_for(g.npix, ppt);
     const dim3 grid(P, nch);
     const int ppb = 256 * ppt;
-    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
-        hipLaunchKernelGGL((k_render<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
+    const bool done = dispatch_model_sh(mi, [&](auto M, auto NL, auto NS, auto SH) {
+        hipLaunchKernelGGL((k_render<decltype(M)::value, decltype(NL)::value, decltype(NS)::value, decltype(SH)::value>),
                            grid, dim3(256), 0, st, consts, g, ppb, img);
     });
     if (!done) return hipErrorInvalidValue;
@@ -1264,9 +1456,10 @@ hipError_t launch_render_split(const ModelInfo& mi, const Geo& g, int P, int ppt
     const int nch = chunks_for(g.npix, ppt);
     const dim3 grid(P, nch);
     const int ppb = 256 * ppt;
-    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
-        hipLaunchKernelGGL((k_render_split<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
-                           grid, dim3(256), 0, st, consts, g, ppb, img);
+    const bool done = dispatch_model_sh(mi, [&](auto M, auto NL, auto NS, auto SH) {
+        hipLaunchKernelGGL(
+            (k_render_split<decltype(M)::value, decltype(NL)::value, decltype(NS)::value, decltype(SH)::value>), grid,
+            dim3(256), 0, st, consts, g, ppb, mi.sh_nmax, img);
     });
     if (!done) return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1277,9 +1470,13 @@ hipError_t launch_adjoint(const ModelInfo& mi, const Geo& g, int P, int ppt, con
     const int nch = chunks_for(g.npix, ppt);
     const dim3 grid(P, nch);
     const int ppb = 256 * ppt;
-    const bool done = dispatch_model(mi, [&](auto M, auto NL, auto NS) {
-        hipLaunchKernelGGL((k_adjoint<decltype(M)::value, decltype(NL)::value, decltype(NS)::value>),
-                           grid, dim3(256), 0, st, consts, g, ppb, gimg, partial);
+    const bool done = dispatch_model_sh(mi, [&](auto M, auto NL, auto NS, auto SH) {
+        constexpr int m = decltype(M)::value, l = decltype(NL)::value, n = decltype(NS)::value,
+                      h = decltype(SH)::value;
+        if constexpr (h != 0)
+            hipLaunchKernelGGL((k_adjoint_sh<m, l, n, h>), grid, dim3(256), 0, st, consts, g, ppb, gimg, partial);
+        else
+            hipLaunchKernelGGL((k_adjoint<m, l, n, h>), grid, dim3(256), 0, st, consts, g, ppb, gimg, partial);
     });
     if (!done) return hipErrorInvalidValue;
     return hipGetLastError();

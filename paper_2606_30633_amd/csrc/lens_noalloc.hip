@@ -8,7 +8,6 @@
 // that device current) and every launch takes that address.
 #include <hip/hip_runtime.h>
 
-#include <cmath>
 #include <mutex>
 
 #include "lens_internal.h"
@@ -39,14 +38,6 @@ lens_status scratch_ptr(void** out) {
     return LENS_OK;
 }
 
-bool desc_valid(const lens_model_desc* d) {
-    return d && d->nx >= 1 && d->ny >= 1 && d->nx <= LENS_MAX_SIDE && d->ny <= LENS_MAX_SIDE &&
-           d->pix_scale > 0.0f && std::isfinite(d->pix_scale) && d->supersample >= 1 &&
-           d->supersample <= 16 && d->psf_size >= 1 && d->psf_size <= LENS_MAX_PSF && (d->psf_size % 2) == 1 &&
-           (d->mass_model == LENS_MASS_SIE || d->mass_model == LENS_MASS_EPL) && d->n_lens_light >= 0 &&
-           d->n_lens_light <= LENS_MAX_LENS_LIGHT && d->n_source >= 1 && d->n_source <= LENS_MAX_SOURCE;
-}
-
 }  // namespace
 
 using namespace lens;
@@ -57,18 +48,14 @@ extern "C" lens_status lens_loglike_grad_noalloc(const lens_model_desc* desc, co
                                                  double* d_logl64, void* stream) {
     if (!desc_valid(desc) || !d_psf || !d_data || !d_invvar || !d_theta || !d_logl || !d_grad || P < 1)
         return LENS_EINVAL;
-    ModelInfo mi;
-    mi.mass_model = desc->mass_model;
-    mi.n_lens_light = desc->n_lens_light;
-    mi.n_source = desc->n_source;
-    mi.d = (desc->mass_model == LENS_MASS_EPL ? 8 : 7) + 7 * (desc->n_lens_light + desc->n_source);
+    const ModelInfo mi = model_info(*desc);
     const Geo g = make_geo(*desc);
     const int K = desc->psf_size;
     if (psf_lds_bytes(g, K) > MAX_LDS_BYTES) return LENS_EUNSUPPORTED;
     // the launch shape of a plan at its default of 4 pixels per thread
     constexpr int kPpt = 4;
     const int nch = chunks_for(g.npix, kPpt);
-    const int nacc = n_acc(desc->n_lens_light + desc->n_source);
+    const int nacc = n_acc(mi);
     const size_t b_flip = align256(sizeof(double) * (size_t)K * K);
     const size_t b_consts = align256(sizeof(float) * (size_t)CSTRIDE * (size_t)P);
     const size_t b_img = align256(sizeof(float) * (size_t)g.npix * (size_t)P);

@@ -33,7 +33,7 @@ class lens_model_desc(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pix_scale", ctypes.c_float),
         ("supersample", ctypes.c_int32), ("psf_size", ctypes.c_int32),
         ("mass_model", ctypes.c_int32), ("n_lens_light", ctypes.c_int32),
-        ("n_source", ctypes.c_int32),
+        ("n_source", ctypes.c_int32), ("n_shapelet", ctypes.c_int32), ("shapelet_nmax", ctypes.c_int32),
     ]
 
 
@@ -135,7 +135,18 @@ _MASS = {"SIE": LENS_MASS_SIE, "EPL": LENS_MASS_EPL}
 def desc_from_spec(spec) -> lens_model_desc:
     return lens_model_desc(
         spec.nx, spec.ny, spec.pix_scale, spec.supersample, spec.psf_size,
-        _MASS.get(spec.mass_model, -1), spec.n_lens_light, spec.n_source)
+        _MASS.get(spec.mass_model, -1), spec.n_lens_light, spec.n_source,
+        int(getattr(spec, "n_shapelet", 0)), int(getattr(spec, "shapelet_nmax", 0)))
+
+
+def n_linear_components(spec) -> int:
+    """Linear light amplitudes solved by the backward likelihood: the Sersic
+    intensities, then the shapelet coefficients."""
+    nb = 0
+    if getattr(spec, "n_shapelet", 0):
+        n = int(spec.shapelet_nmax)
+        nb = (n + 1) * (n + 2) // 2
+    return spec.n_lens_light + spec.n_source + nb
 
 
 def lens_num_params(spec) -> int:
@@ -333,7 +344,7 @@ def lens_loglike_grad_backward(plan: LensPlan, theta: torch.Tensor, stream=None)
     linear inversion, and those intensities [P, K]."""
     th = plan._theta(theta)
     P = th.shape[0]
-    K = plan.spec.n_lens_light + plan.spec.n_source
+    K = n_linear_components(plan.spec)
     logl = torch.empty(P, dtype=torch.float32, device=plan.device)
     grad = torch.empty((P, plan.d), dtype=torch.float32, device=plan.device)
     amp = torch.empty((P, K), dtype=torch.float32, device=plan.device)

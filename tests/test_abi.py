@@ -37,6 +37,15 @@ def test_every_declared_symbol_is_exported():
     assert not missing, missing
 
 
+def test_shapelet_parameter_counts_match_the_oracle():
+    import dataclasses
+    from oracle import lens_oracle as O
+    for nmax in (0, 4, 8):
+        for ns in (0, 1):
+            spec = dataclasses.replace(synth.config1_spec(), n_source=ns, n_shapelet=1, shapelet_nmax=nmax)
+            assert lens.lens_num_params(spec) == O.n_params(spec) == spec.n_params
+
+
 def test_status_strings_and_param_counts():
     assert lens.lens_status_string(0) == "ok"
     assert "invalid" in lens.lens_status_string(-1)
@@ -48,6 +57,8 @@ def test_status_strings_and_param_counts():
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-1), dict(pix_scale=0.0), dict(supersample=0), dict(psf_size=4),
     dict(psf_size=33), dict(mass_model="XYZ"), dict(n_lens_light=4), dict(n_source=0),
+    dict(nx=2049), dict(n_shapelet=2), dict(n_shapelet=1, shapelet_nmax=9),
+    dict(n_shapelet=1, shapelet_nmax=-1), dict(n_shapelet=1, n_source=2),
 ])
 def test_invalid_descriptors_rejected(bad):
     import dataclasses

@@ -42,8 +42,8 @@ def _with_amps(t, spec, A):
 
 
 def _check(spec, psf, data, invvar, th, L, G, A, near=()):
-    K = spec.n_lens_light + spec.n_source
     slots = O.intensity_slots(spec)
+    K = len(slots)
     for p in range(th.shape[0]):
         lo, go, ao = O.loglike_backward(th[p], spec, psf, data, invvar)
         if not np.isfinite(lo):
