@@ -30,14 +30,14 @@ PEAK_FP32_PACKED = 157.3
 # WRITE_SIZE passes, scaled by a plain 256 MiB copy (profiles/
 # map_step_100px_4096p_counters.txt).  Valid only for the kernel source it was
 # measured on; reported as null otherwise.
-TRAFFIC_MEASURED = {"kernel_src_sha256_16": "bb7dec4797a99ba8", "bytes": 206062001}
+TRAFFIC_MEASURED = {"kernel_src_sha256_16": "96f57f91eb94aa67", "bytes": 189861930}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
@@ -120,45 +120,72 @@ def main():
     # observed image: forward model at the truth (GPU) + seeded noise
     plan, data = system_plan(spec, sysm, P, dev)
     table = synth.prior_table(sysm.prior)
-    u = torch.tensor(_to_unconstrained_box(th, table), device=dev)
-    m = torch.zeros_like(u)
-    v = torch.zeros_like(u)
+    u0 = torch.tensor(_to_unconstrained_box(th, table), device=dev)
+    u, m, v = u0.clone(), torch.zeros_like(u0), torch.zeros_like(u0)
     loss = torch.empty(P, device=dev)
-    lens.lens_map_reset(plan)
 
-    def step():
+    def restart():
+        u.copy_(u0)
+        m.zero_()
+        v.zero_()
+        lens.lens_map_reset(plan)
+
+    def step(graph=True):
         # one multi-start MAP step: T(u), log prior, logL + adjoint gradient, Adam
-        lens.lens_map_adam(plan, u, m, v, 1, 1e-2, 0.99, loss=loss)
+        lens.lens_map_adam(plan, u, m, v, 1, 1e-2, 0.99, loss=loss, use_graph=graph)
 
+    restart()
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    plan.enable_timing(True)
+    # the timed region: one gradient-descent run of K graph-replayed steps from the starts
+    restart()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    plan.enable_timing(False)
-    tim = plan.read_timing()
     ms_step = (t1 - t0) * 1e3 / args.steps
     evals_per_s = P / (ms_step * 1e-3)
 
+    # per-call times: 100 graph-replayed steps, each between two events on the launch stream
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    call_ms = sorted(a.elapsed_time(b) for a, b in evs)
+    median_ms = 0.5 * (call_ms[49] + call_ms[50])
+
+    # per-kernel durations (HIP events around every launch on the launch stream), eager steps
+    plan.enable_timing(True)
+    for _ in range(20):
+        step(graph=False)
+    torch.cuda.synchronize()
+    plan.enable_timing(False)
+    tim = plan.read_timing()
+    per = {k: t[0] / max(t[1], 1) for k, t in tim.items() if t[1]}
+
     # dominant kernel: adjoint sub-pixel pass
-    adj_ms, adj_n = tim["adjoint"]
-    adj_avg_ms = adj_ms / max(adj_n, 1)
+    adj_avg_ms = per["adjoint"]
     steps = _series_terms(th, spec).mean(axis=0)
     nsub = (spec.nx * spec.supersample) * (spec.ny * spec.supersample)
-    fl_sub = adjoint_flops_per_subpixel(steps[0], steps[1], spec.n_lens_light, spec.n_source, True)
-    flops_launch = fl_sub * nsub * P
-    achieved = flops_launch / (adj_avg_ms * 1e-3) / 1e12
+    fl_adj = adjoint_flops_per_subpixel(steps[0], steps[1], spec.n_lens_light, spec.n_source, True) * nsub * P
+    fl_ren = render_flops_per_subpixel(steps[0], spec.n_lens_light, spec.n_source, True) * nsub * P
+    fl_psf = 4.0 * spec.psf_size ** 2 * spec.nx * spec.ny * P
+    achieved = fl_adj / (adj_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4),
                 "traffic": _measured_traffic() if P == 4096 else None,
                 "kernel": "k_adjoint", "avg_ms": round(adj_avg_ms, 4),
                 "frac_of_fp32_packed_peak": round(achieved / PEAK_FP32_PACKED, 4),
-                "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
+                "kernel_ms_per_step": {k: round(x, 4) for k, x in per.items()},
+                "kernel_frac": {"adjoint": round(achieved / PEAK_ALU_TFLOPS, 4),
+                                "render": round(fl_ren / (per["render"] * 1e-3) / 1e12 / PEAK_ALU_TFLOPS, 4),
+                                "psf": round(fl_psf / (per["psf"] * 1e-3) / 1e12 / PEAK_ALU_TFLOPS, 4)},
+                "step_frac": round((fl_adj + fl_ren + fl_psf) / (ms_step * 1e-3) / 1e12 / PEAK_ALU_TFLOPS, 4)}
 
     if args.calib_copy_mb > 0:
         nb = args.calib_copy_mb * (1 << 20)
@@ -178,9 +205,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "100x100 px, s=3, EPL+shear, 1 Sersic lens, 2 Sersic sources, "
-                               "21x21 PSF; one multi-start MAP step (bijection, prior, logL + adjoint "
-                               "gradient, Adam) over all particles", "particles": P,
-                   "sub_pixels_per_particle": nsub, "params": spec.n_params},
+                               "21x21 PSF; one multi-start gradient-descent run of K graph-replayed MAP steps "
+                               "(bijection, prior, logL + adjoint gradient, Adam) over all particles",
+                   "particles": P, "sub_pixels_per_particle": nsub, "params": spec.n_params,
+                   "gd_run_evals": P * args.steps, "gd_run_s": round(t1 - t0, 4),
+                   "median_call_ms": round(median_ms, 4),
+                   "median_call_evals_per_s": round(P / (median_ms * 1e-3), 1)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -227,36 +257,66 @@ def _series_terms(th, spec):
     return np.array(out, dtype=np.float64)
 
 
-def cpu_baseline(spec, sysm, th_sample):
-    """The FP64 oracle timed on the host cores on a bounded sample: logL +
-    gradient (the reported value), logL alone on 64 particles, and logL +
-    gradient on one thread (8 particles)."""
+def _oracle_chunk(job):
+    """Worker: the oracle's logL + gradient (or logL only) of a chunk of
+    particles on one torch thread; returns the wall time of the chunk."""
+    spec, psf, data, invvar, th, with_grad = job
+    import torch
+    torch.set_num_threads(1)
+    from oracle import lens_oracle as O
+    fn = O.loglike_and_grad if with_grad else O.loglike
+    fn(th[0], spec, psf, data, invvar)      # warm-up
+    t0 = time.perf_counter()
+    for t in th:
+        fn(t, spec, psf, data, invvar)
+    return time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(spec, sysm, th_sample, workers=None):
+    """The FP64 oracle timed on the host cores on a bounded sample: the
+    particles split over worker processes with one torch thread each (the
+    particles are independent), logL + gradient (the reported value) and
+    logL alone; plus the same on one process and thread (8 particles)."""
+    import multiprocessing as mp
     import torch
     from oracle import lens_oracle as O
     model = O.model_image(sysm.truth, spec, sysm.psf).numpy()
     data = (model + sysm.noise).astype(np.float32)
-    O.loglike_and_grad(th_sample[0], spec, sysm.psf, data, sysm.invvar)   # warm-up
-    t0 = time.perf_counter()
-    for t in th_sample:
-        O.loglike_and_grad(t, spec, sysm.psf, data, sysm.invvar)
-    dt = time.perf_counter() - t0
-    cores = torch.get_num_threads()
-    t0 = time.perf_counter()
-    for t in th_sample[:64]:
-        O.loglike(t, spec, sysm.psf, data, sysm.invvar)
-    dt_l = time.perf_counter() - t0
+    # at most 12 workers: with this process, at most 13 processes hold the GPU
+    # runtime open (importing torch opens it), well inside a 16-process limit
+    n = workers or max(1, min(12, os.cpu_count() or 1))
+    chunks = [c for c in np.array_split(th_sample, n) if len(c)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(len(chunks)) as pool:
+        pool.map(_oracle_chunk, [(spec, sysm.psf, data, sysm.invvar, c[:1], False) for c in chunks])  # start-up
+        t0 = time.perf_counter()
+        pool.map(_oracle_chunk, [(spec, sysm.psf, data, sysm.invvar, c, True) for c in chunks])
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pool.map(_oracle_chunk, [(spec, sysm.psf, data, sysm.invvar, c, False) for c in chunks])
+        dt_l = time.perf_counter() - t0
+    threads = torch.get_num_threads()
     torch.set_num_threads(1)
     try:
-        t0 = time.perf_counter()
-        for t in th_sample[:8]:
-            O.loglike_and_grad(t, spec, sysm.psf, data, sysm.invvar)
-        dt_1 = time.perf_counter() - t0
+        dt_1 = _oracle_chunk((spec, sysm.psf, data, sysm.invvar, th_sample[:8], True))
     finally:
-        torch.set_num_threads(cores)
-    return {"value": round(len(th_sample) / dt, 3), "unit": "evals/s", "cores": cores,
+        torch.set_num_threads(threads)
+    return {"value": round(len(th_sample) / dt, 3), "unit": "evals/s", "cores": len(chunks),
             "kind": "oracle",
-            "sample": f"{len(th_sample)} particles of the same workload, logL+grad (FP64 autograd)",
-            "logl_only_evals_per_s": round(min(64, len(th_sample)) / dt_l, 3),
+            "sample": f"{len(th_sample)} particles of the same workload, logL+grad (FP64 autograd), split over "
+                      f"{len(chunks)} processes with one thread each",
+            "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
+            "logl_only_evals_per_s": round(len(th_sample) / dt_l, 3),
             "one_thread_evals_per_s": round(min(8, len(th_sample)) / dt_1, 3)}
 
 

@@ -160,10 +160,10 @@ lens_status lens_loglike_grad(lens_plan* plan, int32_t P, const float* d_theta,
  * GPU the call runs on, reserved from library load until the process ends;
  * its device address is looked up once per device on the first call there.
  * One call needs, each part rounded up to 256 bytes,
- *   8 K^2 + 4 * 688 P + 4 nx ny P + 8 P ceil(nx ny / 1024) (11 + 8 n_comp)
- * bytes, n_comp = n_lens_light + n_source: about 45.6 KB per particle at
- * 100 x 100 px with three components, so up to ~1470 particles per call
- * there (split larger batches into several calls).
+ *   8 K^2 + 4 * 832 P + 4 nx ny P + 8 P ceil(nx ny / 1024) (11 + 8 n_comp + 48 n_shapelet)
+ * bytes, n_comp = n_lens_light + n_source: about 46.1 KB per particle at
+ * 100 x 100 px with three Sersic components, so up to ~1450 particles per
+ * call there (split larger batches into several calls).
  * Every call on one GPU uses the same array and leaves the last call's
  * contents in it: calls that overlap on one GPU (two streams, or two host
  * threads, without ordering) race and give wrong results; order them.
