@@ -257,6 +257,25 @@ lens_status lens_logpost_grad(lens_plan* plan, int32_t P, const float* d_u,
 lens_status lens_to_unconstrained(lens_plan* plan, int32_t P, const float* d_theta, float* d_u,
                                   void* stream);
 
+/* HIP graphs.  The iterative calls below (lens_map_adam, lens_hmc_run,
+ * lens_hmc_adapt, lens_svi_run, lens_batch_map_adam, lens_batch_loglike_grad)
+ * take a use_graph flag instead of explicit graph handles: with use_graph != 0
+ * the plan captures one step (one transition, one SVI step) on its own stream
+ * into a graph it owns, instantiates it, and replays it on the caller's stream
+ * once per step.  The graph is kept across calls and re-captured only when its
+ * key changes: the particle count, every device pointer the step touches, the
+ * hyper-parameters baked into kernel arguments (learning rate, decay, betas,
+ * eps, step size, leapfrog count, seed, window start, target acceptance) and
+ * the launch tiles.  Values that change from step to step or call to call
+ * live in plan-owned device memory that the kernels read, written by small
+ * kernels outside the graph before the replays: the Adam / SVI step counters,
+ * the HMC transition counter and the index of a run's first transition
+ * (transition0), the adapted step size.  A caller that keeps its buffers and
+ * hyper-parameters fixed therefore replays one instantiated graph for a whole
+ * run.  Captured graphs are dropped by lens_plan_set_backward and destroyed
+ * with the plan.  Timing (lens_plan_enable_timing) records no events inside
+ * replayed graphs. */
+
 /* Multi-start MAP (Sec. 3, Sec. 3.1: every particle descends independently;
  * Sec. 3.2: Adam for MAP).  Runs n_steps Adam updates (Kingma & Ba 2015,
  * bias-corrected) of loss(u) = -(logL + log prior)(T(u)) on all P particles.

@@ -112,7 +112,7 @@ struct lens_plan {
     float* bwd_thx;           // [maxP][d] parameters with unit intensities (backward likelihood; on first use)
     float* bwd_img;           // [maxP][npix] PSF-convolved component images, K per particle
     float* bwd_theta;         // [maxP][d] parameters with the solved intensities
-    int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC base,
+    int* counters;            // [0] MAP step, [1] HMC transitions in this run, [2..3] HMC first transition (64-bit),
                               // [4] SVI step, [5] SVI steps in this run, [6] step of lens_svi_elbo_grad,
                               // [7] window samples of lens_hmc_adapt
     hipStream_t cap_stream;
@@ -652,7 +652,7 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
     a.samples = d_samples; a.accepts = d_accepts;
     a.tcount = plan->counters + 1;
     a.seed = seed;
-    a.transition0 = transition0;
+    a.transition0 = reinterpret_cast<const unsigned long long*>(plan->counters + 2);
     a.eps = eps;
     auto transition = [&](hipStream_t s) -> lens_status {
         {
@@ -673,11 +673,15 @@ lens_status lens_hmc_run(lens_plan* plan, int32_t C, float* d_u, float* d_grad, 
         }
         return hip_status(launch_add_int(plan->counters + 1, 1, s));
     };
-    // transition counter of this run starts at zero (outside any graph)
-    if (launch_set_int(plan->counters + 1, 0, st) != hipSuccess) return LENS_EHIP;
+    // transition counter of this run starts at zero and its first transition's
+    // index is written to device memory (outside any graph: a captured graph
+    // reads both, so it is not re-captured for a new transition0)
+    if (launch_set_int(plan->counters + 1, 0, st) != hipSuccess ||
+        launch_set_u64(reinterpret_cast<unsigned long long*>(plan->counters + 2), transition0, st) != hipSuccess)
+        return LENS_EHIP;
     const std::vector<uint64_t> key = {(uint64_t)C, (uint64_t)(uintptr_t)d_u, (uint64_t)(uintptr_t)d_grad,
                                        (uint64_t)(uintptr_t)d_logp, (uint64_t)(uintptr_t)d_inv_mass,
-                                       fbits(eps), (uint64_t)n_leapfrog, seed, transition0,
+                                       fbits(eps), (uint64_t)n_leapfrog, seed,
                                        (uint64_t)(uintptr_t)d_samples, (uint64_t)(uintptr_t)d_accepts,
                                        (uint64_t)plan->ppt};
     return run_maybe_graph(plan, plan->hmc_graph, key, use_graph != 0, n_transitions, st, transition);
@@ -817,7 +821,7 @@ lens_status lens_hmc_adapt(lens_plan* plan, int32_t C, float* d_u, float* d_grad
     a.p = plan->hmc_p; a.h0 = plan->hmc_h0; a.inv_mass = d_inv_mass;
     a.tcount = plan->counters + 1;
     a.seed = seed;
-    a.transition0 = transition0;
+    a.transition0 = reinterpret_cast<const unsigned long long*>(plan->counters + 2);
     a.eps = eps0;
     a.eps_dev = plan->hmc_eps;
     a.accprob = plan->hmc_accprob;
@@ -853,11 +857,12 @@ lens_status lens_hmc_adapt(lens_plan* plan, int32_t C, float* d_u, float* d_grad
     // state, step size, window sums and counters start afresh (outside any graph)
     if (launch_hmc_adapt_init(C, d, plan->hmc_state, plan->hmc_eps, eps0, plan->hmc_wmean, plan->hmc_wm2, wcount,
                               st) != hipSuccess ||
-        launch_set_int(plan->counters + 1, 0, st) != hipSuccess)
+        launch_set_int(plan->counters + 1, 0, st) != hipSuccess ||
+        launch_set_u64(reinterpret_cast<unsigned long long*>(plan->counters + 2), transition0, st) != hipSuccess)
         return LENS_EHIP;
     const std::vector<uint64_t> key = {(uint64_t)C, (uint64_t)(uintptr_t)d_u, (uint64_t)(uintptr_t)d_grad,
                                        (uint64_t)(uintptr_t)d_logp, (uint64_t)(uintptr_t)d_inv_mass,
-                                       (uint64_t)n_leapfrog, seed, transition0, (uint64_t)window_start,
+                                       (uint64_t)n_leapfrog, seed, (uint64_t)window_start,
                                        fbits(target_accept), (uint64_t)(uintptr_t)d_eps_trace,
                                        (uint64_t)(uintptr_t)d_eps_final, (uint64_t)plan->ppt};
     lens_status r = run_maybe_graph(plan, plan->adapt_graph, key, use_graph != 0, n_transitions, st, transition);

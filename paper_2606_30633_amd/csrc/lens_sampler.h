@@ -31,7 +31,7 @@ struct HmcArgs {
     int* accepts;      // [C] or null
     const int* tcount; // transitions done in this run
     uint64_t seed;
-    uint64_t transition0;
+    const unsigned long long* transition0;   // index of this run's first transition (device memory)
     float eps;
     const float* eps_dev;   // if set: the step size, read on the device (adaptive runs)
     double* accprob;        // [C] or null: min(1, exp(H0 - H1)) of each chain's transition
@@ -98,6 +98,8 @@ hipError_t launch_adam(int P, int d, const float* grad_u, const double* logp, fl
                        hipStream_t st);
 hipError_t launch_add_int(int* c, int inc, hipStream_t st);
 hipError_t launch_set_int(int* c, int val, hipStream_t st);
+// *c = val (a kernel, so that a captured graph can read values set between replays)
+hipError_t launch_set_u64(unsigned long long* c, unsigned long long val, hipStream_t st);
 hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_kick_drift(int C, int d, const HmcArgs& a, hipStream_t st);
 hipError_t launch_hmc_end(int C, int d, const HmcArgs& a, hipStream_t st);

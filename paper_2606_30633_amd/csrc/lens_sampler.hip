@@ -150,6 +150,7 @@ __global__ void k_adam(int P, int d, const float* __restrict__ grad_u, const dou
 
 __global__ void k_add_int(int* c, int inc) { *c += inc; }
 __global__ void k_set_int(int* c, int val) { *c = val; }
+__global__ void k_set_u64(unsigned long long* c, unsigned long long val) { *c = val; }
 
 // Philox4x32-10 and Box-Muller come from lens_philox.h.
 __device__ __forceinline__ uint4 philox(uint4 c, uint2 k) { return philox4x32_10(c, k); }
@@ -171,7 +172,7 @@ __device__ __forceinline__ double momentum(uint2 key, uint32_t chain, uint32_t t
 __global__ void k_hmc_begin(int C, int d, HmcArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
-    const uint32_t t = (uint32_t)(a.transition0 + (uint64_t)*a.tcount);
+    const uint32_t t = (uint32_t)(*a.transition0 + (uint64_t)*a.tcount);
     const uint2 key = make_uint2((uint32_t)(a.seed & 0xffffffffu), (uint32_t)(a.seed >> 32));
     float* u = a.u + (size_t)c * d;
     float* g = a.grad + (size_t)c * d;
@@ -211,7 +212,7 @@ __global__ void k_hmc_end(int C, int d, HmcArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
     const int tl = *a.tcount;
-    const uint32_t t = (uint32_t)(a.transition0 + (uint64_t)tl);
+    const uint32_t t = (uint32_t)(*a.transition0 + (uint64_t)tl);
     const uint2 key = make_uint2((uint32_t)(a.seed & 0xffffffffu), (uint32_t)(a.seed >> 32));
     float* u = a.u + (size_t)c * d;
     float* g = a.grad + (size_t)c * d;
@@ -418,6 +419,11 @@ hipError_t launch_set_int(int* c, int val, hipStream_t st) {
 }
 
 hipError_t launch_set_int_host(int* c, int val, hipStream_t st) { return launch_set_int(c, val, st); }
+
+hipError_t launch_set_u64(unsigned long long* c, unsigned long long val, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, c, val);
+    return hipGetLastError();
+}
 
 hipError_t launch_hmc_begin(int C, int d, const HmcArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_hmc_begin, blocks_for(C, 64), dim3(64), 0, st, C, d, a);
