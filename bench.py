@@ -659,25 +659,49 @@ def run_batch(args):
     for pl in plans:
         pl.close()
     sub = sum(sp.nx * sp.ny * sp.supersample ** 2 for sp in sy.specs) * P
+    # per-kernel durations of eager calls (HIP events on the launch stream)
+    bp.enable_timing(True)
+    for _ in range(5):
+        bp.loglike_grad(theta, logl, grad)
+    torch.cuda.synchronize()
+    bp.enable_timing(False)
+    per = {k: t[0] / max(t[1], 1) for k, t in bp.read_timing().items() if t[1]}
+    # algorithmic flops of the persistent adjoint: every system's sub-pixels x its particles'
+    # mean series lengths (one launch covers all 100 systems)
+    th_np = theta.cpu().numpy()
+    fl_adj = fl_ren = fl_psf = 0.0
+    for k, sp in enumerate(sy.specs):
+        ks = _series_terms(th_np[k * P:(k + 1) * P], sp).mean(axis=0)
+        nsub_k = sp.nx * sp.ny * sp.supersample ** 2
+        fl_adj += adjoint_flops_per_subpixel(ks[0], ks[1], sp.n_lens_light, sp.n_source, True) * nsub_k * P
+        fl_ren += render_flops_per_subpixel(ks[0], sp.n_lens_light, sp.n_source, True) * nsub_k * P
+        fl_psf += 4.0 * sp.psf_size ** 2 * sp.nx * sp.ny * P
+    ach = fl_adj / (per["adjoint"] * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_ALU_TFLOPS, 4), "traffic": None, "kernel": "k_batch_adjoint (persistent)",
+            "avg_ms": round(per["adjoint"], 4), "kernel_ms_per_step": {k: round(x, 4) for k, x in per.items()},
+            "kernel_frac": {"render": round(fl_ren / (per["render"] * 1e-3) / 1e12 / PEAK_ALU_TFLOPS, 4),
+                            "psf": round(fl_psf / (per["psf"] * 1e-3) / 1e12 / PEAK_ALU_TFLOPS, 4)},
+            "step_frac": round((fl_adj + fl_ren + fl_psf) / dt / 1e12 / PEAK_ALU_TFLOPS, 4)}
     _line(args, bp.N / dt, "evals/s", dt * 1e3,
           "uneven batch: 100 systems (side 48-160 px, s 2-4, PSF 11-31), 512 particles each, "
           "one persistent render + adjoint launch per step, autotuned tiles",
           {"particles": bp.N, "sub_pixel_evals_per_s": round(sub / dt, 1), "autotune_s": round(t_tune, 2),
            "tiles": {str(t): tiles.count(t) for t in sorted(set(tiles))},
            "per_system_plans_evals_per_s": round(bp.N / dt_sep, 1),
-           "persistent_gain": round(dt_sep / dt, 3), "per_system_results_identical": same})
+           "persistent_gain": round(dt_sep / dt, 3), "per_system_results_identical": same}, roof)
 
 
 def run_cnn(args):
     """Training throughput of the learned initializer's network (BF16 MFMA)."""
     import torch
     from paper_2606_30633_amd import lens, synth
-    from paper_2606_30633_amd.learned_init import simulate, target_standardization, SIGMA
+    from paper_2606_30633_amd.learned_init import simulate, target_standardization, SIGMA, TARGET_IDX
     dev = torch.device("cuda", 0)
     B = 256
     theta, images = simulate(B * 16, synth.SEED_CNN_TRAIN, dev)
     mean, std = target_standardization(theta)
-    tgt = torch.tensor((theta[:, :14] - mean) / std, dtype=torch.float32, device=dev)
+    tgt = torch.tensor((theta[:, TARGET_IDX] - mean) / std, dtype=torch.float32, device=dev)
     net = lens.Cnn(B, 1, dev)
     xb = net.prepare(images, SIGMA, add_noise=True, seed=1)
     loss = torch.empty(1, device=dev)

@@ -585,6 +585,12 @@ lens_status lens_prior_sample(int32_t d, const float* h_prior_table, int32_t S, 
 
 lens_status lens_plan_enable_timing(lens_plan* plan, int32_t enable);
 lens_status lens_plan_read_timing(lens_plan* plan, double* h_ms, int64_t* h_count);
+/* The same for a batch plan's likelihood sequence (lens_batch_loglike_grad
+ * and the batched posterior): slots PROLOGUE, RENDER (the persistent render
+ * launch), PSF (all PSF-class launches of one call together), ADJOINT (the
+ * persistent adjoint launch), FINALIZE. */
+lens_status lens_batch_enable_timing(lens_batch_plan* plan, int32_t enable);
+lens_status lens_batch_read_timing(lens_batch_plan* plan, double* h_ms, int64_t* h_count);
 
 #ifdef __cplusplus
 }

@@ -10,53 +10,9 @@
 #include "lens_internal.h"
 #include "lens_backward.h"
 #include "lens_sampler.h"
+#include "lens_timer.h"
 
 using namespace lens;
-
-// Event pairs around kernel launches of one plan (diagnostic timing).
-struct KernelTimer {
-    static constexpr int kMaxRecords = 65536;
-    bool enabled = false;
-    bool capturing = false;
-    std::vector<hipEvent_t> ev[LENS_NUM_KERNEL_SLOTS];
-    int used[LENS_NUM_KERNEL_SLOTS] = {0};
-    int64_t count[LENS_NUM_KERNEL_SLOTS] = {0};
-
-    hipEvent_t take(int slot) {
-        auto& v = ev[slot];
-        if (used[slot] >= (int)v.size()) {
-            if ((int)v.size() >= 2 * kMaxRecords) return nullptr;
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            v.push_back(e);
-        }
-        return v[used[slot]++];
-    }
-    void release() {
-        for (auto& v : ev)
-            for (auto e : v) (void)hipEventDestroy(e);
-        for (auto& v : ev) v.clear();
-    }
-};
-
-// Records start/stop events around one launch when timing is enabled.
-struct TimedLaunch {
-    KernelTimer* t;
-    int slot;
-    hipStream_t st;
-    hipEvent_t stop = nullptr;
-    TimedLaunch(KernelTimer* t_, int slot_, hipStream_t st_) : t(t_), slot(slot_), st(st_) {
-        if (!t->enabled || t->capturing) return;
-        t->count[slot]++;
-        hipEvent_t start = t->take(slot);
-        stop = start ? t->take(slot) : nullptr;
-        if (start && stop) (void)hipEventRecord(start, st);
-        else stop = nullptr;
-    }
-    ~TimedLaunch() {
-        if (stop) (void)hipEventRecord(stop, st);
-    }
-};
 
 // One captured HIP graph and the arguments it was captured with.
 struct GraphCache {
@@ -880,23 +836,7 @@ lens_status lens_plan_enable_timing(lens_plan* plan, int32_t enable) {
 
 lens_status lens_plan_read_timing(lens_plan* plan, double* h_ms, int64_t* h_count) {
     if (!plan || !h_ms || !h_count) return LENS_EINVAL;
-    KernelTimer& t = plan->timer;
-    lens_status st = LENS_OK;
-    for (int k = 0; k < LENS_NUM_KERNEL_SLOTS; ++k) {
-        double tot = 0.0;
-        for (int r = 0; r + 1 < t.used[k]; r += 2) {
-            if (hipEventSynchronize(t.ev[k][r + 1]) != hipSuccess) return LENS_EHIP;
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, t.ev[k][r], t.ev[k][r + 1]) != hipSuccess) return LENS_EHIP;
-            tot += ms;
-        }
-        if (t.count[k] * 2 > t.used[k]) st = LENS_EUNSUPPORTED;
-        h_ms[k] = tot;
-        h_count[k] = t.count[k];
-        t.used[k] = 0;
-        t.count[k] = 0;
-    }
-    return st;
+    return plan->timer.read(h_ms, h_count);
 }
 
 }  // extern "C"

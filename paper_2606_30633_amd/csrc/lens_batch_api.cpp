@@ -13,6 +13,7 @@
 
 #include "lens_internal.h"
 #include "lens_sampler.h"
+#include "lens_timer.h"
 
 using namespace lens;
 
@@ -31,6 +32,7 @@ struct PsfClass {
 }  // namespace
 
 struct lens_batch_plan {
+    KernelTimer timer;
     int S = 0;
     int N = 0;
     ModelInfo mi{};
@@ -150,19 +152,33 @@ static lens_status rebuild(lens_batch_plan* b) {
 
 static lens_status enqueue(lens_batch_plan* b, const float* theta, float* logl, float* grad,
                            hipStream_t st, double* logl64 = nullptr) {
-    if (launch_prologue(b->mi, b->N, theta, b->consts, st) != hipSuccess) return LENS_EHIP;
+    KernelTimer* t = &b->timer;
+    {
+        TimedLaunch tl(t, LENS_K_PROLOGUE, st);
+        if (launch_prologue(b->mi, b->N, theta, b->consts, st) != hipSuccess) return LENS_EHIP;
+    }
     if (launch_set_int_host(b->d_counter, 0, st) != hipSuccess) return LENS_EHIP;
-    if (launch_batch_render(b->mi, b->grid_render, b->d_sys, b->d_items, b->n_items, b->d_counter,
-                            b->consts, b->img, st) != hipSuccess)
-        return LENS_EHIP;
-    for (const auto& c : b->classes)
-        if (launch_batch_psf(c.K, c.n, b->d_sys, c.items, b->consts, b->img, logl, logl64, c.shm, c.nt, st) !=
-            hipSuccess)
+    {
+        TimedLaunch tl(t, LENS_K_RENDER, st);
+        if (launch_batch_render(b->mi, b->grid_render, b->d_sys, b->d_items, b->n_items, b->d_counter,
+                                b->consts, b->img, st) != hipSuccess)
             return LENS_EHIP;
+    }
+    {
+        TimedLaunch tl(t, LENS_K_PSF, st);
+        for (const auto& c : b->classes)
+            if (launch_batch_psf(c.K, c.n, b->d_sys, c.items, b->consts, b->img, logl, logl64, c.shm, c.nt, st) !=
+                hipSuccess)
+                return LENS_EHIP;
+    }
     if (launch_set_int_host(b->d_counter + 1, 0, st) != hipSuccess) return LENS_EHIP;
-    if (launch_batch_adjoint(b->mi, b->grid_adjoint, b->d_sys, b->d_items, b->n_items,
-                             b->d_counter + 1, b->consts, b->img, b->partial, st) != hipSuccess)
-        return LENS_EHIP;
+    {
+        TimedLaunch tl(t, LENS_K_ADJOINT, st);
+        if (launch_batch_adjoint(b->mi, b->grid_adjoint, b->d_sys, b->d_items, b->n_items,
+                                 b->d_counter + 1, b->consts, b->img, b->partial, st) != hipSuccess)
+            return LENS_EHIP;
+    }
+    TimedLaunch tl(t, LENS_K_FINALIZE, st);
     if (launch_batch_finalize(b->mi, b->N, b->d_sys, b->d_particle_sys, theta, b->consts, b->partial,
                               grad, st) != hipSuccess)
         return LENS_EHIP;
@@ -184,6 +200,7 @@ lens_status lens_batch_plan_destroy(lens_batch_plan* b) {
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    b->timer.release();
     delete b;
     return LENS_OK;
 }
@@ -323,7 +340,9 @@ lens_status lens_batch_loglike_grad(lens_batch_plan* b, const float* d_theta, fl
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
             return LENS_EHIP;
+        b->timer.capturing = true;
         lens_status s = enqueue(b, d_theta, d_logl, d_grad, b->cap_stream);
+        b->timer.capturing = false;
         const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
         if (s != LENS_OK || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -426,7 +445,9 @@ lens_status lens_batch_map_adam(lens_batch_plan* b, float* d_u, float* d_m, floa
         b->map_key.clear();
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return LENS_EHIP;
+        b->timer.capturing = true;
         lens_status s = step(b->cap_stream);
+        b->timer.capturing = false;
         const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
         if (s != LENS_OK || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -459,6 +480,17 @@ lens_status lens_batch_argmin(lens_batch_plan* b, const float* d_val, float* d_b
 lens_status lens_batch_center_views(lens_batch_plan* b, int32_t side, float* d_out, void* stream) {
     if (!b || !d_out || side < 1 || side > LENS_MAX_SIDE) return LENS_EINVAL;
     return batch_hip(launch_center_views(b->S, side, b->d_views, d_out, (hipStream_t)stream));
+}
+
+lens_status lens_batch_enable_timing(lens_batch_plan* b, int32_t enable) {
+    if (!b) return LENS_EINVAL;
+    b->timer.enabled = enable != 0;
+    return LENS_OK;
+}
+
+lens_status lens_batch_read_timing(lens_batch_plan* b, double* h_ms, int64_t* h_count) {
+    if (!b || !h_ms || !h_count) return LENS_EINVAL;
+    return b->timer.read(h_ms, h_count);
 }
 
 }  // extern "C"

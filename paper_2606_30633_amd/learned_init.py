@@ -8,11 +8,14 @@ kernels (forward model, network training and inference, proposals, prior
 draws, bijection, posterior, Adam, per-system best); this module sequences
 the calls, shuffles indices and keeps the bookkeeping.
 
-Regressed parameters (14): the 8 mass parameters (theta_E, gamma, e1, e2,
-x, y, shear g1, g2) and 6 lens-light shape parameters (R_e, n, e1, e2, x,
-y), i.e. the first 14 of the 22 parameters of the EPL + shear + one Sersic
-lens light + one Sersic source model; lens amplitude and the 7 source
-parameters are drawn from the prior.
+Regressed parameters (14 of the 22 of the EPL + shear + one Sersic lens
+light + one Sersic source model, TARGET_IDX): theta_E, gamma, the mass
+ellipticity (e1, e2), the external shear (g1, g2), the lens light's R_e and
+n, and the source's R_e, n, e1, e2, x, y.  The source position is what
+makes the MAP objective multi-modal, so the network's proposals matter most
+there; the parameters left to the prior (mass centre, lens-light
+ellipticity and centre, both intensities) have tight priors or, for the
+intensities, an objective that gradient descent handles from any start.
 
 Time-to-MAP of a system (per arm): wall-clock from the start of the arm
 (network inference and proposals included, plan creation excluded) until
@@ -36,6 +39,8 @@ import torch
 from . import lens, synth
 
 N_TARGETS = 14
+# columns of the 22-parameter vector regressed by the network (network output k -> parameter TARGET_IDX[k])
+TARGET_IDX = np.array([0, 1, 2, 3, 6, 7, 8, 9, 15, 16, 17, 18, 19, 20])
 SIDE = 64
 SIGMA = synth.SIGMA_NOISE
 
@@ -69,7 +74,7 @@ def simulate(n: int, seed: int, device, chunk: int = 8192):
 
 
 def target_standardization(theta: np.ndarray):
-    t = theta[:, :N_TARGETS].astype(np.float64)
+    t = theta[:, TARGET_IDX].astype(np.float64)
     return t.mean(axis=0).astype(np.float32), t.std(axis=0).astype(np.float32)
 
 
@@ -93,7 +98,7 @@ def train(net: lens.Cnn, images: torch.Tensor, theta: np.ndarray, mean, std, epo
     every pass (Philox, counter = image draw index)."""
     dev = images.device
     n = images.shape[0]
-    tgt = torch.tensor((theta[:, :N_TARGETS] - mean) / std, dtype=torch.float32, device=dev)
+    tgt = torch.tensor((theta[:, TARGET_IDX] - mean) / std, dtype=torch.float32, device=dev)
     xb = torch.empty((batch, SIDE, SIDE), dtype=torch.bfloat16, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     steps = max(1, n // batch)
@@ -138,7 +143,7 @@ def evaluate(net: lens.Cnn, images: torch.Tensor, theta: np.ndarray, mean, std, 
         xb = net.prepare(images[i:j], SIGMA, add_noise=True, seed=seed, counter0=i * SIDE * SIDE)
         outs.append(net.forward(xb))
     out = torch.cat(outs).double().cpu().numpy()
-    z = (theta[:, :N_TARGETS].astype(np.float64) - mean) / std
+    z = (theta[:, TARGET_IDX].astype(np.float64) - mean) / std
     mu, s = out[:, :N_TARGETS], out[:, N_TARGETS:]
     nll = float(np.mean(np.sum(0.5 * (z - mu) ** 2 * np.exp(-s) + 0.5 * s, axis=1)))
     rmse = np.sqrt(np.mean((z - mu) ** 2, axis=0))
@@ -148,7 +153,7 @@ def evaluate(net: lens.Cnn, images: torch.Tensor, theta: np.ndarray, mean, std, 
 def configure(net: lens.Cnn, mean, std):
     table = synth.prior_table(synth.paper_prior_dists())
     slot = np.full(table.shape[0], -1, np.int32)
-    slot[:N_TARGETS] = np.arange(N_TARGETS)
+    slot[TARGET_IDX] = np.arange(N_TARGETS)
     net.set_target_map(table, slot, mean, std, SIGMA)
     return table
 

@@ -96,6 +96,8 @@ _SIGNATURES = {
     "lens_cnn_set_target_map": (_I, [_P, _I, _P, _P, _P, _P, ctypes.c_float]),
     "init_propose": (_I, [_P, _I, _P, _I, ctypes.c_uint64, _P, _P, _P]),
     "lens_plan_enable_timing": (_I, [_P, _I]),
+    "lens_batch_enable_timing": (_I, [_P, _I]),
+    "lens_batch_read_timing": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "lens_plan_read_timing": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 
@@ -589,6 +591,16 @@ class BatchPlan:
     def set_tiles(self, ppt):
         arr = (ctypes.c_int32 * self.S)(*[int(x) for x in ppt])
         _check(_lib.lens_batch_set_tiles(self.handle, arr), "lens_batch_set_tiles")
+
+    def enable_timing(self, on: bool = True):
+        _check(_lib.lens_batch_enable_timing(self.handle, 1 if on else 0), "lens_batch_enable_timing")
+
+    def read_timing(self):
+        """{kernel: (total_ms, launches)} since the last read; synchronises."""
+        ms = (ctypes.c_double * NUM_KERNEL_SLOTS)()
+        cnt = (ctypes.c_int64 * NUM_KERNEL_SLOTS)()
+        _check(_lib.lens_batch_read_timing(self.handle, ms, cnt), "lens_batch_read_timing")
+        return {name: (ms[k], cnt[k]) for k, name in enumerate(KERNEL_SLOTS)}
 
     def autotune(self, theta, cache_path=None, stream=None):
         self._rows(theta, "theta")

@@ -51,6 +51,16 @@ def test_target_standardization_uses_the_regressed_columns():
     rng = np.random.default_rng(1)
     th = rng.normal(size=(5000, 22)) * np.arange(1, 23) + np.arange(22)
     mean, std = target_standardization(th.astype(np.float32))
+    cols = np.array([0, 1, 2, 3, 6, 7, 8, 9, 15, 16, 17, 18, 19, 20])
     assert mean.shape == (14,) and std.shape == (14,)
-    assert np.all(np.abs(mean - np.arange(14)) <= 0.1 * np.arange(1, 15))
-    np.testing.assert_allclose(std, np.arange(1, 15), rtol=0.05)
+    assert np.all(np.abs(mean - cols) <= 0.1 * (cols + 1))
+    np.testing.assert_allclose(std, cols + 1, rtol=0.05)
+
+
+def test_regressed_columns_are_the_named_parameters():
+    from paper_2606_30633_amd import synth
+    from paper_2606_30633_amd.learned_init import TARGET_IDX
+    names = synth.paper_spec(64, 2, 21).param_names()
+    assert [names[j] for j in TARGET_IDX] == [
+        "theta_E", "gamma", "m_e1", "m_e2", "g1", "g2", "l0_R_e", "l0_n",
+        "s0_R_e", "s0_n", "s0_e1", "s0_e2", "s0_x", "s0_y"]
