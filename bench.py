@@ -49,6 +49,7 @@ def parse():
                          "batch: 100 uneven systems x 512 particles; cnn: network training; parity: the small "
                          "60x60 parity system (64 particles), GPU and oracle rates for information; large: "
                          "one MAP step on a 1000x1000 px cutout (s=2, 21x21 PSF, tiled PSF stage), 128 particles")
+    ap.add_argument("--cnn-batch", type=int, default=1024, help="batch of the cnn workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB (plain copy kernel, "
                          "for scaling HBM byte counters)")
@@ -698,7 +699,7 @@ def run_cnn(args):
     from paper_2606_30633_amd import lens, synth
     from paper_2606_30633_amd.learned_init import simulate, target_standardization, SIGMA, TARGET_IDX
     dev = torch.device("cuda", 0)
-    B = 256
+    B = args.cnn_batch
     theta, images = simulate(B * 16, synth.SEED_CNN_TRAIN, dev)
     mean, std = target_standardization(theta)
     tgt = torch.tensor((theta[:, TARGET_IDX] - mean) / std, dtype=torch.float32, device=dev)
@@ -726,7 +727,7 @@ def run_cnn(args):
     achieved = train * B / dt / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": 2500.0, "unit": "TFLOP/s",
             "frac": round(achieved / 2500.0, 5), "traffic": None, "kernel": "training step (all kernels)"}
-    _line(args, B / dt, "images/s", dt * 1e3, "learned-initializer network training, batch 256, 64x64 bf16",
+    _line(args, B / dt, "images/s", dt * 1e3, f"learned-initializer network training, batch {B}, 64x64 bf16",
           {"batch": B, "gflop_per_image_train": round(train / 1e9, 4)}, roof, dtype="bf16")
 
 

@@ -427,7 +427,20 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
                                    const float* const* h_invvar, const int32_t* h_particles,
                                    lens_batch_plan** out);
 lens_status lens_batch_plan_destroy(lens_batch_plan* plan);
+/* Current total particle count N (the sum of the current per-system counts). */
 int64_t lens_batch_total_particles(const lens_batch_plan* plan);
+
+/* Per-call particle counts (Sec. 4.2: each system carries its own number of
+ * particles).  h_particles [S] host, 1 <= h_particles[k] <= the count given
+ * to lens_batch_plan_create for system k (the buffers' capacity).  Later
+ * calls pack parameters, logL and gradients by the new counts, as described
+ * at lens_batch_plan_create; the work list and PSF launch classes are rebuilt
+ * on the host (synchronous: waits for the device), and every captured graph
+ * of the plan is re-captured on its next use.  The Adam step counter of
+ * lens_batch_map_adam is kept.  Equal counts return at once.
+ * Errors: LENS_EINVAL (NULL, or a count out of range), LENS_ENOMEM, LENS_EHIP. */
+lens_status lens_batch_set_particles(lens_batch_plan* plan, const int32_t* h_particles);
+lens_status lens_batch_get_particles(const lens_batch_plan* plan, int32_t* h_particles);
 
 /* logL and dlogL/dtheta for every particle of every system.
  *   d_theta [N][d] in, d_logl [N] out, d_grad [N][d] out, N = total particles.
@@ -441,10 +454,13 @@ lens_status lens_batch_get_tiles(const lens_batch_plan* plan, int32_t* h_ppt);
 lens_status lens_batch_set_tiles(lens_batch_plan* plan, const int32_t* h_ppt);
 
 /* Autotuner: groups the systems into size classes (supersampling x image-side
- * bucket), tries tiles {1, 2, 4, 8} per class by coordinate descent, timing
- * full batch calls on d_theta with HIP events, and keeps the fastest.  If
- * cache_path is not NULL, a cached choice for the same batch geometry is used
- * without timing, and a new choice is written there (JSON).  Synchronous. */
+ * bucket), tries tiles {1, 2, 4, 8} per class by coordinate descent, then the
+ * work-group size {256, 512, 1024} of each PSF launch (one per PSF size and
+ * LDS tile class), timing full batch calls on d_theta with HIP events, and
+ * keeps the fastest.  If cache_path is not NULL, a cached choice for the same
+ * batch geometry (image sizes, PSF sizes and particle counts) is used without
+ * timing, and a new choice is written there (JSON: the tile of each system,
+ * then the work-group size of each PSF launch).  Synchronous. */
 lens_status lens_batch_autotune(lens_batch_plan* plan, const float* d_theta, const char* cache_path,
                                 void* stream);
 

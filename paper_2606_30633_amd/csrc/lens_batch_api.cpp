@@ -22,6 +22,7 @@ namespace {
 bool desc_ok(const lens_model_desc& d) { return desc_valid(&d); }
 
 struct PsfClass {
+    std::pair<int, int> key{0, 0};   // (K, images per CU by LDS)
     int K = 0;
     int n = 0;
     size_t shm = 0;
@@ -38,6 +39,7 @@ struct lens_batch_plan {
     ModelInfo mi{};
     std::vector<lens_model_desc> desc;
     std::vector<int> P, p0, ppt;
+    std::vector<int> Pcap;         // particles per system the buffers were sized for
     std::vector<const float*> psf, data, invvar;
     std::vector<double*> wflip;
     float* consts = nullptr;
@@ -49,6 +51,7 @@ struct lens_batch_plan {
     int* d_counter = nullptr;
     int* d_particle_sys = nullptr;
     std::vector<PsfClass> classes;
+    std::map<std::pair<int, int>, int> psf_nt;   // work-group size chosen by the autotuner, per class
     int grid_render = 0, grid_adjoint = 0;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -73,6 +76,21 @@ static void free_classes(lens_batch_plan* b) {
     for (auto& c : b->classes)
         if (c.items) (void)hipFree(c.items);
     b->classes.clear();
+}
+
+// Uploads the particle packing (the system of each particle, the first
+// particle of each system) for the current counts P.
+static lens_status upload_packing(lens_batch_plan* b) {
+    std::vector<int> psys(b->N);
+    for (int k = 0; k < b->S; ++k)
+        for (int p = 0; p < b->P[k]; ++p) psys[b->p0[k] + p] = k;
+    std::vector<int> p0(b->p0);
+    p0.push_back(b->N);
+    if (hipMemcpy(b->d_particle_sys, psys.data(), sizeof(int) * (size_t)b->N, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(b->d_p0, p0.data(), sizeof(int) * (size_t)(b->S + 1), hipMemcpyHostToDevice) != hipSuccess)
+        return LENS_EHIP;
+    return LENS_OK;
 }
 
 // (Re)builds descriptors and work lists for the current tiles.
@@ -123,23 +141,30 @@ static lens_status rebuild(lens_batch_plan* b) {
         hipMemcpy(b->d_sys, sys.data(), sizeof(BatchSys) * b->S, hipMemcpyHostToDevice) != hipSuccess)
         return LENS_EHIP;
 
-    // PSF size classes: one launch per distinct K over its (system, particle) pairs
+    // PSF classes: one launch per (K, LDS tile class) over its (system,
+    // particle) pairs.  The tile class is the number of an image's LDS tiles
+    // that fit one CU (1, 2, 3, 4 or more), so that small images are not
+    // given the LDS, hence the CU, that the largest image of their K needs.
     free_classes(b);
-    std::map<int, std::vector<WorkItem>> byK;
-    std::map<int, size_t> shm;
-    std::map<int, int> strips;
+    std::map<std::pair<int, int>, std::vector<WorkItem>> byK;
+    std::map<std::pair<int, int>, size_t> shm;
+    std::map<std::pair<int, int>, int> strips;
     for (int k = 0; k < b->S; ++k) {
-        for (int p = 0; p < b->P[k]; ++p) byK[sys[k].K].push_back({k, p, 0});
         const size_t bytes = (size_t)sys[k].stride * sys[k].rows * sizeof(float);
-        shm[sys[k].K] = std::max(shm[sys[k].K], bytes);
-        strips[sys[k].K] = std::max(strips[sys[k].K], psf_strips(sys[k].g));
+        const int fit = std::min<int>(4, std::max<int>(1, (int)((160 * 1024) / bytes)));
+        const std::pair<int, int> key{sys[k].K, fit};
+        for (int p = 0; p < b->P[k]; ++p) byK[key].push_back({k, p, 0});
+        shm[key] = std::max(shm[key], bytes);
+        strips[key] = std::max(strips[key], psf_strips(sys[k].g));
     }
     for (auto& kv : byK) {
         PsfClass c;
-        c.K = kv.first;
+        c.K = kv.first.first;
         c.n = (int)kv.second.size();
         c.shm = shm[kv.first];
-        c.nt = psf_threads(c.shm, strips[kv.first]);
+        c.key = kv.first;
+        const auto ov = b->psf_nt.find(kv.first);
+        c.nt = ov != b->psf_nt.end() ? ov->second : psf_threads(c.shm, strips[kv.first]);
         if (hipMalloc(&c.items, sizeof(WorkItem) * c.n) != hipSuccess) return LENS_ENOMEM;
         b->classes.push_back(c);
         if (hipMemcpy(c.items, kv.second.data(), sizeof(WorkItem) * c.n, hipMemcpyHostToDevice) !=
@@ -230,6 +255,7 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
     for (int k = 0; k < S; ++k) {
         b->desc.push_back(h_descs[k]);
         b->P.push_back(h_particles[k]);
+        b->Pcap.push_back(h_particles[k]);
         b->p0.push_back((int)N);
         b->ppt.push_back(4);
         b->psf.push_back(h_psf[k]);
@@ -246,9 +272,6 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
     }
     b->N = (int)N;
     const int nacc = n_acc(b->mi);
-    std::vector<int> psys(N);
-    for (int k = 0; k < S; ++k)
-        for (int p = 0; p < b->P[k]; ++p) psys[b->p0[k] + p] = k;
     b->wflip.assign(S, nullptr);
     bool ok = hipMalloc(&b->consts, sizeof(float) * CSTRIDE * (size_t)N) == hipSuccess &&
               hipMalloc(&b->img, sizeof(float) * (size_t)npix_tot) == hipSuccess &&
@@ -277,13 +300,9 @@ lens_status lens_batch_plan_create(int32_t S, const lens_model_desc* h_descs,
             lens_batch_plan_destroy(b);
             return LENS_EHIP;
         }
-    std::vector<int> p0(b->p0);
-    p0.push_back((int)N);
     std::vector<ViewSrc> views(S);
     for (int k = 0; k < S; ++k) views[k] = {h_data[k], h_descs[k].nx, h_descs[k].ny};
-    if (hipMemcpy(b->d_particle_sys, psys.data(), sizeof(int) * (size_t)N, hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(b->d_p0, p0.data(), sizeof(int) * (size_t)(S + 1), hipMemcpyHostToDevice) != hipSuccess ||
+    if (upload_packing(b) != LENS_OK ||
         hipMemcpy(b->d_views, views.data(), sizeof(ViewSrc) * (size_t)S, hipMemcpyHostToDevice) !=
             hipSuccess ||
         launch_set_int(b->map_step, 0, nullptr) != hipSuccess ||
@@ -325,6 +344,31 @@ lens_status lens_batch_set_tiles(lens_batch_plan* b, const int32_t* h_ppt) {
     if (hipDeviceSynchronize() != hipSuccess) return LENS_EHIP;
     for (int k = 0; k < b->S; ++k) b->ppt[k] = h_ppt[k];
     return rebuild(b);
+}
+
+lens_status lens_batch_set_particles(lens_batch_plan* b, const int32_t* h_particles) {
+    if (!b || !h_particles) return LENS_EINVAL;
+    for (int k = 0; k < b->S; ++k)
+        if (h_particles[k] < 1 || h_particles[k] > b->Pcap[k]) return LENS_EINVAL;
+    bool same = true;
+    for (int k = 0; k < b->S; ++k) same = same && b->P[k] == h_particles[k];
+    if (same) return LENS_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return LENS_EHIP;
+    int n = 0;
+    for (int k = 0; k < b->S; ++k) {
+        b->P[k] = h_particles[k];
+        b->p0[k] = n;
+        n += h_particles[k];
+    }
+    b->N = n;
+    const lens_status s = upload_packing(b);
+    return s != LENS_OK ? s : rebuild(b);
+}
+
+lens_status lens_batch_get_particles(const lens_batch_plan* b, int32_t* h_particles) {
+    if (!b || !h_particles) return LENS_EINVAL;
+    for (int k = 0; k < b->S; ++k) h_particles[k] = b->P[k];
+    return LENS_OK;
 }
 
 lens_status lens_batch_loglike_grad(lens_batch_plan* b, const float* d_theta, float* d_logl,
@@ -500,6 +544,20 @@ lens_status lens_batch_read_timing(lens_batch_plan* b, double* h_ms, int64_t* h_
 // ---------------------------------------------------------------------------
 namespace {
 
+// Work-group size of each PSF launch class (in the order of b->classes);
+// captured graphs are re-captured on their next use.
+lens_status set_psf_threads(lens_batch_plan* b, const std::vector<int>& nts) {
+    if (nts.size() != b->classes.size()) return LENS_EINVAL;
+    for (int nt : nts)
+        if (nt != 256 && nt != 512 && nt != 1024) return LENS_EINVAL;
+    for (size_t i = 0; i < nts.size(); ++i) {
+        b->classes[i].nt = nts[i];
+        b->psf_nt[b->classes[i].key] = nts[i];
+    }
+    b->tiles_version++;
+    return LENS_OK;
+}
+
 uint64_t geometry_hash(const lens_batch_plan* b) {
     uint64_t h = 1469598103934665603ull;   // FNV-1a over the batch geometry
     auto mix = [&](uint64_t v) {
@@ -521,7 +579,7 @@ uint64_t geometry_hash(const lens_batch_plan* b) {
     return h;
 }
 
-// Cache file: {"<hex hash>": [ppt, ppt, ...], ...}
+// Cache file: {"<hex hash>": [ppt per system..., PSF work-group size per class...], ...}
 std::map<std::string, std::vector<int>> read_cache(const char* path) {
     std::map<std::string, std::vector<int>> out;
     FILE* f = std::fopen(path, "r");
@@ -584,7 +642,13 @@ extern "C" lens_status lens_batch_autotune(lens_batch_plan* b, const float* d_th
     if (cache_path) {
         cache = read_cache(cache_path);
         auto it = cache.find(key);
-        if (it != cache.end() && (int)it->second.size() == b->S) return lens_batch_set_tiles(b, it->second.data());
+        const int C = (int)b->classes.size();
+        if (it != cache.end() && ((int)it->second.size() == b->S || (int)it->second.size() == b->S + C)) {
+            const lens_status r = lens_batch_set_tiles(b, it->second.data());
+            if (r != LENS_OK || (int)it->second.size() == b->S) return r;
+            std::vector<int> nts(it->second.begin() + b->S, it->second.end());
+            return set_psf_threads(b, nts);
+        }
     }
     float* logl = nullptr;
     float* grad = nullptr;
@@ -637,12 +701,33 @@ extern "C" lens_status lens_batch_autotune(lens_batch_plan* b, const float* d_th
         for (int k : kv.second) cur[k] = keep;
     }
     if (s == LENS_OK) s = lens_batch_set_tiles(b, cur.data());
+    // then the work-group size of each PSF launch class, with the tiles fixed
+    std::vector<int> nts;
+    for (const auto& c : b->classes) nts.push_back(c.nt);
+    if (s == LENS_OK) best = time_once();
+    for (size_t i = 0; s == LENS_OK && i < nts.size(); ++i) {
+        int keep = nts[i];
+        for (int nt : {256, 512, 1024}) {
+            if (nt == keep) continue;
+            std::vector<int> trial = nts;
+            trial[i] = nt;
+            if ((s = set_psf_threads(b, trial)) != LENS_OK) break;
+            const float t = time_once();
+            if (t < best) {
+                best = t;
+                keep = nt;
+            }
+        }
+        nts[i] = keep;
+    }
+    if (s == LENS_OK) s = set_psf_threads(b, nts);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(logl);
     (void)hipFree(grad);
     if (s == LENS_OK && cache_path) {
         cache[key] = cur;
+        cache[key].insert(cache[key].end(), nts.begin(), nts.end());
         if (!write_cache(cache_path, cache)) return LENS_EINVAL;
     }
     return s;

@@ -60,6 +60,13 @@ struct CnnNet {
     double* losspart;
     CnnTargetMap* tmap;   // device copy
     __bf16* prep;         // prepared images for init_propose
+    __bf16* img_stage;    // [max_batch][64][64] the training batch (captured step)
+    float* tgt_stage;     // [max_batch][CNN_NT]
+    float* hyper;         // [2] learning rate, Adam step (device)
+    float* loss_dev;      // [1]
+    hipGraphExec_t train_graph;   // one captured training step (forward, backward, Adam)
+    int graph_batch;
+    hipStream_t cap_stream;
     int step;
     float sigma;
     bool has_map;
@@ -67,7 +74,9 @@ struct CnnNet {
 
 hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st);
 hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* target, float* loss, hipStream_t st);
-hipError_t cnn_adam(CnnNet& net, float lr, int step, hipStream_t st);
+// Adam with the learning rate and step of net.hyper (cnn_set_hyper).
+hipError_t cnn_adam(CnnNet& net, hipStream_t st);
+hipError_t cnn_set_hyper(CnnNet& net, float lr, int step, hipStream_t st);
 hipError_t cnn_init(CnnNet& net, uint64_t seed, hipStream_t st);
 hipError_t cnn_params_to_bf16(CnnNet& net, hipStream_t st);
 hipError_t cnn_prepare(long long n, const float* img, float sigma, int add_noise, uint64_t seed, uint64_t counter0,

@@ -255,6 +255,125 @@ __global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, i
             }
 }
 
+// Large tiles: 4 waves arranged WM x WN, each computing 64 x 64 outputs
+// (4 x 4 MFMA 16x16x32 tiles): 128 x 128 (2 x 2), 256 x 64 (4 x 1) or
+// 64 x 256 (1 x 4) per work-group.  Per MFMA a wave reads half a fragment
+// from LDS (8 fragments per 16 MFMAs) against three quarters with the 32-row
+// wave tiles above.
+template <class Op, int R>
+struct WideRegs {
+    bf16x8 v[R / 32];   // R rows x 64 k of one operand, 2 R / 64 chunks of 8 per thread
+};
+
+// rows x 64 k of one operand into registers: along K, chunk c = t + 256 h covers
+// row c / 8 at k 8 (c % 8); K-major, chunk c covers k c % 64 at rows 8 (c / 64).
+template <bool KMAJOR, int R, class F, class FT>
+__device__ __forceinline__ void wide_load(WideRegs<void, R>& r, int r0, int k0, int kend, int rows, F&& ld, FT&& ldt) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < R / 32; ++h) {
+        const int c = t + 256 * h;
+        if constexpr (KMAJOR) {
+            const int k = c & 63, rg = c >> 6;
+            r.v[h] = (k0 + k < kend) ? ldt(k0 + k, r0 + 8 * rg) : zero8();
+        } else {
+            const int row = c >> 3, kc = (c & 7) * 8;
+            r.v[h] = (r0 + row < rows) ? ld(r0 + row, k0 + kc, kend) : zero8();
+        }
+    }
+}
+
+template <bool KMAJOR, int R>
+__device__ __forceinline__ void wide_store(const WideRegs<void, R>& r, __bf16 (*S)[LDSK]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < R / 32; ++h) {
+        const int c = t + 256 * h;
+        if constexpr (KMAJOR) {
+            const int k = c & 63, rg = c >> 6;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) S[8 * rg + i][k] = r.v[h][i];
+        } else {
+            const int row = c >> 3, kc = (c & 7) * 8;
+            *reinterpret_cast<bf16x8*>(&S[row][kc]) = r.v[h];
+        }
+    }
+}
+
+template <class Op, int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, int k_per_split) {
+    constexpr int TM = 64 * WM, TN = 64 * WN;
+    __shared__ __attribute__((aligned(16))) __bf16 As[TM][LDSK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][LDSK];
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int kbeg = blockIdx.z * k_per_split;
+    const int kend = min(K, kbeg + k_per_split);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w / WN, wn = w % WN;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto la = [&](int m, int k, int ke) {
+        if constexpr (!Op::A_KMAJOR) return op.loadA(m, k, ke);
+        else return zero8();
+    };
+    auto lat = [&](int k, int m) {
+        if constexpr (Op::A_KMAJOR) return op.loadAT(k, m);
+        else return zero8();
+    };
+    auto lb = [&](int n, int k, int ke) {
+        if constexpr (!Op::B_KMAJOR) return op.loadB(k, n, ke);
+        else return zero8();
+    };
+    auto lbt = [&](int k, int n) {
+        if constexpr (Op::B_KMAJOR) return op.loadBT(k, n);
+        else return zero8();
+    };
+    WideRegs<void, TM> ra;
+    WideRegs<void, TN> rb;
+    if (kbeg < kend) {
+        wide_load<Op::A_KMAJOR, TM>(ra, m0, kbeg, kend, M, la, lat);
+        wide_load<Op::B_KMAJOR, TN>(rb, n0, kbeg, kend, N, lb, lbt);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        __syncthreads();
+        wide_store<Op::A_KMAJOR, TM>(ra, As);
+        wide_store<Op::B_KMAJOR, TN>(rb, Bs);
+        __syncthreads();
+        if (k0 + GK < kend) {
+            wide_load<Op::A_KMAJOR, TM>(ra, m0, k0 + GK, kend, M, la, lat);
+            wide_load<Op::B_KMAJOR, TN>(rb, n0, k0 + GK, kend, N, lb, lbt);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            bf16x8 av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                av[i] = *reinterpret_cast<const bf16x8*>(&As[64 * wm + 16 * i + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bv[j] = *reinterpret_cast<const bf16x8*>(&Bs[64 * wn + 16 * j + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + 64 * wm + 16 * i + 4 * (lane >> 4) + q;
+                const int n = n0 + 64 * wn + 16 * j + (lane & 15);
+                if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
+            }
+}
+
 // ---------------------------------------------------------------------------
 // Operand maps.  NHWC activations; conv weights W[co][ky][kx][ci] (row co of
 // length 9*Cin); fully connected W[out][in].  Every spatial size and channel
@@ -352,6 +471,54 @@ struct OpConvDgrad {
     }
     __device__ void store(int m, int n, float v, int) const {
         const size_t q = ((size_t)m << s.lCin) + n;
+        dprev[q] = to_bf16(from_bf16(prev[q]) > 0.0f ? v : 0.0f);
+    }
+};
+
+// data gradient of a stride-2 layer, one input-parity class (py, px) per
+// GEMM: input pixel (2 y' + py, 2 x' + px) receives output (y, x) only through
+// taps ky = 1 (py = 0) or ky in {0, 2} (py = 1), likewise kx, so each class
+// sums over 1, 2, 2 or 4 taps instead of 9 (the other taps meet no output).
+// A(m = (b, y', x'), k = (t, co)) = dZ[b, y, x, co] along K; B(k, n = ci) =
+// W[co][tap][ci]: K-major.  Output and ReLU mask as OpConvDgrad.
+struct OpConvDgradS2 {
+    static constexpr bool A_KMAJOR = false, B_KMAJOR = true;
+    ConvShape s;   // stride 2: H = 2 Ho
+    int py, px;
+    const __bf16* dz;
+    const __bf16* w;
+    const __bf16* prev;
+    __bf16* dprev;
+    __device__ __forceinline__ void tap(int t, int& ky, int& kx) const {
+        const int ntx = px ? 2 : 1;
+        const int ty = px ? (t >> 1) : t, tx = px ? (t & 1) : 0;
+        ky = py ? 2 * ty : 1;
+        kx = px ? 2 * tx : 1;
+        (void)ntx;
+    }
+    __device__ bf16x8 loadA(int m, int k, int kend) const {
+        if (k >= kend) return zero8();
+        const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
+        const int yq = r >> s.lWo, xq = r & (s.Wo - 1);
+        const int t = k >> s.lCout, co = k & (s.Cout - 1);
+        int ky, kx;
+        tap(t, ky, kx);
+        const int y = yq + ((py + 1 - ky) >> 1), x = xq + ((px + 1 - kx) >> 1);
+        if (y >= s.Ho || x >= s.Wo) return zero8();
+        return ld8(dz + ((((size_t)b << s.lWo) + y) << s.lWo) * s.Cout + ((size_t)x << s.lCout) + co);
+    }
+    __device__ bf16x8 loadBT(int k, int n) const {
+        if (n >= s.Cin) return zero8();
+        const int t = k >> s.lCout, co = k & (s.Cout - 1);
+        int ky, kx;
+        tap(t, ky, kx);
+        return ld8(w + (size_t)co * 9 * s.Cin + ((size_t)(3 * ky + kx) << s.lCin) + n);
+    }
+    __device__ void store(int m, int n, float v, int) const {
+        const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
+        const int yq = r >> s.lWo, xq = r & (s.Wo - 1);
+        const size_t pix = (((size_t)b << s.lW) + 2 * yq + py) * s.W + 2 * xq + px;
+        const size_t q = (pix << s.lCin) + n;
         dprev[q] = to_bf16(from_bf16(prev[q]) > 0.0f ? v : 0.0f);
     }
 };
@@ -479,6 +646,30 @@ template <class Op>
 static hipError_t gemm_tall(const Op& op, int M, int N, int K, hipStream_t st) {
     hipLaunchKernelGGL(k_gemm_tall<Op>, dim3((M + GT2 - 1) / GT2, (N + GT - 1) / GT, 1), dim3(256), 0, st, op, M,
                        N, K, K);
+    return hipGetLastError();
+}
+
+// Picks the tile for a GEMM shape: the 64 x 64-per-wave tiles where the
+// output is large enough in both directions to fill them, else the tall
+// (large M, no split) or the square 64 x 64 kernel.
+template <class Op>
+static hipError_t gemm_pick(const Op& op, int M, int N, int K, int splits, hipStream_t st) {
+    const int kps = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+    const int nz = (K + kps - 1) / kps;
+    if (M >= 128 && N >= 128) {
+        hipLaunchKernelGGL((k_gemm_wide<Op, 2, 2>), dim3((M + 127) / 128, (N + 127) / 128, nz), dim3(256), 0, st, op,
+                           M, N, K, kps);
+    } else if (N >= 64 && M >= 256) {
+        hipLaunchKernelGGL((k_gemm_wide<Op, 4, 1>), dim3((M + 255) / 256, (N + 63) / 64, nz), dim3(256), 0, st, op, M,
+                           N, K, kps);
+    } else if (M >= 64 && N >= 512) {
+        hipLaunchKernelGGL((k_gemm_wide<Op, 1, 4>), dim3((M + 63) / 64, (N + 255) / 256, nz), dim3(256), 0, st, op, M,
+                           N, K, kps);
+    } else if (nz == 1 && M >= 4096) {
+        return gemm_tall(op, M, N, K, st);
+    } else {
+        return gemm(op, M, N, K, splits, st);
+    }
     return hipGetLastError();
 }
 
@@ -630,11 +821,15 @@ __global__ void k_loss_final(int nb, int B, const double* __restrict__ part, flo
 }
 
 // Adam on the fp32 master parameters; refreshes the bf16 copies of weights.
+// The learning rate and the (1-based) step come from device memory
+// (hyper = {lr, step}), so that a captured training step serves every step.
 __global__ void k_cnn_adam(long long n, float* __restrict__ p, const float* __restrict__ g,
                            float* __restrict__ m, float* __restrict__ v, __bf16* __restrict__ pbf,
-                           float lr, float b1, float b2, float eps, int step) {
+                           const float* __restrict__ hyper, float b1, float b2, float eps) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const float lr = hyper[0];
+    const int step = (int)hyper[1];
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -750,7 +945,7 @@ hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st) {
         const CnnLayer& L = net.conv[l];
         const ConvShape s = conv_shape(B, H, L.cin, H / L.stride, L.cout, L.stride);
         OpConvFwd op{s, x, net.wbf + L.w_off, net.params + L.b_off, net.act[l]};
-        if (gemm_tall(op, B * s.Ho * s.Wo, L.cout, 9 * L.cin, st) != hipSuccess) return hipErrorLaunchFailure;
+        if (gemm_pick(op, B * s.Ho * s.Wo, L.cout, 9 * L.cin, 1, st) != hipSuccess) return hipErrorLaunchFailure;
         x = net.act[l];
         H = s.Ho;
     }
@@ -805,7 +1000,7 @@ hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* targ
         const int K = B * Hout * Hout;
         const int splits = gemm_splits(L.cout, 9 * L.cin, K, wgrad_splits(K));
         OpConvWgrad wg{s, net.dact[l], in, net.wpart};
-        if (gemm(wg, L.cout, 9 * L.cin, K, wgrad_splits(K), st) != hipSuccess) return hipErrorLaunchFailure;
+        if (gemm_pick(wg, L.cout, 9 * L.cin, K, wgrad_splits(K), st) != hipSuccess) return hipErrorLaunchFailure;
         const long long nw = (long long)L.cout * 9 * L.cin;
         if (splits >= 64)
             hipLaunchKernelGGL(k_sum_splits_wave, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, st, splits, nw,
@@ -813,18 +1008,37 @@ hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* targ
         else
             hipLaunchKernelGGL(k_sum_splits, g1(nw), dim3(256), 0, st, splits, nw, net.wpart, net.grads + L.w_off);
         if (bias_grad(net, K, L.cout, net.dact[l], net.grads + L.b_off, st) != hipSuccess) return hipErrorLaunchFailure;
-        if (l > 0) {
+        if (l > 0 && L.stride == 1) {
             OpConvDgrad dg{s, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};
-            if (gemm_tall(dg, B * H * H, L.cin, 9 * L.cout, st) != hipSuccess) return hipErrorLaunchFailure;
+            if (gemm_pick(dg, B * H * H, L.cin, 9 * L.cout, 1, st) != hipSuccess) return hipErrorLaunchFailure;
+        } else if (l > 0) {
+            // stride 2: the four input-parity classes, each over its 1, 2, 2 or 4 taps
+            for (int py = 0; py < 2; ++py)
+                for (int px = 0; px < 2; ++px) {
+                    OpConvDgradS2 dg{s, py, px, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};
+                    const int ntap = (py ? 2 : 1) * (px ? 2 : 1);
+                    if (gemm_pick(dg, B * Hout * Hout, L.cin, ntap * L.cout, 1, st) != hipSuccess)
+                        return hipErrorLaunchFailure;
+                }
         }
         Hout = H;
     }
     return hipGetLastError();
 }
 
-hipError_t cnn_adam(CnnNet& net, float lr, int step, hipStream_t st) {
+__global__ void k_set_hyper(float* __restrict__ hyper, float lr, int step) {
+    hyper[0] = lr;
+    hyper[1] = (float)step;
+}
+
+hipError_t cnn_set_hyper(CnnNet& net, float lr, int step, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_hyper, dim3(1), dim3(1), 0, st, net.hyper, lr, step);
+    return hipGetLastError();
+}
+
+hipError_t cnn_adam(CnnNet& net, hipStream_t st) {
     hipLaunchKernelGGL(k_cnn_adam, g1(net.nparams), dim3(256), 0, st, (long long)net.nparams, net.params, net.grads,
-                       net.adam_m, net.adam_v, net.wbf, lr, 0.9f, 0.999f, 1e-8f, step);
+                       net.adam_m, net.adam_v, net.wbf, (const float*)net.hyper, 0.9f, 0.999f, 1e-8f);
     return hipGetLastError();
 }
 

@@ -55,8 +55,11 @@ int64_t lens_cnn_num_params(void) {
 lens_status lens_cnn_destroy(lens_cnn* c) {
     if (!c) return LENS_EINVAL;
     CnnNet& n = c->net;
+    if (n.train_graph) (void)hipGraphExecDestroy(n.train_graph);
+    if (n.cap_stream) (void)hipStreamDestroy(n.cap_stream);
     void* bufs[] = {n.params, n.grads, n.adam_m, n.adam_v, n.wbf, n.pooled, n.dpooled, n.hidden, n.dhidden, n.out,
-                    n.dout, n.wpart, n.colpart, n.losspart, n.tmap, n.prep};
+                    n.dout, n.wpart, n.colpart, n.losspart, n.tmap, n.prep, n.img_stage, n.tgt_stage, n.hyper,
+                    n.loss_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 0; l < CNN_CONV; ++l) {
@@ -91,7 +94,9 @@ lens_status lens_cnn_create(int32_t max_batch, uint64_t seed, lens_cnn** out) {
     ok = ok && alloc(&n.pooled, B * CNN_C6) && alloc(&n.dpooled, B * CNN_C6) && alloc(&n.hidden, B * CNN_H1) &&
          alloc(&n.dhidden, B * CNN_H1) && alloc(&n.out, B * CNN_OUT) && alloc(&n.dout, B * CNN_OUT) &&
          alloc(&n.wpart, wpart) && alloc(&n.colpart, (B * CNN_IN * CNN_IN / 4096 + 1) * 256) &&
-         alloc(&n.losspart, B / 256 + 1) && alloc(&n.tmap, 1) && alloc(&n.prep, B * CNN_IN * CNN_IN);
+         alloc(&n.losspart, B / 256 + 1) && alloc(&n.tmap, 1) && alloc(&n.prep, B * CNN_IN * CNN_IN) &&
+         alloc(&n.img_stage, B * CNN_IN * CNN_IN) && alloc(&n.tgt_stage, B * CNN_NT) && alloc(&n.hyper, 2) &&
+         alloc(&n.loss_dev, 1) && hipStreamCreateWithFlags(&n.cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         lens_cnn_destroy(c);
         return LENS_ENOMEM;
@@ -159,11 +164,43 @@ lens_status lens_cnn_loss_grad(lens_cnn* c, int32_t B, const uint16_t* d_img, co
 
 lens_status lens_cnn_train_step(lens_cnn* c, int32_t B, const uint16_t* d_img, const float* d_target, float lr,
                                 float* d_loss, void* stream) {
-    if (!c || !(lr > 0.0f)) return LENS_EINVAL;
-    lens_status s = lens_cnn_loss_grad(c, B, d_img, d_target, d_loss, nullptr, stream);
-    if (s != LENS_OK) return s;
-    c->net.step += 1;
-    return cnn_adam(c->net, lr, c->net.step, (hipStream_t)stream) == hipSuccess ? LENS_OK : LENS_EHIP;
+    if (!c || !d_img || !d_target || !d_loss || !(lr > 0.0f) || B < 1 || B > c->net.max_batch) return LENS_EINVAL;
+    CnnNet& n = c->net;
+    hipStream_t st = (hipStream_t)stream;
+    // the batch, the targets, the learning rate and the step go to net-owned
+    // device memory (outside the graph); one captured step per batch size
+    n.step += 1;
+    if (hipMemcpyAsync(n.img_stage, d_img, sizeof(uint16_t) * B * CNN_IN * CNN_IN, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(n.tgt_stage, d_target, sizeof(float) * B * CNN_NT, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess ||
+        cnn_set_hyper(n, lr, n.step, st) != hipSuccess)
+        return LENS_EHIP;
+    if (!n.train_graph || n.graph_batch != B) {
+        if (n.train_graph) (void)hipGraphExecDestroy(n.train_graph);
+        n.train_graph = nullptr;
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(n.cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return LENS_EHIP;
+        const hipError_t e1 = cnn_forward(n, B, n.img_stage, n.cap_stream);
+        const hipError_t e2 = e1 == hipSuccess ? cnn_backward(n, B, n.img_stage, n.tgt_stage, n.loss_dev, n.cap_stream)
+                                               : e1;
+        const hipError_t e3 = e2 == hipSuccess ? cnn_adam(n, n.cap_stream) : e2;
+        const hipError_t ec = hipStreamEndCapture(n.cap_stream, &g);
+        if (e3 != hipSuccess || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return LENS_EHIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&n.train_graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            n.train_graph = nullptr;
+            return LENS_EHIP;
+        }
+        n.graph_batch = B;
+    }
+    if (hipGraphLaunch(n.train_graph, st) != hipSuccess) return LENS_EHIP;
+    return hipMemcpyAsync(d_loss, n.loss_dev, sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess ? LENS_OK
+                                                                                                        : LENS_EHIP;
 }
 
 lens_status lens_cnn_set_target_map(lens_cnn* c, int32_t d, const float* h_prior_table, const int32_t* h_slot,

@@ -916,6 +916,9 @@ __device__ __forceinline__ void correlate(const float* lds, int stride, int i, i
     constexpr int NQ = (RW + K - 1 + 3) / 4;
 #pragma unroll
     for (int r = 0; r < RW; ++r) m[r] = (T)0;
+    // rows stay a loop: unrolled (small K) the compiler would hoist all K^2
+    // taps into registers for the whole strip loop
+#pragma unroll 1
     for (int u = 0; u < K; ++u) {
         const float4* row = reinterpret_cast<const float4*>(lds + (i + u) * stride + j0);
         T seg[4 * NQ];
@@ -1027,8 +1030,11 @@ __device__ __forceinline__ void psf_body(float valid, const Geo& g, float* buf,
     __syncthreads();
 }
 
+// At most 128 VGPRs (four waves per SIMD): with a small K and 256 threads
+// the compiler would otherwise keep all K^2 float64 taps in registers and
+// run one wave per SIMD.
 template <int K, int MODE, int NT>
-__global__ __launch_bounds__(NT) void k_psf(const float* __restrict__ consts, Geo g, float* img,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_psf(const float* __restrict__ consts, Geo g, float* img,
                                              const double* __restrict__ wflip,
                                              const float* __restrict__ wpsf,
                                              const float* __restrict__ data,
@@ -1199,7 +1205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
 // One work-group per (system, particle) of one PSF size class.
 template <int K, int NT>
-__global__ __launch_bounds__(NT) void k_batch_psf(const BatchSys* __restrict__ sys,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_psf(const BatchSys* __restrict__ sys,
                                                    const WorkItem* __restrict__ items,
                                                    const float* __restrict__ consts, float* img,
                                                    float* logl, double* logl64) {

@@ -70,6 +70,8 @@ _SIGNATURES = {
     "lens_batch_plan_create": (_I, [_I, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "lens_batch_plan_destroy": (_I, [_P]),
     "lens_batch_total_particles": (ctypes.c_int64, [_P]),
+    "lens_batch_set_particles": (_I, [_P, _P]),
+    "lens_batch_get_particles": (_I, [_P, _P]),
     "lens_batch_loglike_grad": (_I, [_P, _P, _P, _P, _I, _P]),
     "lens_batch_get_tiles": (_I, [_P, _P]),
     "lens_batch_set_tiles": (_I, [_P, _P]),
@@ -555,6 +557,7 @@ class BatchPlan:
         _check(_lib.lens_batch_plan_create(S, descs, self._keep[1], self._keep[2], self._keep[3],
                                            self._keep[4], ctypes.byref(handle)), "lens_batch_plan_create")
         self.handle = handle
+        self.capacity = list(self.particles)
         self.S = S
         self.N = int(_lib.lens_batch_total_particles(handle))
 
@@ -582,6 +585,23 @@ class BatchPlan:
         _check(_lib.lens_batch_loglike_grad(self.handle, theta.data_ptr(), logl.data_ptr(), grad.data_ptr(),
                                             1 if use_graph else 0, _stream(stream)), "lens_batch_loglike_grad")
         return logl, grad
+
+    def set_particles(self, particles):
+        """Per-call particle counts, each in [1, the count the plan was created with]."""
+        if len(particles) != self.S:
+            raise ValueError(f"particles must have {self.S} entries")
+        for k, n in enumerate(particles):
+            if not 1 <= int(n) <= self.capacity[k]:
+                raise ValueError(f"system {k}: particles must be in [1, {self.capacity[k]}]")
+        arr = (ctypes.c_int32 * self.S)(*[int(n) for n in particles])
+        _check(_lib.lens_batch_set_particles(self.handle, arr), "lens_batch_set_particles")
+        self.particles = [int(n) for n in particles]
+        self.N = int(_lib.lens_batch_total_particles(self.handle))
+
+    def get_particles(self):
+        out = (ctypes.c_int32 * self.S)()
+        _check(_lib.lens_batch_get_particles(self.handle, out), "lens_batch_get_particles")
+        return list(out)
 
     def get_tiles(self):
         out = (ctypes.c_int32 * self.S)()

@@ -75,6 +75,40 @@ def test_batch_graph_replays_and_tiles():
     torch.testing.assert_close(G2, Ge, rtol=2e-6, atol=1e-6 * float(Ge.abs().max()))
 
 
+def test_batch_per_call_particle_counts():
+    """lens_batch_set_particles: fewer particles per system than the plan was
+    created with, then back up; each call equals a plan created with those
+    counts bit for bit (eager and graph), and segment operations follow."""
+    specs, cases = _batch(seed=7, particles=(9, 4, 12, 6, 7, 5))
+    args = ([c[1] for c in cases], [c[2] for c in cases], [c[0].invvar for c in cases])
+    full = [c[3] for c in cases]
+    bp = lens.BatchPlan(specs, *args, [t.shape[0] for t in full], DEV)
+    Lg, Gg = None, None
+    for counts in ([3, 1, 12, 2, 7, 5], [1, 1, 1, 1, 1, 1], [9, 4, 12, 6, 7, 5], [5, 4, 2, 6, 1, 3]):
+        print("counts", counts, flush=True)
+        bp.set_particles(counts)
+        assert bp.get_particles() == counts and bp.N == sum(counts)
+        th = np.concatenate([t[:n] for t, n in zip(full, counts)])
+        tt = torch.tensor(th, device=DEV)
+        Le, Ge = bp.loglike_grad(tt)
+        Lg, Gg = torch.full_like(Le, np.nan), torch.full_like(Ge, np.nan)
+        bp.loglike_grad(tt, Lg, Gg, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(Lg, Le) and torch.equal(Gg, Ge)
+        ref = lens.BatchPlan(specs, *args, counts, DEV)
+        Lr, Gr = ref.loglike_grad(tt)
+        assert torch.equal(Lr, Le) and torch.equal(Gr, Ge)
+        best, arg = bp.argmin(-Le)
+        off = 0
+        Ln = Le.cpu().numpy()
+        for k, n in enumerate(counts):
+            i = int(np.argmax(Ln[off:off + n]))
+            assert int(arg[k]) == off + i
+            off += n
+    with pytest.raises(ValueError):
+        bp.set_particles([10, 4, 12, 6, 7, 5])       # above the capacity of system 0
+
+
 def test_autotune_and_cache(tmp_path):
     specs, cases = _batch(seed=2)
     bp = lens.BatchPlan(specs, [c[1] for c in cases], [c[2] for c in cases], [c[0].invvar for c in cases],
@@ -83,8 +117,9 @@ def test_autotune_and_cache(tmp_path):
     path = tmp_path / "tiles.json"
     tiles = bp.autotune(tt, path)
     assert all(t in (1, 2, 4, 8) for t in tiles)
-    cached = json.loads(path.read_text())
-    assert list(cached.values())[0] == tiles
+    cached = list(json.loads(path.read_text()).values())[0]
+    assert cached[:len(tiles)] == tiles
+    assert len(cached) > len(tiles) and all(nt in (256, 512, 1024) for nt in cached[len(tiles):])
     bp.set_tiles([4] * len(tiles))
     assert bp.autotune(tt, path) == tiles        # read back from the cache
     L, G = bp.loglike_grad(tt)
