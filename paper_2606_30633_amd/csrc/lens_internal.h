@@ -24,14 +24,15 @@ constexpr int D_UA = 12;      // U = (w - eps conj(w)) / (1 + |eps|):
 constexpr int D_UB = 14;      //   Ux = UA wx - UE wy,  Uy = UB wy - UE wx
 constexpr int D_UE = 16;
 constexpr int D_C0 = 18;      // theta_E sqrt(1 - c^2)  (= 2b/(1+q))
-constexpr int D_K0 = 20;      // (t-1) log2 b
-constexpr int D_K1 = 22;      // (t-1)/2
+constexpr int D_K0 = 20;      // 256 (t-1) log2 b   (exponent constants carry a factor 256:
+constexpr int D_K1 = 22;      // 256 (t-1)/2         the float64 exp2 takes 256 v)
 constexpr int D_G1 = 24;      // external shear
 constexpr int D_G2 = 26;
 constexpr int C_SERS = 32;    // Sersic components: SERS_STRIDE words each, float64 fields
 constexpr int SERS_STRIDE = 24;
 constexpr int S_XC = 0, S_YC = 2, S_A11 = 4, S_A12 = 6, S_A22 = 8, S_IE = 10,
-              S_KU = 12, S_KU0 = 14, S_BL = 16;   // float64 (word offsets)
+              S_KU = 12, S_KU0 = 14, S_BL = 16;   // float64 (word offsets); KU = 256/(2n),
+                                                  // KU0 = -256 log2(R_e)/n, BL = 256 b_n/ln 2
 constexpr int S_KAP2 = 18;                         // float32
 constexpr int S_A12X2 = 20;                        // float64: 2 a12
 constexpr int MAX_COMP = LENS_MAX_LENS_LIGHT + LENS_MAX_SOURCE;

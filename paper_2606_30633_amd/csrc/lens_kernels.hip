@@ -95,7 +95,10 @@ __device__ __forceinline__ SersicK load_sersic(const float* __restrict__ S) {
     q.ie = ldd(S, S_IE); q.ku = ldd(S, S_KU); q.ku0 = ldd(S, S_KU0); q.bl = ldd(S, S_BL);
     q.a12x2 = ldd(S, S_A12X2);
     q.a11f = (float)q.a11; q.a12f = (float)q.a12; q.a22f = (float)q.a22;
-    q.ief = (float)q.ie; q.kuf = (float)q.ku; q.ku0f = (float)q.ku0; q.blf = (float)q.bl;
+    // the exponent constants are stored times 256 (exp2_256); the float32
+    // copies undo the power-of-two factor exactly
+    q.ief = (float)q.ie; q.kuf = (float)(q.ku * (1.0 / 256.0)); q.ku0f = (float)(q.ku0 * (1.0 / 256.0));
+    q.blf = (float)(q.bl * (1.0 / 256.0));
     q.kap2 = ldf(S, S_KAP2);
     return q;
 }
@@ -106,7 +109,7 @@ __device__ __forceinline__ PK<NC> load_pk(const float* __restrict__ C) {
     k.x0 = ldd(C, D_X0); k.y0 = ldd(C, D_Y0); k.e1 = ldd(C, D_E1); k.e2 = ldd(C, D_E2);
     k.ua = ldd(C, D_UA); k.ub = ldd(C, D_UB); k.ue = ldd(C, D_UE); k.c0 = ldd(C, D_C0);
     k.k0 = ldd(C, D_K0); k.k1 = ldd(C, D_K1); k.g1 = ldd(C, D_G1); k.g2 = ldd(C, D_G2);
-    k.e1f = (float)k.e1; k.e2f = (float)k.e2; k.k1f = (float)k.k1;
+    k.e1f = (float)k.e1; k.e2f = (float)k.e2; k.k1f = (float)(k.k1 * (1.0 / 256.0));
     k.kp = (int)ldf(C, C_KP);
     k.kpa = (int)ldf(C, C_KPA);
     k.quad = fma(k.e1, k.e1, k.e2 * k.e2) < 0.3025;
@@ -170,11 +173,12 @@ __device__ __forceinline__ double log2_d(double x) {
     return fma(r, p, (double)e + t.y);
 }
 
-// 2^v for v in [-1100, 1100] (callers bound the argument): 256 v = 256 n + i
-// + f, i in [0, 256), |f| <= 1/2; 2^v = 2^n 2^(i/256) e^y, y = f ln2/256,
-// |y| < 0.00136, by e^y = 1 + y + y^2/2 (truncation below 4.2e-10 relative).
-__device__ __forceinline__ double exp2_d(double v) {
-    const double t = v * 256.0;
+// 2^(t/256) for t in [-281600, 281600] (callers bound the argument; they
+// pass t = 256 v for 2^v, with the factor 256 folded into their constants,
+// which is exact): t = 256 n + i + f, i in [0, 256), |f| <= 1/2;
+// 2^(t/256) = 2^n 2^(i/256) e^y, y = f ln2/256, |y| < 0.00136, by
+// e^y = 1 + y + y^2/2 (truncation below 4.2e-10 relative).
+__device__ __forceinline__ double exp2_256(double t) {
     const double jd = rint(t);
     const int ji = (int)jd;
     const double f = t - jd;
@@ -190,8 +194,8 @@ __device__ __forceinline__ double exp2_d(double v) {
 __device__ __forceinline__ double sersic_val(double dx, double dy, const SersicK& s) {
     double r2 = fma(dx, fma(s.a11, dx, s.a12x2 * dy), dy * (s.a22 * dy));
     r2 = fmax(r2, RMIN2D);
-    const double u = exp2_d(fma(s.ku, log2_d(r2), s.ku0));   // (R/R_e)^(1/n)
-    return s.ie * exp2_d(fmin(fmax(fma(-s.bl, u, s.bl), -1100.0), 1100.0));
+    const double u = exp2_256(fma(s.ku, log2_d(r2), s.ku0));   // (R/R_e)^(1/n)
+    return s.ie * exp2_256(fmin(fmax(fma(-s.bl, u, s.bl), -281600.0), 281600.0));
 }
 
 // Accumulates, for the adjoint gs of this sub-pixel value, the sums that
@@ -265,7 +269,7 @@ __device__ __forceinline__ double shapelet_val(double bx, double by, const float
         for (int n1 = 0; n1 <= SH_CAP - n2; ++n1) t = fma(ldd(H, SH_CD + 2 * (sh_row(n2) + n1)), hu[n1], t);
         F = fma(t, hv[n2], F);
     }
-    const double E = ldd(H, SH_E0) * exp2_d(fmax(-(u * u + v * v) * 0.7213475204444817, -1100.0));
+    const double E = ldd(H, SH_E0) * exp2_256(fmax(-(u * u + v * v) * (256.0 * 0.7213475204444817), -281600.0));
     return E * F;
 }
 
@@ -469,7 +473,7 @@ __device__ __forceinline__ void deflect(double x, double y, const PK<NC>& k,
     double f = k.c0, L2 = 0.0;
     if (MASS == LENS_MASS_EPL) {
         L2 = log2_d(r2);
-        f *= exp2_d(fma(-k.k1, L2, k.k0));
+        f *= exp2_256(fma(-k.k1, L2, k.k0));
     }
     ax = inside ? 0.0 : f * fma(vx, sx, -vy * sy);
     ay = inside ? 0.0 : f * fma(vx, sy, vy * sx);
@@ -482,30 +486,118 @@ __device__ __forceinline__ void deflect(double x, double y, const PK<NC>& k,
     }
 }
 
-// The same value with each component's float64 constants loaded right
-// before the component is evaluated: the ~40 float64 constants of a particle
-// do not fit the scalar register file together.
-template <int MASS, int NL, int NS, int SH>
-__device__ __forceinline__ double subpix_value_lean(double x, double y, const float* __restrict__ C) {
-    double v = 0.0;
+// series_d at N points of one particle at once: each point's operations
+// are those of series_d, in the same order; the coefficients are loaded once.
+template <int N>
+__device__ __forceinline__ void series_d_n(const float* __restrict__ C, int kp, const double (&zx)[N],
+                                           const double (&zy)[N], double (&sx)[N], double (&sy)[N]) {
+    cdouble_t* cS = (cdouble_t*)(C + C_COEF_S);
+    double r[N], s[N], b1[N], b2[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        r[n] = 2.0 * zx[n];
+        s[n] = fma(zx[n], zx[n], zy[n] * zy[n]);
+        b1[n] = 0.0;
+        b2[n] = 0.0;
+    }
+    int base = kp - 3;
+    for (; base >= 4; base -= 4) {
+        const double a_[4] = {cS[base + 3], cS[base + 2], cS[base + 1], cS[base]};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                const double b = fma(r[n], b1[n], fma(-s[n], b2[n], a_[q]));
+                b2[n] = b1[n];
+                b1[n] = b;
+            }
+    }
+    const double a_[3] = {cS[3], cS[2], cS[1]};
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const double b = fma(r[n], b1[n], fma(-s[n], b2[n], a_[q]));
+            b2[n] = b1[n];
+            b1[n] = b;
+        }
+    const double c0 = cS[0];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        sx[n] = fma(zx[n], b1[n], fma(-s[n], b2[n], c0));
+        sy[n] = zy[n] * b1[n];
+    }
+}
+
+// Mass deflection (float64) at N points of one particle: per point the
+// operations of deflect, in the same order.
+template <int MASS, int N>
+__device__ __forceinline__ void deflect_n(const double (&x)[N], const double (&y)[N], const PK<0>& k,
+                                          const float* __restrict__ C, double (&ax)[N], double (&ay)[N]) {
+    double r2[N], vx[N], vy[N], zx[N], zy[N];
+    bool inside[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const double wx = x[n] - k.x0, wy = y[n] - k.y0;
+        const double ux = fma(k.ua, wx, -k.ue * wy);
+        const double uy = fma(k.ub, wy, -k.ue * wx);
+        double q = fma(ux, ux, uy * uy);
+        inside[n] = q < RMIN2D;
+        q = inside[n] ? RMIN2D : q;
+        r2[n] = q;
+        const double ir = rsqrt_d(q);
+        vx[n] = ux * ir;
+        vy[n] = uy * ir;
+        const double A = fma(vx[n], vx[n], -vy[n] * vy[n]), B = 2.0 * vx[n] * vy[n];
+        zx[n] = -fma(k.e1, A, k.e2 * B);
+        zy[n] = -fma(k.e1, B, -k.e2 * A);
+    }
+    double sx[N], sy[N];
+    series_d_n<N>(C, k.kp, zx, zy, sx, sy);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        double f = k.c0;
+        if (MASS == LENS_MASS_EPL) f *= exp2_256(fma(-k.k1, log2_d(r2[n]), k.k0));
+        ax[n] = inside[n] ? 0.0 : f * fma(vx[n], sx[n], -vy[n] * sy[n]);
+        ay[n] = inside[n] ? 0.0 : f * fma(vx[n], sy[n], vy[n] * sx[n]);
+    }
+}
+
+// Model values at N sub-pixels of one particle, each component's float64
+// constants loaded right before the component is evaluated (the ~40
+// float64 constants of a particle do not fit the scalar register file
+// together) and shared by the N points.  Per point the sum runs over the
+// lens lights, then the sources, then the shapelet source, as always.
+template <int MASS, int NL, int NS, int SH, int N>
+__device__ __forceinline__ void subpix_value_n(const double (&x)[N], const double (&y)[N],
+                                               const float* __restrict__ C, double (&v)[N]) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = 0.0;
 #pragma unroll
     for (int c = 0; c < NL; ++c) {
         const SersicK s = load_sersic(opaque(C + C_SERS + c * SERS_STRIDE));
-        v += sersic_val(x - s.xc, y - s.yc, s);
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] += sersic_val(x[n] - s.xc, y[n] - s.yc, s);
     }
     const float* Cm = opaque(C);
     const PK<0> k = load_pk<0>(Cm);
-    double ax, ay;
-    deflect<MASS, false, 0>(x, y, k, Cm, ax, ay, nullptr);
-    const double bx = x - ax - fma(k.g1, x, k.g2 * y);
-    const double by = y - ay - fma(k.g2, x, -k.g1 * y);
+    double ax[N], ay[N], bx[N], by[N];
+    deflect_n<MASS, N>(x, y, k, Cm, ax, ay);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        bx[n] = x[n] - ax[n] - fma(k.g1, x[n], k.g2 * y[n]);
+        by[n] = y[n] - ay[n] - fma(k.g2, x[n], -k.g1 * y[n]);
+    }
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
         const SersicK s = load_sersic(opaque(C + C_SERS + (NL + c) * SERS_STRIDE));
-        v += sersic_val(bx - s.xc, by - s.yc, s);
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] += sersic_val(bx[n] - s.xc, by[n] - s.yc, s);
     }
-    if (SH) v += shapelet_val(bx, by, opaque(C));
-    return v;
+    if (SH) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] += shapelet_val(bx[n], by[n], opaque(C));
+    }
 }
 
 // Reverse sweep of one sub-pixel: accumulates into acc[] (layout A_*).
@@ -627,8 +719,8 @@ __global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
     Dm[D_UE / 2] = e2 * ip;
     Dm[D_C0 / 2] = tE * sqrt(fmax(1.0 - c2, 0.0));
     const double b = tE * sqrt(fmax((1.0 - c) / (1.0 + c), 0.0));
-    Dm[D_K0 / 2] = (t - 1.0) * log2(b);
-    Dm[D_K1 / 2] = 0.5 * (t - 1.0);
+    Dm[D_K0 / 2] = 256.0 * ((t - 1.0) * log2(b));   // both times 256 (exp2_256)
+    Dm[D_K1 / 2] = 256.0 * (0.5 * (t - 1.0));
     Dm[D_G1 / 2] = g1; Dm[D_G2 / 2] = g2;
     const int nc = mi.n_lens_light + mi.n_source;
     for (int k = 0; k < nc; ++k, o += 7) {
@@ -645,9 +737,9 @@ __global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
         Sd[S_A12X2 / 2] = -4.0 * se2 / D;
         Sd[S_IE / 2] = th[o + 6];
         const double bn = 1.9992 * n - 0.3271;
-        Sd[S_KU / 2] = 0.5 / n;
-        Sd[S_KU0 / 2] = -log2(Re) / n;
-        Sd[S_BL / 2] = bn * 1.4426950408889634;
+        Sd[S_KU / 2] = 256.0 * (0.5 / n);              // exponent constants times 256 (exp2_256)
+        Sd[S_KU0 / 2] = 256.0 * (-log2(Re) / n);
+        Sd[S_BL / 2] = 256.0 * (bn * 1.4426950408889634);
         S[S_KAP2] = (float)(-bn / n);
     }
     if (mi.n_shapelet) {
@@ -717,7 +809,37 @@ __global__ void k_prologue(ModelInfo mi, int P, const float* __restrict__ theta,
     C[C_VALID] = !finite ? 2.0f : (ok ? 1.0f : 0.0f);
 }
 
-// Renders pixels [pix0, pix1) of one particle (whole work-group).
+// Sub-pixel sum of N pixels of one particle (N = 1 or 2), each at its own
+// (i, j); the pixels' sub-pixels are visited in the same order.
+template <int MASS, int NL, int NS, int SH, int N>
+__device__ __forceinline__ void pixel_values(const float* __restrict__ C, const Geo& g, const int (&pix)[N],
+                                             double (&acc)[N]) {
+    int i[N], j[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        i[n] = pix[n] / g.nx;
+        j[n] = pix[n] - i[n] * g.nx;
+        acc[n] = 0.0;
+    }
+    for (int a = 0; a < g.s; ++a) {
+        double y[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) y[n] = ((double)(g.s * i[n] + a) - g.cy) * g.h;
+        for (int b = 0; b < g.s; ++b) {
+            double x[N], v[N];
+#pragma unroll
+            for (int n = 0; n < N; ++n) x[n] = ((double)(g.s * j[n] + b) - g.cx) * g.h;
+            subpix_value_n<MASS, NL, NS, SH, N>(x, y, C, v);
+#pragma unroll
+            for (int n = 0; n < N; ++n) acc[n] += v[n];
+        }
+    }
+}
+
+// Renders pixels [pix0, pix1) of one particle (whole work-group).  Each
+// thread takes its pixels two at a time (pix and pix + blockDim.x), so that
+// constants and series coefficients are loaded once for both; a last odd
+// pixel is rendered alone, with the same operations.
 template <int MASS, int NL, int NS, int SH>
 __device__ __forceinline__ void render_chunk(const float* __restrict__ C, const Geo& g, int pix0,
                                              int pix1, float* __restrict__ out) {
@@ -725,17 +847,20 @@ __device__ __forceinline__ void render_chunk(const float* __restrict__ C, const 
         for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) out[pix] = __builtin_nanf("");
         return;
     }
-    for (int pix = pix0 + threadIdx.x; pix < pix1; pix += blockDim.x) {
-        const int i = pix / g.nx, j = pix - i * g.nx;
-        double acc = 0.0;
-        for (int a = 0; a < g.s; ++a) {
-            const double y = ((double)(g.s * i + a) - g.cy) * g.h;
-            for (int b = 0; b < g.s; ++b) {
-                const double x = ((double)(g.s * j + b) - g.cx) * g.h;
-                acc += subpix_value_lean<MASS, NL, NS, SH>(x, y, C);
-            }
-        }
-        out[pix] = (float)(acc * (double)g.inv_s2);
+    const int step = blockDim.x;
+    int pix = pix0 + threadIdx.x;
+    for (; pix + step < pix1; pix += 2 * step) {
+        const int pp[2] = {pix, pix + step};
+        double acc[2];
+        pixel_values<MASS, NL, NS, SH, 2>(C, g, pp, acc);
+        out[pix] = (float)(acc[0] * (double)g.inv_s2);
+        out[pix + step] = (float)(acc[1] * (double)g.inv_s2);
+    }
+    if (pix < pix1) {
+        const int pp[1] = {pix};
+        double acc[1];
+        pixel_values<MASS, NL, NS, SH, 1>(C, g, pp, acc);
+        out[pix] = (float)(acc[0] * (double)g.inv_s2);
     }
 }
 
@@ -846,7 +971,7 @@ __global__ __launch_bounds__(256) void k_render_split(const float* __restrict__ 
                     double hu[SH_CAP + 1], hv[SH_CAP + 1];
                     hermite_h(u, hu);
                     hermite_h(v, hv);
-                    const double E = ldd(H, SH_E0) * exp2_d(fmax(-(u * u + v * v) * 0.7213475204444817, -1100.0));
+                    const double E = ldd(H, SH_E0) * exp2_256(fmax(-(u * u + v * v) * (256.0 * 0.7213475204444817), -281600.0));
 #pragma unroll
                     for (int n2 = 0; n2 <= SH_CAP; ++n2) {
                         const double ev = E * hv[n2];
