@@ -139,7 +139,7 @@ __device__ __forceinline__ const float* opaque(const float* p) {
 constexpr double LN2_D = 0.69314718055994530942;
 
 struct MathTab {
-    double2 lg[256];   // (1/c_j, log2 c_j), c_j = 1 + (j + 1/2)/256
+    double2 lg[256];   // (2/c_j, log2(1/c_j) - 1), c_j = 1 + (j + 1/2)/256
     double ex[256];    // 2^(j/256)
 };
 __shared__ MathTab g_tab;
@@ -148,29 +148,28 @@ __shared__ MathTab g_tab;
 __device__ __forceinline__ void init_math_tab() {
     for (int j = threadIdx.x; j < 256; j += blockDim.x) {
         const double ic = 1.0 / (1.0 + (j + 0.5) / 256.0);
-        g_tab.lg[j] = make_double2(ic, -log2(ic));
+        g_tab.lg[j] = make_double2(2.0 * ic, -log2(ic) - 1.0);
         g_tab.ex[j] = exp2(j / 256.0);
     }
     __syncthreads();
 }
 
-// log2 x for normal x > 0: x = m 2^e, m in [1, 2); with the table entry j
-// of m's leading eight fraction bits, log2 m = log2 c_j + log2(1 + r),
-// r = m/c_j - 1, |r| < 2^-9, by the series of log(1 + r) to r^3
-// (truncation below 6e-12).
+// log2 x for normal x > 0: x = f 2^q, f in [1/2, 1) (frexp), so with
+// m = 2 f in [1, 2) and e = q - 1, log2 x = e + log2 c_j + log2(1 + r),
+// c_j the table point of m's leading eight fraction bits (those of x),
+// r = m/c_j - 1 = f (2/c_j) - 1, |r| < 2^-9, by the series of log(1 + r)
+// to r^3 (truncation below 6e-12).  The table folds the -1 of e in.
 __device__ __forceinline__ double log2_d(double x) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(x);
-    const uint32_t hi = (uint32_t)(bits >> 32);
-    const int e = (int)(hi >> 20) - 1023;
+    const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(x) >> 32);
     const int j = (int)((hi >> 12) & 255u);
-    const double m = __longlong_as_double(
-        (long long)(((uint64_t)((hi & 0x000fffffu) | 0x3ff00000u) << 32) | (bits & 0xffffffffull)));
     const double2 t = g_tab.lg[j];
-    const double r = fma(m, t.x, -1.0);
+    const double f = __builtin_amdgcn_frexp_mant(x);
+    const int q = __builtin_amdgcn_frexp_exp(x);
+    const double r = fma(f, t.x, -1.0);
     constexpr double k = 1.0 / LN2_D;
     double p = fma(r, k / 3.0, -k / 2.0);
     p = fma(r, p, k);
-    return fma(r, p, (double)e + t.y);
+    return fma(r, p, (double)q + t.y);
 }
 
 // 2^(t/256) for t in [-281600, 281600] (callers bound the argument; they
