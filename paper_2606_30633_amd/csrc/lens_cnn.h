@@ -58,6 +58,7 @@ struct CnnNet {
     float* wpart;
     double* colpart;
     double* losspart;
+    double* c0part;       // [max_batch][32][10] first-layer weight and bias gradient per image
     CnnTargetMap* tmap;   // device copy
     __bf16* prep;         // prepared images for init_propose
     __bf16* img_stage;    // [max_batch][64][64] the training batch (captured step)

@@ -679,6 +679,133 @@ static int gemm_splits(int M, int N, int K, int splits) {
 }
 
 // ---------------------------------------------------------------------------
+// First convolution (one input channel, 3 x 3, CNN_C1 = 32 outputs, stride 1)
+// as direct VALU kernels: K = 9 is too short for the matrix cores, and the
+// GEMM path pads it to 32 and gathers single bf16 values.  One work-group
+// per image; the image (zero border) is staged in LDS as float; thread
+// t = 4 x + g handles pixel column x and output channels 8 g .. 8 g + 7, one
+// image row at a time, so a wave's 16-byte accesses of the NHWC activation
+// rows are contiguous.
+// ---------------------------------------------------------------------------
+constexpr int C0_OUT = 32;
+constexpr int C0_SIDE = CNN_IN + 2;   // 66: image plus a zero border
+
+__device__ __forceinline__ void c0_stage_image(const __bf16* __restrict__ img, float (*tile)[C0_SIDE]) {
+    for (int q = threadIdx.x; q < C0_SIDE * C0_SIDE; q += blockDim.x) {
+        const int y = q / C0_SIDE - 1, x = q % C0_SIDE - 1;
+        tile[y + 1][x + 1] = (y >= 0 && y < CNN_IN && x >= 0 && x < CNN_IN) ? from_bf16(img[y * CNN_IN + x]) : 0.0f;
+    }
+}
+
+// out[b, y, x, co] = relu(sum_tap W[co][tap] in[b, y + ky - 1, x + kx - 1] + bias[co]) as bf16;
+// the tap sum in float, in tap order, then the bias (the GEMM epilogue's order).
+__global__ __launch_bounds__(256) void k_conv0_fwd(const __bf16* __restrict__ img, const __bf16* __restrict__ w,
+                                                   const float* __restrict__ bias, __bf16* __restrict__ out) {
+    __shared__ float tile[C0_SIDE][C0_SIDE];
+    const int b = blockIdx.x;
+    const int t = threadIdx.x, g = t & 3, x = t >> 2;
+    c0_stage_image(img + (size_t)b * CNN_IN * CNN_IN, tile);
+    float wr[8][9], br[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) wr[c][q] = from_bf16(w[(8 * g + c) * 9 + q]);
+        br[c] = bias[8 * g + c];
+    }
+    __syncthreads();
+    __bf16* o = out + ((size_t)b * CNN_IN * CNN_IN) * C0_OUT + 8 * g;
+    for (int y = 0; y < CNN_IN; ++y) {
+        float v[9];
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) v[3 * ky + kx] = tile[y + ky][x + kx];
+        bf16x8 r;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float a = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) a = fmaf(wr[c][q], v[q], a);
+            r[c] = to_bf16(fmaxf(a + br[c], 0.0f));
+        }
+        *reinterpret_cast<bf16x8*>(o + ((size_t)y * CNN_IN + x) * C0_OUT) = r;
+    }
+}
+
+// Per image b: part[b][co][q] = sum over pixels of dZ[b, y, x, co] times
+// in[b, y + ky - 1, x + kx - 1] (q = 3 ky + kx < 9) or times 1 (q = 9: the
+// bias gradient).  Each thread sums its 64 rows in float; the 16 pixel
+// columns of a wave are combined by a fixed butterfly, the four waves in
+// LDS in float64, in fixed order.
+__global__ __launch_bounds__(256) void k_conv0_wgrad(const __bf16* __restrict__ img, const __bf16* __restrict__ dz,
+                                                     double* __restrict__ part) {
+    __shared__ float tile[C0_SIDE][C0_SIDE];
+    __shared__ double red[4][C0_OUT * 10];
+    const int b = blockIdx.x;
+    const int t = threadIdx.x, g = t & 3, x = t >> 2, lane = t & 63, wv = t >> 6;
+    c0_stage_image(img + (size_t)b * CNN_IN * CNN_IN, tile);
+    __syncthreads();
+    float acc[8][10];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[c][q] = 0.0f;
+    const __bf16* d = dz + ((size_t)b * CNN_IN * CNN_IN) * C0_OUT + 8 * g;
+    for (int y = 0; y < CNN_IN; ++y) {
+        const bf16x8 dv = *reinterpret_cast<const bf16x8*>(d + ((size_t)y * CNN_IN + x) * C0_OUT);
+        float v[9];
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) v[3 * ky + kx] = tile[y + ky][x + kx];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float dc = from_bf16(dv[c]);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc[c][q] = fmaf(dc, v[q], acc[c][q]);
+            acc[c][9] += dc;
+        }
+    }
+    // lanes 4 j + g (j = 0..15) of a wave hold the same channels: butterfly over j
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            float a = acc[c][q];
+#pragma unroll
+            for (int off = 4; off < 64; off <<= 1) a += __shfl_xor(a, off, 64);
+            acc[c][q] = a;
+        }
+    if (lane < 4) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+            for (int q = 0; q < 10; ++q) red[wv][(8 * g + c) * 10 + q] = (double)acc[c][q];
+    }
+    __syncthreads();
+    for (int e = t; e < C0_OUT * 10; e += blockDim.x)
+        part[(size_t)b * C0_OUT * 10 + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
+// dW and db of the first convolution: sum over the B images of part, one wave
+// per entry (lane l sums images l, l + 64, ...; a fixed butterfly combines).
+__global__ __launch_bounds__(256) void k_conv0_wgrad_final(int B, const double* __restrict__ part,
+                                                           float* __restrict__ dw, float* __restrict__ db) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (e >= C0_OUT * 10) return;
+    double s = 0.0;
+    for (int b = lane; b < B; b += 64) s += part[(size_t)b * C0_OUT * 10 + e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        const int co = e / 10, q = e % 10;
+        if (q < 9) dw[co * 9 + q] = (float)s;
+        else db[co] = (float)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Elementwise / reduction kernels
 // ---------------------------------------------------------------------------
 // sum of split-K partials in fixed order: out[i] = sum_z part[z][i]
@@ -939,10 +1066,17 @@ __global__ void k_zero_int(int n, int* __restrict__ x) {
 static inline dim3 g1(long long n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
 hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st) {
+    if (net.conv[0].cin != 1 || net.conv[0].cout != C0_OUT || net.conv[0].stride != 1) return hipErrorInvalidValue;
     const __bf16* x = img;
     int H = CNN_IN;
     for (int l = 0; l < CNN_CONV; ++l) {
         const CnnLayer& L = net.conv[l];
+        if (l == 0) {
+            hipLaunchKernelGGL(k_conv0_fwd, dim3(B), dim3(256), 0, st, x, net.wbf + L.w_off, net.params + L.b_off,
+                               net.act[0]);
+            x = net.act[0];
+            continue;
+        }
         const ConvShape s = conv_shape(B, H, L.cin, H / L.stride, L.cout, L.stride);
         OpConvFwd op{s, x, net.wbf + L.w_off, net.params + L.b_off, net.act[l]};
         if (gemm_pick(op, B * s.Ho * s.Wo, L.cout, 9 * L.cin, 1, st) != hipSuccess) return hipErrorLaunchFailure;
@@ -998,6 +1132,12 @@ hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* targ
         const ConvShape s = conv_shape(B, H, L.cin, Hout, L.cout, L.stride);
         const __bf16* in = l == 0 ? img : net.act[l - 1];
         const int K = B * Hout * Hout;
+        if (l == 0) {   // first layer: direct kernels (and no data gradient)
+            hipLaunchKernelGGL(k_conv0_wgrad, dim3(B), dim3(256), 0, st, img, net.dact[0], net.c0part);
+            hipLaunchKernelGGL(k_conv0_wgrad_final, dim3(C0_OUT * 10 / 4), dim3(256), 0, st, B, net.c0part,
+                               net.grads + L.w_off, net.grads + L.b_off);
+            break;
+        }
         const int splits = gemm_splits(L.cout, 9 * L.cin, K, wgrad_splits(K));
         OpConvWgrad wg{s, net.dact[l], in, net.wpart};
         if (gemm_pick(wg, L.cout, 9 * L.cin, K, wgrad_splits(K), st) != hipSuccess) return hipErrorLaunchFailure;

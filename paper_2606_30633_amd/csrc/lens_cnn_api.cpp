@@ -58,8 +58,8 @@ lens_status lens_cnn_destroy(lens_cnn* c) {
     if (n.train_graph) (void)hipGraphExecDestroy(n.train_graph);
     if (n.cap_stream) (void)hipStreamDestroy(n.cap_stream);
     void* bufs[] = {n.params, n.grads, n.adam_m, n.adam_v, n.wbf, n.pooled, n.dpooled, n.hidden, n.dhidden, n.out,
-                    n.dout, n.wpart, n.colpart, n.losspart, n.tmap, n.prep, n.img_stage, n.tgt_stage, n.hyper,
-                    n.loss_dev};
+                    n.dout, n.wpart, n.colpart, n.losspart, n.c0part, n.tmap, n.prep, n.img_stage, n.tgt_stage,
+                    n.hyper, n.loss_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 0; l < CNN_CONV; ++l) {
@@ -94,7 +94,8 @@ lens_status lens_cnn_create(int32_t max_batch, uint64_t seed, lens_cnn** out) {
     ok = ok && alloc(&n.pooled, B * CNN_C6) && alloc(&n.dpooled, B * CNN_C6) && alloc(&n.hidden, B * CNN_H1) &&
          alloc(&n.dhidden, B * CNN_H1) && alloc(&n.out, B * CNN_OUT) && alloc(&n.dout, B * CNN_OUT) &&
          alloc(&n.wpart, wpart) && alloc(&n.colpart, (B * CNN_IN * CNN_IN / 4096 + 1) * 256) &&
-         alloc(&n.losspart, B / 256 + 1) && alloc(&n.tmap, 1) && alloc(&n.prep, B * CNN_IN * CNN_IN) &&
+         alloc(&n.losspart, B / 256 + 1) && alloc(&n.c0part, B * 32 * 10) && alloc(&n.tmap, 1) &&
+         alloc(&n.prep, B * CNN_IN * CNN_IN) &&
          alloc(&n.img_stage, B * CNN_IN * CNN_IN) && alloc(&n.tgt_stage, B * CNN_NT) && alloc(&n.hyper, 2) &&
          alloc(&n.loss_dev, 1) && hipStreamCreateWithFlags(&n.cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {

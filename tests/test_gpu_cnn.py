@@ -193,21 +193,24 @@ def test_init_propose_clips_to_support_and_flags():
 
 
 def test_trained_network_beats_prior_draws():
-    """What the learned initializer gains over the plain method: on held-out
-    systems (64x64 px, truths from the simulation distribution, data = oracle
-    model + noise), the best of 64 network proposals has a higher
-    log-posterior than the best of 64 prior draws."""
+    """What the learned initializer gains over the plain method: on 16
+    held-out systems (64x64 px, truths from the simulation distribution,
+    data = oracle model + noise), the best of 64 network proposals has a
+    higher log-posterior than the best of 64 prior draws on at least 12, and
+    the median gain is positive.  The network trains 20 epochs: after 5 it
+    barely beats prior draws, and a count over 8 systems then turns on
+    single systems."""
     from oracle import lens_oracle as O
     from paper_2606_30633_amd import learned_init as LI
     dev = torch.device(DEV, 0)
     theta, images = LI.simulate(100000, synth.SEED_CNN_TRAIN, dev)
     mean, std = LI.target_standardization(theta)
     net = lens.Cnn(256, 1, dev)
-    LI.train(net, images, theta, mean, std, 5, 256, lr=2e-3, lr_final=1e-4, log=lambda *_: None)
+    LI.train(net, images, theta, mean, std, 20, 256, lr=2e-3, lr_final=1e-4, log=lambda *_: None)
     del images
     table = LI.configure(net, mean, std)
     spec = LI.train_spec()
-    S, n = 8, 64
+    S, n = 16, 64
     psf = synth.double_gaussian_psf(spec.psf_size, spec.pix_scale)
     truths = synth.draw_params(synth.paper_sim_dists(), S, synth.SEED_CNN_VAL + 777)
     datas = [(O.model_image(truths[k], spec, psf).numpy()
@@ -227,5 +230,6 @@ def test_trained_network_beats_prior_draws():
 
     bl, bpr = best(learned), best(prior)
     gain = bl - bpr
-    print("best logp learned", np.round(bl, 1).tolist(), "prior", np.round(bpr, 1).tolist(), flush=True)
-    assert np.median(gain) > 0 and np.sum(gain > 0) >= 6, gain
+    print("best logp learned", np.round(bl, 1).tolist(), "prior", np.round(bpr, 1).tolist(),
+          "wins", int(np.sum(gain > 0)), flush=True)
+    assert np.median(gain) > 0 and np.sum(gain > 0) >= 12, gain
