@@ -520,9 +520,12 @@ typedef struct lens_cnn lens_cnn;
 #define LENS_CNN_SIDE    64
 #define LENS_CNN_TARGETS 14
 #define LENS_CNN_OUTPUTS 28
+/* Largest max_batch: activation offsets stay within 32-bit integers. */
+#define LENS_CNN_MAX_BATCH 8192
 
-/* Network with room for batches up to max_batch; weights He-initialised from
- * Philox4x32-10 with the given seed.  Errors: LENS_EINVAL, LENS_ENOMEM. */
+/* Network with room for batches up to max_batch (1 .. LENS_CNN_MAX_BATCH);
+ * weights He-initialised from Philox4x32-10 with the given seed.
+ * Errors: LENS_EINVAL, LENS_ENOMEM. */
 lens_status lens_cnn_create(int32_t max_batch, uint64_t seed, lens_cnn** out);
 lens_status lens_cnn_destroy(lens_cnn* net);
 int64_t lens_cnn_num_params(void);

@@ -31,6 +31,8 @@ __device__ __forceinline__ bf16x8 zero8() {
     return z;
 }
 
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
 // ---------------------------------------------------------------------------
 // Generic BF16 MFMA GEMM.  Each operand is read either along K (row-major
 // A[m][k], column-major B[k][n]: 8 consecutive k per 16-byte load) or, in
@@ -48,12 +50,34 @@ constexpr int GT = 64;    // output tile (M and N)
 constexpr int GK = 64;    // K per stage (two MFMA K-steps of 32)
 constexpr int LDSK = 72;  // padded LDS row (bf16)
 
+// Precomputed gathers (ops with CTX_A / CTX_B).  An A row m (along K) is a
+// base offset into the op's source and a mask of the taps that stay inside
+// the image, both fixed across K stages; a K chunk is a tap bit and an
+// offset, the same for every row of a thread:
+//   GatherCtx a_row(int m), int a_koff(int k, int& bit), const __bf16* a_src()
+//   A(m, k..k+7) = (mask >> bit) & 1 ? a_src()[base + koff ..] : 0.
+// A K-major B (weight gradient: k = output position, n = (tap, ci)) has a
+// row part per group of 8 n and a position part per k:
+//   WRow b_row(int n), WPos b_pos(int k), bf16x8 b_load(WRow, WPos).
+struct GatherCtx {
+    int base;
+    uint32_t mask;
+};
+struct WRow {
+    int off, dy, dx;   // element offset and tap displacement; dy < -8: outside B
+};
+struct WPos {
+    int base, iy, ix;
+};
+
 // Loads of one stage into registers: along K, thread t covers row t/4 at
 // k offsets 8 (t%4) and 32 + 8 (t%4); K-major, k t%64 at rows 8 (t/64) and
 // 32 + 8 (t/64).
 template <class Op>
 struct StageRegs {
     bf16x8 a[2], b[2];
+    GatherCtx actx;   // CTX_A: this thread's A row
+    WRow brow[2];     // CTX_B: this thread's B row groups
 };
 
 template <class Op>
@@ -62,16 +86,39 @@ __device__ __forceinline__ void load_stage(const Op& op, StageRegs<Op>& r, int m
     const int t = threadIdx.x;
     const int lr = t >> 2, lk = (t & 3) * 8;
     const int tk = t & 63, tr = (t >> 6) * 8;
+    WPos bp{};
+    if constexpr (Op::CTX_B) {
+        if (k0 + tk < kend) bp = op.b_pos(k0 + tk);
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        if constexpr (Op::A_KMAJOR)
+        if constexpr (Op::A_KMAJOR) {
             r.a[h] = (k0 + tk < kend) ? op.loadAT(k0 + tk, m0 + tr + 32 * h) : zero8();
-        else
+        } else if constexpr (Op::CTX_A) {
+            const int k = k0 + lk + 32 * h;
+            int bit = 0;
+            const int off = k < kend ? op.a_koff(k, bit) : 0;
+            r.a[h] = (k < kend && ((r.actx.mask >> bit) & 1u)) ? ld8(op.a_src() + r.actx.base + off) : zero8();
+        } else {
             r.a[h] = (m0 + lr < M) ? op.loadA(m0 + lr, k0 + lk + 32 * h, kend) : zero8();
-        if constexpr (Op::B_KMAJOR)
+        }
+        if constexpr (Op::CTX_B)
+            r.b[h] = (k0 + tk < kend) ? op.b_load(r.brow[h], bp) : zero8();
+        else if constexpr (Op::B_KMAJOR)
             r.b[h] = (k0 + tk < kend) ? op.loadBT(k0 + tk, n0 + tr + 32 * h) : zero8();
         else
             r.b[h] = (n0 + lr < N) ? op.loadB(k0 + lk + 32 * h, n0 + lr, kend) : zero8();
+    }
+}
+
+// The row parts of a thread's gathers (fixed for the whole K range).
+template <class Op>
+__device__ __forceinline__ void init_stage_ctx(const Op& op, StageRegs<Op>& r, int m0, int n0, int M, int N) {
+    const int t = threadIdx.x;
+    if constexpr (Op::CTX_A && !Op::A_KMAJOR) r.actx = (m0 + (t >> 2) < M) ? op.a_row(m0 + (t >> 2)) : GatherCtx{0, 0u};
+    if constexpr (Op::CTX_B) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) r.brow[h] = op.b_row(n0 + (t >> 6) * 8 + 32 * h);
     }
 }
 
@@ -115,6 +162,7 @@ __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     StageRegs<Op> r;
+    init_stage_ctx(op, r, m0, n0, M, N);
     if (kbeg < kend) load_stage(op, r, m0, n0, kbeg, kend, M, N);
     for (int k0 = kbeg; k0 < kend; k0 += GK) {
         __syncthreads();
@@ -156,6 +204,7 @@ constexpr int GT2 = 128;
 template <class Op>
 struct StageRegs2 {
     bf16x8 a[4], b[2];
+    GatherCtx actx;   // CTX_A: this thread's A row
 };
 
 template <class Op>
@@ -167,10 +216,16 @@ __device__ __forceinline__ void load_stage2(const Op& op, StageRegs2<Op>& r, int
     const int tk = t & 63, tr = (t >> 6) * 8;        // K-major: k t%64, rows 8 (t/64) + 32 h
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-        if constexpr (Op::A_KMAJOR)
+        if constexpr (Op::A_KMAJOR) {
             r.a[h] = (k0 + tk < kend) ? op.loadAT(k0 + tk, m0 + tr + 32 * h) : zero8();
-        else
+        } else if constexpr (Op::CTX_A) {
+            const int k = k0 + ak + 8 * h;
+            int bit = 0;
+            const int off = k < kend ? op.a_koff(k, bit) : 0;
+            r.a[h] = (k < kend && ((r.actx.mask >> bit) & 1u)) ? ld8(op.a_src() + r.actx.base + off) : zero8();
+        } else {
             r.a[h] = (m0 + ar < M) ? op.loadA(m0 + ar, k0 + ak + 8 * h, kend) : zero8();
+        }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -221,6 +276,10 @@ __global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     StageRegs2<Op> r;
+    if constexpr (Op::CTX_A && !Op::A_KMAJOR) {
+        const int row = m0 + (threadIdx.x >> 1);
+        r.actx = row < M ? op.a_row(row) : GatherCtx{0, 0u};
+    }
     if (kbeg < kend) load_stage2(op, r, m0, n0, kbeg, kend, M, N);
     for (int k0 = kbeg; k0 < kend; k0 += GK) {
         __syncthreads();
@@ -264,6 +323,60 @@ template <class Op, int R>
 struct WideRegs {
     bf16x8 v[R / 32];   // R rows x 64 k of one operand, 2 R / 64 chunks of 8 per thread
 };
+
+// Gathered rows of one operand of the wide kernels: along K the thread's
+// rows are r0 + t/8 + 32 h (A rows, GatherCtx); K-major its row groups are
+// r0 + 8 (t/64 + 4 h) (B row groups, WRow).
+template <int R>
+struct WideCtx {
+    GatherCtx a[R / 32];
+    WRow b[R / 32];
+};
+
+template <int R, class Op>
+__device__ __forceinline__ void wide_ctx_a(const Op& op, WideCtx<R>& c, int r0, int rows) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < R / 32; ++h) {
+        const int row = r0 + (t >> 3) + 32 * h;
+        c.a[h] = row < rows ? op.a_row(row) : GatherCtx{0, 0u};
+    }
+}
+
+template <int R, class Op>
+__device__ __forceinline__ void wide_ctx_b(const Op& op, WideCtx<R>& c, int r0) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < R / 32; ++h) c.b[h] = op.b_row(r0 + 8 * ((t >> 6) + 4 * h));
+}
+
+// rows x 64 k of A along K through the row contexts.
+template <int R, class Op>
+__device__ __forceinline__ void wide_load_actx(const Op& op, WideRegs<void, R>& r, const WideCtx<R>& c, int k0,
+                                               int kend) {
+    const int k = k0 + (threadIdx.x & 7) * 8;
+    int bit = 0;
+    const int off = k < kend ? op.a_koff(k, bit) : 0;
+    const __bf16* src = op.a_src();
+#pragma unroll
+    for (int h = 0; h < R / 32; ++h)
+        r.v[h] = (k < kend && ((c.a[h].mask >> bit) & 1u)) ? ld8(src + c.a[h].base + off) : zero8();
+}
+
+// 64 k x rows of a K-major B through the row-group contexts.
+template <int R, class Op>
+__device__ __forceinline__ void wide_load_bctx(const Op& op, WideRegs<void, R>& r, const WideCtx<R>& c, int k0,
+                                               int kend) {
+    const int k = k0 + (threadIdx.x & 63);
+    if (k >= kend) {
+#pragma unroll
+        for (int h = 0; h < R / 32; ++h) r.v[h] = zero8();
+        return;
+    }
+    const WPos p = op.b_pos(k);
+#pragma unroll
+    for (int h = 0; h < R / 32; ++h) r.v[h] = op.b_load(c.b[h], p);
+}
 
 // rows x 64 k of one operand into registers: along K, chunk c = t + 256 h covers
 // row c / 8 at k 8 (c % 8); K-major, chunk c covers k c % 64 at rows 8 (c / 64).
@@ -333,9 +446,21 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
     };
     WideRegs<void, TM> ra;
     WideRegs<void, TN> rb;
+    WideCtx<TM> ca;
+    WideCtx<TN> cb;
+    if constexpr (Op::CTX_A && !Op::A_KMAJOR) wide_ctx_a(op, ca, m0, M);
+    if constexpr (Op::CTX_B) wide_ctx_b(op, cb, n0);
+    auto load_a = [&](int k0) {
+        if constexpr (Op::CTX_A && !Op::A_KMAJOR) wide_load_actx(op, ra, ca, k0, kend);
+        else wide_load<Op::A_KMAJOR, TM>(ra, m0, k0, kend, M, la, lat);
+    };
+    auto load_b = [&](int k0) {
+        if constexpr (Op::CTX_B) wide_load_bctx(op, rb, cb, k0, kend);
+        else wide_load<Op::B_KMAJOR, TN>(rb, n0, k0, kend, N, lb, lbt);
+    };
     if (kbeg < kend) {
-        wide_load<Op::A_KMAJOR, TM>(ra, m0, kbeg, kend, M, la, lat);
-        wide_load<Op::B_KMAJOR, TN>(rb, n0, kbeg, kend, N, lb, lbt);
+        load_a(kbeg);
+        load_b(kbeg);
     }
     for (int k0 = kbeg; k0 < kend; k0 += GK) {
         __syncthreads();
@@ -343,8 +468,8 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
         wide_store<Op::B_KMAJOR, TN>(rb, Bs);
         __syncthreads();
         if (k0 + GK < kend) {
-            wide_load<Op::A_KMAJOR, TM>(ra, m0, k0 + GK, kend, M, la, lat);
-            wide_load<Op::B_KMAJOR, TN>(rb, n0, k0 + GK, kend, N, lb, lbt);
+            load_a(k0 + GK);
+            load_b(k0 + GK);
         }
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
@@ -396,7 +521,6 @@ inline ConvShape conv_shape(int B, int H, int Cin, int Ho, int Cout, int stride)
 
 __device__ __forceinline__ int div3(int tap) { return (tap * 11) >> 5; }   // tap in [0, 9)
 
-__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
 // forward: out[b,y,x,co] = relu(sum in[b, s y + ky - 1, s x + kx - 1, ci] W[co,ky,kx,ci] + bias)
 // A(m = (b, y, x), k = (tap, ci)) along K; B(k, n = co) = W[co][k] along K.
@@ -407,6 +531,24 @@ struct OpConvFwd {
     const __bf16* w;
     const float* bias;
     __bf16* out;
+    static constexpr bool CTX_A = true, CTX_B = false;   // gathers need Cin >= 8
+    __device__ GatherCtx a_row(int m) const {
+        const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
+        const int iy0 = (r >> s.lWo) * s.stride - 1, ix0 = (r & (s.Wo - 1)) * s.stride - 1;
+        uint32_t mask = 0;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx)
+                if (iy0 + ky >= 0 && iy0 + ky < s.H && ix0 + kx >= 0 && ix0 + kx < s.W) mask |= 1u << (3 * ky + kx);
+        return GatherCtx{((b * s.H + iy0) * s.W + ix0) * s.Cin, mask};
+    }
+    __device__ int a_koff(int k, int& bit) const {
+        const int tap = k >> s.lCin, ky = div3(tap);
+        bit = tap;
+        return (ky * s.W + (tap - 3 * ky)) * s.Cin + (k & (s.Cin - 1));
+    }
+    __device__ const __bf16* a_src() const { return in; }
     __device__ bf16x8 loadA(int m, int k, int kend) const {
         const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
         const int y = r >> s.lWo, x = r & (s.Wo - 1);
@@ -453,6 +595,26 @@ struct OpConvDgrad {
     const __bf16* w;
     const __bf16* prev;   // layer input (the previous layer's ReLU output)
     __bf16* dprev;        // [B][H][W][Cin]
+    // gathers: stride 1 only (stride-2 layers use OpConvDgradS2)
+    static constexpr bool CTX_A = true, CTX_B = false;
+    __device__ GatherCtx a_row(int m) const {
+        const int b = m >> (2 * s.lW), r = m & ((1 << (2 * s.lW)) - 1);
+        const int iy = r >> s.lW, ix = r & (s.W - 1);
+        uint32_t mask = 0;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx)
+                if (iy + 1 - ky >= 0 && iy + 1 - ky < s.Ho && ix + 1 - kx >= 0 && ix + 1 - kx < s.Wo)
+                    mask |= 1u << (3 * ky + kx);
+        return GatherCtx{((b * s.Ho + iy + 1) * s.Wo + ix + 1) * s.Cout, mask};
+    }
+    __device__ int a_koff(int k, int& bit) const {
+        const int tap = k >> s.lCout, ky = div3(tap);
+        bit = tap;
+        return (k & (s.Cout - 1)) - (ky * s.Wo + (tap - 3 * ky)) * s.Cout;
+    }
+    __device__ const __bf16* a_src() const { return dz; }
     __device__ bf16x8 loadA(int m, int k, int kend) const {
         const int b = m >> (2 * s.lW), r = m & ((1 << (2 * s.lW)) - 1);
         const int iy = r >> s.lW, ix = r & (s.W - 1);
@@ -496,6 +658,28 @@ struct OpConvDgradS2 {
         kx = px ? 2 * tx : 1;
         (void)ntx;
     }
+    static constexpr bool CTX_A = true, CTX_B = false;
+    // tap t reads dZ at (yq + dy, xq + dx), dy = (py + 1 - ky) / 2 in {0, 1}
+    __device__ GatherCtx a_row(int m) const {
+        const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
+        const int yq = r >> s.lWo, xq = r & (s.Wo - 1);
+        const int ntap = (py ? 2 : 1) * (px ? 2 : 1);
+        uint32_t mask = 0;
+        for (int t = 0; t < ntap; ++t) {
+            int ky, kx;
+            tap(t, ky, kx);
+            if (yq + ((py + 1 - ky) >> 1) < s.Ho && xq + ((px + 1 - kx) >> 1) < s.Wo) mask |= 1u << t;
+        }
+        return GatherCtx{((b * s.Ho + yq) * s.Wo + xq) * s.Cout, mask};
+    }
+    __device__ int a_koff(int k, int& bit) const {
+        const int t = k >> s.lCout;
+        int ky, kx;
+        tap(t, ky, kx);
+        bit = t;
+        return (((py + 1 - ky) >> 1) * s.Wo + ((px + 1 - kx) >> 1)) * s.Cout + (k & (s.Cout - 1));
+    }
+    __device__ const __bf16* a_src() const { return dz; }
     __device__ bf16x8 loadA(int m, int k, int kend) const {
         if (k >= kend) return zero8();
         const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
@@ -532,6 +716,22 @@ struct OpConvWgrad {
     const __bf16* dz;   // [B*Ho*Wo][Cout]
     const __bf16* in;   // layer input [B][H][W][Cin]
     float* part;        // [splits][Cout][9*Cin]
+    // gathers of B: Cin >= 8 (the first layer has its own kernel)
+    static constexpr bool CTX_A = false, CTX_B = true;
+    __device__ WRow b_row(int n) const {
+        if (n >= 9 * s.Cin) return WRow{0, -100, 0};
+        const int tap = n >> s.lCin, ky = div3(tap), kx = tap - 3 * ky;
+        return WRow{((ky - 1) * s.W + (kx - 1)) * s.Cin + (n & (s.Cin - 1)), ky - 1, kx - 1};
+    }
+    __device__ WPos b_pos(int k) const {
+        const int b = k >> (2 * s.lWo), r = k & ((1 << (2 * s.lWo)) - 1);
+        const int iy = (r >> s.lWo) * s.stride, ix = (r & (s.Wo - 1)) * s.stride;
+        return WPos{((b * s.H + iy) * s.W + ix) * s.Cin, iy, ix};
+    }
+    __device__ bf16x8 b_load(const WRow& w, const WPos& p) const {
+        const int iy = p.iy + w.dy, ix = p.ix + w.dx;
+        return ((unsigned)iy < (unsigned)s.H && (unsigned)ix < (unsigned)s.W) ? ld8(in + p.base + w.off) : zero8();
+    }
     __device__ bf16x8 loadAT(int k, int m) const {
         return m < s.Cout ? ld8(dz + ((size_t)k << s.lCout) + m) : zero8();
     }
@@ -564,6 +764,7 @@ struct OpConvWgrad {
 // fully connected forward: y[b][n] = act(sum_k x[b][k] W[n][k] + bias[n])
 struct OpFcFwd {
     static constexpr bool A_KMAJOR = false, B_KMAJOR = false;
+    static constexpr bool CTX_A = false, CTX_B = false;
     int In, Out, relu;
     const __bf16* x;
     const __bf16* w;
@@ -589,6 +790,7 @@ struct OpFcFwd {
 // along K; B(k = out, n = in) = W[out][in]: K-major.
 struct OpFcDgrad {
     static constexpr bool A_KMAJOR = false, B_KMAJOR = true;
+    static constexpr bool CTX_A = false, CTX_B = false;
     int In, Out;
     const __bf16* dy;     // [B][Out]
     const __bf16* w;      // [Out][In]
@@ -616,6 +818,7 @@ struct OpFcDgrad {
 // A(m = out, k = b) = dy[b][out], B(k = b, n = in) = x[b][in]: both K-major.
 struct OpFcWgrad {
     static constexpr bool A_KMAJOR = true, B_KMAJOR = true;
+    static constexpr bool CTX_A = false, CTX_B = false;
     int In, Out;
     const __bf16* dy;   // [B][Out]
     const __bf16* x;    // [B][In]

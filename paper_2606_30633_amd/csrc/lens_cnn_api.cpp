@@ -73,7 +73,7 @@ lens_status lens_cnn_destroy(lens_cnn* c) {
 lens_status lens_cnn_create(int32_t max_batch, uint64_t seed, lens_cnn** out) {
     if (!out) return LENS_EINVAL;
     *out = nullptr;
-    if (max_batch < 1 || max_batch > 65536) return LENS_EINVAL;
+    if (max_batch < 1 || max_batch > LENS_CNN_MAX_BATCH) return LENS_EINVAL;
     lens_cnn* c = new (std::nothrow) lens_cnn();
     if (!c) return LENS_ENOMEM;
     CnnNet& n = c->net;
