@@ -32,6 +32,13 @@ __device__ __forceinline__ bf16x8 zero8() {
 }
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+// v where the layer input was positive, +0 elsewhere (the ReLU's data gradient)
+__device__ __forceinline__ bf16x8 relu_mask8(bf16x8 v, bf16x8 prev) {
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = from_bf16(prev[e]) > 0.0f ? v[e] : to_bf16(0.0f);
+    return r;
+}
 
 // ---------------------------------------------------------------------------
 // Generic BF16 MFMA GEMM.  Each operand is read either along K (row-major
@@ -262,10 +269,27 @@ __device__ __forceinline__ void store_stage2(const StageRegs2<Op>& r, __bf16 (*A
     }
 }
 
+// Epilogue of ops with STORE8 (bf16 row-major outputs, N a multiple of 8):
+// the tile is converted (op.pre: bias, activation) and staged as bf16 in
+// LDS, then written 8 columns (16 bytes) per thread with op.store8.
+// C points at TM x (TN + 8) bf16 of LDS that no wave reads any more.
+template <class Op, int TM, int TN>
+__device__ __forceinline__ void store_tile8(const Op& op, __bf16* C, int m0, int n0, int M, int N) {
+    constexpr int CW = TN + 8;
+#pragma unroll
+    for (int h = 0; h < TM * TN / 2048; ++h) {
+        const int c = threadIdx.x + 256 * h;
+        const int ml = c / (TN / 8), nl = (c % (TN / 8)) * 8;
+        if (m0 + ml < M && n0 + nl < N)
+            op.store8(m0 + ml, n0 + nl, *reinterpret_cast<const bf16x8*>(&C[ml * CW + nl]));
+    }
+}
+
 template <class Op>
 __global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, int k_per_split) {
-    __shared__ __attribute__((aligned(16))) __bf16 As[GT2][LDSK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[GT][LDSK];
+    __shared__ __attribute__((aligned(16))) __bf16 smem[(GT2 + GT) * LDSK];
+    __bf16 (*As)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem);
+    __bf16 (*Bs)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem + GT2 * LDSK);
     const int m0 = blockIdx.x * GT2, n0 = blockIdx.y * GT;
     const int kbeg = blockIdx.z * k_per_split;
     const int kend = min(K, kbeg + k_per_split);
@@ -302,16 +326,32 @@ __global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, i
             }
         }
     }
+    if constexpr (Op::STORE8) {
+        static_assert(GT2 * (GT + 8) <= (GT2 + GT) * LDSK, "staged tile fits the operand tiles");
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int m = m0 + 32 * w + 16 * i + 4 * (lane >> 4) + q;
-                const int n = n0 + 16 * j + (lane & 15);
-                if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
-            }
+                for (int q = 0; q < 4; ++q) {
+                    const int ml = 32 * w + 16 * i + 4 * (lane >> 4) + q, nl = 16 * j + (lane & 15);
+                    smem[ml * (GT + 8) + nl] = n0 + nl < N ? op.pre(m0 + ml, n0 + nl, acc[i][j][q]) : to_bf16(0.0f);
+                }
+        __syncthreads();
+        store_tile8<Op, GT2, GT>(op, smem, m0, n0, M, N);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = m0 + 32 * w + 16 * i + 4 * (lane >> 4) + q;
+                    const int n = n0 + 16 * j + (lane & 15);
+                    if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
+                }
+    }
 }
 
 // Large tiles: 4 waves arranged WM x WN, each computing 64 x 64 outputs
@@ -416,8 +456,9 @@ __device__ __forceinline__ void wide_store(const WideRegs<void, R>& r, __bf16 (*
 template <class Op, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, int k_per_split) {
     constexpr int TM = 64 * WM, TN = 64 * WN;
-    __shared__ __attribute__((aligned(16))) __bf16 As[TM][LDSK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][LDSK];
+    __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSK];
+    __bf16 (*As)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem);
+    __bf16 (*Bs)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem + TM * LDSK);
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
     const int kbeg = blockIdx.z * k_per_split;
     const int kend = min(K, kbeg + k_per_split);
@@ -487,16 +528,32 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
     }
+    if constexpr (Op::STORE8) {
+        static_assert(TM * (TN + 8) <= (TM + TN) * LDSK, "staged tile fits the operand tiles");
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int m = m0 + 64 * wm + 16 * i + 4 * (lane >> 4) + q;
-                const int n = n0 + 64 * wn + 16 * j + (lane & 15);
-                if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
-            }
+                for (int q = 0; q < 4; ++q) {
+                    const int ml = 64 * wm + 16 * i + 4 * (lane >> 4) + q, nl = 64 * wn + 16 * j + (lane & 15);
+                    smem[ml * (TN + 8) + nl] = n0 + nl < N ? op.pre(m0 + ml, n0 + nl, acc[i][j][q]) : to_bf16(0.0f);
+                }
+        __syncthreads();
+        store_tile8<Op, TM, TN>(op, smem, m0, n0, M, N);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = m0 + 64 * wm + 16 * i + 4 * (lane >> 4) + q;
+                    const int n = n0 + 64 * wn + 16 * j + (lane & 15);
+                    if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
+                }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -582,6 +639,11 @@ struct OpConvFwd {
     __device__ void store(int m, int n, float v, int) const {
         out[((size_t)m << s.lCout) + n] = to_bf16(fmaxf(v + bias[n], 0.0f));
     }
+    static constexpr bool STORE8 = true;
+    __device__ __bf16 pre(int, int n, float v) const { return to_bf16(fmaxf(v + bias[n], 0.0f)); }
+    __device__ void store8(int m, int n, bf16x8 v) const {
+        *reinterpret_cast<bf16x8*>(out + ((size_t)m << s.lCout) + n) = v;
+    }
 };
 
 // data gradient: dX[b,iy,ix,ci] = sum dZ[b,y,x,co] W[co,ky,kx,ci] over iy = s y + ky - 1,
@@ -634,6 +696,12 @@ struct OpConvDgrad {
     __device__ void store(int m, int n, float v, int) const {
         const size_t q = ((size_t)m << s.lCin) + n;
         dprev[q] = to_bf16(from_bf16(prev[q]) > 0.0f ? v : 0.0f);
+    }
+    static constexpr bool STORE8 = true;
+    __device__ __bf16 pre(int, int, float v) const { return to_bf16(v); }
+    __device__ void store8(int m, int n, bf16x8 v) const {
+        const size_t q = ((size_t)m << s.lCin) + n;
+        *reinterpret_cast<bf16x8*>(dprev + q) = relu_mask8(v, ld8(prev + q));
     }
 };
 
@@ -705,6 +773,15 @@ struct OpConvDgradS2 {
         const size_t q = (pix << s.lCin) + n;
         dprev[q] = to_bf16(from_bf16(prev[q]) > 0.0f ? v : 0.0f);
     }
+    static constexpr bool STORE8 = true;
+    __device__ __bf16 pre(int, int, float v) const { return to_bf16(v); }
+    __device__ void store8(int m, int n, bf16x8 v) const {
+        const int b = m >> (2 * s.lWo), r = m & ((1 << (2 * s.lWo)) - 1);
+        const int yq = r >> s.lWo, xq = r & (s.Wo - 1);
+        const size_t pix = (((size_t)b << s.lW) + 2 * yq + py) * s.W + 2 * xq + px;
+        const size_t q = (pix << s.lCin) + n;
+        *reinterpret_cast<bf16x8*>(dprev + q) = relu_mask8(v, ld8(prev + q));
+    }
 };
 
 // weight gradient (split over K = B*Ho*Wo): dW[co][tap*Cin+ci] partial per split.
@@ -718,6 +795,7 @@ struct OpConvWgrad {
     float* part;        // [splits][Cout][9*Cin]
     // gathers of B: Cin >= 8 (the first layer has its own kernel)
     static constexpr bool CTX_A = false, CTX_B = true;
+    static constexpr bool STORE8 = false;
     __device__ WRow b_row(int n) const {
         if (n >= 9 * s.Cin) return WRow{0, -100, 0};
         const int tap = n >> s.lCin, ky = div3(tap), kx = tap - 3 * ky;
@@ -765,6 +843,7 @@ struct OpConvWgrad {
 struct OpFcFwd {
     static constexpr bool A_KMAJOR = false, B_KMAJOR = false;
     static constexpr bool CTX_A = false, CTX_B = false;
+    static constexpr bool STORE8 = false;
     int In, Out, relu;
     const __bf16* x;
     const __bf16* w;
@@ -791,6 +870,7 @@ struct OpFcFwd {
 struct OpFcDgrad {
     static constexpr bool A_KMAJOR = false, B_KMAJOR = true;
     static constexpr bool CTX_A = false, CTX_B = false;
+    static constexpr bool STORE8 = false;
     int In, Out;
     const __bf16* dy;     // [B][Out]
     const __bf16* w;      // [Out][In]
@@ -819,6 +899,7 @@ struct OpFcDgrad {
 struct OpFcWgrad {
     static constexpr bool A_KMAJOR = true, B_KMAJOR = true;
     static constexpr bool CTX_A = false, CTX_B = false;
+    static constexpr bool STORE8 = false;
     int In, Out;
     const __bf16* dy;   // [B][Out]
     const __bf16* x;    // [B][In]
@@ -953,9 +1034,12 @@ __global__ __launch_bounds__(256) void k_conv0_wgrad(const __bf16* __restrict__ 
     for (int c = 0; c < 8; ++c)
 #pragma unroll
         for (int q = 0; q < 10; ++q) acc[c][q] = 0.0f;
-    const __bf16* d = dz + ((size_t)b * CNN_IN * CNN_IN) * C0_OUT + 8 * g;
+    const __bf16* d = dz + ((size_t)b * CNN_IN * CNN_IN) * C0_OUT + 8 * g + (size_t)x * C0_OUT;
+    // the next row's 16 bytes are requested before this row's products
+    bf16x8 dn = *reinterpret_cast<const bf16x8*>(d);
     for (int y = 0; y < CNN_IN; ++y) {
-        const bf16x8 dv = *reinterpret_cast<const bf16x8*>(d + ((size_t)y * CNN_IN + x) * C0_OUT);
+        const bf16x8 dv = dn;
+        if (y + 1 < CNN_IN) dn = *reinterpret_cast<const bf16x8*>(d + (size_t)(y + 1) * CNN_IN * C0_OUT);
         float v[9];
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
