@@ -356,7 +356,8 @@ __global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, i
 
 // Large tiles: 4 waves arranged WM x WN, each computing 64 x 64 outputs
 // (4 x 4 MFMA 16x16x32 tiles): 128 x 128 (2 x 2), 256 x 64 (4 x 1) or
-// 64 x 256 (1 x 4) per work-group.  Per MFMA a wave reads half a fragment
+// 64 x 256 (1 x 4) per work-group; or 64 x 32 each (4 x 2 tiles, JT = 2)
+// for 256 x 32.  Per MFMA a wave reads half a fragment
 // from LDS (8 fragments per 16 MFMAs) against three quarters with the 32-row
 // wave tiles above.
 template <class Op, int R>
@@ -453,9 +454,9 @@ __device__ __forceinline__ void wide_store(const WideRegs<void, R>& r, __bf16 (*
     }
 }
 
-template <class Op, int WM, int WN>
+template <class Op, int WM, int WN, int JT = 4>
 __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, int k_per_split) {
-    constexpr int TM = 64 * WM, TN = 64 * WN;
+    constexpr int TM = 64 * WM, TN = 16 * JT * WN;   // each wave: 64 x 16 JT outputs
     __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSK];
     __bf16 (*As)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem);
     __bf16 (*Bs)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem + TM * LDSK);
@@ -464,11 +465,11 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
     const int kend = min(K, kbeg + k_per_split);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w / WN, wn = w % WN;
-    f32x4 acc[4][4];
+    f32x4 acc[4][JT];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < JT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     auto la = [&](int m, int k, int ke) {
         if constexpr (!Op::A_KMAJOR) return op.loadA(m, k, ke);
         else return zero8();
@@ -514,17 +515,18 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
         }
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
-            bf16x8 av[4], bv[4];
+            bf16x8 av[4], bv[JT];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 av[i] = *reinterpret_cast<const bf16x8*>(&As[64 * wm + 16 * i + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bv[j] = *reinterpret_cast<const bf16x8*>(&Bs[64 * wn + 16 * j + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
+            for (int j = 0; j < JT; ++j)
+                bv[j] = *reinterpret_cast<const bf16x8*>(
+                    &Bs[16 * JT * wn + 16 * j + (lane & 15)][32 * kk + 8 * (lane >> 4)]);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < JT; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
     }
@@ -534,10 +536,10 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < JT; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int ml = 64 * wm + 16 * i + 4 * (lane >> 4) + q, nl = 64 * wn + 16 * j + (lane & 15);
+                    const int ml = 64 * wm + 16 * i + 4 * (lane >> 4) + q, nl = 16 * JT * wn + 16 * j + (lane & 15);
                     smem[ml * (TN + 8) + nl] = n0 + nl < N ? op.pre(m0 + ml, n0 + nl, acc[i][j][q]) : to_bf16(0.0f);
                 }
         __syncthreads();
@@ -546,11 +548,11 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < JT; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int m = m0 + 64 * wm + 16 * i + 4 * (lane >> 4) + q;
-                    const int n = n0 + 64 * wn + 16 * j + (lane & 15);
+                    const int n = n0 + 16 * JT * wn + 16 * j + (lane & 15);
                     if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
                 }
     }
@@ -934,8 +936,9 @@ static hipError_t gemm_tall(const Op& op, int M, int N, int K, hipStream_t st) {
 }
 
 // Picks the tile for a GEMM shape: the 64 x 64-per-wave tiles where the
-// output is large enough in both directions to fill them, else the tall
-// (large M, no split) or the square 64 x 64 kernel.
+// output is large enough in both directions to fill them, 256 x 32 for
+// 32-column outputs, else the tall (large M, no split) or the square 64 x 64
+// kernel.
 template <class Op>
 static hipError_t gemm_pick(const Op& op, int M, int N, int K, int splits, hipStream_t st) {
     const int kps = ((K + splits - 1) / splits + GK - 1) / GK * GK;
@@ -949,6 +952,9 @@ static hipError_t gemm_pick(const Op& op, int M, int N, int K, int splits, hipSt
     } else if (M >= 64 && N >= 512) {
         hipLaunchKernelGGL((k_gemm_wide<Op, 1, 4>), dim3((M + 63) / 64, (N + 255) / 256, nz), dim3(256), 0, st, op, M,
                            N, K, kps);
+    } else if (N <= 32 && M >= 256) {
+        hipLaunchKernelGGL((k_gemm_wide<Op, 4, 1, 2>), dim3((M + 255) / 256, 1, nz), dim3(256), 0, st, op, M, N, K,
+                           kps);
     } else if (nz == 1 && M >= 4096) {
         return gemm_tall(op, M, N, K, st);
     } else {
