@@ -77,6 +77,30 @@ struct WPos {
     int base, iy, ix;
 };
 
+// XCD-aware tile order.  The dispatcher hands work-group L (in x, y, z order)
+// to XCD L mod 8, and each XCD has its own L2, so neighbouring tiles that
+// read the same operand rows (the N tiles of one K split, adjacent M tiles
+// with shared halo rows) would each fetch them from HBM.  The logical tile
+// of work-group L is taken so that every XCD runs one contiguous range of
+// logical tiles (x fastest, then y, then z): a bijection of the grid.  Used
+// where several N tiles or K splits exist (the weight gradients).
+struct TileIdx {
+    int x, y, z;
+};
+constexpr int N_XCD = 8;
+
+__device__ __forceinline__ TileIdx xcd_tile() {
+    const int gx = gridDim.x, gy = gridDim.y;
+    // one N tile and no K split: dispatch order (measured faster there)
+    if (gy == 1 && gridDim.z == 1) return TileIdx{(int)blockIdx.x, 0, 0};
+    const int n = gx * gy * gridDim.z;
+    const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int per = n / N_XCD, rem = n % N_XCD;
+    const int x = L % N_XCD, i = L / N_XCD;
+    const int g = x * per + min(x, rem) + i;   // XCD x: logical tiles [x per + min(x, rem), ...)
+    return TileIdx{g % gx, (g / gx) % gy, g / (gx * gy)};
+}
+
 // Loads of one stage into registers: along K, thread t covers row t/4 at
 // k offsets 8 (t%4) and 32 + 8 (t%4); K-major, k t%64 at rows 8 (t/64) and
 // 32 + 8 (t/64).
@@ -158,8 +182,9 @@ template <class Op>
 __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_per_split) {
     __shared__ __attribute__((aligned(16))) __bf16 As[GT][LDSK];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[GT][LDSK];
-    const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
-    const int kbeg = blockIdx.z * k_per_split;
+    const TileIdx tb = xcd_tile();
+    const int m0 = tb.x * GT, n0 = tb.y * GT;
+    const int kbeg = tb.z * k_per_split;
     const int kend = min(K, kbeg + k_per_split);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
@@ -199,7 +224,7 @@ __global__ __launch_bounds__(256) void k_gemm(Op op, int M, int N, int K, int k_
             for (int q = 0; q < 4; ++q) {
                 const int m = m0 + 32 * wm + 16 * i + 4 * (lane >> 4) + q;
                 const int n = n0 + 32 * wn + 16 * j + (lane & 15);
-                if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
+                if (m < M && n < N) op.store(m, n, acc[i][j][q], tb.z);
             }
 }
 
@@ -290,8 +315,9 @@ __global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, i
     __shared__ __attribute__((aligned(16))) __bf16 smem[(GT2 + GT) * LDSK];
     __bf16 (*As)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem);
     __bf16 (*Bs)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem + GT2 * LDSK);
-    const int m0 = blockIdx.x * GT2, n0 = blockIdx.y * GT;
-    const int kbeg = blockIdx.z * k_per_split;
+    const TileIdx tb = xcd_tile();
+    const int m0 = tb.x * GT2, n0 = tb.y * GT;
+    const int kbeg = tb.z * k_per_split;
     const int kend = min(K, kbeg + k_per_split);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     f32x4 acc[2][4];
@@ -349,7 +375,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall(Op op, int M, int N, int K, i
                 for (int q = 0; q < 4; ++q) {
                     const int m = m0 + 32 * w + 16 * i + 4 * (lane >> 4) + q;
                     const int n = n0 + 16 * j + (lane & 15);
-                    if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
+                    if (m < M && n < N) op.store(m, n, acc[i][j][q], tb.z);
                 }
     }
 }
@@ -460,8 +486,9 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
     __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSK];
     __bf16 (*As)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem);
     __bf16 (*Bs)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem + TM * LDSK);
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
-    const int kbeg = blockIdx.z * k_per_split;
+    const TileIdx tb = xcd_tile();
+    const int m0 = tb.x * TM, n0 = tb.y * TN;
+    const int kbeg = tb.z * k_per_split;
     const int kend = min(K, kbeg + k_per_split);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w / WN, wn = w % WN;
@@ -553,7 +580,7 @@ __global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, i
                 for (int q = 0; q < 4; ++q) {
                     const int m = m0 + 64 * wm + 16 * i + 4 * (lane >> 4) + q;
                     const int n = n0 + 16 * JT * wn + 16 * j + (lane & 15);
-                    if (m < M && n < N) op.store(m, n, acc[i][j][q], blockIdx.z);
+                    if (m < M && n < N) op.store(m, n, acc[i][j][q], tb.z);
                 }
     }
 }
