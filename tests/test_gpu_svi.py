@@ -267,7 +267,7 @@ def test_svi_study_miniature():
     stage returns finite samples and diagnostics."""
     from paper_2606_30633_amd.svi_study import StudyConfig, run_study
     cfg = StudyConfig(systems=1, n_map=1024, steps_map=600, n_vi=256, steps_vi=300, lr_vi=1e-4, chains=64,
-                      burn=60, n_hmc=60, mass_burn_factor=2)
+                      burn=60, n_hmc=60, burn_rerun=40, n_rerun=80, mass_burn_factor=2)
     res = run_study(cfg, log=_log)
     r = res["per_system"][0]
     assert np.isfinite(r["map_logp"]) and np.isfinite(r["truth_logp"])
@@ -278,6 +278,8 @@ def test_svi_study_miniature():
     h = r["hmc"]
     assert 0.0 <= h["acceptance"] <= 1.0 and h["eps"] > 0
     assert np.isfinite(h["rhat_max"]) and np.isfinite(h["ess_min"])
+    # the Sec. 4.2 rerun happens exactly when the first run missed split-R-hat < 1.1
+    assert h["rerun"] == (h["rhat_max_first"] >= 1.1)
     assert set(res["summary"]) >= {"adabelief_lower_final_elbo", "hmc_converged"}
 
 
