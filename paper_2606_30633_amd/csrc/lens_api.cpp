@@ -273,9 +273,12 @@ static hipError_t plan_psf(lens_plan* plan, int mode, int P, float* img, float* 
 static hipError_t plan_finalize(lens_plan* plan, int P, const float* d_theta, float* d_grad, hipStream_t st) {
     constexpr int kPreSumRows = 64;
     const int nch = chunks_for(plan->geo.npix, plan->ppt);
-    if (nch <= kPreSumRows) return launch_finalize(plan->mi, P, nch, d_theta, plan->consts, plan->partial, d_grad, st);
-    const hipError_t e =
-        launch_partial_sum(P, nch, n_acc(plan->mi), plan->partial, st);
+    if (nch == 1) return launch_finalize(plan->mi, P, 1, d_theta, plan->consts, plan->partial, d_grad, st);
+    // the chunk sums in many threads, then the chain rule per particle: few
+    // rows are summed in row order (results equal the direct finalize bit for
+    // bit), many by the lane-parallel tree
+    const hipError_t e = nch <= kPreSumRows ? launch_presum_rows(P, nch, n_acc(plan->mi), plan->partial, st)
+                                            : launch_partial_sum(P, nch, n_acc(plan->mi), plan->partial, st);
     if (e != hipSuccess) return e;
     return launch_finalize(plan->mi, P, 1, d_theta, plan->consts, plan->partial, d_grad, st, nch);
 }
@@ -462,11 +465,11 @@ static lens_status logpost_enqueue(lens_plan* plan, int32_t P, const float* d_u,
         TimedLaunch tl(&plan->timer, LENS_K_POSTERIOR, st);
         if (launch_bijection(P, d, plan->prior, d_u, th, st) != hipSuccess) return LENS_EHIP;
     }
-    uint64_t skip = 0;
+    ParamMask skip;
     lens_status s;
     if (plan->backward) {
         const BwdSlots bs = bwd_slots(plan);
-        for (int k = 0; k < bs.K; ++k) skip |= (uint64_t)1 << bs.slot[k];
+        for (int k = 0; k < bs.K; ++k) skip.set(bs.slot[k]);
         s = backward_enqueue(plan, P, th, plan->logl, plan->gtheta, nullptr, plan->logl64, st);
     } else {
         s = loglike_grad_enqueue(plan, P, th, plan->logl, plan->gtheta, plan->logl64, st);

@@ -170,7 +170,10 @@ hipError_t launch_psf_tiled(const Geo& g, int K, int mode, int P, const float* c
                             const double* wflip, const float* wpsf, const float* data, const float* invvar,
                             float* out, float* logl, double* logl64, double* chi_part, hipStream_t st);
 int psf_num_tiles(const Geo& g);
-// Sums each particle's nch partial rows into its first row (k_finalize then takes nchunks = 1).
+// Sum each particle's nch partial rows into its first row (k_finalize then
+// takes nchunks = 1): in row order (the direct finalize's order) ...
+hipError_t launch_presum_rows(int P, int nch, int nacc, double* partial, hipStream_t st);
+// ... or lane-strided with a fixed butterfly (many rows).
 hipError_t launch_partial_sum(int P, int nch, int nacc, double* partial, hipStream_t st);
 size_t psf_lds_bytes(const Geo& g, int K);
 constexpr size_t MAX_LDS_BYTES = 160 * 1024 - 256;   // dynamic part; statics need < 256 B

@@ -1501,6 +1501,20 @@ __global__ __launch_bounds__(64) void k_partial_sum(int nch, int nacc, double* _
     if (lane == 0) base[a] = s;
 }
 
+// In place, for every (particle, accumulator): the sum over the particle's
+// nch partial rows in row order (the order k_finalize sums them) into row 0,
+// so k_finalize then reads one row with the same result.  Each thread writes
+// only its own column.
+__global__ void k_presum_rows(int P, int nch, int nacc, double* __restrict__ partial) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)P * nacc) return;
+    const int p = (int)(i / nacc), a = (int)(i % nacc);
+    double* base = partial + (size_t)p * nch * nacc;
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += base[(size_t)ch * nacc + a];
+    base[a] = s;
+}
+
 __global__ void k_flip(int K, const float* __restrict__ psf, double* __restrict__ flipped) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= K * K) return;
@@ -1844,6 +1858,12 @@ hipError_t launch_psf_tiled(const Geo& g, int K, int mode, int P, const float* c
 #undef LENS_TPSF_CASE
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_presum_rows(int P, int nch, int nacc, double* partial, hipStream_t st) {
+    const long long n = (long long)P * nacc;
+    hipLaunchKernelGGL(k_presum_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, nch, nacc, partial);
+    return hipGetLastError();
 }
 
 hipError_t launch_partial_sum(int P, int nch, int nacc, double* partial, hipStream_t st) {

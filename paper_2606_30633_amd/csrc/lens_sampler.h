@@ -89,10 +89,21 @@ bool build_prior_rows(int d, const float* h_table, PriorRow* rows);
 
 hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u, float* theta,
                             hipStream_t st);
-// skip: bit j set -> entry j is not a parameter (no prior or Jacobian term, gradient 0).
+// A set of parameter indices 0..127 (the largest model, EPL with one lens
+// light, one Sersic source and an n_max = 8 shapelet source, has 70).
+constexpr int PARAM_MASK_BITS = 128;
+struct ParamMask {
+    uint64_t w[2] = {0, 0};
+    __host__ __device__ bool test(int j) const { return (w[j >> 6] >> (j & 63)) & 1u; }
+    __host__ void set(int j) { w[j >> 6] |= (uint64_t)1 << (j & 63); }
+};
+
+// skip: j in skip -> entry j is not a parameter (no prior or Jacobian term, gradient 0).
+// One wave per particle (parameters over the lanes); the log-prior and
+// log-Jacobian sums run in parameter order.  d <= PARAM_MASK_BITS.
 hipError_t launch_posterior(int P, int d, const PriorRow* table, const float* u, const double* logl,
                             const float* gtheta, int with_jac, double* logp, float* grad_u,
-                            hipStream_t st, uint64_t skip = 0);
+                            hipStream_t st, const ParamMask& skip = ParamMask{});
 hipError_t launch_adam(int P, int d, const float* grad_u, const double* logp, float* u, float* m,
                        float* v, const int* step, const AdamHyper& hp, float* loss,
                        hipStream_t st);

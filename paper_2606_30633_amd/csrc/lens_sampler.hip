@@ -93,37 +93,56 @@ __global__ void k_bijection(int P, int d, const PriorRow* __restrict__ table,
     theta[q] = (float)th;
 }
 
-// logp = logL(theta) + log prior(theta) [+ log J]; grad_u = (g_theta + dlp) dth [+ dlogJ]
-__global__ void k_posterior(int P, int d, const PriorRow* __restrict__ table,
-                            const float* __restrict__ u, const double* __restrict__ logl,
-                            const float* __restrict__ gtheta, int with_jac, uint64_t skip,
-                            double* __restrict__ logp, float* __restrict__ grad_u) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const double L = logl[p];
-    const float* up = u + (size_t)p * d;
-    const float* gp = gtheta + (size_t)p * d;
-    float* go = grad_u + (size_t)p * d;
-    if (!isfinite(L)) {
-        logp[p] = L;
+// logp = logL(theta) + log prior(theta) [+ log J]; grad_u = (g_theta + dlp) dth [+ dlogJ].
+// One wave per particle: lane j (and j + 64) evaluates parameter j; lane 0
+// then sums the log-prior and log-Jacobian terms in parameter order.
+constexpr int POST_WAVES = 4;   // particles per 256-thread work-group
+
+__global__ __launch_bounds__(256) void k_posterior(int P, int d, const PriorRow* __restrict__ table,
+                                                   const float* __restrict__ u, const double* __restrict__ logl,
+                                                   const float* __restrict__ gtheta, int with_jac, ParamMask skip,
+                                                   double* __restrict__ logp, float* __restrict__ grad_u) {
+    __shared__ double terms[POST_WAVES][2][PARAM_MASK_BITS];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = blockIdx.x * POST_WAVES + wv;
+    const bool active = p < P;
+    const double L = active ? logl[p] : 0.0;
+    const bool finite = isfinite(L);
+    if (active) {
+        const float* up = u + (size_t)p * d;
+        const float* gp = gtheta + (size_t)p * d;
+        float* go = grad_u + (size_t)p * d;
         const float z = isnan(L) ? __builtin_nanf("") : 0.0f;
-        for (int j = 0; j < d; ++j) go[j] = z;
-        return;
-    }
-    double lp_sum = 0.0, lj_sum = 0.0;
-    for (int j = 0; j < d; ++j) {
-        if ((skip >> j) & 1u) {          // not a parameter (backward-modelled intensity)
-            go[j] = 0.0f;
-            continue;
+        for (int j = lane; j < d; j += 64) {
+            double lp = 0.0, lj = 0.0;
+            if (!finite) {
+                go[j] = z;
+            } else if (skip.test(j)) {   // not a parameter (backward-modelled intensity)
+                go[j] = 0.0f;
+            } else {
+                double th, dth, dlj, dlp;
+                bijection(table[j], (double)up[j], th, dth, lj, dlj);
+                log_prior(table[j], th, lp, dlp);
+                go[j] = (float)(((double)gp[j] + dlp) * dth + (with_jac ? dlj : 0.0));
+            }
+            terms[wv][0][j] = lp;
+            terms[wv][1][j] = lj;
         }
-        double th, dth, lj, dlj, lp, dlp;
-        bijection(table[j], (double)up[j], th, dth, lj, dlj);
-        log_prior(table[j], th, lp, dlp);
-        lp_sum += lp;
-        lj_sum += lj;
-        go[j] = (float)(((double)gp[j] + dlp) * dth + (with_jac ? dlj : 0.0));
     }
-    logp[p] = L + lp_sum + (with_jac ? lj_sum : 0.0);
+    __syncthreads();
+    if (active && lane == 0) {
+        if (!finite) {
+            logp[p] = L;
+        } else {
+            double lp_sum = 0.0, lj_sum = 0.0;
+            for (int j = 0; j < d; ++j) {
+                if (skip.test(j)) continue;
+                lp_sum += terms[wv][0][j];
+                lj_sum += terms[wv][1][j];
+            }
+            logp[p] = L + lp_sum + (with_jac ? lj_sum : 0.0);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -394,9 +413,10 @@ hipError_t launch_bijection(int P, int d, const PriorRow* table, const float* u,
 
 hipError_t launch_posterior(int P, int d, const PriorRow* table, const float* u, const double* logl,
                             const float* gtheta, int with_jac, double* logp, float* grad_u,
-                            hipStream_t st, uint64_t skip) {
-    hipLaunchKernelGGL(k_posterior, blocks_for(P, 64), dim3(64), 0, st, P, d, table, u, logl,
-                       gtheta, with_jac, skip, logp, grad_u);
+                            hipStream_t st, const ParamMask& skip) {
+    if (d < 1 || d > PARAM_MASK_BITS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_posterior, dim3((P + POST_WAVES - 1) / POST_WAVES), dim3(64 * POST_WAVES), 0, st, P, d,
+                       table, u, logl, gtheta, with_jac, skip, logp, grad_u);
     return hipGetLastError();
 }
 

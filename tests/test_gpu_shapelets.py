@@ -121,3 +121,36 @@ def test_nonpositive_scale_is_invalid_and_batch_plans_refuse_shapelets():
     with pytest.raises(lens.LensError) as e:
         lens.BatchPlan([spec], [psf], [data], [sysm.invvar], [4], DEV)
     assert e.value.status == lens.LENS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("jac", [False, True])
+def test_backward_posterior_with_more_than_64_parameters(jac):
+    """EPL + one lens light + one Sersic source + an n_max = 8 shapelet source
+    has d = 70, so backward-modelled intensity slots lie beyond the 64th
+    parameter: the posterior must skip exactly those (no prior or Jacobian
+    term, zero gradient) and agree with the oracle's backward posterior."""
+    spec, psf, sysm, data, th = shapelet_case("EPL", 1, 1, 8, n_prior=3, n_near=1)
+    assert spec.n_params == 70
+    slots = O.intensity_slots(spec)
+    assert max(slots) >= 64
+    dists = synth.uniform_box_dists(spec) + [synth.U(0.05, 0.6), synth.U(-0.2, 0.2), synth.U(-0.2, 0.2)] + \
+        [synth.N(0.0, 1.0)] * spec.n_shapelet_coeffs
+    table = synth.prior_table(dists)
+    assert table.shape[0] == spec.n_params
+    # starting points inside the box (the shapelet block of the case is inside these ranges)
+    thp = th.astype(np.float64).copy()
+    lo = np.array([d.row()[1] for d in dists[:22]]); hi = np.array([d.row()[2] for d in dists[:22]])
+    thp[:, :22] = np.clip(thp[:, :22], lo + 1e-3 * (hi - lo), hi - 1e-3 * (hi - lo))
+    u = np.stack([O.to_unconstrained(torch.tensor(t, dtype=torch.float64), table).numpy() for t in thp])
+    u = u.astype(np.float32)
+    K = len(slots)
+    plan = lens.LensPlan(spec, psf, data, sysm.invvar, u.shape[0] * K, DEV)
+    plan.set_prior(table)
+    plan.set_backward(True)
+    _log(f"backward posterior d = {spec.n_params}, K = {K}, jac {jac}")
+    lp, g = (t.cpu().numpy() for t in lens.lens_logpost_grad(plan, torch.tensor(u, device=DEV), jac))
+    for p in range(u.shape[0]):
+        lo_, go = O.log_posterior_backward(u[p], spec, psf, data, sysm.invvar, table, jac, theta_float32=True)
+        assert np.all(g[p][slots] == 0), p
+        assert abs(lp[p] - lo_) <= 1e-5 * abs(lo_), (p, lp[p], lo_)
+        assert np.linalg.norm(g[p] - go) <= 1e-5 * np.linalg.norm(go), p
