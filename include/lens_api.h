@@ -442,6 +442,13 @@ int64_t lens_batch_total_particles(const lens_batch_plan* plan);
 lens_status lens_batch_set_particles(lens_batch_plan* plan, const int32_t* h_particles);
 lens_status lens_batch_get_particles(const lens_batch_plan* plan, int32_t* h_particles);
 
+/* The same per-call form in one call: lens_batch_set_particles(h_particles)
+ * then lens_batch_loglike_grad; d_theta [N][d], N = sum of h_particles.
+ * Errors: those of the two calls. */
+lens_status lens_batch_loglike_grad_counts(lens_batch_plan* plan, const int32_t* h_particles,
+                                           const float* d_theta, float* d_logl, float* d_grad,
+                                           int32_t use_graph, void* stream);
+
 /* logL and dlogL/dtheta for every particle of every system.
  *   d_theta [N][d] in, d_logl [N] out, d_grad [N][d] out, N = total particles.
  * use_graph != 0: the whole sequence is captured into a HIP graph on first

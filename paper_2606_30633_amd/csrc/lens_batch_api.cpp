@@ -365,6 +365,14 @@ lens_status lens_batch_set_particles(lens_batch_plan* b, const int32_t* h_partic
     return s != LENS_OK ? s : rebuild(b);
 }
 
+lens_status lens_batch_loglike_grad_counts(lens_batch_plan* b, const int32_t* h_particles, const float* d_theta,
+                                           float* d_logl, float* d_grad, int32_t use_graph, void* stream) {
+    if (!b || !h_particles || !d_theta || !d_logl || !d_grad) return LENS_EINVAL;
+    const lens_status s = lens_batch_set_particles(b, h_particles);
+    if (s != LENS_OK) return s;
+    return lens_batch_loglike_grad(b, d_theta, d_logl, d_grad, use_graph, stream);
+}
+
 lens_status lens_batch_get_particles(const lens_batch_plan* b, int32_t* h_particles) {
     if (!b || !h_particles) return LENS_EINVAL;
     for (int k = 0; k < b->S; ++k) h_particles[k] = b->P[k];

@@ -72,6 +72,7 @@ _SIGNATURES = {
     "lens_batch_total_particles": (ctypes.c_int64, [_P]),
     "lens_batch_set_particles": (_I, [_P, _P]),
     "lens_batch_get_particles": (_I, [_P, _P]),
+    "lens_batch_loglike_grad_counts": (_I, [_P, _P, _P, _P, _P, _I, _P]),
     "lens_batch_loglike_grad": (_I, [_P, _P, _P, _P, _I, _P]),
     "lens_batch_get_tiles": (_I, [_P, _P]),
     "lens_batch_set_tiles": (_I, [_P, _P]),
@@ -597,6 +598,24 @@ class BatchPlan:
         _check(_lib.lens_batch_set_particles(self.handle, arr), "lens_batch_set_particles")
         self.particles = [int(n) for n in particles]
         self.N = int(_lib.lens_batch_total_particles(self.handle))
+
+    def loglike_grad_counts(self, particles, theta, use_graph=False, stream=None):
+        """logL and gradient with per-call particle counts (one C call)."""
+        if len(particles) != self.S or any(not 1 <= int(n) <= c for n, c in zip(particles, self.capacity)):
+            raise ValueError(f"particles must be {self.S} counts within the plan's capacity {self.capacity}")
+        n = sum(int(x) for x in particles)
+        if theta.dtype != torch.float32 or theta.device != self.device or not theta.is_contiguous() \
+                or theta.shape != (n, self.d):
+            raise ValueError(f"theta must be contiguous float32 [{n}, {self.d}] on the plan's device")
+        logl = torch.empty(n, dtype=torch.float32, device=self.device)
+        grad = torch.empty((n, self.d), dtype=torch.float32, device=self.device)
+        arr = (ctypes.c_int32 * self.S)(*[int(x) for x in particles])
+        _check(_lib.lens_batch_loglike_grad_counts(self.handle, arr, theta.data_ptr(), logl.data_ptr(),
+                                                   grad.data_ptr(), 1 if use_graph else 0, _stream(stream)),
+               "lens_batch_loglike_grad_counts")
+        self.particles = [int(x) for x in particles]
+        self.N = n
+        return logl, grad
 
     def get_particles(self):
         out = (ctypes.c_int32 * self.S)()

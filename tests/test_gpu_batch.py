@@ -98,6 +98,8 @@ def test_batch_per_call_particle_counts():
         ref = lens.BatchPlan(specs, *args, counts, DEV)
         Lr, Gr = ref.loglike_grad(tt)
         assert torch.equal(Lr, Le) and torch.equal(Gr, Ge)
+        Lc, Gc = bp.loglike_grad_counts(counts, tt)            # the one-call form
+        assert torch.equal(Lc, Le) and torch.equal(Gc, Ge)
         best, arg = bp.argmin(-Le)
         off = 0
         Ln = Le.cpu().numpy()
