@@ -571,11 +571,14 @@ lens_status lens_cnn_set_target_map(lens_cnn* net, int32_t d, const float* h_pri
 
 /* Starting particles for S systems: d_img64 [S][64][64] float images (crop or
  * zero-pad to 64x64 at the native pixel scale), n_per_system draws each:
- * mapped parameters theta_j = mean_k + std_k (mu_k + e^{s_k/2} z), z ~ N(0,1),
- * the others from the prior; Philox4x32-10 with the given seed, counter
- * (system, draw, parameter).  d_theta_out [S][n][d]; d_flags [S] (optional):
- * 1 if a proposal had to be clipped into the prior support, else 0.  Falling
- * back to prior-sampled starts is the caller's decision (see the time-to-MAP
+ * a mapped parameter is drawn from the network's Gaussian
+ * N(mean_k + std_k mu_k, (std_k e^{s_k/2})^2) truncated to the parameter's
+ * prior support (inverse CDF), or from its prior when the support holds less
+ * than half of that Gaussian; the others from the prior; Philox4x32-10 with
+ * the given seed, counter (system, draw, parameter).  d_theta_out [S][n][d];
+ * d_flags [S] (optional): 1 if, for some mapped parameter, the support holds
+ * less than 99 % of the network's Gaussian, else 0.  Falling back to
+ * prior-sampled starts is the caller's decision (see the time-to-MAP
  * driver).  Requires lens_cnn_set_target_map. */
 lens_status init_propose(lens_cnn* net, int32_t S, const float* d_img64, int32_t n_per_system,
                          uint64_t seed, float* d_theta_out, int32_t* d_flags, void* stream);

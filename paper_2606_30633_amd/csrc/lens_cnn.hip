@@ -1329,9 +1329,20 @@ __global__ void k_prepare(long long n, const float* __restrict__ img, float sigm
 // ---------------------------------------------------------------------------
 __device__ double ndtri_d(double p) { return 1.4142135623730951 * erfinv(2.0 * p - 1.0); }
 __device__ double ndtr_d(double z) { return 0.5 * erfc(-z * 0.7071067811865476); }
+// the same inverse for small p (no loss in 2p - 1): -sqrt(2) erfcinv(2p)
+__device__ double ndtri_lo(double p) { return -1.4142135623730951 * erfcinv(2.0 * p); }
 
 // One thread per proposal (system s0 + s, draw i); counters use the global
 // system index so that chunked calls draw the same numbers.
+// A draw from prior row (kind, a, b, lo, hi) by inverse CDF of u in (0, 1).
+__device__ double prior_draw(int kind, double a, double b, double lo, double hi, double u) {
+    if (kind == LENS_PRIOR_UNIFORM) return a + (b - a) * u;
+    if (kind == LENS_PRIOR_NORMAL) return a + b * ndtri_d(u);
+    if (kind == LENS_PRIOR_LOGNORMAL) return exp(a + b * ndtri_d(u));
+    const double pl = ndtr_d((lo - a) / b), ph = ndtr_d((hi - a) / b);
+    return a + b * ndtri_d(pl + u * (ph - pl));
+}
+
 __global__ void k_propose(int S, int s0, int n, int d, const float* __restrict__ net_out,
                           const CnnTargetMap* __restrict__ tm, uint64_t seed, float* __restrict__ theta,
                           int* __restrict__ flags) {
@@ -1347,28 +1358,50 @@ __global__ void k_propose(int S, int s0, int n, int d, const float* __restrict__
         const int c = tm->cnn_slot[j];
         double v;
         if (c >= 0) {
+            // the network's Gaussian N(m, sd^2) truncated to the prior's support,
+            // drawn by inverse CDF on tail probabilities when the support lies
+            // in a tail (so that they stay accurate); the system is flagged
+            // when the truncation removes more than 1 % of the mass
             const double mu = net_out[(size_t)s * CNN_OUT + c];
             const double ls = fmin(fmax((double)net_out[(size_t)s * CNN_OUT + CNN_NT + c], -30.0), 10.0);
-            const double z = normal_at(seed, sg, (uint32_t)i, 16u + (uint32_t)j);
-            v = tm->mean[c] + tm->stdv[c] * (mu + exp(0.5 * ls) * z);
+            const double m = tm->mean[c] + tm->stdv[c] * mu, sd = tm->stdv[c] * exp(0.5 * ls);
             double vlo = -INFINITY, vhi = INFINITY;
             if (kind == LENS_PRIOR_UNIFORM) { vlo = a; vhi = b; }
             else if (kind == LENS_PRIOR_TRUNCNORMAL) { vlo = lo; vhi = hi; }
             else if (kind == LENS_PRIOR_LOGNORMAL) { vlo = 0.0; }
-            const double eps = 1e-6 * (vhi - vlo < INFINITY ? (vhi - vlo) : 1.0);
-            if (v <= vlo) { v = vlo + eps; clipped = 1; }
-            if (v >= vhi) { v = vhi - eps; clipped = 1; }
+            const double al = (vlo - m) / sd, be = (vhi - m) / sd;
+            const uint4 w = philox_c(make_uint4(sg, (uint32_t)i, 16u + (uint32_t)j, 0x7e1u),
+                                     make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+            const double u = unif(w.x);
+            double z, mass;
+            if (be < 0.0) {            // support in the lower tail: small probabilities
+                const double pa = ndtr_d(al), pb = ndtr_d(be);
+                mass = pb - pa;
+                z = ndtri_lo(pa + u * mass);
+            } else if (al > 0.0) {     // upper tail, by symmetry
+                const double pa = ndtr_d(-be), pb = ndtr_d(-al);
+                mass = pb - pa;
+                z = -ndtri_lo(pa + u * mass);
+            } else {                   // the support holds the mean
+                const double pa = ndtr_d(al), pb = ndtr_d(be);
+                mass = pb - pa;
+                z = ndtri_d(pa + u * mass);
+            }
+            if (!(mass >= 0.99)) clipped = 1;
+            if (mass >= 0.5) {
+                v = m + sd * z;
+                // rounding guard: keep the draw strictly inside the support
+                const double eps = 1e-9 * (vhi - vlo < INFINITY ? (vhi - vlo) : 1.0);
+                v = fmin(fmax(v, vlo + eps), vhi - eps);
+            } else {
+                // the network's Gaussian lies mostly outside the support (its
+                // truncation would hug the bound): a prior draw instead
+                v = prior_draw(kind, a, b, lo, hi, u);
+            }
         } else {
             const uint4 w = philox_c(make_uint4(sg, (uint32_t)i, 64u + (uint32_t)j, 0x9a1u),
                                      make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
-            const double u = unif(w.x);
-            if (kind == LENS_PRIOR_UNIFORM) v = a + (b - a) * u;
-            else if (kind == LENS_PRIOR_NORMAL) v = a + b * ndtri_d(u);
-            else if (kind == LENS_PRIOR_LOGNORMAL) v = exp(a + b * ndtri_d(u));
-            else {
-                const double pl = ndtr_d((lo - a) / b), ph = ndtr_d((hi - a) / b);
-                v = a + b * ndtri_d(pl + u * (ph - pl));
-            }
+            v = prior_draw(kind, a, b, lo, hi, unif(w.x));
         }
         th[j] = (float)v;
     }

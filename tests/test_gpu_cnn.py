@@ -175,20 +175,36 @@ def test_init_propose_distribution():
         assert pv > 1e-4, (j, pv)
 
 
-def test_init_propose_clips_to_support_and_flags():
+def test_init_propose_truncates_to_support_and_flags():
     table = synth.prior_table(synth.paper_prior_dists())
     cs = [_center_scale(table[k]) for k in range(C.NT)]
     mean = np.array([c[0] for c in cs], np.float32)
     std = np.array([0.1 * c[1] for c in cs], np.float32)
     mean[1] = 3.5          # power-law slope: truncated normal on [1, 3]
     net = _fixed_output_net(table, mean, std)
-    th, flags = lens.init_propose(net, torch.zeros((5, 64, 64), device=DEV), 100, 3)
+    th, flags = lens.init_propose(net, torch.zeros((5, 64, 64), device=DEV), 4000, 3)
     assert flags.cpu().tolist() == [1] * 5
-    g = th[..., 1].cpu().numpy()
+    g = th[..., 1].cpu().numpy().astype(np.float64)
     assert (g > 1.0).all() and (g < 3.0).all()
+    # the network's Gaussian (mean 3.5) lies outside the support [1, 3]: the
+    # slope comes from its prior (normal (2, 0.5) truncated to [1, 3])
+    kind, a, b, lo, hi = (float(x) for x in table[1])
+    tn = stats.truncnorm((lo - a) / b, (hi - a) / b, loc=a, scale=b)
+    assert stats.kstest(g[0], tn.cdf).pvalue > 1e-4
+    # a Gaussian straddling the upper bound (mean 2.95, sd 0.1): the truncated
+    # network Gaussian, flagged (more than 1 % of it lies outside)
+    mean2 = mean.copy()
+    std2 = std.copy()
+    mean2[1], std2[1] = 2.9, 0.1            # m = 2.9 + 0.05 = 2.95, sd = 0.05
+    net3 = _fixed_output_net(table, mean2, std2)
+    th3, flags3 = lens.init_propose(net3, torch.zeros((2, 64, 64), device=DEV), 4000, 5)
+    assert flags3.cpu().tolist() == [1, 1]
+    g3 = th3[0, :, 1].cpu().numpy().astype(np.float64)
+    tn3 = stats.truncnorm((1.0 - 2.95) / 0.05, (3.0 - 2.95) / 0.05, loc=2.95, scale=0.05)
+    assert (g3 < 3.0).all() and stats.kstest(g3, tn3.cdf).pvalue > 1e-4
     # chunked evaluation (max batch 4 < 5 systems) draws the same numbers as one call
     net2 = _fixed_output_net(table, mean, std, n=8)
-    th2, _ = lens.init_propose(net2, torch.zeros((5, 64, 64), device=DEV), 100, 3)
+    th2, _ = lens.init_propose(net2, torch.zeros((5, 64, 64), device=DEV), 4000, 3)
     assert torch.equal(th, th2)
 
 
