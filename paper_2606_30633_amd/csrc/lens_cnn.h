@@ -28,6 +28,18 @@ struct CnnLayer {
     long long w_off, b_off;   // offsets into the flat parameter vector
 };
 
+// Bias gradients are column sums over row chunks (fixed order): rows per
+// chunk for a matrix of `rows` rows, and the chunk-partial buffer size that
+// covers every layer at a batch limit (chunks <= max(batch, 288), columns <= 256).
+inline int colsum_rows_per_chunk(int rows) {
+    if (rows >= 262144) return 1024;
+    const int r = rows / 256;
+    return r < 8 ? 8 : r;
+}
+inline long long colpart_capacity(int max_batch) {
+    return ((long long)(max_batch > 288 ? max_batch : 288) + 1) * CNN_H1;
+}
+
 // Where the network's outputs go in a parameter vector, and the prior of the rest.
 struct CnnTargetMap {
     int d;

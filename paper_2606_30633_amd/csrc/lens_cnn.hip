@@ -1068,22 +1068,32 @@ __global__ __launch_bounds__(256) void k_conv0_wgrad(const __bf16* __restrict__ 
 #pragma unroll
         for (int q = 0; q < 10; ++q) acc[c][q] = 0.0f;
     const __bf16* d = dz + ((size_t)b * CNN_IN * CNN_IN) * C0_OUT + 8 * g + (size_t)x * C0_OUT;
-    // the next row's 16 bytes are requested before this row's products
-    bf16x8 dn = *reinterpret_cast<const bf16x8*>(d);
-    for (int y = 0; y < CNN_IN; ++y) {
-        const bf16x8 dv = dn;
-        if (y + 1 < CNN_IN) dn = *reinterpret_cast<const bf16x8*>(d + (size_t)(y + 1) * CNN_IN * C0_OUT);
-        float v[9];
+    // the 16 bytes of row y + PF are requested before row y's products (a
+    // ring of PF rows in flight; one work-group per image leaves few waves
+    // per SIMD to hide the latency)
+    constexpr int PF = 4;
+    constexpr size_t ROW = (size_t)CNN_IN * C0_OUT;
+    bf16x8 ring[PF];
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
+    for (int q = 0; q < PF; ++q) ring[q] = *reinterpret_cast<const bf16x8*>(d + q * ROW);
+    for (int y0 = 0; y0 < CNN_IN; y0 += PF) {
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) v[3 * ky + kx] = tile[y + ky][x + kx];
+        for (int q = 0; q < PF; ++q) {
+            const int y = y0 + q;
+            const bf16x8 dv = ring[q];
+            if (y + PF < CNN_IN) ring[q] = *reinterpret_cast<const bf16x8*>(d + (y + PF) * ROW);
+            float v[9];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float dc = from_bf16(dv[c]);
+            for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-            for (int q = 0; q < 9; ++q) acc[c][q] = fmaf(dc, v[q], acc[c][q]);
-            acc[c][9] += dc;
+                for (int kx = 0; kx < 3; ++kx) v[3 * ky + kx] = tile[y + ky][x + kx];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float dc = from_bf16(dv[c]);
+#pragma unroll
+                for (int r = 0; r < 9; ++r) acc[c][r] = fmaf(dc, v[r], acc[c][r]);
+                acc[c][9] += dc;
+            }
         }
     }
     // lanes 4 j + g (j = 0..15) of a wave hold the same channels: butterfly over j
@@ -1137,18 +1147,28 @@ __global__ void k_sum_splits(int nz, long long n, const float* __restrict__ part
     out[i] = (float)s;
 }
 
-// The same with one wave per output (many splits, few outputs): lane l sums
-// splits l, l + 64, ...; the lanes are then combined by a fixed butterfly.
-__global__ __launch_bounds__(256) void k_sum_splits_wave(int nz, long long n, const float* __restrict__ part,
-                                                         float* __restrict__ out) {
-    const long long i = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= n) return;
+// The same for many splits, read coalesced: a work-group of 64 G threads
+// takes 64 consecutive outputs; wave g sums splits [g zc, (g + 1) zc) in
+// order (64 consecutive floats per split row), then the G wave sums are
+// added in g order.  Each output's order is fixed by (nz, zc).
+__global__ __launch_bounds__(1024) void k_sum_splits_cols(int nz, int zc, long long n,
+                                                          const float* __restrict__ part, float* __restrict__ out) {
+    __shared__ double red[16][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6, G = blockDim.x >> 6;
+    const long long i = (long long)blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int z = lane; z < nz; z += 64) s += part[(size_t)z * n + i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) out[i] = (float)s;
+    if (i < n) {
+        const int z1 = min(nz, (g + 1) * zc);
+#pragma unroll 8
+        for (int z = g * zc; z < z1; ++z) s += part[(size_t)z * n + i];
+    }
+    red[g][lane] = s;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        double t = red[0][lane];
+        for (int q = 1; q < G; ++q) t += red[q][lane];
+        out[i] = (float)t;
+    }
 }
 
 // column sums of a bf16 matrix [rows][cols] (bias gradients), fixed order:
@@ -1447,8 +1467,10 @@ hipError_t cnn_forward(CnnNet& net, int B, const __bf16* img, hipStream_t st) {
 // bias gradient = column sums of dz [rows][cols]
 static hipError_t bias_grad(CnnNet& net, int rows, int cols, const __bf16* dz, float* db, hipStream_t st) {
     // chunks of rows_per_chunk rows: about 1 KB of a column group per thread
-    const int rpc = (cols & 7) == 0 && cols <= 2048 ? 1024 : 4096;
+    // for tall matrices, and at least ~256 chunks (work-groups) for short ones
+    const int rpc = colsum_rows_per_chunk(rows);
     const int chunks = (rows + rpc - 1) / rpc;
+    if ((long long)chunks * cols > colpart_capacity(net.max_batch)) return hipErrorInvalidValue;
     if ((cols & 7) == 0 && cols <= 2048)
         hipLaunchKernelGGL(k_colsum8_partial, dim3(chunks), dim3(256), 0, st, rows, cols, rpc, dz, net.colpart);
     else
@@ -1495,10 +1517,11 @@ hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* targ
         OpConvWgrad wg{s, net.dact[l], in, net.wpart};
         if (gemm_pick(wg, L.cout, 9 * L.cin, K, wgrad_splits(K), st) != hipSuccess) return hipErrorLaunchFailure;
         const long long nw = (long long)L.cout * 9 * L.cin;
-        if (splits >= 64)
-            hipLaunchKernelGGL(k_sum_splits_wave, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, st, splits, nw,
-                               net.wpart, net.grads + L.w_off);
-        else
+        if (splits >= 64) {
+            const int G = splits >= 512 ? 16 : (splits + 31) / 32, zc = (splits + G - 1) / G;
+            hipLaunchKernelGGL(k_sum_splits_cols, dim3((unsigned)((nw + 63) / 64)), dim3(64 * G), 0, st, splits, zc,
+                               nw, net.wpart, net.grads + L.w_off);
+        } else
             hipLaunchKernelGGL(k_sum_splits, g1(nw), dim3(256), 0, st, splits, nw, net.wpart, net.grads + L.w_off);
         if (bias_grad(net, K, L.cout, net.dact[l], net.grads + L.b_off, st) != hipSuccess) return hipErrorLaunchFailure;
         if (l > 0 && L.stride == 1) {

@@ -93,7 +93,7 @@ lens_status lens_cnn_create(int32_t max_batch, uint64_t seed, lens_cnn** out) {
     }
     ok = ok && alloc(&n.pooled, B * CNN_C6) && alloc(&n.dpooled, B * CNN_C6) && alloc(&n.hidden, B * CNN_H1) &&
          alloc(&n.dhidden, B * CNN_H1) && alloc(&n.out, B * CNN_OUT) && alloc(&n.dout, B * CNN_OUT) &&
-         alloc(&n.wpart, wpart) && alloc(&n.colpart, (B * CNN_IN * CNN_IN / 4096 + 1) * 256) &&
+         alloc(&n.wpart, wpart) && alloc(&n.colpart, (size_t)colpart_capacity(max_batch)) &&
          alloc(&n.losspart, B / 256 + 1) && alloc(&n.c0part, B * 32 * 10) && alloc(&n.tmap, 1) &&
          alloc(&n.prep, B * CNN_IN * CNN_IN) &&
          alloc(&n.img_stage, B * CNN_IN * CNN_IN) && alloc(&n.tgt_stage, B * CNN_NT) && alloc(&n.hyper, 2) &&
