@@ -101,6 +101,40 @@ __device__ __forceinline__ TileIdx xcd_tile() {
     return TileIdx{g % gx, (g / gx) % gy, g / (gx * gy)};
 }
 
+// Ops that run several GEMMs of one output shape in one launch (the four
+// input-parity classes of a stride-2 data gradient) define CLASSES = true,
+// set_class(c) and class_k() (the K extent of class c); the launch has
+// gridDim.z = number of classes and no K split.
+template <class Op, class = void>
+struct has_classes {
+    static constexpr bool value = false;
+};
+template <class Op>
+struct has_classes<Op, decltype((void)Op::CLASSES)> {
+    static constexpr bool value = Op::CLASSES;
+};
+
+// Tile order of a class launch: the classes of one output tile are read
+// from the same operand rows, so they run back to back on one XCD (one L2).
+// Work-group L goes to XCD L mod 8 as its (L / 8)-th group there; in each
+// run of 32 work-groups the four classes of tile i / 4 * 8 + L mod 8 follow
+// each other on that XCD.  The remainder (fewer than 32) is in dispatch order.
+__device__ __forceinline__ TileIdx class_tile() {
+    const int gx = gridDim.x, nc = gridDim.z;
+    const int L = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int n = gx * gridDim.y * nc, full = n / (N_XCD * nc) * (N_XCD * nc);
+    int cls, t;
+    if (L < full) {
+        const int x = L % N_XCD, i = L / N_XCD;
+        cls = i % nc;
+        t = (i / nc) * N_XCD + x;
+    } else {
+        cls = (L - full) % nc;
+        t = full / nc + (L - full) / nc;
+    }
+    return TileIdx{t % gx, t / gx, cls};
+}
+
 // Loads of one stage into registers: along K, thread t covers row t/4 at
 // k offsets 8 (t%4) and 32 + 8 (t%4); K-major, k t%64 at rows 8 (t/64) and
 // 32 + 8 (t/64).
@@ -481,14 +515,21 @@ __device__ __forceinline__ void wide_store(const WideRegs<void, R>& r, __bf16 (*
 }
 
 template <class Op, int WM, int WN, int JT = 4>
-__global__ __launch_bounds__(256) void k_gemm_wide(Op op, int M, int N, int K, int k_per_split) {
+__global__ __launch_bounds__(256) void k_gemm_wide(Op op0, int M, int N, int K, int k_per_split) {
     constexpr int TM = 64 * WM, TN = 16 * JT * WN;   // each wave: 64 x 16 JT outputs
+    constexpr bool CLS = has_classes<Op>::value;
     __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSK];
     __bf16 (*As)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem);
     __bf16 (*Bs)[LDSK] = reinterpret_cast<__bf16 (*)[LDSK]>(smem + TM * LDSK);
-    const TileIdx tb = xcd_tile();
+    const TileIdx tb = CLS ? class_tile() : xcd_tile();
+    Op op = op0;
+    if constexpr (CLS) {
+        op.set_class(tb.z);
+        K = op.class_k();
+        k_per_split = K;
+    }
     const int m0 = tb.x * TM, n0 = tb.y * TN;
-    const int kbeg = tb.z * k_per_split;
+    const int kbeg = CLS ? 0 : tb.z * k_per_split;
     const int kend = min(K, kbeg + k_per_split);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w / WN, wn = w % WN;
@@ -813,6 +854,18 @@ struct OpConvDgradS2 {
     }
 };
 
+// The four parity classes of OpConvDgradS2 in one launch (gridDim.z = 4,
+// class c = 2 py + px, K = taps(c) Cout), so that the classes of one output
+// tile, which read the same dZ rows, run back to back on one XCD.
+struct OpConvDgradS2All : OpConvDgradS2 {
+    static constexpr bool CLASSES = true;
+    __device__ void set_class(int c) {
+        py = c >> 1;
+        px = c & 1;
+    }
+    __device__ int class_k() const { return ((py ? 2 : 1) * (px ? 2 : 1)) << s.lCout; }
+};
+
 // weight gradient (split over K = B*Ho*Wo): dW[co][tap*Cin+ci] partial per split.
 // A(m = co, k = pos) = dZ[pos][co]: K-major; B(k = pos, n = (tap, ci)) =
 // in[b, s y + ky - 1, s x + kx - 1, ci]: K-major when Cin >= 8, else gathered.
@@ -988,6 +1041,19 @@ static hipError_t gemm_pick(const Op& op, int M, int N, int K, int splits, hipSt
         return gemm(op, M, N, K, splits, st);
     }
     return hipGetLastError();
+}
+
+// One launch over nc classes of an op with CLASSES, for outputs of at most
+// 32 columns (the 256 x 32 tile, no K split); false for other shapes, whose
+// classes the caller launches one by one.  Measured on the network's
+// stride-2 data gradients at batch 1024: the first (32 channels, 64 x 64
+// output) 265 -> 219 us in one launch; the 64- and 128-channel ones gain
+// nothing (135 -> 133 us) or lose (79 -> 87 us) with their wider tiles.
+template <class Op>
+static bool gemm_classes(const Op& op, int M, int N, int nc, hipStream_t st) {
+    if (!(N <= 32 && M >= 256)) return false;
+    hipLaunchKernelGGL((k_gemm_wide<Op, 4, 1, 2>), dim3((M + 255) / 256, 1, nc), dim3(256), 0, st, op, M, N, 0, 0);
+    return true;
 }
 
 static int gemm_splits(int M, int N, int K, int splits) {
@@ -1528,14 +1594,25 @@ hipError_t cnn_backward(CnnNet& net, int B, const __bf16* img, const float* targ
             OpConvDgrad dg{s, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};
             if (gemm_pick(dg, B * H * H, L.cin, 9 * L.cout, 1, st) != hipSuccess) return hipErrorLaunchFailure;
         } else if (l > 0) {
-            // stride 2: the four input-parity classes, each over its 1, 2, 2 or 4 taps
-            for (int py = 0; py < 2; ++py)
-                for (int px = 0; px < 2; ++px) {
-                    OpConvDgradS2 dg{s, py, px, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};
-                    const int ntap = (py ? 2 : 1) * (px ? 2 : 1);
-                    if (gemm_pick(dg, B * Hout * Hout, L.cin, ntap * L.cout, 1, st) != hipSuccess)
-                        return hipErrorLaunchFailure;
-                }
+            // stride 2: the four input-parity classes, each over its 1, 2, 2 or 4 taps,
+            // in one launch where the shape takes a wide tile
+            OpConvDgradS2All all{};
+            all.s = s;
+            all.dz = net.dact[l];
+            all.w = net.wbf + L.w_off;
+            all.prev = net.act[l - 1];
+            all.dprev = net.dact[l - 1];
+            if (gemm_classes(all, B * Hout * Hout, L.cin, 4, st)) {
+                if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+            } else {
+                for (int py = 0; py < 2; ++py)
+                    for (int px = 0; px < 2; ++px) {
+                        OpConvDgradS2 dg{s, py, px, net.dact[l], net.wbf + L.w_off, net.act[l - 1], net.dact[l - 1]};
+                        const int ntap = (py ? 2 : 1) * (px ? 2 : 1);
+                        if (gemm_pick(dg, B * Hout * Hout, L.cin, ntap * L.cout, 1, st) != hipSuccess)
+                            return hipErrorLaunchFailure;
+                    }
+            }
         }
         Hout = H;
     }
