@@ -1115,18 +1115,42 @@ __global__ __launch_bounds__(256) void k_conv0_fwd(const __bf16* __restrict__ im
     }
 }
 
+// Rows r and r + 1 of the zero-bordered image as bf16 pairs: pairs[r][c] =
+// (tile[r][c], tile[r + 1][c]) in the low and high halves, tile row r being
+// image row r - 1 (the staging of c0_stage_image, two rows at once).
+__device__ __forceinline__ void c0_stage_pairs(const __bf16* __restrict__ img, uint32_t (*pairs)[C0_SIDE]) {
+    auto px = [&](int y, int x) -> uint32_t {
+        return (y >= 0 && y < CNN_IN && x >= 0 && x < CNN_IN)
+                   ? (uint32_t)__builtin_bit_cast(unsigned short, img[y * CNN_IN + x])
+                   : 0u;
+    };
+    for (int q = threadIdx.x; q < (C0_SIDE - 1) * C0_SIDE; q += blockDim.x) {
+        const int r = q / C0_SIDE, c = q % C0_SIDE;
+        pairs[r][c] = px(r - 1, c - 1) | (px(r, c - 1) << 16);
+    }
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// a.x b.x + a.y b.y + c (bf16 products are exact in float)
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
+}
+
 // Per image b: part[b][co][q] = sum over pixels of dZ[b, y, x, co] times
 // in[b, y + ky - 1, x + kx - 1] (q = 3 ky + kx < 9) or times 1 (q = 9: the
-// bias gradient).  Each thread sums its 64 rows in float; the 16 pixel
-// columns of a wave are combined by a fixed butterfly, the four waves in
-// LDS in float64, in fixed order.
+// bias gradient).  Thread t = 4 x + g takes pixel column x and channels
+// 8 g .. 8 g + 7 and sums its 64 rows in float, two rows at a time: each
+// pair of products (row y, row y + 1) is one bf16 dot instruction.  The 16
+// pixel columns of a wave are combined by a fixed butterfly, the four waves
+// in LDS in float64, in fixed order.
 __global__ __launch_bounds__(256) void k_conv0_wgrad(const __bf16* __restrict__ img, const __bf16* __restrict__ dz,
                                                      double* __restrict__ part) {
-    __shared__ float tile[C0_SIDE][C0_SIDE];
+    __shared__ uint32_t pairs[C0_SIDE - 1][C0_SIDE];
     __shared__ double red[4][C0_OUT * 10];
     const int b = blockIdx.x;
     const int t = threadIdx.x, g = t & 3, x = t >> 2, lane = t & 63, wv = t >> 6;
-    c0_stage_image(img + (size_t)b * CNN_IN * CNN_IN, tile);
+    c0_stage_pairs(img + (size_t)b * CNN_IN * CNN_IN, pairs);
     __syncthreads();
     float acc[8][10];
 #pragma unroll
@@ -1139,26 +1163,38 @@ __global__ __launch_bounds__(256) void k_conv0_wgrad(const __bf16* __restrict__ 
     // per SIMD to hide the latency)
     constexpr int PF = 4;
     constexpr size_t ROW = (size_t)CNN_IN * C0_OUT;
+    constexpr uint32_t ONES = 0x3F803F80u;   // bf16 (1, 1)
     bf16x8 ring[PF];
 #pragma unroll
     for (int q = 0; q < PF; ++q) ring[q] = *reinterpret_cast<const bf16x8*>(d + q * ROW);
     for (int y0 = 0; y0 < CNN_IN; y0 += PF) {
 #pragma unroll
-        for (int q = 0; q < PF; ++q) {
+        for (int q = 0; q < PF; q += 2) {
             const int y = y0 + q;
-            const bf16x8 dv = ring[q];
-            if (y + PF < CNN_IN) ring[q] = *reinterpret_cast<const bf16x8*>(d + (y + PF) * ROW);
-            float v[9];
+            const bf16x8 d0 = ring[q], d1 = ring[q + 1];
+            if (y + PF < CNN_IN) {
+                ring[q] = *reinterpret_cast<const bf16x8*>(d + (y + PF) * ROW);
+                ring[q + 1] = *reinterpret_cast<const bf16x8*>(d + (y + 1 + PF) * ROW);
+            }
+            uint32_t v[9];
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-                for (int kx = 0; kx < 3; ++kx) v[3 * ky + kx] = tile[y + ky][x + kx];
+                for (int kx = 0; kx < 3; ++kx) v[3 * ky + kx] = pairs[y + ky][x + kx];
+            const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&d0);
+            const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&d1);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const float dc = from_bf16(dv[c]);
+            for (int k = 0; k < 4; ++k) {
+                // channels 2k and 2k + 1 of rows y and y + 1 as (row y, row y + 1) pairs
+                const uint32_t lo = __builtin_amdgcn_perm(w1[k], w0[k], 0x05040100u);
+                const uint32_t hi = __builtin_amdgcn_perm(w1[k], w0[k], 0x07060302u);
 #pragma unroll
-                for (int r = 0; r < 9; ++r) acc[c][r] = fmaf(dc, v[r], acc[c][r]);
-                acc[c][9] += dc;
+                for (int r = 0; r < 9; ++r) {
+                    acc[2 * k][r] = dot2(lo, v[r], acc[2 * k][r]);
+                    acc[2 * k + 1][r] = dot2(hi, v[r], acc[2 * k + 1][r]);
+                }
+                acc[2 * k][9] = dot2(lo, ONES, acc[2 * k][9]);
+                acc[2 * k + 1][9] = dot2(hi, ONES, acc[2 * k + 1][9]);
             }
         }
     }
