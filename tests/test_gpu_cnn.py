@@ -27,8 +27,22 @@ def test_exact_arithmetic_forward_and_gradients_match_oracle(B):
     so the network output agrees bit for bit.  Every gradient entry agrees
     to the float rounding of its own sum: |a - r| <= 2^-16 (|r| + S), S the
     sum of |terms| of that entry (a chain of fp32 MFMA accumulations over a
-    K-split, then the fixed-order float64 sum of the splits).  B = 64 gives
-    the first layer's weight gradient 128 K-splits."""
+    K-split, then the fixed-order float64 sum of the splits).  B = 64: the
+    first 32 x 32 layers' weight gradients sum 32 K-splits."""
+    _check_exact(B)
+
+
+def test_exact_arithmetic_batch_256_split_sums_and_chunks():
+    """B = 256 (the oracle takes ~30 s on the host): the weight gradients of
+    the two 32 x 32 layers sum 128 K-splits of 2048 positions through the
+    coalesced split-sum kernel (four wave groups of 32 splits), their bias
+    gradients take 1024-row chunks and the first stride-2 data gradient runs
+    its four parity classes as one launch of 4096 work-groups: the code
+    paths of the 1024-image training batch.  Bounds as above."""
+    _check_exact(256)
+
+
+def _check_exact(B):
     p, img, tgt = cnn_cases.exact_case(B)
     net = lens.Cnn(B, 0, DEV)
     net.set_params(torch.tensor(p, dtype=torch.float32))
@@ -51,8 +65,8 @@ def test_exact_arithmetic_forward_and_gradients_match_oracle(B):
 
 @pytest.mark.parametrize("B", [5, 16, 64])
 def test_random_network_close_to_oracle(B):
-    """B = 64 gives the first layer's weight gradient 128 K-splits (the
-    wave-parallel split sum)."""
+    """B = 5, 16, 64: ragged and full tiles of every GEMM shape; at B = 64
+    the 32 x 32 layers' weight gradients sum 32 K-splits."""
     rng = np.random.default_rng(21)
     net = lens.Cnn(B, 5, DEV)
     p = net.get_params().cpu().numpy().astype(np.float64)

@@ -94,7 +94,7 @@ def _finest_unit(t):
     return float((2.0 ** (torch.floor(torch.log2(a)) - 7)).min())
 
 
-@pytest.mark.parametrize("batch", [cnn_cases.EXACT_BATCH, 64])
+@pytest.mark.parametrize("batch", [cnn_cases.EXACT_BATCH, 64, 256])
 def test_exact_fixture_partial_sums_fit_fp32(batch):
     """The sparse-integer fixture used for the bitwise kernel comparison:
     every forward and data-gradient sum, bounded by the sum of absolute
