@@ -1034,6 +1034,13 @@ __global__ __launch_bounds__(256) void k_adjoint_sh(const float* __restrict__ co
 // Register-blocked correlation of an LDS tile with a K x K kernel:
 // m[r] = sum_{u,v} w[u][v] tile[i+u][j0+v+r]; accumulator type T (float64 for
 // the model convolution, float32 for the adjoint).
+// Global-memory load through a pointer the compiler cannot place (one read
+// from a descriptor in memory would otherwise be a flat load).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
 template <int K, int RW, typename T>
 __device__ __forceinline__ void correlate(const float* lds, int stride, int i, int j0,
                                           const T* __restrict__ w, T (&m)[RW]) {
@@ -1055,7 +1062,10 @@ __device__ __forceinline__ void correlate(const float* lds, int stride, int i, i
         const T* wr = w + u * K;
 #pragma unroll
         for (int v = 0; v < K; ++v) {
-            const T wv = wr[v];
+            // PSF weights: wave-uniform, read-only during the kernel, read as
+            // constant memory so that they are scalar loads also where the
+            // pointer comes from a descriptor in memory (batch plans)
+            const T wv = *(const __attribute__((address_space(4))) T*)(wr + v);
 #pragma unroll
             for (int r = 0; r < RW; ++r) m[r] = fma(wv, seg[v + r], m[r]);
         }
@@ -1116,8 +1126,8 @@ __device__ __forceinline__ void psf_body(float valid, const Geo& g, float* buf,
                 if (MODE == 0) {
                     out[idx] = (float)m[r];
                 } else {
-                    const double dlt = (double)data[idx] - m[r];
-                    const double w = (double)invvar[idx];
+                    const double dlt = (double)ldg(data + idx) - m[r];
+                    const double w = (double)ldg(invvar + idx);
                     chi = fma(w * dlt, dlt, chi);
                     if (MODE == 2) buf[idx] = (float)(w * dlt);
                 }
@@ -1431,8 +1441,8 @@ __global__ __launch_bounds__(256) void k_psf_tile(const float* __restrict__ cons
                 if (MODE == 0) {
                     out[base + idx] = (float)m[r];
                 } else {
-                    const double dlt = (double)data[idx] - m[r];
-                    const double w = (double)invvar[idx];
+                    const double dlt = (double)ldg(data + idx) - m[r];
+                    const double w = (double)ldg(invvar + idx);
                     chi = fma(w * dlt, dlt, chi);
                     if (MODE == 2) res[base + idx] = (float)(w * dlt);
                 }
