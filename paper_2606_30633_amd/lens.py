@@ -13,7 +13,9 @@ from typing import Optional, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblens.so")
+# LENS_LIB selects another build of the same library (the sanitizer-instrumented
+# one of the host-code checks); by default the in-tree liblens.so.
+LIB_PATH = os.environ.get("LENS_LIB") or os.path.join(_HERE, "liblens.so")
 
 LENS_OK, LENS_EINVAL, LENS_EUNSUPPORTED, LENS_EHIP, LENS_ENOMEM, LENS_ESCRATCH = 0, -1, -2, -3, -4, -5
 LENS_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
